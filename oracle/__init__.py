@@ -1,0 +1,335 @@
+"""CPU oracle for the MCF phase-unwrapping hot path (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It wraps ``ww_oracle.c`` (plain C,
+single-threaded, FP64 and integer arithmetic, built with gcc -O2
+-ffp-contract=off) and shares no code, header or table with the HIP library.
+
+Parity status by function (the pins live in ``tests/test_oracle_*.py``):
+  residues         pinned (exact rationals, vortex closed form, Stokes)
+  f_eta, touzi     pinned (300-digit published forms, closed forms, norms)
+  ftilde, mass     pinned (adaptive quadrature, normalisation, symmetry)
+  sigma_alpha      parity unpinned as to the paper's formula (uniform limit pinned)
+  build_lut        table values parity unpinned (the paper prints none);
+                   shape properties of Section II-B pinned
+  edge_costs       pinned (independent numpy recomputation, mirror, mask, cap)
+  mcf              pinned (brute force, LP optimum, network simplex, certificate)
+  integrate        pinned (path independence, congruence, exact recovery)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ww_oracle.c")
+_LIB = os.path.join(_HERE, "libww_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+OK, E_INVALID_ARG, E_OOM, E_INFEASIBLE, E_CERT = 0, -1, -2, -3, -6
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (single-threaded, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            _lib = C.CDLL(build())
+            _declare(_lib)
+    return _lib
+
+
+P = C.c_void_p
+I32 = C.c_int
+I64 = C.c_int64
+D = C.c_double
+
+
+class LutParams(C.Structure):
+    _fields_ = [("n_alpha", C.c_int32), ("n_gamma", C.c_int32), ("n_eta", C.c_int32),
+                ("n_gpanel", C.c_int32), ("n_gnode", C.c_int32), ("n_aquad", C.c_int32),
+                ("sigma_span", C.c_double)]
+
+
+def lut_params(n_alpha=128, n_gamma=64, n_eta=2048, n_gpanel=64, n_gnode=16, n_aquad=513,
+               sigma_span=8.0) -> LutParams:
+    return LutParams(n_alpha, n_gamma, n_eta, n_gpanel, n_gnode, n_aquad, sigma_span)
+
+
+def _declare(L):
+    L.wwo_residues.argtypes = [P, P, I32, I32, P, P, P]
+    L.wwo_f_eta.argtypes = [D, D, I32]
+    L.wwo_f_eta.restype = D
+    L.wwo_touzi.argtypes = [D, D, I32]
+    L.wwo_touzi.restype = D
+    L.wwo_gauss_legendre.argtypes = [I32, P, P]
+    L.wwo_ftilde.argtypes = [I32, D, P, P]
+    L.wwo_edge_mass.argtypes = [P, I32, P]
+    L.wwo_branch_q.argtypes = [P, I32, D, P, P]
+    L.wwo_slope_marginal.argtypes = [P, I32, D, D, I32, D, P, P]
+    L.wwo_sigma_alpha.argtypes = [D, I32, I32]
+    L.wwo_sigma_alpha.restype = D
+    L.wwo_build_lut.argtypes = [I32, P, P, P, P, P]
+    L.wwo_edge_costs.argtypes = [P, P, P, I32, I32, P, I32, I32, I32, I32, D, I32, P, P, P, P, P]
+    L.wwo_mcf.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P, P]
+    L.wwo_check_optimal.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P]
+    L.wwo_fixed_edges.argtypes = [I32, I32, P, P, P, P, P, P, P, P, P]
+    L.wwo_integrate.argtypes = [P, P, P, P, I32, I32, I32, I32, C.c_float, P, P]
+    L.wwo_certified_pixels.argtypes = [I32, I32, P, P, I64, P, P]
+    L.wwo_bruteforce.argtypes = [I32, I32, P, P, P, P, P, P, P, P]
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what} failed with status {code}")
+        self.code = code
+
+
+def _chk(rc, what):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+# ---------------------------------------------------------------- residues ---
+
+def residues(psi, valid=None):
+    """(res int8 [(m-1),(n-1)], perim int8 [2(n-1)+2(m-1)], ground int)."""
+    psi = _c(psi, np.float32)
+    valid = _c(valid, np.uint8)
+    m, n = psi.shape
+    res = np.zeros((max(m - 1, 0), max(n - 1, 0)), np.int8)
+    perim = np.zeros(max(2 * (n - 1) + 2 * (m - 1), 0), np.int8)
+    g = np.zeros(1, np.int64)
+    _chk(lib().wwo_residues(_p(psi), _p(valid), m, n, _p(res), _p(perim), _p(g)), "residues")
+    return res, perim, int(g[0])
+
+
+# --------------------------------------------------------------------- LUT ---
+
+def f_eta(eta, gamma, L):
+    return lib().wwo_f_eta(float(eta), float(gamma), int(L))
+
+
+def touzi(gh, gamma, L):
+    return lib().wwo_touzi(float(gh), float(gamma), int(L))
+
+
+def gauss_legendre(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().wwo_gauss_legendre(n, _p(x), _p(w))
+    return x, w
+
+
+def ftilde(L, gh, params=None):
+    params = params or lut_params()
+    out = np.zeros(params.n_eta)
+    _chk(lib().wwo_ftilde(L, float(gh), C.byref(params), _p(out)), "ftilde")
+    return out
+
+
+def edge_mass(ft):
+    ft = _c(ft, np.float64)
+    N = ft.shape[0]
+    pm = np.zeros(2 * N - 1)
+    lib().wwo_edge_mass(_p(ft), N, _p(pm))
+    return pm
+
+
+def branch_q(pm, alpha):
+    pm = _c(pm, np.float64)
+    N = (pm.shape[0] + 1) // 2
+    q0 = np.zeros(1)
+    qp = np.zeros(1)
+    _chk(lib().wwo_branch_q(_p(pm), N, float(alpha), _p(q0), _p(qp)), "branch_q")
+    return float(q0[0]), float(qp[0])
+
+
+def slope_marginal(pm, alpha_hat, sigma, n_aquad=513, span=8.0):
+    """(P0, P+) of eq. 7 for edge-noise masses pm."""
+    pm = _c(pm, np.float64)
+    N = (pm.shape[0] + 1) // 2
+    P0 = np.zeros(1)
+    Pp = np.zeros(1)
+    _chk(lib().wwo_slope_marginal(_p(pm), N, float(alpha_hat), float(sigma), int(n_aquad),
+                                  float(span), _p(P0), _p(Pp)), "slope_marginal")
+    return float(P0[0]), float(Pp[0])
+
+
+def sigma_alpha(gh, L, n_eta=2048):
+    return lib().wwo_sigma_alpha(float(gh), int(L), int(n_eta))
+
+
+def build_lut(L, params=None, want_probs=False):
+    """int16 table [n_gamma, n_alpha] (+ P0, P+, sigma_alpha if asked)."""
+    params = params or lut_params()
+    T = np.zeros((params.n_gamma, params.n_alpha), np.int16)
+    P0 = np.zeros((params.n_gamma, params.n_alpha)) if want_probs else None
+    Pp = np.zeros((params.n_gamma, params.n_alpha)) if want_probs else None
+    sg = np.zeros(params.n_gamma) if want_probs else None
+    _chk(lib().wwo_build_lut(int(L), C.byref(params), _p(T), _p(P0), _p(Pp), _p(sg)), "build_lut")
+    if want_probs:
+        return T, P0, Pp, sg
+    return T
+
+
+# ------------------------------------------------------------------- costs ---
+
+def edge_costs(psi, coh, valid, lut, box_half=2, steep_rule=1, steep_thresh=1.0, steep_cap_pct=3,
+               want_stats=False):
+    psi = _c(psi, np.float32)
+    coh = _c(coh, np.float32)
+    valid = _c(valid, np.uint8)
+    lut = _c(lut, np.int16)
+    m, n = psi.shape
+    ng, na = lut.shape
+    cxp = np.zeros((m, max(n - 1, 0)), np.int16)
+    cxn = np.zeros_like(cxp)
+    cyp = np.zeros((max(m - 1, 0), n), np.int16)
+    cyn = np.zeros_like(cyp)
+    st = np.zeros(3, np.int64)
+    _chk(lib().wwo_edge_costs(_p(psi), _p(coh), _p(valid), m, n, _p(lut), na, ng, box_half,
+                              steep_rule, float(steep_thresh), steep_cap_pct,
+                              _p(cxp), _p(cxn), _p(cyp), _p(cyn), _p(st)), "edge_costs")
+    out = (cxp, cxn, cyp, cyn)
+    if want_stats:
+        return out, dict(valid_edges=int(st[0]), steep_candidates=int(st[1]), steep_zeroed=int(st[2]))
+    return out
+
+
+# --------------------------------------------------------------------- MCF ---
+
+def mcf(res, costs, m=None, n=None, want_stats=False):
+    """Successive shortest paths.  Returns (dk_x, dk_y, pot, total_cost)."""
+    res = _c(res, np.int8)
+    cxp, cxn, cyp, cyn = [_c(c, np.int16) for c in costs]
+    if m is None:
+        m, n = cxp.shape[0], cyp.shape[1]
+    dkx = np.zeros((m, max(n - 1, 0)), np.int8)
+    dky = np.zeros((max(m - 1, 0), n), np.int8)
+    pot = np.zeros(max((m - 1) * (n - 1), 0) + 1, np.int64)
+    tot = np.zeros(1, np.int64)
+    st = np.zeros(3, np.int64)
+    _chk(lib().wwo_mcf(_p(res), m, n, _p(cxp), _p(cxn), _p(cyp), _p(cyn), _p(dkx), _p(dky),
+                       _p(pot), _p(tot), _p(st)), "mcf")
+    out = (dkx, dky, pot, int(tot[0]))
+    if want_stats:
+        return out, dict(augmentations=int(st[0]), settled=int(st[1]), scanned=int(st[2]))
+    return out
+
+
+def check_optimal(res, costs, dkx, dky, pot):
+    """Return dict(ok, divergence_violations, negative_reduced_costs, min_reduced_cost)."""
+    res = _c(res, np.int8)
+    cxp, cxn, cyp, cyn = [_c(c, np.int16) for c in costs]
+    dkx = _c(dkx, np.int8)
+    dky = _c(dky, np.int8)
+    pot = _c(pot, np.int64)
+    m, n = cxp.shape[0], cyp.shape[1]
+    out = np.zeros(3, np.int64)
+    rc = lib().wwo_check_optimal(_p(res), m, n, _p(cxp), _p(cxn), _p(cyp), _p(cyn), _p(dkx),
+                                 _p(dky), _p(pot), _p(out))
+    if rc not in (OK, E_CERT):
+        raise OracleError(rc, "check_optimal")
+    return dict(ok=rc == OK, divergence_violations=int(out[0]),
+                negative_reduced_costs=int(out[1]), min_reduced_cost=int(out[2]))
+
+
+def fixed_edges(costs, dkx, dky, pot):
+    cxp, cxn, cyp, cyn = [_c(c, np.int16) for c in costs]
+    dkx = _c(dkx, np.int8)
+    dky = _c(dky, np.int8)
+    pot = _c(pot, np.int64)
+    m, n = cxp.shape[0], cyp.shape[1]
+    fx = np.zeros(dkx.shape, np.uint8)
+    fy = np.zeros(dky.shape, np.uint8)
+    _chk(lib().wwo_fixed_edges(m, n, _p(cxp), _p(cxn), _p(cyp), _p(cyn), _p(dkx), _p(dky),
+                               _p(pot), _p(fx), _p(fy)), "fixed_edges")
+    return fx, fy
+
+
+def certified_pixels(fx, fy, ref):
+    fx = _c(fx, np.uint8)
+    fy = _c(fy, np.uint8)
+    m, n = fx.shape[0], fy.shape[1]
+    cert = np.zeros((m, n), np.uint8)
+    comp = np.zeros((m, n), np.int64)
+    _chk(lib().wwo_certified_pixels(m, n, _p(fx), _p(fy), int(ref), _p(cert), _p(comp)),
+         "certified_pixels")
+    return cert.astype(bool), comp
+
+
+# --------------------------------------------------------------- integrate ---
+
+def integrate(psi, valid, dkx, dky, ref=None, nodata=float("nan")):
+    psi = _c(psi, np.float32)
+    valid = _c(valid, np.uint8)
+    dkx = _c(dkx, np.int8)
+    dky = _c(dky, np.int8)
+    m, n = psi.shape
+    K = np.zeros((m, n), np.int32)
+    phi = np.zeros((m, n), np.float32)
+    ri, rj = (-1, -1) if ref is None else ref
+    _chk(lib().wwo_integrate(_p(psi), _p(valid), _p(dkx), _p(dky), m, n, ri, rj,
+                             C.c_float(nodata), _p(K), _p(phi)), "integrate")
+    return K, phi
+
+
+def ref_index(valid, m, n):
+    if valid is None:
+        return 0
+    v = np.asarray(valid).reshape(-1)
+    nz = np.flatnonzero(v)
+    return int(nz[0]) if nz.size else 0
+
+
+# ------------------------------------------------------------- brute force ---
+
+def bruteforce(wx, wy, costs):
+    wx = _c(wx, np.int8)
+    wy = _c(wy, np.int8)
+    cxp, cxn, cyp, cyn = [_c(c, np.int16) for c in costs]
+    m, n = cxp.shape[0], cyp.shape[1]
+    best = np.zeros(1, np.int64)
+    cnt = np.zeros(1, np.int64)
+    _chk(lib().wwo_bruteforce(m, n, _p(wx), _p(wy), _p(cxp), _p(cxn), _p(cyp), _p(cyn),
+                              _p(best), _p(cnt)), "bruteforce")
+    return int(best[0]), int(cnt[0])
+
+
+# ------------------------------------------------------------ whole path ----
+
+def unwrap(psi, coh, valid, looks, lut=None, box_half=2, steep_rule=1, want=False):
+    """Residues -> LUT -> costs -> SSP -> integration, all on the CPU."""
+    if lut is None:
+        lut = build_lut(looks)
+    res, perim, ground = residues(psi, valid)
+    costs = edge_costs(psi, coh, valid, lut, box_half=box_half, steep_rule=steep_rule)
+    dkx, dky, pot, total = mcf(res, costs, m=psi.shape[0], n=psi.shape[1])
+    K, phi = integrate(psi, valid, dkx, dky)
+    if want:
+        return dict(res=res, perim=perim, ground=ground, costs=costs, dkx=dkx, dky=dky, pot=pot,
+                    total=total, K=K, phi=phi, lut=lut)
+    return K, phi, total
