@@ -1,0 +1,185 @@
+/*
+ * ww.h -- C ABI of the MI355X (gfx950) minimum-cost-flow phase unwrapper.
+ *
+ * The calls follow the problem statement of Section II-A of "A
+ * Probabilistic-Cost Algorithm for Large-Scale 2D Phase Unwrapping": a
+ * wrapped phase psi in (-pi, pi], a sample coherence per pixel (eq. 3), the
+ * number of looks L and a validity mask go in; the integer cycle field K and
+ * the unwrapped phase phi = psi + 2 pi K come out.
+ *
+ * Conventions shared by every call
+ *   - Images are row-major, m rows (slow axis i) by n columns (fast axis j),
+ *     contiguous, no padding.  1 <= m, n and m*n < 2^31.
+ *   - x-edge hx(i,j) joins pixel (i,j) to (i,j+1): array of m*(n-1).
+ *     y-edge vy(i,j) joins pixel (i,j) to (i+1,j): array of (m-1)*n.
+ *     loop p(i,j) has corners (i,j),(i,j+1),(i+1,j+1),(i+1,j): (m-1)*(n-1).
+ *   - Pointers without a _host suffix are DEVICE pointers on the current HIP
+ *     device; the caller allocates and owns them.  The library owns only its
+ *     internal workspace and its cost-table cache, which it keeps until the
+ *     process ends.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls that return a value through a _host
+ *     pointer synchronise that stream before returning.
+ *   - No exception crosses the ABI.  A non-zero status leaves the outputs
+ *     unspecified; ww_last_error() then describes it (per thread).
+ *   - Repeated calls with the same inputs produce identical bytes.
+ */
+#ifndef WW_H
+#define WW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ww_status;
+#define WW_OK 0
+#define WW_E_INVALID_ARG (-1) /* bad shape, NULL pointer or parameter      */
+#define WW_E_OOM (-2)         /* device or host allocation failed          */
+#define WW_E_INFEASIBLE (-3)  /* a supply can reach no demand              */
+#define WW_E_DEVICE (-4)      /* a HIP call failed                         */
+#define WW_E_OVERFLOW (-5)    /* an integer range guard tripped            */
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *ww_last_error(void);
+
+/* Library version string. */
+const char *ww_version(void);
+
+/* Discretisation of the cost table of Section II-B (eqs. 4-7).
+ *   n_alpha  slope bins over [-pi, pi] (bin centres -pi + (b+1/2) 2pi/n_alpha)
+ *   n_gamma  coherence bins over [0, 1] (bin centres (c+1/2)/n_gamma)
+ *   n_eta    phase-noise samples over (-pi, pi] (midpoints)
+ *   n_gpanel, n_gnode  composite Gauss-Legendre rule over the true coherence
+ *            for the marginalisation of eq. 5 (panels x nodes per panel)
+ *   n_aquad  nodes of the slope marginalisation of eq. 7 over
+ *            alpha_hat +- sigma_span * sigma_alpha                        */
+typedef struct {
+    int32_t n_alpha, n_gamma, n_eta, n_gpanel, n_gnode, n_aquad;
+    double sigma_span;
+} ww_lut_params;
+
+/* Per-edge cost rules of Section II-B.
+ *   box_half      half-width h of the (2h+1)^2 slope box filter (>= 0)
+ *   steep_rule    1: edges with |wrapped gradient| > steep_thresh_rad cost 0,
+ *                 at most floor(steep_cap_pct * valid_edges / 100) of them
+ *   ref_i, ref_j  pixel with K = 0 (-1: first valid pixel, row-major)
+ *   nodata        phi written at invalid pixels                           */
+typedef struct {
+    int32_t box_half;
+    int32_t steep_rule;
+    double steep_thresh_rad;
+    int32_t steep_cap_pct;
+    int32_t ref_i, ref_j;
+    float nodata;
+} ww_cost_params;
+
+/* Solver counters (all optional outputs). */
+typedef struct {
+    int64_t passes;          /* multi-source shortest-path passes            */
+    int64_t windows;         /* distance windows processed                  */
+    int64_t rounds;          /* tile relaxation rounds (kernel launches)    */
+    int64_t tile_visits;     /* tiles relaxed, summed over rounds           */
+    int64_t augmentations;   /* unit augmenting paths                       */
+    int64_t path_arcs;       /* arcs flipped by augmentations               */
+    int64_t supplies;        /* initial positive charge incl. the ground    */
+    int64_t max_potential;   /* largest node potential at exit              */
+} ww_mcf_stats;
+
+/* Defaults: n_alpha 128, n_gamma 64, n_eta 2048, 64 x 16 Gauss-Legendre
+ * nodes, n_aquad 513, sigma_span 8; box_half 2, steep rule on at 1 rad and
+ * 3 %, reference = first valid pixel, nodata = NaN. */
+void ww_default_lut_params(ww_lut_params *p);
+void ww_default_cost_params(ww_cost_params *p);
+
+/* Residues, eq. 1 (Section II-A), and the balancing boundary charges of the
+ * outer ring of zero-cost, unbounded arcs (Section II-A).
+ *   psi    float32 [m*n] wrapped phase; pixels with valid == 0 are read as 0.
+ *   valid  uint8 [m*n] validity mask (non-zero = valid); NULL = all valid.
+ *   res    int8 [(m-1)*(n-1)] out: charge of loop p(i,j) in {-1,0,1}, loop
+ *          traversed (i,j)->(i,j+1)->(i+1,j+1)->(i+1,j).
+ *   perim  int8 [2(n-1)+2(m-1)] out, nullable: one-sided charges of the ring
+ *          beside the top x-edges, bottom x-edges, left y-edges, right
+ *          y-edges, in that order.
+ *   ground_charge_host  int64 out, nullable (synchronises): -(sum of res).
+ * Errors: WW_E_INVALID_ARG on m, n < 1 or NULL psi/res; WW_E_DEVICE. */
+ww_status ww_residues(const float *psi, const uint8_t *valid, int32_t m, int32_t n,
+                      int8_t *res, int8_t *perim, int64_t *ground_charge_host, void *stream);
+
+/* Integer cost table of Section II-B, eqs. 4-7: entry [c][b] is
+ * min(32767, floor(100 max{0, -ln(P+/P0)})) at coherence bin c and slope bin
+ * b; 32767 where P+ = 0.  Built in FP64 by HIP kernels on the current device
+ * and copied to the host buffer.
+ *   looks     number of looks L, 2 <= L <= 64.
+ *   p         discretisation, NULL = defaults.
+ *   lut_host  int16 [n_gamma * n_alpha] out, row = coherence bin.
+ * Synchronous.  Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
+ww_status ww_build_cost_lut(int32_t looks, const ww_lut_params *p, int16_t *lut_host);
+
+/* Per-edge integer costs of Section II-B.  For every edge e = (u -> v):
+ *   cx_pos/cy_pos  cost of the arc that raises the edge's cycle difference by
+ *                  one: T[bg][ba], ba = bin of the box-filtered wrapped
+ *                  gradient (fixed point 2^-20 rad, clipped window, samples
+ *                  with two valid endpoints), bg = bin of min(coh_u, coh_v);
+ *   cx_neg/cy_neg  the reverse correction: T[bg][n_alpha-1-ba];
+ * 0 for edges with an invalid endpoint and for the steep edges.
+ *   psi, coh  float32 [m*n]; coh is clamped to [0,1], NaN read as 0.
+ *   valid     uint8 [m*n], NULL = all valid.
+ *   lut       int16 [n_gamma*n_alpha] DEVICE copy of ww_build_cost_lut.
+ *   lp        table shape (only n_alpha, n_gamma are read), NULL = defaults.
+ *   cp        cost rules, NULL = defaults.
+ *   cx_pos, cx_neg  int16 [m*(n-1)] out; cy_pos, cy_neg int16 [(m-1)*n] out.
+ * Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
+ww_status ww_edge_costs(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
+                        int32_t n, const int16_t *lut, const ww_lut_params *lp,
+                        const ww_cost_params *cp, int16_t *cx_pos, int16_t *cx_neg,
+                        int16_t *cy_pos, int16_t *cy_neg, void *stream);
+
+/* Minimum-cost flow of eq. 2 (Section II-A) on the loop graph plus one
+ * ground node standing for the outer ring, solved exactly by successive
+ * shortest paths with potentials (Section II-C): every pass grows a
+ * shortest-path forest from all supplies at once over integer reduced costs
+ * and augments one unit along vertex-disjoint forest paths.
+ *   res      int8 [(m-1)*(n-1)] loop charges (supply +1, demand -1).
+ *   costs    the four int16 planes of ww_edge_costs (all >= 0).
+ *   dk_x     int8 [m*(n-1)] out: cycle difference of each x-edge in {-1,0,1}.
+ *   dk_y     int8 [(m-1)*n] out: same for y-edges.
+ *   potentials  int64 [(m-1)*(n-1)+1] out, nullable: optimal node potentials
+ *            (ground last); every residual arc has cost - pot(u) + pot(v) >= 0.
+ *   total_cost_host  int64 out: sum of the costs of the chosen corrections.
+ *   stats_host  ww_mcf_stats out, nullable.
+ * Synchronous.  m or n = 1: no loops, zero flow, cost 0.
+ * Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_INFEASIBLE, WW_E_OVERFLOW,
+ * WW_E_DEVICE. */
+ww_status ww_mcf_solve(const int8_t *res, int32_t m, int32_t n, const int16_t *cx_pos,
+                       const int16_t *cx_neg, const int16_t *cy_pos, const int16_t *cy_neg,
+                       int8_t *dk_x, int8_t *dk_y, int64_t *potentials, int64_t *total_cost_host,
+                       ww_mcf_stats *stats_host, void *stream);
+
+/* Integration of the corrected gradients (Sections II-A, II-C): K(ref) = 0
+ * and K_v - K_u = dk_e - w_e along every edge, w_e the wrap count of psi;
+ * phi = (float)((double)psi + 2 pi K) at valid pixels, cp->nodata elsewhere.
+ *   psi, valid  as for ww_residues; dk_x, dk_y from ww_mcf_solve.
+ *   cp       reference pixel and nodata, NULL = defaults.
+ *   K        int32 [m*n] out (written at every pixel); phi float32 [m*n] out.
+ * Errors: WW_E_INVALID_ARG, WW_E_DEVICE. */
+ww_status ww_integrate(const float *psi, const uint8_t *valid, const int8_t *dk_x,
+                       const int8_t *dk_y, int32_t m, int32_t n, const ww_cost_params *cp,
+                       int32_t *K, float *phi, void *stream);
+
+/* The whole path: residues -> cost table (cached per L) -> edge costs ->
+ * min-cost flow -> integration, on one device with library workspace.
+ *   coh    float32 [m*n] sample coherence; looks as ww_build_cost_lut.
+ *   cp     NULL = defaults.   K, phi as ww_integrate.
+ *   total_cost_host  int64 out, nullable (the call synchronises anyway).
+ * Errors: as the five calls above. */
+ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
+                    int32_t n, int32_t looks, const ww_cost_params *cp, int32_t *K, float *phi,
+                    int64_t *total_cost_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WW_H */

@@ -1,0 +1,311 @@
+// C ABI entry points: argument checks, workspace, error reporting.  Every
+// numeric step runs in the HIP kernels of the sibling sources.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "ww_internal.h"
+
+namespace ww {
+
+static thread_local std::string g_error;
+
+ww_status fail(ww_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+std::mutex &lock() {
+    static std::mutex mu;
+    return mu;
+}
+
+int current_device() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return 0;
+    return d;
+}
+
+struct DeviceBuffers {
+    Buffer slot[SLOT_COUNT];
+};
+
+static std::map<int, DeviceBuffers> &buffers() {
+    static std::map<int, DeviceBuffers> b;
+    return b;
+}
+
+ww_status scratch(int slot, size_t bytes, void **out) {
+    if (bytes == 0) bytes = 256;
+    Buffer &b = buffers()[current_device()].slot[slot];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            // the buffer may still be read by queued work on any stream
+            WW_HIP(hipDeviceSynchronize());
+            WW_HIP(hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 8;
+        void *p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(WW_E_OOM, "device allocation of %zu bytes failed", want);
+        }
+        b.ptr = p;
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return WW_OK;
+}
+
+ww_status host_scratch(size_t bytes, void **out) {
+    static void *p = nullptr;
+    static size_t have = 0;
+    if (have < bytes) {
+        if (p) WW_HIP(hipHostFree(p));
+        p = nullptr;
+        have = 0;
+        if (hipHostMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(WW_E_OOM, "pinned host allocation of %zu bytes failed", bytes);
+        }
+        have = bytes;
+    }
+    *out = p;
+    return WW_OK;
+}
+
+ww_status check_lut_params(const ww_lut_params &p) {
+    if (p.n_alpha < 2 || p.n_alpha > 4096 || p.n_gamma < 1 || p.n_gamma > 4096 ||
+        p.n_eta < 8 || p.n_eta > 16384 || (p.n_eta & 1) || p.n_gpanel < 1 || p.n_gnode < 1 ||
+        p.n_gnode > 64 || (int64_t)p.n_gpanel * p.n_gnode > 65536 || p.n_aquad < 2 ||
+        p.n_aquad > 65536 || !(p.sigma_span > 0.0) || !(p.sigma_span < 64.0))
+        return fail(WW_E_INVALID_ARG, "cost-table parameters out of range");
+    return WW_OK;
+}
+
+ww_status check_cost_params(const ww_cost_params &p) {
+    if (p.box_half < 0 || p.box_half > 16)
+        return fail(WW_E_INVALID_ARG, "box_half must lie in [0, 16]");
+    if (p.steep_cap_pct < 0 || p.steep_cap_pct > 100 || !(p.steep_thresh_rad >= 0.0))
+        return fail(WW_E_INVALID_ARG, "steep-rule parameters out of range");
+    return WW_OK;
+}
+
+static ww_status check_shape(int32_t m, int32_t n) {
+    if (m < 1 || n < 1 || (int64_t)m * n >= ((int64_t)1 << 31))
+        return fail(WW_E_INVALID_ARG, "image shape %d x %d outside 1 <= m,n, m*n < 2^31", m, n);
+    return WW_OK;
+}
+
+// Device-resident cost tables, one per (device, looks, parameters).
+struct LutKey {
+    int dev, looks;
+    ww_lut_params p;
+    bool operator<(const LutKey &o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (looks != o.looks) return looks < o.looks;
+        return memcmp(&p, &o.p, sizeof(p)) < 0;
+    }
+};
+
+ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, const int16_t **out) {
+    static std::map<LutKey, int16_t *> cache;
+    LutKey key;
+    memset(&key, 0, sizeof(key));
+    key.dev = current_device();
+    key.looks = looks;
+    key.p = p;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return WW_OK;
+    }
+    int16_t *d = nullptr;
+    size_t bytes = sizeof(int16_t) * (size_t)p.n_alpha * p.n_gamma;
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(WW_E_OOM, "cost-table allocation failed");
+    }
+    ww_status s = build_lut_impl(looks, p, d, stream);
+    if (s != WW_OK) {
+        (void)hipFree(d);
+        return s;
+    }
+    cache[key] = d;
+    *out = d;
+    return WW_OK;
+}
+
+}  // namespace ww
+
+using namespace ww;
+
+extern "C" {
+
+const char *ww_last_error(void) { return g_error.c_str(); }
+
+const char *ww_version(void) { return "ww-gfx950 0.1"; }
+
+void ww_default_lut_params(ww_lut_params *p) {
+    if (!p) return;
+    p->n_alpha = 128;
+    p->n_gamma = 64;
+    p->n_eta = 2048;
+    p->n_gpanel = 64;
+    p->n_gnode = 16;
+    p->n_aquad = 513;
+    p->sigma_span = 8.0;
+}
+
+void ww_default_cost_params(ww_cost_params *p) {
+    if (!p) return;
+    p->box_half = 2;
+    p->steep_rule = 1;
+    p->steep_thresh_rad = 1.0;
+    p->steep_cap_pct = 3;
+    p->ref_i = -1;
+    p->ref_j = -1;
+    p->nodata = std::nanf("");
+}
+
+ww_status ww_residues(const float *psi, const uint8_t *valid, int32_t m, int32_t n, int8_t *res,
+                      int8_t *perim, int64_t *ground_charge_host, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    if (!psi || (!res && (int64_t)(m - 1) * (n - 1) > 0))
+        return fail(WW_E_INVALID_ARG, "psi and res must be non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t *gdev = nullptr;
+    WW_TRY(scratch(SLOT_COUNTERS, 64, (void **)&gdev));
+    WW_TRY(residues_impl(psi, valid, m, n, res, perim, gdev, st));
+    if (ground_charge_host) {
+        WW_HIP(hipMemcpyAsync(ground_charge_host, gdev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        WW_HIP(hipStreamSynchronize(st));
+    }
+    return WW_OK;
+}
+
+ww_status ww_build_cost_lut(int32_t looks, const ww_lut_params *pin, int16_t *lut_host) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    ww_lut_params p;
+    if (pin) p = *pin;
+    else ww_default_lut_params(&p);
+    WW_TRY(check_lut_params(p));
+    if (looks < 2 || looks > 64) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
+    if (!lut_host) return fail(WW_E_INVALID_ARG, "lut_host must be non-NULL");
+    const int16_t *d = nullptr;
+    WW_TRY(lut_device(looks, p, nullptr, &d));
+    WW_HIP(hipMemcpy(lut_host, d, sizeof(int16_t) * (size_t)p.n_alpha * p.n_gamma,
+                     hipMemcpyDeviceToHost));
+    return WW_OK;
+}
+
+ww_status ww_edge_costs(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
+                        int32_t n, const int16_t *lut, const ww_lut_params *lp,
+                        const ww_cost_params *cpin, int16_t *cx_pos, int16_t *cx_neg,
+                        int16_t *cy_pos, int16_t *cy_neg, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    ww_lut_params p;
+    if (lp) p = *lp;
+    else ww_default_lut_params(&p);
+    ww_cost_params cp;
+    if (cpin) cp = *cpin;
+    else ww_default_cost_params(&cp);
+    WW_TRY(check_cost_params(cp));
+    if (p.n_alpha < 2 || p.n_gamma < 1 || p.n_alpha > 4096 || p.n_gamma > 4096)
+        return fail(WW_E_INVALID_ARG, "table shape out of range");
+    if (!psi || !coh || !lut) return fail(WW_E_INVALID_ARG, "psi, coh and lut must be non-NULL");
+    if ((n > 1 && (!cx_pos || !cx_neg)) || (m > 1 && (!cy_pos || !cy_neg)))
+        return fail(WW_E_INVALID_ARG, "cost planes must be non-NULL");
+    return edge_costs_impl(psi, coh, valid, m, n, lut, p.n_alpha, p.n_gamma, cp, cx_pos, cx_neg,
+                           cy_pos, cy_neg, (hipStream_t)stream);
+}
+
+ww_status ww_mcf_solve(const int8_t *res, int32_t m, int32_t n, const int16_t *cx_pos,
+                       const int16_t *cx_neg, const int16_t *cy_pos, const int16_t *cy_neg,
+                       int8_t *dk_x, int8_t *dk_y, int64_t *potentials, int64_t *total_cost_host,
+                       ww_mcf_stats *stats_host, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    if (!total_cost_host) return fail(WW_E_INVALID_ARG, "total_cost_host must be non-NULL");
+    if ((m > 1 && n > 1 && !res) || (n > 1 && (!cx_pos || !cx_neg || !dk_x)) ||
+        (m > 1 && (!cy_pos || !cy_neg || !dk_y)))
+        return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    return mcf_impl(res, m, n, cx_pos, cx_neg, cy_pos, cy_neg, dk_x, dk_y, potentials,
+                    total_cost_host, stats_host, (hipStream_t)stream);
+}
+
+ww_status ww_integrate(const float *psi, const uint8_t *valid, const int8_t *dk_x,
+                       const int8_t *dk_y, int32_t m, int32_t n, const ww_cost_params *cpin,
+                       int32_t *K, float *phi, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    ww_cost_params cp;
+    if (cpin) cp = *cpin;
+    else ww_default_cost_params(&cp);
+    if (cp.ref_i >= 0 && (cp.ref_i >= m || cp.ref_j < 0 || cp.ref_j >= n))
+        return fail(WW_E_INVALID_ARG, "reference pixel outside the image");
+    if (!psi || !K || !phi || (n > 1 && !dk_x) || (m > 1 && !dk_y))
+        return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    return integrate_impl(psi, valid, dk_x, dk_y, m, n, cp, K, phi, (hipStream_t)stream);
+}
+
+ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
+                    int32_t n, int32_t looks, const ww_cost_params *cpin, int32_t *K, float *phi,
+                    int64_t *total_cost_host, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    if (looks < 2 || looks > 64) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
+    if (!psi || !coh || !K || !phi) return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    ww_cost_params cp;
+    if (cpin) cp = *cpin;
+    else ww_default_cost_params(&cp);
+    WW_TRY(check_cost_params(cp));
+    if (cp.ref_i >= 0 && (cp.ref_i >= m || cp.ref_j < 0 || cp.ref_j >= n))
+        return fail(WW_E_INVALID_ARG, "reference pixel outside the image");
+    hipStream_t st = (hipStream_t)stream;
+    ww_lut_params lp;
+    ww_default_lut_params(&lp);
+    const int16_t *lut = nullptr;
+    WW_TRY(lut_device(looks, lp, st, &lut));
+    int64_t nl = (int64_t)(m - 1) * (n - 1), nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
+    int8_t *res, *dkx, *dky;
+    int16_t *cxp, *cxn, *cyp, *cyn;
+    int64_t *gdev;
+    WW_TRY(scratch(SLOT_RES, nl, (void **)&res));
+    WW_TRY(scratch(SLOT_CXP, 2 * nx, (void **)&cxp));
+    WW_TRY(scratch(SLOT_CXN, 2 * nx, (void **)&cxn));
+    WW_TRY(scratch(SLOT_CYP, 2 * ny, (void **)&cyp));
+    WW_TRY(scratch(SLOT_CYN, 2 * ny, (void **)&cyn));
+    WW_TRY(scratch(SLOT_DKX, nx, (void **)&dkx));
+    WW_TRY(scratch(SLOT_DKY, ny, (void **)&dky));
+    WW_TRY(scratch(SLOT_COUNTERS, 64, (void **)&gdev));
+    WW_TRY(residues_impl(psi, valid, m, n, res, nullptr, gdev, st));
+    WW_TRY(edge_costs_impl(psi, coh, valid, m, n, lut, lp.n_alpha, lp.n_gamma, cp, cxp, cxn, cyp,
+                           cyn, st));
+    int64_t total = 0;
+    WW_TRY(mcf_impl(res, m, n, cxp, cxn, cyp, cyn, dkx, dky, nullptr, &total, nullptr, st));
+    WW_TRY(integrate_impl(psi, valid, dkx, dky, m, n, cp, K, phi, st));
+    WW_HIP(hipStreamSynchronize(st));
+    if (total_cost_host) *total_cost_host = total;
+    return WW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,364 @@
+// Per-edge integer arc costs (Section II-B).
+//
+// k_edge_costs: one workgroup per 16 x 64 pixel tile.  The tile's wrapped
+// phase and mask, plus a halo of h+1, are staged in LDS; each x- and y-edge
+// sample gets its wrapped gradient in 2^-20 rad fixed point; separable
+// integer box sums give the clipped (2h+1)^2 mean slope of every output edge,
+// which selects the slope bin; min(coh_u, coh_v) selects the coherence bin;
+// the table gather gives c+ and its mirror c-.  Masked edges cost 0.  Edges
+// steeper than the threshold are appended (wave-aggregated) to a candidate
+// list with the key (|d| as IEEE bits, edge id) for the steep rule.
+//
+// Steep rule: at most floor(pct * valid_edges / 100) candidates get cost 0,
+// the largest |d| first and ties by the smaller edge id (x-edges row-major,
+// then y-edges row-major).  The selection is an exact 96-bit radix select
+// over (|d| bits, ~id) decided on the device, so the zeroed set does not
+// depend on the order in which candidates were appended.
+#include <cmath>
+
+#include "ww_internal.h"
+
+namespace ww {
+
+constexpr int CT_H = 16;   // tile rows
+constexpr int CT_W = 64;   // tile cols
+constexpr int CT_THREADS = 256;
+
+struct SteepState {
+    unsigned long long nvalid, ncand, cap, remaining;
+    unsigned long long prefix_hi, mask_hi;
+    unsigned int prefix_lo, mask_lo;
+    unsigned int hist[256];
+};
+
+__device__ __forceinline__ int coh_bin(float c, int NG) {
+    double g = (double)c;
+    if (!(g > 0.0)) g = 0.0;  // NaN and negatives read as 0
+    if (g > 1.0) g = 1.0;
+    int b = (int)floor(g * NG);
+    return b > NG - 1 ? NG - 1 : b;
+}
+
+__global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
+    const float *__restrict__ psi, const float *__restrict__ coh, const uint8_t *__restrict__ valid,
+    int m, int n, const int16_t *__restrict__ lut, int NA, int NG, int h, double steep_thresh,
+    int steep_on, int16_t *__restrict__ cxp, int16_t *__restrict__ cxn, int16_t *__restrict__ cyp,
+    int16_t *__restrict__ cyn, unsigned long long *__restrict__ cand_key,
+    unsigned int *__restrict__ cand_id, SteepState *__restrict__ st) {
+    extern __shared__ unsigned char smem[];
+    const int i0 = blockIdx.y * CT_H, j0 = blockIdx.x * CT_W;
+    const int PR = CT_H + 2 * h + 1, PC = CT_W + 2 * h + 1;  // pixel tile
+    const int ER = CT_H + 2 * h, EC = CT_W + 2 * h;          // edge samples
+    float *ph = (float *)smem;                               // PR x PC
+    int *qx = (int *)(ph + PR * PC);                         // ER x EC
+    int *qy = qx + ER * EC;                                  // ER x EC
+    int *sx = qy + ER * EC;                                  // ER x CT_W row sums
+    int *sy = sx + ER * CT_W;
+    unsigned short *kx = (unsigned short *)(sy + ER * CT_W); // ER x CT_W row counts
+    unsigned short *ky = kx + ER * CT_W;
+    unsigned char *vd = (unsigned char *)(ky + ER * CT_W);   // PR x PC pixel validity
+    unsigned char *ex = vd + PR * PC;                        // ER x EC x-sample validity
+    unsigned char *ey = ex + ER * EC;
+    const int tid = threadIdx.x;
+
+    // 1. stage phase (0 at invalid pixels) and validity; outside = invalid
+    for (int t = tid; t < PR * PC; t += CT_THREADS) {
+        const int r = t / PC, c = t % PC;
+        const int i = i0 - h + r, j = j0 - h + c;
+        float v = 0.f;
+        unsigned char ok = 0;
+        if (i >= 0 && i < m && j >= 0 && j < n) {
+            const int64_t a = (int64_t)i * n + j;
+            ok = valid ? (valid[a] != 0) : 1;
+            v = ok ? psi[a] : 0.f;
+        }
+        ph[t] = v;
+        vd[t] = ok;
+    }
+    __syncthreads();
+    // 2. fixed-point wrapped gradients of every sample in the window
+    for (int t = tid; t < ER * EC; t += CT_THREADS) {
+        const int r = t / EC, c = t % EC;
+        const int p = r * PC + c;
+        // x-sample (r, c): pixel (r,c) -> (r,c+1)
+        {
+            const unsigned char ok = vd[p] & vd[p + 1];
+            int q = 0;
+            if (ok) {
+                double diff = (double)ph[p + 1] - (double)ph[p];
+                double d = diff - TWO_PI_D * wrap_cycles(diff);
+                q = (int)floor(d * 1048576.0);
+            }
+            qx[t] = q;
+            ex[t] = ok;
+        }
+        // y-sample (r, c): pixel (r,c) -> (r+1,c)
+        {
+            const unsigned char ok = vd[p] & vd[p + PC];
+            int q = 0;
+            if (ok) {
+                double diff = (double)ph[p + PC] - (double)ph[p];
+                double d = diff - TWO_PI_D * wrap_cycles(diff);
+                q = (int)floor(d * 1048576.0);
+            }
+            qy[t] = q;
+            ey[t] = ok;
+        }
+    }
+    __syncthreads();
+    // 3. horizontal window sums for the output columns
+    const int W = 2 * h + 1;
+    for (int t = tid; t < ER * CT_W; t += CT_THREADS) {
+        const int r = t / CT_W, c = t % CT_W;
+        int s1 = 0, s2 = 0, k1 = 0, k2 = 0;
+        const int base = r * EC + c;  // sample columns c .. c+2h
+        for (int d = 0; d < W; ++d) {
+            s1 += qx[base + d];
+            k1 += ex[base + d];
+            s2 += qy[base + d];
+            k2 += ey[base + d];
+        }
+        sx[t] = s1;
+        kx[t] = (unsigned short)k1;
+        sy[t] = s2;
+        ky[t] = (unsigned short)k2;
+    }
+    __syncthreads();
+    // 4. vertical window sums, bins, table gather, steep candidates
+    const int nx_cols = n - 1;
+    const int64_t nx_total = (int64_t)m * (n - 1);
+    int nvalid = 0;
+    const int c = tid % CT_W;
+    const int rstart = tid / CT_W;
+    for (int r = rstart; r < CT_H; r += CT_THREADS / CT_W) {
+        const int i = i0 + r, j = j0 + c;
+        int64_t S1 = 0, S2 = 0;
+        int K1 = 0, K2 = 0;
+        for (int d = 0; d < W; ++d) {
+            S1 += sx[(r + d) * CT_W + c];
+            K1 += kx[(r + d) * CT_W + c];
+            S2 += sy[(r + d) * CT_W + c];
+            K2 += ky[(r + d) * CT_W + c];
+        }
+        const int sc = (r + h) * EC + (c + h);  // own sample
+        // ---- x-edge hx(i, j)
+        bool candx = false;
+        unsigned long long keyx = 0;
+        int64_t idx_x = (int64_t)i * nx_cols + j;
+        if (i < m && j < n - 1) {
+            int16_t cp = 0, cn = 0;
+            if (ex[sc]) {
+                ++nvalid;
+                const int64_t num = (S1 + (int64_t)K1 * PI_FIX) * NA;
+                const int64_t den = 2 * (int64_t)K1 * PI_FIX;
+                int ba = (int)floor((double)num / (double)den);
+                ba = ba < 0 ? 0 : (ba > NA - 1 ? NA - 1 : ba);
+                const int64_t a = (int64_t)i * n + j;
+                float c0 = coh[a], c1 = coh[a + 1];
+                c0 = (c0 != c0) ? 0.f : c0;  // NaN reads as 0 (fminf would drop it)
+                c1 = (c1 != c1) ? 0.f : c1;
+                const int bg = coh_bin(fminf(c0, c1), NG);
+                cp = lut[bg * NA + ba];
+                cn = lut[bg * NA + (NA - 1 - ba)];
+                const int p = (r + h) * PC + (c + h);
+                double diff = (double)ph[p + 1] - (double)ph[p];
+                double dd = fabs(diff - TWO_PI_D * wrap_cycles(diff));
+                if (steep_on && dd > steep_thresh) {
+                    candx = true;
+                    keyx = (unsigned long long)__double_as_longlong(dd);
+                }
+            }
+            cxp[idx_x] = cp;
+            cxn[idx_x] = cn;
+        }
+        // ---- y-edge vy(i, j)
+        bool candy = false;
+        unsigned long long keyy = 0;
+        int64_t idx_y = (int64_t)i * n + j;
+        if (i < m - 1 && j < n) {
+            int16_t cp = 0, cn = 0;
+            if (ey[sc]) {
+                ++nvalid;
+                const int64_t num = (S2 + (int64_t)K2 * PI_FIX) * NA;
+                const int64_t den = 2 * (int64_t)K2 * PI_FIX;
+                int ba = (int)floor((double)num / (double)den);
+                ba = ba < 0 ? 0 : (ba > NA - 1 ? NA - 1 : ba);
+                const int64_t a = (int64_t)i * n + j;
+                float c0 = coh[a], c1 = coh[a + n];
+                c0 = (c0 != c0) ? 0.f : c0;
+                c1 = (c1 != c1) ? 0.f : c1;
+                const int bg = coh_bin(fminf(c0, c1), NG);
+                cp = lut[bg * NA + ba];
+                cn = lut[bg * NA + (NA - 1 - ba)];
+                const int p = (r + h) * PC + (c + h);
+                double diff = (double)ph[p + PC] - (double)ph[p];
+                double dd = fabs(diff - TWO_PI_D * wrap_cycles(diff));
+                if (steep_on && dd > steep_thresh) {
+                    candy = true;
+                    keyy = (unsigned long long)__double_as_longlong(dd);
+                }
+            }
+            cyp[idx_y] = cp;
+            cyn[idx_y] = cn;
+        }
+        // wave-aggregated append of steep candidates
+        const unsigned long long bx = __ballot(candx), by = __ballot(candy);
+        const int tot = __popcll(bx) + __popcll(by);
+        if (tot) {
+            const int lane = threadIdx.x & 63;
+            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&st->ncand, (unsigned long long)tot);
+            base = __shfl(base, 0, 64);
+            if (candx) {
+                unsigned long long pos = base + __popcll(bx & below);
+                cand_key[pos] = keyx;
+                cand_id[pos] = (unsigned int)idx_x;
+            }
+            if (candy) {
+                unsigned long long pos = base + __popcll(bx) + __popcll(by & below);
+                cand_key[pos] = keyy;
+                cand_id[pos] = (unsigned int)(nx_total + idx_y);
+            }
+        }
+    }
+    // valid-edge count
+    for (int off = 32; off > 0; off >>= 1) nvalid += __shfl_down(nvalid, off, 64);
+    if ((threadIdx.x & 63) == 0 && nvalid) atomicAdd(&st->nvalid, (unsigned long long)nvalid);
+}
+
+// cap = floor(pct * valid / 100); remaining = cap
+__global__ void k_steep_init(SteepState *st, int pct) {
+    st->cap = st->nvalid * (unsigned long long)pct / 100ull;
+    st->remaining = st->cap;
+    st->prefix_hi = 0;
+    st->mask_hi = 0;
+    st->prefix_lo = 0;
+    st->mask_lo = 0;
+}
+
+__device__ __forceinline__ bool steep_selecting(const SteepState *st) {
+    return st->ncand > st->cap && st->cap > 0;
+}
+
+__global__ void k_steep_hist(const unsigned long long *key, const unsigned int *id, SteepState *st,
+                             int pass) {
+    if (!steep_selecting(st)) return;
+    __shared__ unsigned int h[256];
+    for (int t = threadIdx.x; t < 256; t += blockDim.x) h[t] = 0;
+    __syncthreads();
+    const unsigned long long nc = st->ncand;
+    const unsigned long long ph = st->prefix_hi, mh = st->mask_hi;
+    const unsigned int pl = st->prefix_lo, ml = st->mask_lo;
+    for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; k < nc;
+         k += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long hi = key[k];
+        const unsigned int lo = ~id[k];
+        if ((hi & mh) != ph || (lo & ml) != pl) continue;
+        unsigned int digit = pass < 8 ? (unsigned int)((hi >> (8 * (7 - pass))) & 0xff)
+                                      : ((lo >> (8 * (11 - pass))) & 0xffu);
+        atomicAdd(&h[digit], 1u);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 256; t += blockDim.x)
+        if (h[t]) atomicAdd(&st->hist[t], h[t]);
+}
+
+__global__ void k_steep_pick(SteepState *st, int pass) {
+    if (threadIdx.x != 0) return;
+    if (steep_selecting(st)) {
+        unsigned long long acc = 0;
+        int digit = 0;
+        for (int d = 255; d >= 0; --d) {
+            if (acc + st->hist[d] >= st->remaining) {
+                digit = d;
+                break;
+            }
+            acc += st->hist[d];
+        }
+        st->remaining -= acc;
+        if (pass < 8) {
+            const int sh = 8 * (7 - pass);
+            st->prefix_hi |= (unsigned long long)digit << sh;
+            st->mask_hi |= 0xffull << sh;
+        } else {
+            const int sh = 8 * (11 - pass);
+            st->prefix_lo |= (unsigned int)digit << sh;
+            st->mask_lo |= 0xffu << sh;
+        }
+    }
+    for (int d = 0; d < 256; ++d) st->hist[d] = 0;
+}
+
+// Zero the selected candidates: all of them when they fit under the cap,
+// otherwise those whose (|d| bits, ~id) is at least the selected threshold.
+__global__ void k_steep_zero(const unsigned long long *key, const unsigned int *id,
+                             const SteepState *st, long long nx_total, int16_t *cxp, int16_t *cxn,
+                             int16_t *cyp, int16_t *cyn) {
+    const unsigned long long nc = st->ncand;
+    if (st->cap == 0) return;
+    const bool all = nc <= st->cap;
+    const unsigned long long th = st->prefix_hi;
+    const unsigned int tl = st->prefix_lo;
+    for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; k < nc;
+         k += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long hi = key[k];
+        const unsigned int e = id[k];
+        const unsigned int lo = ~e;
+        if (!all && !(hi > th || (hi == th && lo >= tl))) continue;
+        if ((long long)e < nx_total) {
+            cxp[e] = 0;
+            cxn[e] = 0;
+        } else {
+            cyp[e - nx_total] = 0;
+            cyn[e - nx_total] = 0;
+        }
+    }
+}
+
+ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
+                          const int16_t *lut, int NA, int NG, const ww_cost_params &cp,
+                          int16_t *cxp, int16_t *cxn, int16_t *cyp, int16_t *cyn,
+                          hipStream_t stream) {
+    const int64_t nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
+    if (nx + ny == 0) return WW_OK;
+    if (nx + ny >= ((int64_t)1 << 32)) return fail(WW_E_INVALID_ARG, "too many edges");
+    SteepState *st = nullptr;
+    unsigned long long *keys = nullptr;
+    unsigned int *ids = nullptr;
+    WW_TRY(scratch(SLOT_STEEP, sizeof(SteepState), (void **)&st));
+    const int steep_on = cp.steep_rule != 0;
+    const int64_t capn = steep_on ? (nx + ny) : 1;
+    char *kbuf = nullptr;
+    WW_TRY(scratch(SLOT_STEEP_KEYS, (size_t)capn * 12 + 512, (void **)&kbuf));
+    keys = (unsigned long long *)kbuf;
+    ids = (unsigned int *)(kbuf + ((size_t)capn * 8 + 255) / 256 * 256);
+    WW_HIP(hipMemsetAsync(st, 0, sizeof(SteepState), stream));
+    const int h = cp.box_half;
+    const int PR = CT_H + 2 * h + 1, PC = CT_W + 2 * h + 1, ER = CT_H + 2 * h, EC = CT_W + 2 * h;
+    const size_t lds = (size_t)PR * PC * 4 + 2 * (size_t)ER * EC * 4 + 2 * (size_t)ER * CT_W * 4 +
+                       2 * (size_t)ER * CT_W * 2 + (size_t)PR * PC + 2 * (size_t)ER * EC;
+    if (lds > 64 * 1024) return fail(WW_E_INVALID_ARG, "box_half %d too large for the tile (max 8)", h);
+    dim3 grid(ceil_div(n, CT_W), ceil_div(m, CT_H));
+    hipLaunchKernelGGL(k_edge_costs, grid, dim3(CT_THREADS), lds, stream, psi, coh, valid, m, n,
+                       lut, NA, NG, h, cp.steep_thresh_rad, steep_on, cxp, cxn, cyp, cyn, keys, ids,
+                       st);
+    WW_LAUNCH_CHECK();
+    if (steep_on) {
+        hipLaunchKernelGGL(k_steep_init, dim3(1), dim3(1), 0, stream, st, cp.steep_cap_pct);
+        WW_LAUNCH_CHECK();
+        const int hb = (int)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(nx + ny, 1024)));
+        for (int pass = 0; pass < 12; ++pass) {
+            hipLaunchKernelGGL(k_steep_hist, dim3(hb), dim3(256), 0, stream, keys, ids, st, pass);
+            WW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_steep_pick, dim3(1), dim3(64), 0, stream, st, pass);
+            WW_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_steep_zero, dim3(hb), dim3(256), 0, stream, keys, ids, st,
+                           (long long)nx, cxp, cxn, cyp, cyn);
+        WW_LAUNCH_CHECK();
+    }
+    return WW_OK;
+}
+
+}  // namespace ww

@@ -1,0 +1,901 @@
+// Exact minimum-cost flow of eq. 2 by successive shortest paths with node
+// potentials (Section II-C), on the loop graph of an m x n image plus one
+// ground node G that stands for the outer ring of zero-cost, unbounded arcs.
+//
+// State: the net flow of every pixel edge is its cycle difference dk in
+// {-1,0,1} (the dk_x / dk_y outputs).  A residual move of +1 on an edge with
+// dk = 0 costs c+, of -1 costs c-; undoing a correction refunds its cost;
+// moving past +-1 is not allowed.  Potentials pot (int32, guarded) keep every
+// residual arc's reduced cost c - pot(u) + pot(v) >= 0.
+//
+// One pass:
+//  1. Multi-source shortest paths from every node with positive excess over
+//     reduced costs.  Labels are 64-bit (dist:32 | hops:29 | dir:3) and every
+//     node keeps the lexicographic minimum over its in-arcs, so the fixpoint
+//     is unique (independent of scheduling) and predecessor links form a
+//     forest (hops strictly grow along them).  The search is bounded by a
+//     distance window B; candidates beyond B are parked and the window grows
+//     until enough deficits are reached.
+//     Relaxation runs on 32 x 32 node tiles: a workgroup stages the tile's
+//     labels and reduced in-arc costs in LDS and iterates to local
+//     convergence; tiles whose border labels changed activate their
+//     neighbours through rotating worklists (one launch per round).
+//  2. Every reached deficit walks its predecessor chain to its tree root;
+//     each root keeps its nearest deficit (64-bit atomicMin on dist|node).
+//  3. One unit is augmented along each root's chosen path.  Different trees
+//     are vertex-disjoint, so all paths are applied in parallel.  Trees that
+//     hang off the ground as a supply are split at the ground's arcs and at
+//     most its excess of them augment.
+//  4. pot(v) += B - d(v) for every reached node.  Every tree arc is then
+//     tight and reversing it keeps all reduced costs >= 0, so the final flow
+//     is optimal whatever the window and the number of paths per pass.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "ww_internal.h"
+
+namespace ww {
+
+namespace {
+
+constexpr int TS = 32;            // tile side in loop nodes
+constexpr int SS_THREADS = 256;   // 4 nodes per thread
+constexpr unsigned long long LINF = ~0ull;
+constexpr int RC_INF = 0x7fffffff;
+constexpr int DIR_NONE = 0, DIR_UP = 1, DIR_DOWN = 2, DIR_LEFT = 3, DIR_RIGHT = 4;
+constexpr int POT_LIMIT = 1 << 30;
+constexpr int MAX_ITERS = 1 << 16;
+
+enum : int { ERR_NEG_RC = 1, ERR_POT = 2, ERR_WALK = 4, ERR_ITERS = 8 };
+
+struct Ctl {
+    unsigned long long glab;   // ground label
+    long long gex;             // ground excess
+    long long gpot;            // ground potential
+    unsigned int count[3];     // rotating tile worklists
+    unsigned int pend_count;   // tiles with parked candidates
+    unsigned int touch_count;  // tiles relaxed in this pass
+    unsigned int nsrc, ndef;   // node lists
+    unsigned int nsrc2, ndef2; // compaction targets
+    unsigned int gsub_count;   // ground-rooted subtrees with a deficit
+    unsigned int gpred;        // ground predecessor (perimeter arc index)
+    unsigned int settled;      // deficits reached in the window
+    unsigned int naug;         // augmentations in this pass
+    unsigned long long arcs;   // arcs flipped in this pass
+    int error;
+    int max_pot;
+    long long total_cost;
+    long long sum_res;
+    unsigned long long visits; // tiles relaxed, all rounds
+};
+
+struct Graph {
+    int R, C, n;               // loop rows, loop cols, image cols (= C + 1)
+    int TR, TC;                // tile grid
+    const int16_t *cxp, *cxn, *cyp, *cyn;
+    int8_t *fx, *fy;
+    unsigned long long *lab;
+    int *pot;
+    int8_t *ex;
+    unsigned long long *best;
+};
+
+__device__ __forceinline__ unsigned int ldist(unsigned long long l) { return (unsigned int)(l >> 32); }
+__device__ __forceinline__ unsigned int lhops(unsigned long long l) {
+    return (unsigned int)((l >> 3) & 0x1fffffffu);
+}
+
+// cost of moving an edge's net flow f by delta, RC_INF if not allowed
+__device__ __forceinline__ int move_cost(int f, int delta, int cp, int cn) {
+    if (f == 0) return delta > 0 ? cp : cn;
+    if (f == -delta) return -(f > 0 ? cp : cn);
+    return RC_INF;
+}
+
+__device__ __forceinline__ void enqueue(unsigned int item, unsigned int stamp, unsigned int *stamps,
+                                        unsigned int *list, unsigned int *count) {
+    if (atomicExch(&stamps[item], stamp) != stamp) {
+        unsigned int pos = atomicAdd(count, 1u);
+        list[pos] = item;
+    }
+}
+
+// perimeter arc a -> (node row, node col, edge kind, edge index, delta of
+// the move node -> ground)
+__device__ __forceinline__ void ground_arc(const Graph &g, unsigned int a, int &i, int &j,
+                                           int &kind, long long &e, int &delta) {
+    const int C = g.C, R = g.R;
+    if (a < (unsigned)C) {  // top: up across hx(0, j)
+        i = 0; j = a; kind = 0; e = j; delta = -1;
+    } else if (a < 2u * C) {  // bottom: down across hx(R, j)
+        i = R - 1; j = a - C; kind = 0; e = (long long)R * C + j; delta = +1;
+    } else if (a < 2u * C + R) {  // left: left across vy(i, 0)
+        i = a - 2 * C; j = 0; kind = 1; e = (long long)i * g.n; delta = +1;
+    } else {  // right: right across vy(i, C)
+        i = a - 2 * C - R; j = C - 1; kind = 1; e = (long long)i * g.n + C; delta = -1;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ set-up ------
+
+__global__ void k_mcf_init(Graph g, const int8_t *__restrict__ res, Ctl *ctl,
+                           unsigned int *src, unsigned int *def) {
+    const long long N = (long long)g.R * g.C;
+    long long s = 0;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+         v += (long long)gridDim.x * blockDim.x) {
+        int r = res[v];
+        g.ex[v] = (int8_t)r;
+        g.pot[v] = 0;
+        g.lab[v] = LINF;
+        g.best[v] = LINF;
+        s += r;
+        if (r > 0) src[atomicAdd(&ctl->nsrc, 1u)] = (unsigned int)v;
+        else if (r < 0) def[atomicAdd(&ctl->ndef, 1u)] = (unsigned int)v;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->sum_res,
+                                               (unsigned long long)s);
+}
+
+__global__ void k_mcf_finish_init(Ctl *ctl) {
+    ctl->gex = -ctl->sum_res;
+    ctl->gpot = 0;
+    ctl->glab = LINF;
+}
+
+// Pass start: sources get label 0 and their tiles are queued.
+__global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned int *stamps,
+                            unsigned int stamp, unsigned int *list0, int ground_source,
+                            unsigned int *perim_tiles, int nperim) {
+    const unsigned int ns = ctl->nsrc;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
+        unsigned int v = src[k];
+        g.lab[v] = 0ull;
+        unsigned int t = (v / g.C / TS) * g.TC + (v % g.C) / TS;
+        enqueue(t, stamp, stamps, list0, &ctl->count[0]);
+    }
+    if (ground_source) {
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x)
+            enqueue(perim_tiles[k], stamp, stamps, list0, &ctl->count[0]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->glab = ground_source ? 0ull : LINF;
+}
+
+// ------------------------------------------------------ relaxation round ---
+
+struct RoundArgs {
+    unsigned int *lists;        // 3 x NT
+    unsigned int *qstamp;       // per-tile queue stamps
+    unsigned int *pstamp;       // per-tile pending stamps
+    unsigned int *tstamp;       // per-tile touched stamps
+    unsigned int *pend_list, *touch_list, *perim_tiles;
+    int nperim;
+    unsigned int NT;
+};
+
+__global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
+                                                           int cur, unsigned int next_stamp,
+                                                           unsigned int window_stamp,
+                                                           unsigned int pass_stamp,
+                                                           unsigned int bound) {
+    __shared__ unsigned long long L[TS + 2][TS + 3];
+    __shared__ int P[TS + 2][TS + 2];
+    __shared__ int RCs[4][TS][TS];
+    __shared__ int flags[4];  // changed border: top, bottom, left, right
+    __shared__ int sh_pending, sh_any;
+    __shared__ unsigned long long sh_gcand;
+
+    const unsigned int cnt = ctl->count[cur];
+    const int nxt = (cur + 1) % 3, clr = (cur + 2) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[clr] = 0;
+        ctl->visits += cnt;
+    }
+    unsigned int *list = ra.lists + (size_t)cur * ra.NT;
+    unsigned int *nlist = ra.lists + (size_t)nxt * ra.NT;
+    const unsigned long long glab = ctl->glab;
+    const int gpot = (int)ctl->gpot;
+    const int R = g.R, C = g.C;
+
+    for (unsigned int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
+        const unsigned int tile = list[idx];
+        const int ti = tile / g.TC, tj = tile % g.TC;
+        const int i0 = ti * TS, j0 = tj * TS;
+        const int rows = min(TS, R - i0), cols = min(TS, C - j0);
+        if (threadIdx.x < 4) flags[threadIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            sh_pending = 0;
+            sh_gcand = LINF;
+        }
+        // stage labels and potentials with a one-node halo; outside = ground
+        for (int t = threadIdx.x; t < (TS + 2) * (TS + 2); t += SS_THREADS) {
+            const int r = t / (TS + 2), c = t % (TS + 2);
+            const int i = i0 - 1 + r, j = j0 - 1 + c;
+            unsigned long long l = LINF;
+            int p = 0;
+            if (r <= rows + 1 && c <= cols + 1) {
+                if (i >= 0 && i < R && j >= 0 && j < C) {
+                    const long long v = (long long)i * C + j;
+                    l = g.lab[v];
+                    p = g.pot[v];
+                } else {
+                    l = glab;
+                    p = gpot;
+                }
+            }
+            L[r][c] = l;
+            P[r][c] = p;
+        }
+        __syncthreads();
+        // reduced costs of the four in-arcs of every node
+        for (int t = threadIdx.x; t < TS * TS; t += SS_THREADS) {
+            const int li = t / TS, lj = t % TS;
+            int ru = RC_INF, rd = RC_INF, rl = RC_INF, rr = RC_INF;
+            if (li < rows && lj < cols) {
+                const int i = i0 + li, j = j0 + lj;
+                const int pv = P[li + 1][lj + 1];
+                long long e;
+                int c;
+                e = (long long)i * C + j;  // hx(i,j): from above, +1
+                c = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
+                if (c != RC_INF) ru = c - P[li][lj + 1] + pv;
+                e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
+                c = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
+                if (c != RC_INF) rd = c - P[li + 2][lj + 1] + pv;
+                e = (long long)i * g.n + j;  // vy(i,j): from the left, -1
+                c = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
+                if (c != RC_INF) rl = c - P[li + 1][lj] + pv;
+                e = (long long)i * g.n + j + 1;  // vy(i,j+1): from the right, +1
+                c = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
+                if (c != RC_INF) rr = c - P[li + 1][lj + 2] + pv;
+                if (ru < 0 || rd < 0 || rl < 0 || rr < 0) {
+                    atomicOr(&ctl->error, ERR_NEG_RC);
+                    ru = max(ru, 0); rd = max(rd, 0); rl = max(rl, 0); rr = max(rr, 0);
+                }
+            }
+            RCs[0][li][lj] = ru;
+            RCs[1][li][lj] = rd;
+            RCs[2][li][lj] = rl;
+            RCs[3][li][lj] = rr;
+        }
+        __syncthreads();
+        // owned nodes: column lj, rows 4*q .. 4*q+3
+        const int lj = threadIdx.x % TS, q = threadIdx.x / TS;
+        unsigned long long init[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) init[k] = L[q * 4 + k + 1][lj + 1];
+        int pending = 0;
+        for (int it = 0; it < MAX_ITERS; ++it) {
+            int changed = 0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = s < 4 ? s : 7 - s;  // down then up
+                const int li = q * 4 + k;
+                if (li >= rows || lj >= cols) continue;
+                const unsigned long long cur_l = L[li + 1][lj + 1];
+                unsigned long long bestl = cur_l;
+                const unsigned long long nb[4] = {L[li][lj + 1], L[li + 2][lj + 1], L[li + 1][lj],
+                                                  L[li + 1][lj + 2]};
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int rc = RCs[d][li][lj];
+                    const unsigned long long u = nb[d];
+                    if (rc == RC_INF || u == LINF) continue;
+                    const unsigned long long nd = (unsigned long long)ldist(u) + (unsigned)rc;
+                    if (nd > bound) {
+                        pending = 1;
+                        continue;
+                    }
+                    const unsigned long long cand =
+                        (nd << 32) | ((unsigned long long)(lhops(u) + 1) << 3) | (unsigned)(d + 1);
+                    if (cand < bestl) bestl = cand;
+                }
+                if (bestl < cur_l) {
+                    L[li + 1][lj + 1] = bestl;
+                    changed = 1;
+                }
+            }
+            if (!__syncthreads_or(changed)) break;
+            if (it == MAX_ITERS - 1 && threadIdx.x == 0) atomicOr(&ctl->error, ERR_ITERS);
+        }
+        // write back, note changed borders
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int li = q * 4 + k;
+            if (li >= rows || lj >= cols) continue;
+            const unsigned long long l = L[li + 1][lj + 1];
+            if (l != init[k]) {
+                g.lab[(long long)(i0 + li) * C + (j0 + lj)] = l;
+                if (li == 0) flags[0] = 1;
+                if (li == rows - 1) flags[1] = 1;
+                if (lj == 0) flags[2] = 1;
+                if (lj == cols - 1) flags[3] = 1;
+            }
+        }
+        // candidate labels for the ground from perimeter nodes of this tile
+        unsigned long long gc = LINF;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int li = q * 4 + k;
+            if (li >= rows || lj >= cols) continue;
+            const int i = i0 + li, j = j0 + lj;
+            const unsigned long long l = L[li + 1][lj + 1];
+            if (l == LINF) continue;
+            const int pv = P[li + 1][lj + 1];
+            for (int side = 0; side < 4; ++side) {
+                long long e;
+                int c;
+                if (side == 0) {
+                    if (i != 0) continue;
+                    e = j;
+                    c = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
+                } else if (side == 1) {
+                    if (i != R - 1) continue;
+                    e = (long long)R * C + j;
+                    c = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
+                } else if (side == 2) {
+                    if (j != 0) continue;
+                    e = (long long)i * g.n;
+                    c = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
+                } else {
+                    if (j != C - 1) continue;
+                    e = (long long)i * g.n + C;
+                    c = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
+                }
+                if (c == RC_INF) continue;
+                int rc = c - pv + gpot;
+                if (rc < 0) {
+                    atomicOr(&ctl->error, ERR_NEG_RC);
+                    rc = 0;
+                }
+                const unsigned long long nd = (unsigned long long)ldist(l) + (unsigned)rc;
+                if (nd > bound) {
+                    pending = 1;
+                    continue;
+                }
+                const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
+                if (cand < gc) gc = cand;
+            }
+        }
+        if (gc != LINF) atomicMin(&sh_gcand, gc);
+        if (pending) sh_pending = 1;
+        __syncthreads();
+        // activations
+        if (threadIdx.x == 0) {
+            if (flags[0] && ti > 0) enqueue(tile - g.TC, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+            if (flags[1] && ti < g.TR - 1) enqueue(tile + g.TC, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+            if (flags[2] && tj > 0) enqueue(tile - 1, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+            if (flags[3] && tj < g.TC - 1) enqueue(tile + 1, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+            if (sh_pending) enqueue(tile, window_stamp, ra.pstamp, ra.pend_list, &ctl->pend_count);
+            if (atomicExch(&ra.tstamp[tile], pass_stamp) != pass_stamp)
+                ra.touch_list[atomicAdd(&ctl->touch_count, 1u)] = tile;
+            sh_any = 0;
+            if (sh_gcand != LINF && sh_gcand < ctl->glab) {
+                unsigned long long old = atomicMin(&ctl->glab, sh_gcand);
+                if (sh_gcand < old) sh_any = 1;
+            }
+        }
+        __syncthreads();
+        if (sh_any) {
+            for (int k = threadIdx.x; k < ra.nperim; k += SS_THREADS)
+                enqueue(ra.perim_tiles[k], next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+        }
+        __syncthreads();
+    }
+}
+
+// re-queue tiles with parked candidates after the window grew
+__global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pend, unsigned int *qstamp,
+                                  unsigned int stamp, unsigned int *list0, int cur) {
+    const unsigned int np = ctl->pend_count;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x)
+        enqueue(pend[k], stamp, qstamp, list0, &ctl->count[cur]);
+}
+
+__global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsigned int bound) {
+    const unsigned int nd = ctl->ndef;
+    unsigned int c = 0;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += gridDim.x * blockDim.x) {
+        const unsigned long long l = g.lab[def[k]];
+        if (l != LINF && ldist(l) <= bound) ++c;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&ctl->settled, c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long gl = ctl->glab;
+        if (ctl->gex < 0 && gl != LINF && ldist(gl) <= bound) atomicAdd(&ctl->settled, 1u);
+    }
+}
+
+// ---------------------------------------------------------- augmentation ---
+
+// The ground's predecessor: the smallest perimeter arc index whose label
+// candidate equals the ground label.
+__global__ void k_ground_pred(Graph g, Ctl *ctl, unsigned int bound) {
+    const unsigned long long gl = ctl->glab;
+    if (gl == LINF || ldist(gl) > bound || ctl->gex > 0) return;
+    const unsigned int na = 2u * g.C + 2u * g.R;
+    const int gpot = (int)ctl->gpot;
+    for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < na; a += gridDim.x * blockDim.x) {
+        int i, j, kind, delta;
+        long long e;
+        ground_arc(g, a, i, j, kind, e, delta);
+        const long long v = (long long)i * g.C + j;
+        const unsigned long long l = g.lab[v];
+        if (l == LINF) continue;
+        const int c = kind == 0 ? move_cost(g.fx[e], delta, g.cxp[e], g.cxn[e])
+                                : move_cost(g.fy[e], delta, g.cyp[e], g.cyn[e]);
+        if (c == RC_INF) continue;
+        const long long rc = (long long)c - g.pot[v] + gpot;
+        const unsigned long long nd = (unsigned long long)ldist(l) + (unsigned long long)max(rc, 0ll);
+        const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
+        if (cand == gl) atomicMin(&ctl->gpred, a);
+    }
+}
+
+// predecessor of loop node v (i,j) along direction dir; -1 = ground
+__device__ __forceinline__ long long pred_node(const Graph &g, int i, int j, int dir) {
+    switch (dir) {
+        case DIR_UP: return i > 0 ? (long long)(i - 1) * g.C + j : -1;
+        case DIR_DOWN: return i < g.R - 1 ? (long long)(i + 1) * g.C + j : -1;
+        case DIR_LEFT: return j > 0 ? (long long)i * g.C + j - 1 : -1;
+        default: return j < g.C - 1 ? (long long)i * g.C + j + 1 : -1;
+    }
+}
+
+// Walk from v to its root.  Returns the root node; *gsub = 1 when the root
+// is a child of the ground acting as a supply.
+__device__ long long walk_root(const Graph &g, Ctl *ctl, long long v, int gsrc, int *gsub) {
+    *gsub = 0;
+    const long long N = (long long)g.R * g.C;
+    for (long long steps = 0; steps <= N + 2; ++steps) {
+        const unsigned long long l = g.lab[v];
+        const int dir = (int)(l & 7);
+        if (dir == DIR_NONE) return v;
+        const int i = (int)(v / g.C), j = (int)(v % g.C);
+        long long u = pred_node(g, i, j, dir);
+        if (u < 0) {
+            if (gsrc) {
+                *gsub = 1;
+                return v;
+            }
+            const unsigned int a = ctl->gpred;
+            if (a >= 2u * g.C + 2u * g.R) break;  // no ground predecessor: report below
+            int pi, pj, kind, delta;
+            long long e;
+            ground_arc(g, a, pi, pj, kind, e, delta);
+            u = (long long)pi * g.C + pj;
+        }
+        v = u;
+    }
+    atomicOr(&ctl->error, ERR_WALK);
+    return -1;
+}
+
+__global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned int bound,
+                        unsigned int *gsub_list) {
+    const unsigned int nd = ctl->ndef;
+    const int gsrc = ctl->gex > 0;
+    const long long N = (long long)g.R * g.C;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k <= nd; k += gridDim.x * blockDim.x) {
+        long long start;
+        unsigned long long key;
+        if (k < nd) {
+            const unsigned int t = def[k];
+            const unsigned long long l = g.lab[t];
+            if (l == LINF || ldist(l) > bound) continue;
+            start = t;
+            key = ((unsigned long long)ldist(l) << 32) | t;
+        } else {
+            // the ground as a demand: its path enters through gpred
+            const unsigned long long gl = ctl->glab;
+            if (!(ctl->gex < 0 && gl != LINF && ldist(gl) <= bound)) continue;
+            if (ctl->gpred >= 2u * g.C + 2u * g.R) {
+                atomicOr(&ctl->error, ERR_WALK);
+                continue;
+            }
+            int pi, pj, kind, delta;
+            long long e;
+            ground_arc(g, ctl->gpred, pi, pj, kind, e, delta);
+            start = (long long)pi * g.C + pj;
+            key = ((unsigned long long)ldist(gl) << 32) | (unsigned long long)N;
+        }
+        int gsub = 0;
+        const long long root = walk_root(g, ctl, start, gsrc, &gsub);
+        if (root < 0) continue;
+        const unsigned long long old = atomicMin(&g.best[root], key);
+        if (gsub && old == LINF) gsub_list[atomicAdd(&ctl->gsub_count, 1u)] = (unsigned int)root;
+    }
+}
+
+// Keep at most gex ground-rooted subtrees: those with the smallest
+// (best key, root id).  O(k^2), k <= perimeter length.
+__global__ void k_gsub_select(Graph g, Ctl *ctl, const unsigned int *gsub_list,
+                              unsigned char *drop) {
+    const unsigned int k = ctl->gsub_count;
+    const long long allow = ctl->gex;
+    for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < k; a += gridDim.x * blockDim.x) {
+        drop[a] = 0;
+        if ((long long)k <= allow) continue;
+        const unsigned int ra = gsub_list[a];
+        const unsigned long long ka = g.best[ra];
+        long long rank = 0;
+        for (unsigned int b = 0; b < k; ++b) {
+            const unsigned int rb = gsub_list[b];
+            const unsigned long long kb = g.best[rb];
+            if (kb < ka || (kb == ka && rb < ra)) ++rank;
+        }
+        if (rank >= allow) drop[a] = 1;
+    }
+}
+
+__device__ __forceinline__ void flip_into(Graph &g, long long v, int dir) {
+    const int i = (int)(v / g.C), j = (int)(v % g.C);
+    switch (dir) {
+        case DIR_UP: g.fx[(long long)i * g.C + j] += 1; break;
+        case DIR_DOWN: g.fx[(long long)(i + 1) * g.C + j] -= 1; break;
+        case DIR_LEFT: g.fy[(long long)i * g.n + j] -= 1; break;
+        default: g.fy[(long long)i * g.n + j + 1] += 1; break;
+    }
+}
+
+__device__ __forceinline__ void flip_ground_arc(Graph &g, unsigned int a) {
+    int i, j, kind, delta;
+    long long e;
+    ground_arc(g, a, i, j, kind, e, delta);
+    if (kind == 0) g.fx[e] += (int8_t)delta;
+    else g.fy[e] += (int8_t)delta;
+}
+
+// Apply one unit along root r's chosen path: from the deficit back to r.
+__global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *gsub_list,
+                          const unsigned char *drop) {
+    const unsigned int ns = ctl->nsrc, ng = ctl->gsub_count;
+    const long long N = (long long)g.R * g.C;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns + ng;
+         k += gridDim.x * blockDim.x) {
+        const bool is_g = k >= ns;
+        const unsigned int r = is_g ? gsub_list[k - ns] : src[k];
+        const unsigned long long b = g.best[r];
+        if (b == LINF) continue;
+        g.best[r] = LINF;
+        if (is_g && drop[k - ns]) continue;
+        const long long t = (long long)(b & 0xffffffffull);
+        long long v;
+        unsigned long long flips = 0;
+        const unsigned int na = 2u * g.C + 2u * g.R;
+        if (ctl->gpred >= na && !is_g) {
+            // a path that needs the ground's predecessor cannot be traced
+            bool needs = (t == N);
+            for (long long w = t == N ? -1 : t, steps = 0; !needs && w >= 0 && steps <= N + 2; ++steps) {
+                const int dir = (int)(g.lab[w] & 7);
+                if (dir == DIR_NONE) break;
+                w = pred_node(g, (int)(w / g.C), (int)(w % g.C), dir);
+                if (w < 0) needs = true;
+            }
+            if (needs) {
+                atomicOr(&ctl->error, ERR_WALK);
+                continue;
+            }
+        }
+        if (t == N) {  // into the ground through its predecessor arc
+            const unsigned int a = ctl->gpred;
+            flip_ground_arc(g, a);
+            int pi, pj, kind, delta;
+            long long e;
+            ground_arc(g, a, pi, pj, kind, e, delta);
+            v = (long long)pi * g.C + pj;
+            ++flips;
+        } else {
+            v = t;
+        }
+        for (long long steps = 0; steps <= N + 2; ++steps) {
+            const int dir = (int)(g.lab[v] & 7);
+            if (dir == DIR_NONE) break;  // reached the supply r
+            flip_into(g, v, dir);
+            ++flips;
+            const int i = (int)(v / g.C), j = (int)(v % g.C);
+            long long u = pred_node(g, i, j, dir);
+            if (u < 0) {
+                if (is_g) break;  // the ground is the supply
+                const unsigned int a = ctl->gpred;
+                flip_ground_arc(g, a);
+                ++flips;
+                int pi, pj, kind, delta;
+                long long e;
+                ground_arc(g, a, pi, pj, kind, e, delta);
+                u = (long long)pi * g.C + pj;
+            }
+            v = u;
+        }
+        if (is_g) atomicAdd((unsigned long long *)&ctl->gex, (unsigned long long)-1ll);
+        else g.ex[r] -= 1;
+        if (t == N) atomicAdd((unsigned long long *)&ctl->gex, 1ull);
+        else g.ex[t] += 1;
+        atomicAdd(&ctl->naug, 1u);
+        atomicAdd(&ctl->arcs, flips);
+    }
+}
+
+// pot(v) += B - d(v) on every reached node, labels back to infinity.
+__global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *touch, unsigned int bound) {
+    const unsigned int nt = ctl->touch_count;
+    int mx = 0;
+    for (unsigned int idx = blockIdx.x; idx < nt; idx += gridDim.x) {
+        const unsigned int tile = touch[idx];
+        const int i0 = (tile / g.TC) * TS, j0 = (tile % g.TC) * TS;
+        for (int t = threadIdx.x; t < TS * TS; t += blockDim.x) {
+            const int i = i0 + t / TS, j = j0 + t % TS;
+            if (i >= g.R || j >= g.C) continue;
+            const long long v = (long long)i * g.C + j;
+            const unsigned long long l = g.lab[v];
+            if (l == LINF) continue;
+            g.lab[v] = LINF;
+            const unsigned int d = ldist(l);
+            if (d > bound) continue;
+            const long long np = (long long)g.pot[v] + (bound - d);
+            if (np > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
+            g.pot[v] = (int)min(np, (long long)POT_LIMIT);
+            mx = max(mx, (int)min(np, (long long)POT_LIMIT));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_down(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&ctl->max_pot, mx);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long gl = ctl->glab;
+        if (gl != LINF && ldist(gl) <= bound) {
+            ctl->gpot += bound - ldist(gl);
+            if (ctl->gpot > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
+        }
+        ctl->glab = LINF;
+    }
+}
+
+// keep supplies / demands that still carry excess
+__global__ void k_compact(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *def,
+                          unsigned int *src2, unsigned int *def2) {
+    const unsigned int ns = ctl->nsrc, nd = ctl->ndef;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns + nd;
+         k += gridDim.x * blockDim.x) {
+        if (k < ns) {
+            const unsigned int v = src[k];
+            if (g.ex[v] > 0) src2[atomicAdd(&ctl->nsrc2, 1u)] = v;
+        } else {
+            const unsigned int v = def[k - ns];
+            if (g.ex[v] < 0) def2[atomicAdd(&ctl->ndef2, 1u)] = v;
+        }
+    }
+}
+
+// per-pass counters back to zero (node lists untouched)
+__global__ void k_pass_reset(Ctl *ctl) {
+    ctl->count[0] = ctl->count[1] = ctl->count[2] = 0;
+    ctl->settled = 0;
+    ctl->naug = 0;
+    ctl->gsub_count = 0;
+    ctl->gpred = 0xffffffffu;
+    ctl->pend_count = 0;
+    ctl->touch_count = 0;
+    ctl->arcs = 0;
+    ctl->nsrc2 = 0;
+    ctl->ndef2 = 0;
+}
+
+__global__ void k_clear_settled(Ctl *ctl) { ctl->settled = 0; }
+__global__ void k_clear_pending(Ctl *ctl) { ctl->pend_count = 0; }
+
+__global__ void k_swap_lists(Ctl *ctl) {
+    ctl->nsrc = ctl->nsrc2;
+    ctl->ndef = ctl->ndef2;
+}
+
+__global__ void k_total_cost(const int8_t *fx, const int8_t *fy, const int16_t *cxp,
+                             const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
+                             long long nx, long long ny, Ctl *ctl) {
+    long long s = 0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nx + ny;
+         e += (long long)gridDim.x * blockDim.x) {
+        int f;
+        int cp, cn;
+        if (e < nx) { f = fx[e]; cp = cxp[e]; cn = cxn[e]; }
+        else { f = fy[e - nx]; cp = cyp[e - nx]; cn = cyn[e - nx]; }
+        s += f > 0 ? cp : (f < 0 ? cn : 0);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->total_cost,
+                                               (unsigned long long)s);
+}
+
+__global__ void k_export_pot(const int *pot, const Ctl *ctl, long long N, int64_t *out) {
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v <= N;
+         v += (long long)gridDim.x * blockDim.x)
+        out[v] = v < N ? (int64_t)pot[v] : (int64_t)ctl->gpot;
+}
+
+// ------------------------------------------------------------------ host ---
+
+static ww_status decode_error(int e) {
+    if (e & ERR_NEG_RC) return fail(WW_E_DEVICE, "min-cost flow: negative reduced cost (invariant broken)");
+    if (e & ERR_POT) return fail(WW_E_OVERFLOW, "min-cost flow: node potential above 2^30");
+    if (e & ERR_WALK) return fail(WW_E_DEVICE, "min-cost flow: predecessor walk did not end");
+    if (e & ERR_ITERS) return fail(WW_E_DEVICE, "min-cost flow: tile relaxation did not converge");
+    return fail(WW_E_DEVICE, "min-cost flow: error flags 0x%x", e);
+}
+
+ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const int16_t *cxn,
+                   const int16_t *cyp, const int16_t *cyn, int8_t *dkx, int8_t *dky,
+                   int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t st) {
+    const long long nx = (long long)m * (n - 1), ny = (long long)(m - 1) * n;
+    if (nx > 0) WW_HIP(hipMemsetAsync(dkx, 0, nx, st));
+    if (ny > 0) WW_HIP(hipMemsetAsync(dky, 0, ny, st));
+    ww_mcf_stats S;
+    memset(&S, 0, sizeof(S));
+    const int R = m - 1, C = n - 1;
+    if (R < 1 || C < 1) {
+        if (pot_out) WW_HIP(hipMemsetAsync(pot_out, 0, sizeof(int64_t), st));
+        WW_HIP(hipStreamSynchronize(st));
+        *total = 0;
+        if (stats) *stats = S;
+        return WW_OK;
+    }
+    const long long N = (long long)R * C;
+    if (N >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
+    Graph g;
+    g.R = R; g.C = C; g.n = n;
+    g.TR = ceil_div(R, TS); g.TC = ceil_div(C, TS);
+    g.cxp = cxp; g.cxn = cxn; g.cyp = cyp; g.cyn = cyn;
+    g.fx = dkx; g.fy = dky;
+    const unsigned int NT = (unsigned)g.TR * g.TC;
+    const int nperim_arcs = 2 * C + 2 * R;
+    WW_TRY(scratch(SLOT_MCF_LAB, sizeof(unsigned long long) * N, (void **)&g.lab));
+    WW_TRY(scratch(SLOT_MCF_BEST, sizeof(unsigned long long) * N, (void **)&g.best));
+    WW_TRY(scratch(SLOT_MCF_POT, sizeof(int) * N, (void **)&g.pot));
+    WW_TRY(scratch(SLOT_MCF_EX, N, (void **)&g.ex));
+    unsigned int *tiles = nullptr;
+    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * (size_t)NT * 9 + 4096, (void **)&tiles));
+    RoundArgs ra;
+    ra.NT = NT;
+    ra.lists = tiles;
+    ra.pend_list = tiles + 3 * (size_t)NT;
+    ra.touch_list = tiles + 4 * (size_t)NT;
+    ra.perim_tiles = tiles + 5 * (size_t)NT;
+    ra.qstamp = tiles + 6 * (size_t)NT;
+    ra.pstamp = tiles + 7 * (size_t)NT;
+    ra.tstamp = tiles + 8 * (size_t)NT;
+    char *nodes = nullptr;
+    const size_t nl_bytes = sizeof(unsigned int) * (size_t)N;
+    const size_t gs_bytes = sizeof(unsigned int) * (size_t)nperim_arcs + 256;
+    WW_TRY(scratch(SLOT_MCF_NODES, 4 * nl_bytes + gs_bytes + nperim_arcs + 1024, (void **)&nodes));
+    unsigned int *src = (unsigned int *)nodes, *def = src + N, *src2 = def + N, *def2 = src2 + N;
+    unsigned int *gsub_list = def2 + N;
+    unsigned char *drop = (unsigned char *)(nodes + 4 * nl_bytes + gs_bytes);
+    Ctl *ctl = nullptr;
+    WW_TRY(scratch(SLOT_MCF_LISTS, sizeof(Ctl), (void **)&ctl));
+    Ctl *h = nullptr;
+    WW_TRY(host_scratch(sizeof(Ctl), (void **)&h));
+
+    std::vector<unsigned int> ptiles;
+    for (int ti = 0; ti < g.TR; ++ti)
+        for (int tj = 0; tj < g.TC; ++tj)
+            if (ti == 0 || tj == 0 || ti == g.TR - 1 || tj == g.TC - 1)
+                ptiles.push_back((unsigned)(ti * g.TC + tj));
+    ra.nperim = (int)ptiles.size();
+    WW_HIP(hipMemcpyAsync(ra.perim_tiles, ptiles.data(), sizeof(unsigned int) * ptiles.size(),
+                          hipMemcpyHostToDevice, st));
+    WW_HIP(hipMemsetAsync(ra.qstamp, 0, sizeof(unsigned int) * 3 * (size_t)NT, st));
+    WW_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+    const int IB = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(N, 256)));
+    hipLaunchKernelGGL(k_mcf_init, dim3(IB), dim3(256), 0, st, g, res, ctl, src, def);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mcf_finish_init, dim3(1), dim3(1), 0, st, ctl);
+    WW_LAUNCH_CHECK();
+    auto sync_ctl = [&]() -> ww_status {
+        WW_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        WW_HIP(hipStreamSynchronize(st));
+        if (h->error) return decode_error(h->error);
+        return WW_OK;
+    };
+    WW_TRY(sync_ctl());
+    S.supplies = (long long)h->nsrc + std::max<long long>(h->gex, 0);
+
+    const int rounds_per_sync = 4;
+    const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
+    const unsigned int bound_cap = 0xffff0000u;
+    unsigned int qs = 0, wstamp = 0, pstamp = 0;
+    const int SB = 256;
+    const int list_grid = (int)std::min<long long>(4096, std::max<long long>(1, ceil_div(N, 256)));
+    for (;;) {
+        if (h->nsrc == 0 && h->gex <= 0) break;
+        const int gsrc = h->gex > 0;
+        ++pstamp;
+        hipLaunchKernelGGL(k_pass_reset, dim3(1), dim3(1), 0, st, ctl);
+        WW_LAUNCH_CHECK();
+        int cur = 0;
+        ++qs;
+        hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.qstamp, qs,
+                           ra.lists, gsrc, ra.perim_tiles, ra.nperim);
+        WW_LAUNCH_CHECK();
+        unsigned int bound = 1024;
+        for (;;) {  // windows
+            ++wstamp;
+            ++S.windows;
+            for (;;) {  // rounds
+                for (int k = 0; k < rounds_per_sync; ++k) {
+                    hipLaunchKernelGGL(k_sssp_round, dim3(round_grid), dim3(SS_THREADS), 0, st, g,
+                                       ctl, ra, cur, qs + 1, wstamp, pstamp, bound);
+                    WW_LAUNCH_CHECK();
+                    ++qs;
+                    cur = (cur + 1) % 3;
+                }
+                S.rounds += rounds_per_sync;
+                if (S.rounds > 50000000)
+                    return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
+                WW_TRY(sync_ctl());
+                if (h->count[cur] == 0) break;
+            }
+            hipLaunchKernelGGL(k_clear_settled, dim3(1), dim3(1), 0, st, ctl);
+            WW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_count_settled, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, bound);
+            WW_LAUNCH_CHECK();
+            WW_TRY(sync_ctl());
+            const long long units = (long long)h->nsrc + std::max<long long>(h->gex, 0);
+            const long long need = std::max<long long>(1, (units + 1) / 2);
+            if ((long long)h->settled >= need || h->pend_count == 0) break;
+            if (bound >= bound_cap)
+                return fail(WW_E_OVERFLOW, "min-cost flow: shortest-path distance above 2^32");
+            bound = (bound > bound_cap / 2) ? bound_cap : bound * 2;
+            ++qs;
+            hipLaunchKernelGGL(k_requeue_pending, dim3(list_grid), dim3(SB), 0, st, ctl,
+                               ra.pend_list, ra.qstamp, qs, ra.lists + (size_t)cur * NT, cur);
+            WW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(1), 0, st, ctl);
+            WW_LAUNCH_CHECK();
+        }
+        if (h->settled == 0)
+            return fail(WW_E_INFEASIBLE, "min-cost flow: %u supplies reach no demand", h->nsrc);
+        const int pg = (int)std::min<long long>(1024, ceil_div(nperim_arcs, SB));
+        hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, bound);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_roots, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, bound, gsub_list);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gsub_select, dim3(pg), dim3(SB), 0, st, g, ctl, gsub_list, drop);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_augment, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, gsub_list, drop);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_potentials, dim3(round_grid), dim3(SB), 0, st, g, ctl, ra.touch_list,
+                           bound);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_compact, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, def, src2, def2);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_swap_lists, dim3(1), dim3(1), 0, st, ctl);
+        WW_LAUNCH_CHECK();
+        std::swap(src, src2);
+        std::swap(def, def2);
+        WW_TRY(sync_ctl());
+        ++S.passes;
+        S.augmentations += h->naug;
+        S.path_arcs += (long long)h->arcs;
+        if (h->naug == 0)
+            return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
+    }
+    const int cg = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(nx + ny, 256)));
+    hipLaunchKernelGGL(k_total_cost, dim3(cg), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn, nx,
+                       ny, ctl);
+    WW_LAUNCH_CHECK();
+    if (pot_out) {
+        hipLaunchKernelGGL(k_export_pot, dim3(IB), dim3(256), 0, st, g.pot, ctl, N, pot_out);
+        WW_LAUNCH_CHECK();
+    }
+    WW_TRY(sync_ctl());
+    *total = h->total_cost;
+    S.tile_visits = (long long)h->visits;
+    S.max_potential = std::max<long long>(h->max_pot, h->gpot);
+    if (stats) *stats = S;
+    return WW_OK;
+}
+
+}  // namespace ww

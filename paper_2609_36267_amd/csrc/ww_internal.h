@@ -1,0 +1,105 @@
+// Internal declarations of the gfx950 unwrapper library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+
+#include "../../include/ww.h"
+
+namespace ww {
+
+// ---------------------------------------------------------------- errors ---
+
+ww_status fail(ww_status code, const char *fmt, ...);
+void clear_error();
+
+#define WW_HIP(call)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return ::ww::fail(WW_E_DEVICE, "%s failed: %s (%s:%d)", #call,         \
+                              hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+#define WW_TRY(expr)                           \
+    do {                                       \
+        ww_status s_ = (expr);                 \
+        if (s_ != WW_OK) return s_;            \
+    } while (0)
+
+#define WW_LAUNCH_CHECK() WW_HIP(hipGetLastError())
+
+// ------------------------------------------------------------- workspace ---
+
+// Grow-only device buffers owned by the library, one set per device.  All
+// entry points serialise on `lock()`, so a buffer is never shared by two
+// calls at once.
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex &lock();
+int current_device();
+// Returns a device buffer of at least `bytes` for (device, slot); contents
+// are unspecified.
+ww_status scratch(int slot, size_t bytes, void **out);
+// Pinned host staging area (for counters read back by the solver loop).
+ww_status host_scratch(size_t bytes, void **out);
+
+enum Slot {
+    SLOT_RES = 0, SLOT_CXP, SLOT_CXN, SLOT_CYP, SLOT_CYN, SLOT_DKX, SLOT_DKY, SLOT_LUT,
+    SLOT_COUNTERS, SLOT_STEEP, SLOT_STEEP_KEYS,
+    SLOT_MCF_LAB, SLOT_MCF_POT, SLOT_MCF_EX, SLOT_MCF_BEST, SLOT_MCF_TILES,
+    SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_INTEG,
+    SLOT_LUT_WORK,
+    SLOT_COUNT
+};
+
+// ------------------------------------------------------------- constants ---
+
+// Double nearest to pi and to 2 pi.  The double nearest pi lies below pi and
+// no double lies in (PI_D, pi], so "diff > PI_D" is the exact test diff > pi.
+constexpr double PI_D = 3.141592653589793115997963468544185161590576171875;
+constexpr double TWO_PI_D = 6.28318530717958623199592693708837032318115234375;
+constexpr int64_t PI_FIX = 3294199;  // round(pi * 2^20)
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------ device helpers ---
+
+// Cycles removed by wrapping a phase difference into (-pi, pi].
+__device__ __forceinline__ int wrap_cycles(double diff) {
+    return (diff > PI_D) ? 1 : ((diff <= -PI_D) ? -1 : 0);
+}
+
+__device__ __forceinline__ double phase_at(const float *psi, const uint8_t *valid, int64_t k) {
+    return (valid == nullptr || valid[k]) ? (double)psi[k] : 0.0;
+}
+
+// -------------------------------------------------------- entry helpers ---
+
+ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, const int16_t **out);
+ww_status residues_impl(const float *psi, const uint8_t *valid, int m, int n, int8_t *res,
+                        int8_t *perim, int64_t *ground_dev, hipStream_t stream);
+ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
+                          const int16_t *lut, int n_alpha, int n_gamma, const ww_cost_params &cp,
+                          int16_t *cxp, int16_t *cxn, int16_t *cyp, int16_t *cyn,
+                          hipStream_t stream);
+ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const int16_t *cxn,
+                   const int16_t *cyp, const int16_t *cyn, int8_t *dkx, int8_t *dky,
+                   int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t stream);
+ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *dkx,
+                         const int8_t *dky, int m, int n, const ww_cost_params &cp, int32_t *K,
+                         float *phi, hipStream_t stream);
+ww_status build_lut_impl(int looks, const ww_lut_params &p, int16_t *lut_dev, hipStream_t stream);
+
+ww_status check_lut_params(const ww_lut_params &p);
+ww_status check_cost_params(const ww_cost_params &p);
+
+}  // namespace ww

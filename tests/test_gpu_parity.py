@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by
+element, on seeded inputs that span several tiles and ragged tails."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_36267_amd import binding as ww
+from paper_2609_36267_amd import synth
+from tests.helpers import (assert_same_on_certified_pixels, assert_same_on_fixed_edges, flow_cost,
+                           np_, phase_tolerance_ok)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    ww.load()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return synth.config("c0", keep_truth=False)
+
+
+@pytest.fixture(scope="module")
+def lut9():
+    return oracle.build_lut(9)
+
+
+def rand_scene(seed, m, n, mask_frac=0.1, nan=True):
+    rng = np.random.default_rng(seed)
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    # smooth part so that not everything is noise
+    i = np.arange(m)[:, None]
+    j = np.arange(n)[None, :]
+    smooth = np.angle(np.exp(1j * (0.3 * j + 0.1 * i + 5 * np.sin(i / 7.0)))).astype(np.float32)
+    pick = rng.random((m, n)) < 0.7
+    psi = np.where(pick, smooth, psi).astype(np.float32)
+    coh = rng.uniform(-0.05, 1.05, (m, n)).astype(np.float32)
+    if nan and m * n > 4:
+        coh.reshape(-1)[rng.integers(0, m * n, 3)] = np.nan
+    valid = (rng.random((m, n)) > mask_frac).astype(np.uint8)
+    return psi, coh, valid
+
+
+SHAPES = [(1, 1), (1, 9), (9, 1), (2, 2), (3, 70), (70, 3), (37, 45), (64, 64), (65, 97), (130, 257)]
+
+
+# ------------------------------------------------------------- residues ---
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_residues_parity(torch_cuda, shape):
+    m, n = shape
+    psi, _, valid = rand_scene(m * 1000 + n, m, n)
+    for v in (valid, None):
+        res_g, perim_g, g_g = ww.residues(psi, v)
+        res_o, perim_o, g_o = oracle.residues(psi, v)
+        assert np.array_equal(np_(res_g), res_o)
+        assert np.array_equal(np_(perim_g), perim_o)
+        assert g_g == g_o
+
+
+def test_residues_parity_c0(torch_cuda, c0):
+    res_g, perim_g, g_g = ww.residues(c0.psi, c0.valid)
+    res_o, perim_o, g_o = oracle.residues(c0.psi, c0.valid)
+    assert np.array_equal(np_(res_g), res_o) and np.array_equal(np_(perim_g), perim_o)
+    assert g_g == g_o and np.abs(res_o).sum() > 100
+
+
+# ------------------------------------------------------------------ LUT ---
+
+@pytest.mark.parametrize("L", [9, 15, 5, 2, 64])
+def test_lut_parity(torch_cuda, L):
+    T_g = ww.build_cost_lut(L)
+    T_o = oracle.build_lut(L)
+    diff = np.argwhere(T_g != T_o)
+    assert diff.size == 0, f"{len(diff)} entries differ, first {diff[:5].tolist()}"
+
+
+def test_lut_parity_other_discretisation(torch_cuda):
+    p = ww.default_lut_params()
+    p.n_alpha, p.n_gamma, p.n_eta, p.n_gpanel, p.n_gnode, p.n_aquad = 64, 32, 512, 16, 8, 129
+    T_g = ww.build_cost_lut(9, p)
+    T_o = oracle.build_lut(9, oracle.lut_params(64, 32, 512, 16, 8, 129, 8.0))
+    assert np.array_equal(T_g, T_o)
+
+
+# ---------------------------------------------------------------- costs ---
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("h", [0, 2])
+def test_costs_parity(torch_cuda, lut9, shape, h):
+    m, n = shape
+    psi, coh, valid = rand_scene(7 + m * 31 + n, m, n)
+    cp = ww.default_cost_params(box_half=h)
+    got = ww.edge_costs(psi, coh, valid, lut9, cp)
+    want = oracle.edge_costs(psi, coh, valid, lut9, box_half=h)
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+
+
+@pytest.mark.parametrize("h", [1, 3, 8])
+def test_costs_parity_box_sizes(torch_cuda, lut9, h):
+    psi, coh, valid = rand_scene(99 + h, 77, 150)
+    got = ww.edge_costs(psi, coh, valid, lut9, ww.default_cost_params(box_half=h))
+    want = oracle.edge_costs(psi, coh, valid, lut9, box_half=h)
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+
+
+def test_costs_parity_steep_cap_binds(torch_cuda, lut9):
+    rng = np.random.default_rng(3)
+    m, n = 90, 110
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    coh = np.full((m, n), 0.9, np.float32)
+    (want, st) = oracle.edge_costs(psi, coh, None, lut9, want_stats=True)
+    assert st["steep_candidates"] > st["steep_zeroed"] > 0
+    got = ww.edge_costs(psi, coh, None, lut9)
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+    # steep rule off, and a cap of zero
+    for kw, okw in ((dict(steep_rule=0), dict(steep_rule=0)), (dict(steep_cap_pct=0), dict(steep_cap_pct=0))):
+        got = ww.edge_costs(psi, coh, None, lut9, ww.default_cost_params(**kw))
+        want = oracle.edge_costs(psi, coh, None, lut9, **okw)
+        for g, w in zip(got, want):
+            assert np.array_equal(np_(g), w)
+
+
+def test_costs_parity_c0_with_gpu_table(torch_cuda, c0):
+    T = ww.build_cost_lut(9)
+    got = ww.edge_costs(c0.psi, c0.coh, c0.valid, T)
+    want = oracle.edge_costs(c0.psi, c0.coh, c0.valid, T)
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+
+
+# ------------------------------------------------------------------ MCF ---
+
+def _mcf_case(psi, costs, m, n):
+    res_o, _, _ = oracle.residues(psi)
+    dkx_o, dky_o, pot_o, tot_o = oracle.mcf(res_o, costs, m=m, n=n)
+    r = ww.mcf_solve(res_o, costs, m, n, want_potentials=True)
+    dkx_g, dky_g, pot_g = np_(r.dk_x), np_(r.dk_y), np_(r.potentials)
+    assert r.total_cost == tot_o, (r.total_cost, tot_o, r.stats)
+    assert flow_cost(dkx_g, dky_g, costs) == tot_o
+    cert = oracle.check_optimal(res_o, costs, dkx_g, dky_g, pot_g)
+    assert cert["ok"], cert
+    fx, fy = assert_same_on_fixed_edges(costs, dkx_o, dky_o, pot_o, dkx_g, dky_g)
+    return r, (dkx_o, dky_o, pot_o, tot_o), (fx, fy)
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (2, 9), (9, 2), (5, 5), (33, 33), (34, 70), (65, 97), (130, 257)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mcf_parity_random(torch_cuda, shape, seed):
+    m, n = shape
+    rng = np.random.default_rng(seed * 7919 + m * 13 + n)
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    costs = []
+    for s in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)):
+        c = rng.integers(0, [50, 3000][seed], s).astype(np.int16)
+        c[rng.random(s) < 0.1] = 0
+        costs.append(c)
+    _mcf_case(psi, tuple(costs), m, n)
+
+
+def test_mcf_degenerate_shapes(torch_cuda):
+    for m, n in ((1, 1), (1, 12), (12, 1)):
+        costs = (np.ones((m, max(n - 1, 0)), np.int16), np.ones((m, max(n - 1, 0)), np.int16),
+                 np.ones((max(m - 1, 0), n), np.int16), np.ones((max(m - 1, 0), n), np.int16))
+        r = ww.mcf_solve(np.zeros((max(m - 1, 0), max(n - 1, 0)), np.int8), costs, m, n)
+        assert r.total_cost == 0
+        assert not np_(r.dk_x).any() and not np_(r.dk_y).any()
+
+
+def test_mcf_parity_c0(torch_cuda, c0, lut9):
+    costs = oracle.edge_costs(c0.psi, c0.coh, c0.valid, lut9)
+    r, _, (fx, fy) = _mcf_case(c0.psi, costs, 256, 256)
+    assert r.stats["augmentations"] > 100
+    assert fx.mean() > 0.9
+
+
+@pytest.mark.parametrize("i0,j0", [(700, 300), (1200, 1500)])
+def test_mcf_parity_c1_crop(torch_cuda, lut9, i0, j0):
+    """512 x 512 windows of the c1 recipe (low-coherence disks, 5 % mask)."""
+    sc = synth.make(2048, 2048, looks=9, seed=1, disks=6, mask_frac=0.05, keep_truth=False)
+    psi = sc.psi[i0:i0 + 512, j0:j0 + 512]
+    coh = sc.coh[i0:i0 + 512, j0:j0 + 512]
+    valid = sc.valid[i0:i0 + 512, j0:j0 + 512]
+    costs = oracle.edge_costs(psi, coh, valid, lut9)
+    res_o, _, _ = oracle.residues(psi, valid)
+    dkx_o, dky_o, pot_o, tot_o = oracle.mcf(res_o, costs, m=512, n=512)
+    r = ww.mcf_solve(res_o, costs, 512, 512, want_potentials=True)
+    assert r.total_cost == tot_o
+    cert = oracle.check_optimal(res_o, costs, np_(r.dk_x), np_(r.dk_y), np_(r.potentials))
+    assert cert["ok"], cert
+    assert_same_on_fixed_edges(costs, dkx_o, dky_o, pot_o, np_(r.dk_x), np_(r.dk_y))
+
+
+# ------------------------------------------------------------ integrate ---
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_integrate_parity(torch_cuda, lut9, shape):
+    m, n = shape
+    psi, coh, valid = rand_scene(5 + m * 17 + n, m, n)
+    out = oracle.unwrap(psi, coh, valid, 9, lut=lut9, want=True)
+    K_g, phi_g = ww.integrate(psi, valid, out["dkx"], out["dky"])
+    K_g, phi_g = np_(K_g), np_(phi_g)
+    assert np.array_equal(K_g, out["K"])
+    ok, err = phase_tolerance_ok(phi_g, psi, K_g, valid)
+    assert ok, err
+    inv = valid == 0
+    assert np.all(np.isnan(phi_g[inv]))
+    # explicit reference pixel and nodata
+    K2, phi2 = ww.integrate(psi, valid, out["dkx"], out["dky"], ref=(m - 1, n - 1), nodata=-7.0)
+    K2o, _ = oracle.integrate(psi, valid, out["dkx"], out["dky"], ref=(m - 1, n - 1), nodata=-7.0)
+    assert np.array_equal(np_(K2), K2o)
+    assert np.all(np_(phi2)[inv] == -7.0)
+
+
+# ---------------------------------------------------------------- whole ---
+
+def test_unwrap_c0_end_to_end(torch_cuda, c0, lut9):
+    K_g, phi_g, tot_g = ww.unwrap(c0.psi, c0.coh, c0.valid, 9)
+    out = oracle.unwrap(c0.psi, c0.coh, c0.valid, 9, lut=lut9, want=True)
+    assert tot_g == out["total"]
+    K_g, phi_g = np_(K_g), np_(phi_g)
+    fx, fy = oracle.fixed_edges(out["costs"], out["dkx"], out["dky"], out["pot"])
+    frac = assert_same_on_certified_pixels(K_g, out["K"], fx, fy, oracle.ref_index(c0.valid, 256, 256))
+    assert frac > 0.5
+    ok, err = phase_tolerance_ok(phi_g, c0.psi, K_g, c0.valid)
+    assert ok, err
+
+
+def test_unwrap_is_deterministic(torch_cuda, c0):
+    a = [np_(x) for x in ww.unwrap(c0.psi, c0.coh, c0.valid, 9)[:2]]
+    b = [np_(x) for x in ww.unwrap(c0.psi, c0.coh, c0.valid, 9)[:2]]
+    assert np.array_equal(a[0], b[0])
+    assert a[1].tobytes() == b[1].tobytes()
+
+
+def test_errors_raise(torch_cuda, c0):
+    with pytest.raises(ww.WWError) as e:
+        ww.unwrap(c0.psi, c0.coh, c0.valid, 1)
+    assert e.value.code == ww.E_INVALID_ARG
+    with pytest.raises(ww.WWError):
+        ww.edge_costs(c0.psi, c0.coh, c0.valid, np.zeros((64, 128), np.int16),
+                      ww.default_cost_params(box_half=40))
