@@ -85,7 +85,13 @@ typedef struct {
     int64_t path_arcs;       /* arcs flipped by augmentations               */
     int64_t supplies;        /* initial positive charge incl. the ground    */
     int64_t max_potential;   /* largest node potential at exit              */
+    double relax_ms;         /* device time of the relaxation rounds        */
+    double solve_ms;         /* wall time of the whole solve                */
 } ww_mcf_stats;
+
+/* Counters of the most recent min-cost-flow solve made by this process
+ * (through ww_mcf_solve or ww_unwrap).  Writes zeros before the first. */
+void ww_last_mcf_stats(ww_mcf_stats *out);
 
 /* Defaults: n_alpha 128, n_gamma 64, n_eta 2048, 64 x 16 Gauss-Legendre
  * nodes, n_aquad 513, sigma_span 8; box_half 2, steep rule on at 1 rad and

@@ -23,7 +23,7 @@ OK, E_INVALID_ARG, E_OOM, E_INFEASIBLE, E_DEVICE, E_OVERFLOW = 0, -1, -2, -3, -4
 _NAMES = {E_INVALID_ARG: "WW_E_INVALID_ARG", E_OOM: "WW_E_OOM", E_INFEASIBLE: "WW_E_INFEASIBLE",
           E_DEVICE: "WW_E_DEVICE", E_OVERFLOW: "WW_E_OVERFLOW"}
 
-EXPORTS = ["ww_last_error", "ww_version", "ww_default_lut_params", "ww_default_cost_params",
+EXPORTS = ["ww_last_error", "ww_version", "ww_last_mcf_stats", "ww_default_lut_params", "ww_default_cost_params",
            "ww_residues", "ww_build_cost_lut", "ww_edge_costs", "ww_mcf_solve", "ww_integrate",
            "ww_unwrap"]
 
@@ -49,10 +49,18 @@ class CostParams(C.Structure):
 class McfStats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("passes", "windows", "rounds", "tile_visits",
                                          "augmentations", "path_arcs", "supplies",
-                                         "max_potential")]
+                                         "max_potential")] + [("relax_ms", C.c_double),
+                                                              ("solve_ms", C.c_double)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+def last_mcf_stats() -> dict:
+    st = McfStats()
+    load().ww_last_mcf_stats(C.byref(st))
+    return st.as_dict()
 
 
 def load(path: str = LIB_PATH):
@@ -73,6 +81,7 @@ def _declare(L):
     P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
     L.ww_last_error.restype = C.c_char_p
     L.ww_version.restype = C.c_char_p
+    L.ww_last_mcf_stats.argtypes = [P]
     L.ww_default_lut_params.argtypes = [P]
     L.ww_default_cost_params.argtypes = [P]
     L.ww_residues.argtypes = [P, P, I32, I32, P, P, P, P]

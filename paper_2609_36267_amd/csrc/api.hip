@@ -156,6 +156,12 @@ const char *ww_last_error(void) { return g_error.c_str(); }
 
 const char *ww_version(void) { return "ww-gfx950 0.1"; }
 
+void ww_last_mcf_stats(ww_mcf_stats *out) {
+    if (!out) return;
+    std::lock_guard<std::mutex> g(lock());
+    *out = last_mcf_stats();
+}
+
 void ww_default_lut_params(ww_lut_params *p) {
     if (!p) return;
     p->n_alpha = 128;

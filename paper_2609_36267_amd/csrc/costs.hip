@@ -24,7 +24,10 @@ constexpr int CT_H = 16;   // tile rows
 constexpr int CT_W = 64;   // tile cols
 constexpr int CT_THREADS = 256;
 
+constexpr int STRIPES = 256;
+
 struct SteepState {
+    unsigned long long nvalid_part[STRIPES];  // per-stripe valid-edge counts
     unsigned long long nvalid, ncand, cap, remaining;
     unsigned long long prefix_hi, mask_hi;
     unsigned int prefix_lo, mask_lo;
@@ -130,7 +133,13 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
     int nvalid = 0;
     const int c = tid % CT_W;
     const int rstart = tid / CT_W;
-    for (int r = rstart; r < CT_H; r += CT_THREADS / CT_W) {
+    constexpr int ITERS = CT_H / (CT_THREADS / CT_W);
+    unsigned long long ckey[2 * ITERS];
+    unsigned int cid[2 * ITERS];
+    unsigned int cmask = 0;  // fixed slots 2*it (x-edge) and 2*it+1 (y-edge)
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int r = rstart + it * (CT_THREADS / CT_W);
         const int i = i0 + r, j = j0 + c;
         int64_t S1 = 0, S2 = 0;
         int K1 = 0, K2 = 0;
@@ -142,10 +151,8 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
         }
         const int sc = (r + h) * EC + (c + h);  // own sample
         // ---- x-edge hx(i, j)
-        bool candx = false;
-        unsigned long long keyx = 0;
-        int64_t idx_x = (int64_t)i * nx_cols + j;
         if (i < m && j < n - 1) {
+            const int64_t idx_x = (int64_t)i * nx_cols + j;
             int16_t cp = 0, cn = 0;
             if (ex[sc]) {
                 ++nvalid;
@@ -164,18 +171,17 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
                 double diff = (double)ph[p + 1] - (double)ph[p];
                 double dd = fabs(diff - TWO_PI_D * wrap_cycles(diff));
                 if (steep_on && dd > steep_thresh) {
-                    candx = true;
-                    keyx = (unsigned long long)__double_as_longlong(dd);
+                    ckey[2 * it] = (unsigned long long)__double_as_longlong(dd);
+                    cid[2 * it] = (unsigned int)idx_x;
+                    cmask |= 1u << (2 * it);
                 }
             }
             cxp[idx_x] = cp;
             cxn[idx_x] = cn;
         }
         // ---- y-edge vy(i, j)
-        bool candy = false;
-        unsigned long long keyy = 0;
-        int64_t idx_y = (int64_t)i * n + j;
         if (i < m - 1 && j < n) {
+            const int64_t idx_y = (int64_t)i * n + j;
             int16_t cp = 0, cn = 0;
             if (ey[sc]) {
                 ++nvalid;
@@ -194,42 +200,61 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
                 double diff = (double)ph[p + PC] - (double)ph[p];
                 double dd = fabs(diff - TWO_PI_D * wrap_cycles(diff));
                 if (steep_on && dd > steep_thresh) {
-                    candy = true;
-                    keyy = (unsigned long long)__double_as_longlong(dd);
+                    ckey[2 * it + 1] = (unsigned long long)__double_as_longlong(dd);
+                    cid[2 * it + 1] = (unsigned int)(nx_total + idx_y);
+                    cmask |= 1u << (2 * it + 1);
                 }
             }
             cyp[idx_y] = cp;
             cyn[idx_y] = cn;
         }
-        // wave-aggregated append of steep candidates
-        const unsigned long long bx = __ballot(candx), by = __ballot(candy);
-        const int tot = __popcll(bx) + __popcll(by);
-        if (tot) {
-            const int lane = threadIdx.x & 63;
-            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&st->ncand, (unsigned long long)tot);
-            base = __shfl(base, 0, 64);
-            if (candx) {
-                unsigned long long pos = base + __popcll(bx & below);
-                cand_key[pos] = keyx;
-                cand_id[pos] = (unsigned int)idx_x;
-            }
-            if (candy) {
-                unsigned long long pos = base + __popcll(bx) + __popcll(by & below);
-                cand_key[pos] = keyy;
-                cand_id[pos] = (unsigned int)(nx_total + idx_y);
+    }
+    // block totals: one striped atomic for the valid count, one reservation
+    // for the candidates
+    __shared__ int red_valid[CT_THREADS / 64], red_cand[CT_THREADS / 64];
+    __shared__ unsigned long long cand_base;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int ncand = __popc(cmask);
+    int v = nvalid, incl = ncand;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    for (int off = 1; off < 64; off <<= 1) {
+        int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 0) red_valid[wid] = v;
+    if (lane == 63) red_cand[wid] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int tv = 0, tc = 0;
+        for (int w = 0; w < CT_THREADS / 64; ++w) {
+            tv += red_valid[w];
+            tc += red_cand[w];
+        }
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        if (tv) atomicAdd(&st->nvalid_part[blk % STRIPES], (unsigned long long)tv);
+        cand_base = tc ? atomicAdd(&st->ncand, (unsigned long long)tc) : 0ull;
+    }
+    __syncthreads();
+    if (ncand) {
+        unsigned long long pos = cand_base + (unsigned long long)(incl - ncand);
+        for (int w = 0; w < wid; ++w) pos += red_cand[w];
+#pragma unroll
+        for (int k = 0; k < 2 * ITERS; ++k) {
+            if (cmask & (1u << k)) {
+                cand_key[pos] = ckey[k];
+                cand_id[pos] = cid[k];
+                ++pos;
             }
         }
     }
-    // valid-edge count
-    for (int off = 32; off > 0; off >>= 1) nvalid += __shfl_down(nvalid, off, 64);
-    if ((threadIdx.x & 63) == 0 && nvalid) atomicAdd(&st->nvalid, (unsigned long long)nvalid);
 }
 
 // cap = floor(pct * valid / 100); remaining = cap
 __global__ void k_steep_init(SteepState *st, int pct) {
-    st->cap = st->nvalid * (unsigned long long)pct / 100ull;
+    unsigned long long nv = 0;
+    for (int k = 0; k < STRIPES; ++k) nv += st->nvalid_part[k];
+    st->nvalid = nv;
+    st->cap = nv * (unsigned long long)pct / 100ull;
     st->remaining = st->cap;
     st->prefix_hi = 0;
     st->mask_hi = 0;

@@ -27,21 +27,28 @@ struct IntegState {
     int pad;
 };
 
-__global__ void k_first_valid(const uint8_t *__restrict__ valid, int64_t N, IntegState *st) {
-    int64_t best = N;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        if (valid[k]) {
-            best = k;
-            break;  // indices grow with k for this thread
+// First valid pixel (row-major).  One workgroup scans chunks from the start
+// and stops at the first chunk holding a valid pixel: typical masks end the
+// search in the first chunk, an all-invalid image reads the mask once.
+__global__ __launch_bounds__(1024) void k_first_valid(const uint8_t *__restrict__ valid, int64_t N,
+                                                     IntegState *st) {
+    __shared__ unsigned long long best;
+    if (threadIdx.x == 0) best = (unsigned long long)N;
+    __syncthreads();
+    for (int64_t base = 0; base < N; base += 1024 * 16) {
+        const int64_t k0 = base + (int64_t)threadIdx.x * 16;
+        for (int q = 0; q < 16; ++q) {
+            const int64_t k = k0 + q;
+            if (k < N && valid[k]) {
+                atomicMin(&best, (unsigned long long)k);
+                break;
+            }
         }
+        __syncthreads();
+        if (best < (unsigned long long)N) break;
+        __syncthreads();
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        int64_t o = __shfl_down(best, off, 64);
-        best = o < best ? o : best;
-    }
-    if ((threadIdx.x & 63) == 0 && best < N) atomicMin((unsigned long long *)&st->first_valid,
-                                                       (unsigned long long)best);
+    if (threadIdx.x == 0) st->first_valid = (long long)best;
 }
 
 // Block-wide exclusive scan of one int per thread; returns the exclusive
@@ -186,9 +193,7 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
     init.pad = 0;
     WW_HIP(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
     if (valid && cp.ref_i < 0) {
-        const int blocks = (int)std::min<int64_t>(4096, ceil_div(N, 256 * 64));
-        hipLaunchKernelGGL(k_first_valid, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, stream,
-                           valid, N, st);
+        hipLaunchKernelGGL(k_first_valid, dim3(1), dim3(1024), 0, stream, valid, N, st);
         WW_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_col0, dim3(1), dim3(IT_THREADS), 0, stream, psi, valid, dkx, dky, m, n,

@@ -30,6 +30,10 @@
 //     tight and reversing it keeps all reduced costs >= 0, so the final flow
 //     is optimal whatever the window and the number of paths per pass.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <cstring>
 #include <vector>
 
@@ -68,6 +72,7 @@ struct Ctl {
     long long total_cost;
     long long sum_res;
     unsigned long long visits; // tiles relaxed, all rounds
+    unsigned long long min_rej; // smallest candidate label beyond the window
 };
 
 struct Graph {
@@ -121,30 +126,126 @@ __device__ __forceinline__ void ground_arc(const Graph &g, unsigned int a, int &
 
 // ------------------------------------------------------------ set-up ------
 
-__global__ void k_mcf_init(Graph g, const int8_t *__restrict__ res, Ctl *ctl,
-                           unsigned int *src, unsigned int *def) {
+// Set-up in three launches with no contended atomics: every block of
+// INIT_CHUNK nodes initialises its state and counts its supplies / demands;
+// one block scans the counts; every block then writes its supplies and
+// demands in node order.
+constexpr int INIT_THREADS = 256;
+constexpr int INIT_PER = 16;
+constexpr int INIT_CHUNK = INIT_THREADS * INIT_PER;
+
+__device__ __forceinline__ int block_sum_int(int v, int *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// exclusive block scan (blockDim.x <= 1024), returns the prefix, *total = sum
+__device__ __forceinline__ int block_scan_int(int v, int *red, int *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) red[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        if (w < wid) before += red[w];
+        tot += red[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const int8_t *__restrict__ res,
+                                                                int *__restrict__ bc) {
+    __shared__ int red[INIT_THREADS / 64];
     const long long N = (long long)g.R * g.C;
-    long long s = 0;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N;
-         v += (long long)gridDim.x * blockDim.x) {
-        int r = res[v];
+    const long long base = (long long)blockIdx.x * INIT_CHUNK;
+    int np = 0, nn = 0, sum = 0;
+    for (int k = 0; k < INIT_PER; ++k) {
+        const long long v = base + k * INIT_THREADS + threadIdx.x;
+        if (v >= N) break;
+        const int r = res[v];
         g.ex[v] = (int8_t)r;
         g.pot[v] = 0;
         g.lab[v] = LINF;
         g.best[v] = LINF;
-        s += r;
-        if (r > 0) src[atomicAdd(&ctl->nsrc, 1u)] = (unsigned int)v;
-        else if (r < 0) def[atomicAdd(&ctl->ndef, 1u)] = (unsigned int)v;
+        np += r > 0;
+        nn += r < 0;
+        sum += r;
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->sum_res,
-                                               (unsigned long long)s);
+    np = block_sum_int(np, red);
+    nn = block_sum_int(nn, red);
+    sum = block_sum_int(sum, red);
+    if (threadIdx.x == 0) {
+        bc[3 * blockIdx.x + 0] = np;
+        bc[3 * blockIdx.x + 1] = nn;
+        bc[3 * blockIdx.x + 2] = sum;
+    }
 }
 
-__global__ void k_mcf_finish_init(Ctl *ctl) {
-    ctl->gex = -ctl->sum_res;
-    ctl->gpot = 0;
-    ctl->glab = LINF;
+// one block: exclusive scans of the per-block counts, totals into ctl
+__global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict__ bc, Ctl *ctl) {
+    __shared__ int red[16];
+    int carry_p = 0, carry_n = 0;
+    long long sum = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        int p = 0, q = 0, s = 0;
+        if (b < nb) {
+            p = bc[3 * b];
+            q = bc[3 * b + 1];
+            s = bc[3 * b + 2];
+        }
+        int tp, tq;
+        const int ep = block_scan_int(p, red, &tp);
+        const int eq = block_scan_int(q, red, &tq);
+        const int ts = block_sum_int(s, red);
+        if (b < nb) {
+            bc[3 * b] = carry_p + ep;
+            bc[3 * b + 1] = carry_n + eq;
+        }
+        carry_p += tp;
+        carry_n += tq;
+        sum += ts;
+    }
+    if (threadIdx.x == 0) {
+        ctl->nsrc = carry_p;
+        ctl->ndef = carry_n;
+        ctl->sum_res = sum;
+        ctl->gex = -sum;
+        ctl->gpot = 0;
+        ctl->glab = LINF;
+    }
+}
+
+__global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const int8_t *__restrict__ res,
+                                                                const int *__restrict__ bc,
+                                                                unsigned int *__restrict__ src,
+                                                                unsigned int *__restrict__ def) {
+    __shared__ int red[INIT_THREADS / 64];
+    const long long N = (long long)g.R * g.C;
+    const long long base = (long long)blockIdx.x * INIT_CHUNK;
+    int op = bc[3 * blockIdx.x], on = bc[3 * blockIdx.x + 1];
+    for (int k = 0; k < INIT_PER; ++k) {
+        const long long v = base + k * INIT_THREADS + threadIdx.x;
+        const int r = v < N ? res[v] : 0;
+        int tp, tn;
+        const int ep = block_scan_int(r > 0, red, &tp);
+        const int en = block_scan_int(r < 0, red, &tn);
+        if (r > 0) src[op + ep] = (unsigned int)v;
+        if (r < 0) def[on + en] = (unsigned int)v;
+        op += tp;
+        on += tn;
+    }
 }
 
 // Pass start: sources get label 0 and their tiles are queued.
@@ -153,10 +254,18 @@ __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned
                             unsigned int *perim_tiles, int nperim) {
     const unsigned int ns = ctl->nsrc;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
-        unsigned int v = src[k];
+        const unsigned int v = src[k];
         g.lab[v] = 0ull;
-        unsigned int t = (v / g.C / TS) * g.TC + (v % g.C) / TS;
+        const int i = v / g.C, j = v % g.C;
+        const int ti = i / TS, tj = j / TS, li = i % TS, lj = j % TS;
+        const unsigned int t = ti * g.TC + tj;
         enqueue(t, stamp, stamps, list0, &ctl->count[0]);
+        // a supply on a tile border also feeds the tile across that border,
+        // whose relaxation must run although this label never "changes"
+        if (li == 0 && ti > 0) enqueue(t - g.TC, stamp, stamps, list0, &ctl->count[0]);
+        if (li == TS - 1 && ti < g.TR - 1) enqueue(t + g.TC, stamp, stamps, list0, &ctl->count[0]);
+        if (lj == 0 && tj > 0) enqueue(t - 1, stamp, stamps, list0, &ctl->count[0]);
+        if (lj == TS - 1 && tj < g.TC - 1) enqueue(t + 1, stamp, stamps, list0, &ctl->count[0]);
     }
     if (ground_source) {
         for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x)
@@ -173,6 +282,7 @@ struct RoundArgs {
     unsigned int *pstamp;       // per-tile pending stamps
     unsigned int *tstamp;       // per-tile touched stamps
     unsigned int *pend_list, *touch_list, *perim_tiles;
+    unsigned long long *tile_rej;  // smallest rejected candidate of each tile
     int nperim;
     unsigned int NT;
 };
@@ -181,13 +291,13 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
                                                            int cur, unsigned int next_stamp,
                                                            unsigned int window_stamp,
                                                            unsigned int pass_stamp,
-                                                           unsigned int bound) {
+                                                           unsigned long long lb) {
     __shared__ unsigned long long L[TS + 2][TS + 3];
     __shared__ int P[TS + 2][TS + 2];
     __shared__ int RCs[4][TS][TS];
     __shared__ int flags[4];  // changed border: top, bottom, left, right
-    __shared__ int sh_pending, sh_any;
-    __shared__ unsigned long long sh_gcand;
+    __shared__ int sh_any;
+    __shared__ unsigned long long sh_gcand, sh_rej;
 
     const unsigned int cnt = ctl->count[cur];
     const int nxt = (cur + 1) % 3, clr = (cur + 2) % 3;
@@ -208,7 +318,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
         const int rows = min(TS, R - i0), cols = min(TS, C - j0);
         if (threadIdx.x < 4) flags[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
-            sh_pending = 0;
+            sh_rej = LINF;
             sh_gcand = LINF;
         }
         // stage labels and potentials with a one-node halo; outside = ground
@@ -268,7 +378,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
         unsigned long long init[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) init[k] = L[q * 4 + k + 1][lj + 1];
-        int pending = 0;
+        unsigned long long rej = LINF;  // smallest candidate beyond the window
         for (int it = 0; it < MAX_ITERS; ++it) {
             int changed = 0;
 #pragma unroll
@@ -286,12 +396,13 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
                     const unsigned long long u = nb[d];
                     if (rc == RC_INF || u == LINF) continue;
                     const unsigned long long nd = (unsigned long long)ldist(u) + (unsigned)rc;
-                    if (nd > bound) {
-                        pending = 1;
-                        continue;
-                    }
+                    if (nd > 0xffffffffull) continue;
                     const unsigned long long cand =
                         (nd << 32) | ((unsigned long long)(lhops(u) + 1) << 3) | (unsigned)(d + 1);
+                    if (cand > lb) {
+                        if (cand < rej) rej = cand;
+                        continue;
+                    }
                     if (cand < bestl) bestl = cand;
                 }
                 if (bestl < cur_l) {
@@ -353,16 +464,17 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
                     rc = 0;
                 }
                 const unsigned long long nd = (unsigned long long)ldist(l) + (unsigned)rc;
-                if (nd > bound) {
-                    pending = 1;
+                if (nd > 0xffffffffull) continue;
+                const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
+                if (cand > lb) {
+                    if (cand < rej) rej = cand;
                     continue;
                 }
-                const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
                 if (cand < gc) gc = cand;
             }
         }
         if (gc != LINF) atomicMin(&sh_gcand, gc);
-        if (pending) sh_pending = 1;
+        if (rej != LINF) atomicMin(&sh_rej, rej & ~7ull);
         __syncthreads();
         // activations
         if (threadIdx.x == 0) {
@@ -370,7 +482,9 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
             if (flags[1] && ti < g.TR - 1) enqueue(tile + g.TC, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
             if (flags[2] && tj > 0) enqueue(tile - 1, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
             if (flags[3] && tj < g.TC - 1) enqueue(tile + 1, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
-            if (sh_pending) enqueue(tile, window_stamp, ra.pstamp, ra.pend_list, &ctl->pend_count);
+            // the tile's parked candidates (recomputed in full at every visit)
+            ra.tile_rej[tile] = sh_rej;
+            if (sh_rej != LINF) enqueue(tile, pass_stamp, ra.pstamp, ra.pend_list, &ctl->pend_count);
             if (atomicExch(&ra.tstamp[tile], pass_stamp) != pass_stamp)
                 ra.touch_list[atomicAdd(&ctl->touch_count, 1u)] = tile;
             sh_any = 0;
@@ -388,26 +502,45 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
     }
 }
 
-// re-queue tiles with parked candidates after the window grew
-__global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pend, unsigned int *qstamp,
-                                  unsigned int stamp, unsigned int *list0, int cur) {
+// smallest parked candidate over the pass's pending tiles
+__global__ void k_min_pending(Ctl *ctl, const unsigned int *pend, const unsigned long long *tile_rej) {
     const unsigned int np = ctl->pend_count;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x)
-        enqueue(pend[k], stamp, qstamp, list0, &ctl->count[cur]);
+    unsigned long long mn = LINF;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
+        const unsigned long long r = tile_rej[pend[k]];
+        mn = r < mn ? r : mn;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_down(mn, off, 64);
+        mn = o < mn ? o : mn;
+    }
+    if ((threadIdx.x & 63) == 0 && mn != LINF) atomicMin(&ctl->min_rej, mn);
 }
 
-__global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsigned int bound) {
+// re-queue the pending tiles whose parked candidates the new window admits
+__global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pend,
+                                  const unsigned long long *tile_rej, unsigned long long lb,
+                                  unsigned int *qstamp, unsigned int stamp, unsigned int *list0,
+                                  int cur) {
+    const unsigned int np = ctl->pend_count;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
+        const unsigned int t = pend[k];
+        if (tile_rej[t] <= lb) enqueue(t, stamp, qstamp, list0, &ctl->count[cur]);
+    }
+}
+
+__global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb) {
     const unsigned int nd = ctl->ndef;
     unsigned int c = 0;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += gridDim.x * blockDim.x) {
         const unsigned long long l = g.lab[def[k]];
-        if (l != LINF && ldist(l) <= bound) ++c;
+        if (l <= lb) ++c;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&ctl->settled, c);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
-        if (ctl->gex < 0 && gl != LINF && ldist(gl) <= bound) atomicAdd(&ctl->settled, 1u);
+        if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->settled, 1u);
     }
 }
 
@@ -415,9 +548,9 @@ __global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsi
 
 // The ground's predecessor: the smallest perimeter arc index whose label
 // candidate equals the ground label.
-__global__ void k_ground_pred(Graph g, Ctl *ctl, unsigned int bound) {
+__global__ void k_ground_pred(Graph g, Ctl *ctl, unsigned long long lb) {
     const unsigned long long gl = ctl->glab;
-    if (gl == LINF || ldist(gl) > bound || ctl->gex > 0) return;
+    if (gl > lb || ctl->gex > 0) return;
     const unsigned int na = 2u * g.C + 2u * g.R;
     const int gpot = (int)ctl->gpot;
     for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < na; a += gridDim.x * blockDim.x) {
@@ -476,7 +609,7 @@ __device__ long long walk_root(const Graph &g, Ctl *ctl, long long v, int gsrc, 
     return -1;
 }
 
-__global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned int bound,
+__global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb,
                         unsigned int *gsub_list) {
     const unsigned int nd = ctl->ndef;
     const int gsrc = ctl->gex > 0;
@@ -487,13 +620,13 @@ __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned int
         if (k < nd) {
             const unsigned int t = def[k];
             const unsigned long long l = g.lab[t];
-            if (l == LINF || ldist(l) > bound) continue;
+            if (l > lb) continue;
             start = t;
             key = ((unsigned long long)ldist(l) << 32) | t;
         } else {
             // the ground as a demand: its path enters through gpred
             const unsigned long long gl = ctl->glab;
-            if (!(ctl->gex < 0 && gl != LINF && ldist(gl) <= bound)) continue;
+            if (!(ctl->gex < 0 && gl <= lb)) continue;
             if (ctl->gpred >= 2u * g.C + 2u * g.R) {
                 atomicOr(&ctl->error, ERR_WALK);
                 continue;
@@ -622,7 +755,8 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 }
 
 // pot(v) += B - d(v) on every reached node, labels back to infinity.
-__global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *touch, unsigned int bound) {
+__global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *touch, unsigned long long lb) {
+    const unsigned int bound = ldist(lb);
     const unsigned int nt = ctl->touch_count;
     int mx = 0;
     for (unsigned int idx = blockIdx.x; idx < nt; idx += gridDim.x) {
@@ -636,7 +770,7 @@ __global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *touch, unsig
             if (l == LINF) continue;
             g.lab[v] = LINF;
             const unsigned int d = ldist(l);
-            if (d > bound) continue;
+            if (l > lb) continue;
             const long long np = (long long)g.pot[v] + (bound - d);
             if (np > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
             g.pot[v] = (int)min(np, (long long)POT_LIMIT);
@@ -647,11 +781,63 @@ __global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *touch, unsig
     if ((threadIdx.x & 63) == 0) atomicMax(&ctl->max_pot, mx);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
-        if (gl != LINF && ldist(gl) <= bound) {
+        if (gl <= lb) {
             ctl->gpot += bound - ldist(gl);
             if (ctl->gpot > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
         }
         ctl->glab = LINF;
+    }
+}
+
+// Debug check (WW_MCF_CHECK=1): every residual arc must have a non-negative
+// reduced cost after a pass.  Records the first offending arc.
+struct CheckRec {
+    int found;
+    int kind;          // in-arc direction at v (1..4) or 8+side for an arc into the ground
+    long long u, v;    // tail, head (-1 = ground)
+    long long rc;
+    long long pu, pv;
+    unsigned long long lu, lv;  // labels before the potential update
+    int f, cp, cn;
+};
+
+__global__ void k_check_rc(Graph g, const Ctl *ctl, const unsigned long long *lab_before,
+                           CheckRec *rec) {
+    const long long N = (long long)g.R * g.C;
+    const long long gpot = ctl->gpot;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+         v += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(v / g.C), j = (int)(v % g.C);
+        for (int dir = 1; dir <= 4; ++dir) {
+            long long e;
+            int kind, delta;
+            if (dir == DIR_UP) { e = (long long)i * g.C + j; kind = 0; delta = +1; }
+            else if (dir == DIR_DOWN) { e = (long long)(i + 1) * g.C + j; kind = 0; delta = -1; }
+            else if (dir == DIR_LEFT) { e = (long long)i * g.n + j; kind = 1; delta = -1; }
+            else { e = (long long)i * g.n + j + 1; kind = 1; delta = +1; }
+            const int f = kind == 0 ? g.fx[e] : g.fy[e];
+            const int cp = kind == 0 ? g.cxp[e] : g.cyp[e];
+            const int cn = kind == 0 ? g.cxn[e] : g.cyn[e];
+            const int c = move_cost(f, delta, cp, cn);
+            if (c == RC_INF) continue;
+            const long long u = pred_node(g, i, j, dir);
+            const long long pu = u < 0 ? gpot : g.pot[u];
+            const long long rc = (long long)c - pu + g.pot[v];
+            if (rc < 0 && atomicCAS(&rec->found, 0, 1) == 0) {
+                rec->kind = dir; rec->u = u; rec->v = v; rec->rc = rc; rec->pu = pu; rec->pv = g.pot[v];
+                rec->lu = u < 0 ? 0 : lab_before[u]; rec->lv = lab_before[v];
+                rec->f = f; rec->cp = cp; rec->cn = cn;
+            }
+            // the reverse move (v -> u) of the same edge
+            const int c2 = move_cost(f, -delta, cp, cn);
+            if (c2 == RC_INF) continue;
+            const long long rc2 = (long long)c2 - g.pot[v] + pu;
+            if (rc2 < 0 && atomicCAS(&rec->found, 0, 1) == 0) {
+                rec->kind = 8 + dir; rec->u = v; rec->v = u; rec->rc = rc2; rec->pu = g.pot[v]; rec->pv = pu;
+                rec->lu = lab_before[v]; rec->lv = u < 0 ? 0 : lab_before[u];
+                rec->f = f; rec->cp = cp; rec->cn = cn;
+            }
+        }
     }
 }
 
@@ -679,6 +865,7 @@ __global__ void k_pass_reset(Ctl *ctl) {
     ctl->gsub_count = 0;
     ctl->gpred = 0xffffffffu;
     ctl->pend_count = 0;
+    ctl->min_rej = LINF;
     ctl->touch_count = 0;
     ctl->arcs = 0;
     ctl->nsrc2 = 0;
@@ -686,28 +873,41 @@ __global__ void k_pass_reset(Ctl *ctl) {
 }
 
 __global__ void k_clear_settled(Ctl *ctl) { ctl->settled = 0; }
-__global__ void k_clear_pending(Ctl *ctl) { ctl->pend_count = 0; }
+__global__ void k_clear_minrej(Ctl *ctl) { ctl->min_rej = LINF; }
 
 __global__ void k_swap_lists(Ctl *ctl) {
     ctl->nsrc = ctl->nsrc2;
     ctl->ndef = ctl->ndef2;
 }
 
-__global__ void k_total_cost(const int8_t *fx, const int8_t *fy, const int16_t *cxp,
-                             const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
-                             long long nx, long long ny, Ctl *ctl) {
+__global__ __launch_bounds__(256) void k_total_cost(const int8_t *fx, const int8_t *fy,
+                                                   const int16_t *cxp, const int16_t *cxn,
+                                                   const int16_t *cyp, const int16_t *cyn,
+                                                   long long nx, long long ny,
+                                                   long long *__restrict__ part) {
     long long s = 0;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nx + ny;
          e += (long long)gridDim.x * blockDim.x) {
-        int f;
-        int cp, cn;
+        int f, cp, cn;
         if (e < nx) { f = fx[e]; cp = cxp[e]; cn = cxn[e]; }
         else { f = fy[e - nx]; cp = cyp[e - nx]; cn = cyn[e - nx]; }
         s += f > 0 ? cp : (f < 0 ? cn : 0);
     }
+    __shared__ long long red[4];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&ctl->total_cost,
-                                               (unsigned long long)s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_total_finish(int nb, const long long *part, Ctl *ctl) {
+    __shared__ long long red[4];
+    long long s = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) ctl->total_cost = red[0] + red[1] + red[2] + red[3];
 }
 
 __global__ void k_export_pot(const int *pot, const Ctl *ctl, long long N, int64_t *out) {
@@ -717,6 +917,19 @@ __global__ void k_export_pot(const int *pot, const Ctl *ctl, long long N, int64_
 }
 
 // ------------------------------------------------------------------ host ---
+
+ww_mcf_stats &last_mcf_stats() {
+    static ww_mcf_stats s;
+    return s;
+}
+
+constexpr unsigned int H0 = 64;        // hop limit of a pass's first window
+constexpr unsigned int DSTEP0 = 1024;  // first distance increment
+constexpr unsigned int HMAX = 0x1fffffffu;
+
+static unsigned long long mk_label(unsigned int d, unsigned int h) {
+    return ((unsigned long long)d << 32) | ((unsigned long long)h << 3) | 7ull;
+}
 
 static ww_status decode_error(int e) {
     if (e & ERR_NEG_RC) return fail(WW_E_DEVICE, "min-cost flow: negative reduced cost (invariant broken)");
@@ -734,6 +947,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     if (ny > 0) WW_HIP(hipMemsetAsync(dky, 0, ny, st));
     ww_mcf_stats S;
     memset(&S, 0, sizeof(S));
+    last_mcf_stats() = S;
+    const auto t_start = std::chrono::steady_clock::now();
     const int R = m - 1, C = n - 1;
     if (R < 1 || C < 1) {
         if (pot_out) WW_HIP(hipMemsetAsync(pot_out, 0, sizeof(int64_t), st));
@@ -741,6 +956,11 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         *total = 0;
         if (stats) *stats = S;
         return WW_OK;
+    }
+    static hipEvent_t ev[2] = {nullptr, nullptr};
+    if (!ev[0]) {
+        WW_HIP(hipEventCreate(&ev[0]));
+        WW_HIP(hipEventCreate(&ev[1]));
     }
     const long long N = (long long)R * C;
     if (N >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
@@ -756,7 +976,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     WW_TRY(scratch(SLOT_MCF_POT, sizeof(int) * N, (void **)&g.pot));
     WW_TRY(scratch(SLOT_MCF_EX, N, (void **)&g.ex));
     unsigned int *tiles = nullptr;
-    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * (size_t)NT * 9 + 4096, (void **)&tiles));
+    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * (size_t)NT * 11 + 4096, (void **)&tiles));
     RoundArgs ra;
     ra.NT = NT;
     ra.lists = tiles;
@@ -766,6 +986,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     ra.qstamp = tiles + 6 * (size_t)NT;
     ra.pstamp = tiles + 7 * (size_t)NT;
     ra.tstamp = tiles + 8 * (size_t)NT;
+    ra.tile_rej = (unsigned long long *)(tiles + 9 * (size_t)NT + ((9 * (size_t)NT) & 1));
     char *nodes = nullptr;
     const size_t nl_bytes = sizeof(unsigned int) * (size_t)N;
     const size_t gs_bytes = sizeof(unsigned int) * (size_t)nperim_arcs + 256;
@@ -789,9 +1010,14 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     WW_HIP(hipMemsetAsync(ra.qstamp, 0, sizeof(unsigned int) * 3 * (size_t)NT, st));
     WW_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
     const int IB = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(N, 256)));
-    hipLaunchKernelGGL(k_mcf_init, dim3(IB), dim3(256), 0, st, g, res, ctl, src, def);
+    const int nib = ceil_div(N, INIT_CHUNK);
+    int *bc = nullptr;
+    WW_TRY(scratch(SLOT_MCF_PART, sizeof(long long) * (size_t)std::max(3 * nib, 8192) + 256, (void **)&bc));
+    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res, bc);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mcf_finish_init, dim3(1), dim3(1), 0, st, ctl);
+    hipLaunchKernelGGL(k_mcf_init_scan, dim3(1), dim3(1024), 0, st, nib, bc, ctl);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mcf_init_write, dim3(nib), dim3(INIT_THREADS), 0, st, g, res, bc, src, def);
     WW_LAUNCH_CHECK();
     auto sync_ctl = [&]() -> ww_status {
         WW_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -802,6 +1028,17 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     WW_TRY(sync_ctl());
     S.supplies = (long long)h->nsrc + std::max<long long>(h->gex, 0);
 
+    const char *trace_env = getenv("WW_MCF_TRACE");
+    const bool trace = trace_env && trace_env[0] == '1';
+    const char *check_env = getenv("WW_MCF_CHECK");
+    const bool check = check_env && check_env[0] == '1';
+    unsigned long long *lab_copy = nullptr;
+    CheckRec *crec = nullptr, *hcrec = nullptr;
+    if (check) {
+        WW_HIP(hipMalloc(&lab_copy, sizeof(unsigned long long) * N));
+        WW_HIP(hipMalloc(&crec, sizeof(CheckRec)));
+        WW_HIP(hipHostMalloc(&hcrec, sizeof(CheckRec)));
+    }
     const int rounds_per_sync = 4;
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
     const unsigned int bound_cap = 0xffff0000u;
@@ -811,6 +1048,11 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     for (;;) {
         if (h->nsrc == 0 && h->gex <= 0) break;
         const int gsrc = h->gex > 0;
+        const auto tp0 = std::chrono::steady_clock::now();
+        const long long r0 = S.rounds, w0 = S.windows;
+        const unsigned long long v0 = h->visits;
+        const unsigned int nsrc0 = h->nsrc;
+        const long long gex0 = h->gex;
         ++pstamp;
         hipLaunchKernelGGL(k_pass_reset, dim3(1), dim3(1), 0, st, ctl);
         WW_LAUNCH_CHECK();
@@ -819,56 +1061,106 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.qstamp, qs,
                            ra.lists, gsrc, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
-        unsigned int bound = 1024;
+        // Windows in lexicographic (distance, hops) order: every label <= lb
+        // is exact at the end of a window.  The first window admits only
+        // zero-distance labels within H0 hops; later windows jump to the
+        // smallest rejected candidate and grow the hop or distance limit.
+        unsigned long long lb = mk_label(0, H0);
+        unsigned int dstep = DSTEP0;
         for (;;) {  // windows
             ++wstamp;
             ++S.windows;
             for (;;) {  // rounds
+                WW_HIP(hipEventRecord(ev[0], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
                     hipLaunchKernelGGL(k_sssp_round, dim3(round_grid), dim3(SS_THREADS), 0, st, g,
-                                       ctl, ra, cur, qs + 1, wstamp, pstamp, bound);
+                                       ctl, ra, cur, qs + 1, wstamp, pstamp, lb);
                     WW_LAUNCH_CHECK();
                     ++qs;
                     cur = (cur + 1) % 3;
                 }
+                WW_HIP(hipEventRecord(ev[1], st));
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
                     return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
                 WW_TRY(sync_ctl());
+                float ms = 0.f;
+                WW_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                S.relax_ms += ms;
                 if (h->count[cur] == 0) break;
             }
             hipLaunchKernelGGL(k_clear_settled, dim3(1), dim3(1), 0, st, ctl);
             WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_count_settled, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, bound);
+            hipLaunchKernelGGL(k_count_settled, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, lb);
             WW_LAUNCH_CHECK();
             WW_TRY(sync_ctl());
             const long long units = (long long)h->nsrc + std::max<long long>(h->gex, 0);
             const long long need = std::max<long long>(1, (units + 1) / 2);
-            if ((long long)h->settled >= need || h->pend_count == 0) break;
-            if (bound >= bound_cap)
-                return fail(WW_E_OVERFLOW, "min-cost flow: shortest-path distance above 2^32");
-            bound = (bound > bound_cap / 2) ? bound_cap : bound * 2;
+            if ((long long)h->settled >= need) break;
+            hipLaunchKernelGGL(k_clear_minrej, dim3(1), dim3(1), 0, st, ctl);
+            WW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_min_pending, dim3(list_grid), dim3(SB), 0, st, ctl, ra.pend_list,
+                               ra.tile_rej);
+            WW_LAUNCH_CHECK();
+            WW_TRY(sync_ctl());
+            const unsigned long long mr = h->min_rej;
+            if (mr == LINF) break;  // every reachable node is settled
+            const unsigned int d = (unsigned int)(lb >> 32), hcur = (unsigned int)((lb >> 3) & 0x1fffffffu);
+            if ((unsigned int)(mr >> 32) == d && d == 0) {
+                // the zero-distance plateau: widen the hop limit
+                unsigned long long hn = std::max<unsigned long long>((mr >> 3) & 0x1fffffffu, 2ull * hcur);
+                lb = mk_label(0, (unsigned int)std::min<unsigned long long>(hn, HMAX));
+            } else {
+                unsigned long long dn = std::max<unsigned long long>(mr >> 32, (unsigned long long)d + dstep);
+                if (dn > bound_cap)
+                    return fail(WW_E_OVERFLOW, "min-cost flow: shortest-path distance above 2^32");
+                dstep = dstep > (1u << 30) ? dstep : dstep * 2;
+                lb = mk_label((unsigned int)dn, HMAX);
+            }
             ++qs;
             hipLaunchKernelGGL(k_requeue_pending, dim3(list_grid), dim3(SB), 0, st, ctl,
-                               ra.pend_list, ra.qstamp, qs, ra.lists + (size_t)cur * NT, cur);
-            WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(1), 0, st, ctl);
+                               ra.pend_list, ra.tile_rej, lb, ra.qstamp, qs,
+                               ra.lists + (size_t)cur * NT, cur);
             WW_LAUNCH_CHECK();
         }
         if (h->settled == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: %u supplies reach no demand", h->nsrc);
         const int pg = (int)std::min<long long>(1024, ceil_div(nperim_arcs, SB));
-        hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, bound);
+        hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, lb);
         WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_roots, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, bound, gsub_list);
+        hipLaunchKernelGGL(k_roots, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_gsub_select, dim3(pg), dim3(SB), 0, st, g, ctl, gsub_list, drop);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_augment, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, gsub_list, drop);
         WW_LAUNCH_CHECK();
+        if (check)
+            WW_HIP(hipMemcpyAsync(lab_copy, g.lab, sizeof(unsigned long long) * N,
+                                  hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_potentials, dim3(round_grid), dim3(SB), 0, st, g, ctl, ra.touch_list,
-                           bound);
+                           lb);
         WW_LAUNCH_CHECK();
+        if (check) {
+            WW_HIP(hipMemsetAsync(crec, 0, sizeof(CheckRec), st));
+            hipLaunchKernelGGL(k_check_rc, dim3(IB), dim3(256), 0, st, g, ctl, lab_copy, crec);
+            WW_LAUNCH_CHECK();
+            WW_HIP(hipMemcpyAsync(hcrec, crec, sizeof(CheckRec), hipMemcpyDeviceToHost, st));
+            WW_HIP(hipStreamSynchronize(st));
+            if (hcrec->found) {
+                auto pl = [](unsigned long long l) {
+                    return l == LINF ? std::string("inf") :
+                        std::to_string(l >> 32) + "/" + std::to_string((l >> 3) & 0x1fffffff) + "/" + std::to_string(l & 7);
+                };
+                fprintf(stderr,
+                        "[ww-mcf-check] pass %lld lb %u/%u: arc kind %d u %lld v %lld rc %lld pot %lld %lld "
+                        "labels %s %s flow %d c+ %d c- %d gex %lld\n",
+                        (long long)S.passes + 1, (unsigned)(lb >> 32), (unsigned)((lb >> 3) & 0x1fffffff),
+                        hcrec->kind, hcrec->u, hcrec->v, hcrec->rc, hcrec->pu, hcrec->pv,
+                        pl(hcrec->lu).c_str(), pl(hcrec->lv).c_str(), hcrec->f, hcrec->cp, hcrec->cn,
+                        (long long)h->gex);
+                return fail(WW_E_DEVICE, "min-cost flow check failed (details on stderr)");
+            }
+        }
         hipLaunchKernelGGL(k_compact, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, def, src2, def2);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_swap_lists, dim3(1), dim3(1), 0, st, ctl);
@@ -879,12 +1171,23 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         ++S.passes;
         S.augmentations += h->naug;
         S.path_arcs += (long long)h->arcs;
+        if (trace)
+            fprintf(stderr,
+                    "[ww-mcf] pass %lld src %u gex %lld bound %u/%u windows %lld rounds %lld "
+                    "tile_visits %llu touched %u aug %u arcs %llu ms %.3f\n",
+                    (long long)S.passes, nsrc0, gex0, (unsigned)(lb >> 32),
+                    (unsigned)((lb >> 3) & 0x1fffffffu), S.windows - w0, S.rounds - r0,
+                    h->visits - v0, h->touch_count, h->naug, (unsigned long long)h->arcs,
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
         if (h->naug == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
     }
-    const int cg = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(nx + ny, 256)));
+    const int cg = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(nx + ny, 256 * 8)));
+    long long *part = (long long *)bc;
     hipLaunchKernelGGL(k_total_cost, dim3(cg), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn, nx,
-                       ny, ctl);
+                       ny, part);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_total_finish, dim3(1), dim3(256), 0, st, cg, part, ctl);
     WW_LAUNCH_CHECK();
     if (pot_out) {
         hipLaunchKernelGGL(k_export_pot, dim3(IB), dim3(256), 0, st, g.pot, ctl, N, pot_out);
@@ -894,6 +1197,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     *total = h->total_cost;
     S.tile_visits = (long long)h->visits;
     S.max_potential = std::max<long long>(h->max_pot, h->gpot);
+    S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    last_mcf_stats() = S;
     if (stats) *stats = S;
     return WW_OK;
 }

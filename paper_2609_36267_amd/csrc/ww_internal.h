@@ -56,7 +56,7 @@ enum Slot {
     SLOT_RES = 0, SLOT_CXP, SLOT_CXN, SLOT_CYP, SLOT_CYN, SLOT_DKX, SLOT_DKY, SLOT_LUT,
     SLOT_COUNTERS, SLOT_STEEP, SLOT_STEEP_KEYS,
     SLOT_MCF_LAB, SLOT_MCF_POT, SLOT_MCF_EX, SLOT_MCF_BEST, SLOT_MCF_TILES,
-    SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_INTEG,
+    SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_MCF_PART, SLOT_INTEG,
     SLOT_LUT_WORK,
     SLOT_COUNT
 };
@@ -98,6 +98,8 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
                          const int8_t *dky, int m, int n, const ww_cost_params &cp, int32_t *K,
                          float *phi, hipStream_t stream);
 ww_status build_lut_impl(int looks, const ww_lut_params &p, int16_t *lut_dev, hipStream_t stream);
+
+ww_mcf_stats &last_mcf_stats();
 
 ww_status check_lut_params(const ww_lut_params &p);
 ww_status check_cost_params(const ww_cost_params &p);
