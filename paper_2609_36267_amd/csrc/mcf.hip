@@ -19,7 +19,12 @@
 //     Relaxation runs on 32 x 32 node tiles: a workgroup stages the tile's
 //     labels and reduced in-arc costs in LDS and iterates to local
 //     convergence; tiles whose border labels changed activate their
-//     neighbours through rotating worklists (one launch per round).
+//     neighbours for the next round (one launch per round).  Round r works
+//     through list r % 3 and appends to list (r + 1) % 3; a per-tile round
+//     stamp (atomic exchange) keeps a tile from being listed twice, and a
+//     visit reserves list slots for all the tiles it activates with one
+//     atomic add.  Tiles relaxed in a pass, and tiles holding candidates
+//     beyond the current window, are marked with plain-store pass stamps.
 //  2. Every reached deficit walks its predecessor chain to its tree root;
 //     each root keeps its nearest deficit (64-bit atomicMin on dist|node).
 //  3. One unit is augmented along each root's chosen path.  Different trees
@@ -43,8 +48,6 @@ namespace ww {
 
 namespace {
 
-constexpr int TS = 32;            // tile side in loop nodes
-constexpr int SS_THREADS = 256;   // 4 nodes per thread
 constexpr unsigned long long LINF = ~0ull;
 constexpr int RC_INF = 0x7fffffff;
 constexpr int DIR_NONE = 0, DIR_UP = 1, DIR_DOWN = 2, DIR_LEFT = 3, DIR_RIGHT = 4;
@@ -57,9 +60,7 @@ struct Ctl {
     unsigned long long glab;   // ground label
     long long gex;             // ground excess
     long long gpot;            // ground potential
-    unsigned int count[3];     // rotating tile worklists
-    unsigned int pend_count;   // tiles with parked candidates
-    unsigned int touch_count;  // tiles relaxed in this pass
+    unsigned int count[3][32]; // list lengths (one 128-byte line each)
     unsigned int nsrc, ndef;   // node lists
     unsigned int nsrc2, ndef2; // compaction targets
     unsigned int gsub_count;   // ground-rooted subtrees with a deficit
@@ -71,12 +72,16 @@ struct Ctl {
     int max_pot;
     long long total_cost;
     long long sum_res;
-    unsigned long long visits; // tiles relaxed, all rounds
     unsigned long long min_rej; // smallest candidate label beyond the window
+    unsigned long long iters;   // in-tile relaxation iterations, all visits
+    unsigned long long vt_sum;  // visit durations (wall-clock ticks), all visits
+    unsigned long long vt_max;  // longest visit
+    unsigned long long vt_stage;  // staging part of the visits
 };
 
 struct Graph {
     int R, C, n;               // loop rows, loop cols, image cols (= C + 1)
+    int th, tw;                // tile shape (rows, cols)
     int TR, TC;                // tile grid
     const int16_t *cxp, *cxn, *cyp, *cyn;
     int8_t *fx, *fy;
@@ -98,11 +103,13 @@ __device__ __forceinline__ int move_cost(int f, int delta, int cp, int cn) {
     return RC_INF;
 }
 
-__device__ __forceinline__ void enqueue(unsigned int item, unsigned int stamp, unsigned int *stamps,
-                                        unsigned int *list, unsigned int *count) {
-    if (atomicExch(&stamps[item], stamp) != stamp) {
-        unsigned int pos = atomicAdd(count, 1u);
-        list[pos] = item;
+// Append tile t to the list of round r unless it is already there
+// (act[t] == r).  Lists: lists[(r % 3) * NT ...], lengths ctl->count[r % 3].
+__device__ __forceinline__ void activate(unsigned int *act, unsigned int *lists, unsigned int NT,
+                                         Ctl *ctl, unsigned int t, unsigned int r) {
+    if (atomicExch(&act[t], r) != r) {
+        const unsigned int pos = atomicAdd(&ctl->count[r % 3][0], 1u);
+        lists[(size_t)(r % 3) * NT + pos] = t;
     }
 }
 
@@ -248,28 +255,28 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const 
     }
 }
 
-// Pass start: sources get label 0 and their tiles are queued.
-__global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned int *stamps,
-                            unsigned int stamp, unsigned int *list0, int ground_source,
-                            unsigned int *perim_tiles, int nperim) {
+// Pass start: sources get label 0 and their tiles are activated for round rr.
+__global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned int *act,
+                            unsigned int *lists, unsigned int NT, unsigned int rr,
+                            int ground_source, const unsigned int *perim_tiles, int nperim) {
     const unsigned int ns = ctl->nsrc;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
         const unsigned int v = src[k];
         g.lab[v] = 0ull;
         const int i = v / g.C, j = v % g.C;
-        const int ti = i / TS, tj = j / TS, li = i % TS, lj = j % TS;
+        const int ti = i / g.th, tj = j / g.tw, li = i % g.th, lj = j % g.tw;
         const unsigned int t = ti * g.TC + tj;
-        enqueue(t, stamp, stamps, list0, &ctl->count[0]);
+        activate(act, lists, NT, ctl, t, rr);
         // a supply on a tile border also feeds the tile across that border,
         // whose relaxation must run although this label never "changes"
-        if (li == 0 && ti > 0) enqueue(t - g.TC, stamp, stamps, list0, &ctl->count[0]);
-        if (li == TS - 1 && ti < g.TR - 1) enqueue(t + g.TC, stamp, stamps, list0, &ctl->count[0]);
-        if (lj == 0 && tj > 0) enqueue(t - 1, stamp, stamps, list0, &ctl->count[0]);
-        if (lj == TS - 1 && tj < g.TC - 1) enqueue(t + 1, stamp, stamps, list0, &ctl->count[0]);
+        if (li == 0 && ti > 0) activate(act, lists, NT, ctl, t - g.TC, rr);
+        if (li == g.th - 1 && ti < g.TR - 1) activate(act, lists, NT, ctl, t + g.TC, rr);
+        if (lj == 0 && tj > 0) activate(act, lists, NT, ctl, t - 1, rr);
+        if (lj == g.tw - 1 && tj < g.TC - 1) activate(act, lists, NT, ctl, t + 1, rr);
     }
     if (ground_source) {
         for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x)
-            enqueue(perim_tiles[k], stamp, stamps, list0, &ctl->count[0]);
+            activate(act, lists, NT, ctl, perim_tiles[k], rr);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->glab = ground_source ? 0ull : LINF;
 }
@@ -277,53 +284,54 @@ __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned
 // ------------------------------------------------------ relaxation round ---
 
 struct RoundArgs {
-    unsigned int *lists;        // 3 x NT
-    unsigned int *qstamp;       // per-tile queue stamps
-    unsigned int *pstamp;       // per-tile pending stamps
-    unsigned int *tstamp;       // per-tile touched stamps
-    unsigned int *pend_list, *touch_list, *perim_tiles;
-    unsigned long long *tile_rej;  // smallest rejected candidate of each tile
+    unsigned int *act;          // round stamp: the tile is in that round's list
+    unsigned int *lists;        // 3 x NT tile lists
+    unsigned int *pstamp;       // pass stamp: the tile parked a candidate
+    unsigned int *tstamp;       // pass stamp: the tile was relaxed
+    unsigned long long *tile_rej;  // smallest parked candidate of each tile
+    unsigned long long *vpart;  // striped visit counters (64 x 16)
+    const unsigned int *perim_tiles;
     int nperim;
     unsigned int NT;
 };
 
-__global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
-                                                           int cur, unsigned int next_stamp,
-                                                           unsigned int window_stamp,
-                                                           unsigned int pass_stamp,
-                                                           unsigned long long lb) {
-    __shared__ unsigned long long L[TS + 2][TS + 3];
-    __shared__ int P[TS + 2][TS + 2];
-    __shared__ int RCs[4][TS][TS];
+// Jacobi variant: 32 x 32 tiles, 256 threads, 4 nodes per thread.
+constexpr int TJ = 32;
+__global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
+                                                   unsigned int round, unsigned int pass_stamp,
+                                                   unsigned long long lb, int stats) {
+    __shared__ unsigned long long L[TJ + 2][TJ + 3];
+    __shared__ int P[TJ + 2][TJ + 2];
+    __shared__ int RCs[4][TJ][TJ];
     __shared__ int flags[4];  // changed border: top, bottom, left, right
     __shared__ int sh_any;
     __shared__ unsigned long long sh_gcand, sh_rej;
 
-    const unsigned int cnt = ctl->count[cur];
-    const int nxt = (cur + 1) % 3, clr = (cur + 2) % 3;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->count[clr] = 0;
-        ctl->visits += cnt;
-    }
-    unsigned int *list = ra.lists + (size_t)cur * ra.NT;
-    unsigned int *nlist = ra.lists + (size_t)nxt * ra.NT;
+    const unsigned int NT = ra.NT;
+    const unsigned int cnt = ctl->count[round % 3][0];
+    const unsigned int *list = ra.lists + (size_t)(round % 3) * NT;
+    // list (round + 2) % 3 was consumed by the previous round
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->count[(round + 2) % 3][0] = 0;
     const unsigned long long glab = ctl->glab;
     const int gpot = (int)ctl->gpot;
     const int R = g.R, C = g.C;
+    unsigned int my_visits = 0;
 
     for (unsigned int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
         const unsigned int tile = list[idx];
+        ++my_visits;
+        const unsigned long long t_start = stats ? wall_clock64() : 0ull;
         const int ti = tile / g.TC, tj = tile % g.TC;
-        const int i0 = ti * TS, j0 = tj * TS;
-        const int rows = min(TS, R - i0), cols = min(TS, C - j0);
+        const int i0 = ti * TJ, j0 = tj * TJ;
+        const int rows = min(TJ, R - i0), cols = min(TJ, C - j0);
         if (threadIdx.x < 4) flags[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             sh_rej = LINF;
             sh_gcand = LINF;
         }
         // stage labels and potentials with a one-node halo; outside = ground
-        for (int t = threadIdx.x; t < (TS + 2) * (TS + 2); t += SS_THREADS) {
-            const int r = t / (TS + 2), c = t % (TS + 2);
+        for (int t = threadIdx.x; t < (TJ + 2) * (TJ + 2); t += 256) {
+            const int r = t / (TJ + 2), c = t % (TJ + 2);
             const int i = i0 - 1 + r, j = j0 - 1 + c;
             unsigned long long l = LINF;
             int p = 0;
@@ -342,8 +350,8 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
         }
         __syncthreads();
         // reduced costs of the four in-arcs of every node
-        for (int t = threadIdx.x; t < TS * TS; t += SS_THREADS) {
-            const int li = t / TS, lj = t % TS;
+        for (int t = threadIdx.x; t < TJ * TJ; t += 256) {
+            const int li = t / TJ, lj = t % TJ;
             int ru = RC_INF, rd = RC_INF, rl = RC_INF, rr = RC_INF;
             if (li < rows && lj < cols) {
                 const int i = i0 + li, j = j0 + lj;
@@ -373,8 +381,9 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
             RCs[3][li][lj] = rr;
         }
         __syncthreads();
+        const unsigned long long t_staged = stats ? wall_clock64() : 0ull;
         // owned nodes: column lj, rows 4*q .. 4*q+3
-        const int lj = threadIdx.x % TS, q = threadIdx.x / TS;
+        const int lj = threadIdx.x % TJ, q = threadIdx.x / TJ;
         unsigned long long init[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) init[k] = L[q * 4 + k + 1][lj + 1];
@@ -410,7 +419,10 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
                     changed = 1;
                 }
             }
-            if (!__syncthreads_or(changed)) break;
+            if (!__syncthreads_or(changed)) {
+                if (stats && threadIdx.x == 0) atomicAdd(&ctl->iters, (unsigned long long)(it + 1));
+                break;
+            }
             if (it == MAX_ITERS - 1 && threadIdx.x == 0) atomicOr(&ctl->error, ERR_ITERS);
         }
         // write back, note changed borders
@@ -476,40 +488,59 @@ __global__ __launch_bounds__(SS_THREADS) void k_sssp_round(Graph g, Ctl *ctl, Ro
         if (gc != LINF) atomicMin(&sh_gcand, gc);
         if (rej != LINF) atomicMin(&sh_rej, rej & ~7ull);
         __syncthreads();
-        // activations
+        // activations for the next round, stamps for this pass
         if (threadIdx.x == 0) {
-            if (flags[0] && ti > 0) enqueue(tile - g.TC, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
-            if (flags[1] && ti < g.TR - 1) enqueue(tile + g.TC, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
-            if (flags[2] && tj > 0) enqueue(tile - 1, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
-            if (flags[3] && tj < g.TC - 1) enqueue(tile + 1, next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+            const unsigned int nr = round + 1;
+            unsigned int nb[4];
+            int k = 0;
+            if (flags[0] && ti > 0) nb[k++] = tile - g.TC;
+            if (flags[1] && ti < g.TR - 1) nb[k++] = tile + g.TC;
+            if (flags[2] && tj > 0) nb[k++] = tile - 1;
+            if (flags[3] && tj < g.TC - 1) nb[k++] = tile + 1;
+            int fresh = 0;
+            for (int q = 0; q < k; ++q)
+                if (atomicExch(&ra.act[nb[q]], nr) != nr) nb[fresh++] = nb[q];
+            if (fresh) {
+                const unsigned int pos = atomicAdd(&ctl->count[nr % 3][0], (unsigned int)fresh);
+                unsigned int *dst = ra.lists + (size_t)(nr % 3) * NT + pos;
+                for (int q = 0; q < fresh; ++q) dst[q] = nb[q];
+            }
             // the tile's parked candidates (recomputed in full at every visit)
             ra.tile_rej[tile] = sh_rej;
-            if (sh_rej != LINF) enqueue(tile, pass_stamp, ra.pstamp, ra.pend_list, &ctl->pend_count);
-            if (atomicExch(&ra.tstamp[tile], pass_stamp) != pass_stamp)
-                ra.touch_list[atomicAdd(&ctl->touch_count, 1u)] = tile;
+            if (sh_rej != LINF) ra.pstamp[tile] = pass_stamp;
+            ra.tstamp[tile] = pass_stamp;
             sh_any = 0;
             if (sh_gcand != LINF && sh_gcand < ctl->glab) {
                 unsigned long long old = atomicMin(&ctl->glab, sh_gcand);
                 if (sh_gcand < old) sh_any = 1;
             }
+            if (stats) {
+                const unsigned long long t_end = wall_clock64();
+                atomicAdd(&ctl->vt_sum, t_end - t_start);
+                atomicAdd(&ctl->vt_stage, t_staged - t_start);
+                atomicMax(&ctl->vt_max, t_end - t_start);
+            }
         }
         __syncthreads();
         if (sh_any) {
-            for (int k = threadIdx.x; k < ra.nperim; k += SS_THREADS)
-                enqueue(ra.perim_tiles[k], next_stamp, ra.qstamp, nlist, &ctl->count[nxt]);
+            for (int k = threadIdx.x; k < ra.nperim; k += 256)
+                activate(ra.act, ra.lists, NT, ctl, ra.perim_tiles[k], round + 1);
         }
         __syncthreads();
     }
+    if (threadIdx.x == 0 && my_visits)
+        atomicAdd(&ra.vpart[(blockIdx.x % 64) * 16], (unsigned long long)my_visits);
 }
 
-// smallest parked candidate over the pass's pending tiles
-__global__ void k_min_pending(Ctl *ctl, const unsigned int *pend, const unsigned long long *tile_rej) {
-    const unsigned int np = ctl->pend_count;
+// smallest parked candidate over the tiles that parked one in this pass
+__global__ void k_min_pending(Ctl *ctl, const unsigned int *pstamp, unsigned int pass,
+                              const unsigned long long *tile_rej, unsigned int NT) {
     unsigned long long mn = LINF;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
-        const unsigned long long r = tile_rej[pend[k]];
-        mn = r < mn ? r : mn;
-    }
+    for (unsigned int t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x)
+        if (pstamp[t] == pass) {
+            const unsigned long long r = tile_rej[t];
+            mn = r < mn ? r : mn;
+        }
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long o = __shfl_down(mn, off, 64);
         mn = o < mn ? o : mn;
@@ -517,16 +548,13 @@ __global__ void k_min_pending(Ctl *ctl, const unsigned int *pend, const unsigned
     if ((threadIdx.x & 63) == 0 && mn != LINF) atomicMin(&ctl->min_rej, mn);
 }
 
-// re-queue the pending tiles whose parked candidates the new window admits
-__global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pend,
+// activate, for round rr, the tiles whose parked candidates the window admits
+__global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pstamp, unsigned int pass,
                                   const unsigned long long *tile_rej, unsigned long long lb,
-                                  unsigned int *qstamp, unsigned int stamp, unsigned int *list0,
-                                  int cur) {
-    const unsigned int np = ctl->pend_count;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < np; k += gridDim.x * blockDim.x) {
-        const unsigned int t = pend[k];
-        if (tile_rej[t] <= lb) enqueue(t, stamp, qstamp, list0, &ctl->count[cur]);
-    }
+                                  unsigned int *act, unsigned int *lists, unsigned int NT,
+                                  unsigned int rr) {
+    for (unsigned int t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x)
+        if (pstamp[t] == pass && tile_rej[t] <= lb) activate(act, lists, NT, ctl, t, rr);
 }
 
 __global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb) {
@@ -755,15 +783,15 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 }
 
 // pot(v) += B - d(v) on every reached node, labels back to infinity.
-__global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *touch, unsigned long long lb) {
+__global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp, unsigned int pass,
+                             unsigned int NT, unsigned long long lb) {
     const unsigned int bound = ldist(lb);
-    const unsigned int nt = ctl->touch_count;
     int mx = 0;
-    for (unsigned int idx = blockIdx.x; idx < nt; idx += gridDim.x) {
-        const unsigned int tile = touch[idx];
-        const int i0 = (tile / g.TC) * TS, j0 = (tile % g.TC) * TS;
-        for (int t = threadIdx.x; t < TS * TS; t += blockDim.x) {
-            const int i = i0 + t / TS, j = j0 + t % TS;
+    for (unsigned int tile = blockIdx.x; tile < NT; tile += gridDim.x) {
+        if (tstamp[tile] != pass) continue;
+        const int i0 = (tile / g.TC) * g.th, j0 = (tile % g.TC) * g.tw;
+        for (int t = threadIdx.x; t < g.th * g.tw; t += blockDim.x) {
+            const int i = i0 + t / g.tw, j = j0 + t % g.tw;
             if (i >= g.R || j >= g.C) continue;
             const long long v = (long long)i * g.C + j;
             const unsigned long long l = g.lab[v];
@@ -859,14 +887,11 @@ __global__ void k_compact(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 
 // per-pass counters back to zero (node lists untouched)
 __global__ void k_pass_reset(Ctl *ctl) {
-    ctl->count[0] = ctl->count[1] = ctl->count[2] = 0;
     ctl->settled = 0;
     ctl->naug = 0;
     ctl->gsub_count = 0;
     ctl->gpred = 0xffffffffu;
-    ctl->pend_count = 0;
     ctl->min_rej = LINF;
-    ctl->touch_count = 0;
     ctl->arcs = 0;
     ctl->nsrc2 = 0;
     ctl->ndef2 = 0;
@@ -966,7 +991,9 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     if (N >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
     Graph g;
     g.R = R; g.C = C; g.n = n;
-    g.TR = ceil_div(R, TS); g.TC = ceil_div(C, TS);
+    g.th = TJ;
+    g.tw = TJ;
+    g.TR = ceil_div(R, g.th); g.TC = ceil_div(C, g.tw);
     g.cxp = cxp; g.cxn = cxn; g.cyp = cyp; g.cyn = cyn;
     g.fx = dkx; g.fy = dky;
     const unsigned int NT = (unsigned)g.TR * g.TC;
@@ -975,18 +1002,21 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     WW_TRY(scratch(SLOT_MCF_BEST, sizeof(unsigned long long) * N, (void **)&g.best));
     WW_TRY(scratch(SLOT_MCF_POT, sizeof(int) * N, (void **)&g.pot));
     WW_TRY(scratch(SLOT_MCF_EX, N, (void **)&g.ex));
+    // per-tile state: act, pstamp, tstamp (NT each, cleared per call),
+    // lists (3 NT), perim_tiles (NT), tile_rej (NT x 8 B), vpart (64 x 16 x 8 B)
     unsigned int *tiles = nullptr;
-    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * (size_t)NT * 11 + 4096, (void **)&tiles));
+    const size_t tiles_words = 8 * (size_t)NT + 2;
+    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * (tiles_words + 2 * (size_t)NT) + 8192 + 256,
+                   (void **)&tiles));
     RoundArgs ra;
     ra.NT = NT;
-    ra.lists = tiles;
-    ra.pend_list = tiles + 3 * (size_t)NT;
-    ra.touch_list = tiles + 4 * (size_t)NT;
-    ra.perim_tiles = tiles + 5 * (size_t)NT;
-    ra.qstamp = tiles + 6 * (size_t)NT;
-    ra.pstamp = tiles + 7 * (size_t)NT;
-    ra.tstamp = tiles + 8 * (size_t)NT;
-    ra.tile_rej = (unsigned long long *)(tiles + 9 * (size_t)NT + ((9 * (size_t)NT) & 1));
+    ra.act = tiles;
+    ra.pstamp = tiles + (size_t)NT;
+    ra.tstamp = tiles + 2 * (size_t)NT;
+    ra.lists = tiles + 3 * (size_t)NT;
+    ra.perim_tiles = tiles + 6 * (size_t)NT;
+    ra.tile_rej = (unsigned long long *)(tiles + 7 * (size_t)NT + ((7 * (size_t)NT) & 1));
+    ra.vpart = (unsigned long long *)(tiles + tiles_words + 2 * (size_t)NT);
     char *nodes = nullptr;
     const size_t nl_bytes = sizeof(unsigned int) * (size_t)N;
     const size_t gs_bytes = sizeof(unsigned int) * (size_t)nperim_arcs + 256;
@@ -1005,9 +1035,11 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             if (ti == 0 || tj == 0 || ti == g.TR - 1 || tj == g.TC - 1)
                 ptiles.push_back((unsigned)(ti * g.TC + tj));
     ra.nperim = (int)ptiles.size();
-    WW_HIP(hipMemcpyAsync(ra.perim_tiles, ptiles.data(), sizeof(unsigned int) * ptiles.size(),
+    WW_HIP(hipMemcpyAsync((void *)ra.perim_tiles, ptiles.data(), sizeof(unsigned int) * ptiles.size(),
                           hipMemcpyHostToDevice, st));
-    WW_HIP(hipMemsetAsync(ra.qstamp, 0, sizeof(unsigned int) * 3 * (size_t)NT, st));
+    // stamps start at zero on every call: rounds and passes count from 1
+    WW_HIP(hipMemsetAsync(ra.act, 0, sizeof(unsigned int) * 3 * (size_t)NT, st));
+    WW_HIP(hipMemsetAsync(ra.vpart, 0, 8192, st));
     WW_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
     const int IB = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(N, 256)));
     const int nib = ceil_div(N, INIT_CHUNK);
@@ -1042,24 +1074,30 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const int rounds_per_sync = 4;
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
     const unsigned int bound_cap = 0xffff0000u;
-    unsigned int qs = 0, wstamp = 0, pstamp = 0;
+    unsigned int rr = 1, pass = 0;  // next round, current pass
     const int SB = 256;
     const int list_grid = (int)std::min<long long>(4096, std::max<long long>(1, ceil_div(N, 256)));
+    std::vector<unsigned long long> hv(64 * 16);
+    auto host_visits = [&]() -> unsigned long long {
+        if (hipMemcpy(hv.data(), ra.vpart, 8192, hipMemcpyDeviceToHost) != hipSuccess) return 0;
+        unsigned long long s = 0;
+        for (int k = 0; k < 64; ++k) s += hv[k * 16];
+        return s;
+    };
     for (;;) {
         if (h->nsrc == 0 && h->gex <= 0) break;
         const int gsrc = h->gex > 0;
         const auto tp0 = std::chrono::steady_clock::now();
         const long long r0 = S.rounds, w0 = S.windows;
-        const unsigned long long v0 = h->visits;
+        const unsigned long long v0 = trace ? host_visits() : 0, it0 = h->iters, vs0 = h->vt_sum,
+                                 vst0 = h->vt_stage;
         const unsigned int nsrc0 = h->nsrc;
         const long long gex0 = h->gex;
-        ++pstamp;
+        ++pass;
         hipLaunchKernelGGL(k_pass_reset, dim3(1), dim3(1), 0, st, ctl);
         WW_LAUNCH_CHECK();
-        int cur = 0;
-        ++qs;
-        hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.qstamp, qs,
-                           ra.lists, gsrc, ra.perim_tiles, ra.nperim);
+        hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.act,
+                           ra.lists, NT, rr, gsrc, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
         // Windows in lexicographic (distance, hops) order: every label <= lb
         // is exact at the end of a window.  The first window admits only
@@ -1068,16 +1106,14 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         unsigned long long lb = mk_label(0, H0);
         unsigned int dstep = DSTEP0;
         for (;;) {  // windows
-            ++wstamp;
             ++S.windows;
             for (;;) {  // rounds
                 WW_HIP(hipEventRecord(ev[0], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
-                    hipLaunchKernelGGL(k_sssp_round, dim3(round_grid), dim3(SS_THREADS), 0, st, g,
-                                       ctl, ra, cur, qs + 1, wstamp, pstamp, lb);
+                    hipLaunchKernelGGL(k_sssp_round, dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
+                                       rr, pass, lb, trace ? 1 : 0);
                     WW_LAUNCH_CHECK();
-                    ++qs;
-                    cur = (cur + 1) % 3;
+                    ++rr;
                 }
                 WW_HIP(hipEventRecord(ev[1], st));
                 S.rounds += rounds_per_sync;
@@ -1087,7 +1123,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 float ms = 0.f;
                 WW_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
                 S.relax_ms += ms;
-                if (h->count[cur] == 0) break;
+                if (h->count[rr % 3][0] == 0) break;
             }
             hipLaunchKernelGGL(k_clear_settled, dim3(1), dim3(1), 0, st, ctl);
             WW_LAUNCH_CHECK();
@@ -1099,8 +1135,9 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             if ((long long)h->settled >= need) break;
             hipLaunchKernelGGL(k_clear_minrej, dim3(1), dim3(1), 0, st, ctl);
             WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_min_pending, dim3(list_grid), dim3(SB), 0, st, ctl, ra.pend_list,
-                               ra.tile_rej);
+            const int tg = (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB);
+            hipLaunchKernelGGL(k_min_pending, dim3(tg), dim3(SB), 0, st, ctl, ra.pstamp, pass,
+                               ra.tile_rej, NT);
             WW_LAUNCH_CHECK();
             WW_TRY(sync_ctl());
             const unsigned long long mr = h->min_rej;
@@ -1117,10 +1154,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 dstep = dstep > (1u << 30) ? dstep : dstep * 2;
                 lb = mk_label((unsigned int)dn, HMAX);
             }
-            ++qs;
-            hipLaunchKernelGGL(k_requeue_pending, dim3(list_grid), dim3(SB), 0, st, ctl,
-                               ra.pend_list, ra.tile_rej, lb, ra.qstamp, qs,
-                               ra.lists + (size_t)cur * NT, cur);
+            hipLaunchKernelGGL(k_requeue_pending, dim3(tg), dim3(SB), 0, st, ctl, ra.pstamp, pass,
+                               ra.tile_rej, lb, ra.act, ra.lists, NT, rr);
             WW_LAUNCH_CHECK();
         }
         if (h->settled == 0)
@@ -1137,8 +1172,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         if (check)
             WW_HIP(hipMemcpyAsync(lab_copy, g.lab, sizeof(unsigned long long) * N,
                                   hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_potentials, dim3(round_grid), dim3(SB), 0, st, g, ctl, ra.touch_list,
-                           lb);
+        hipLaunchKernelGGL(k_potentials, dim3(round_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass,
+                           NT, lb);
         WW_LAUNCH_CHECK();
         if (check) {
             WW_HIP(hipMemsetAsync(crec, 0, sizeof(CheckRec), st));
@@ -1171,14 +1206,19 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         ++S.passes;
         S.augmentations += h->naug;
         S.path_arcs += (long long)h->arcs;
-        if (trace)
+        if (trace) {
+            const unsigned long long v1 = host_visits();
             fprintf(stderr,
                     "[ww-mcf] pass %lld src %u gex %lld bound %u/%u windows %lld rounds %lld "
-                    "tile_visits %llu touched %u aug %u arcs %llu ms %.3f\n",
+                    "tile_visits %llu iters %llu visit_us %.2f stage_us %.2f maxvisit_us %.1f aug %u arcs %llu ms %.3f\n",
                     (long long)S.passes, nsrc0, gex0, (unsigned)(lb >> 32),
                     (unsigned)((lb >> 3) & 0x1fffffffu), S.windows - w0, S.rounds - r0,
-                    h->visits - v0, h->touch_count, h->naug, (unsigned long long)h->arcs,
+                    v1 - v0, h->iters - it0,
+                    (h->vt_sum - vs0) * 0.01 / std::max<double>(1.0, (double)(v1 - v0)),
+                    (h->vt_stage - vst0) * 0.01 / std::max<double>(1.0, (double)(v1 - v0)),
+                    h->vt_max * 0.01, h->naug, (unsigned long long)h->arcs,
                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
+        }
         if (h->naug == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
     }
@@ -1195,7 +1235,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     }
     WW_TRY(sync_ctl());
     *total = h->total_cost;
-    S.tile_visits = (long long)h->visits;
+    S.tile_visits = (long long)host_visits();
     S.max_potential = std::max<long long>(h->max_pot, h->gpot);
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     last_mcf_stats() = S;

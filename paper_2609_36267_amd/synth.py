@@ -131,7 +131,9 @@ def smooth_field(m, n, sigma, lo, hi, rng):
 
 def rect_mask(m, n, frac, rng, side_lo=16, side_hi=256):
     """Random axis-aligned nodata rectangles until ``frac`` of pixels are
-    covered.  Returns uint8 valid mask (1 = valid)."""
+    covered; sides U[side_lo, side_hi], at most a quarter of the image side
+    (so that small scenes keep several rectangles).  Returns uint8 valid
+    mask (1 = valid)."""
     valid = np.ones((m, n), np.uint8)
     if frac <= 0:
         return valid
@@ -140,8 +142,8 @@ def rect_mask(m, n, frac, rng, side_lo=16, side_hi=256):
     while covered < target:
         h = int(rng.integers(side_lo, side_hi + 1))
         w = int(rng.integers(side_lo, side_hi + 1))
-        h = min(h, m)
-        w = min(w, n)
+        h = max(1, min(h, m // 4 if m >= 4 else m))
+        w = max(1, min(w, n // 4 if n >= 4 else n))
         i0 = int(rng.integers(0, m - h + 1))
         j0 = int(rng.integers(0, n - w + 1))
         blk = valid[i0:i0 + h, j0:j0 + w]
