@@ -295,14 +295,33 @@ struct RoundArgs {
     unsigned int NT;
 };
 
-// Jacobi variant: 32 x 32 tiles, 256 threads, 4 nodes per thread.
+// 32 x 32 loop tiles, 256 threads, 4 nodes per thread.
 constexpr int TJ = 32;
+
+// Candidate label of a node reached from neighbour label u over an arc of
+// reduced cost rc (direction code dir).  Candidates inside the window lower
+// best; one beyond it is kept in rej, but only for a node without a label:
+// every label is inside the window, so such a candidate can never lower one.
+__device__ __forceinline__ void relax_one(unsigned long long &best, unsigned long long u, int rc,
+                                          unsigned int dir, unsigned long long lb,
+                                          unsigned long long &rej) {
+    // branch-free, so that best and rej stay in registers
+    const unsigned long long nd = (u >> 32) + (unsigned long long)(unsigned)rc;
+    const bool ok = rc != RC_INF && u != LINF && nd <= 0xffffffffull;
+    const unsigned int lo = (((unsigned int)u | 7u) + 1u) | dir;  // hops + 1, direction
+    const unsigned long long cand = (nd << 32) | lo;
+    const bool beyond = cand > lb;
+    rej = (ok && beyond && best == LINF && cand < rej) ? cand : rej;
+    best = (ok && !beyond && cand < best) ? cand : best;
+}
+
 __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
                                                    unsigned int round, unsigned int pass_stamp,
                                                    unsigned long long lb, int stats) {
     __shared__ unsigned long long L[TJ + 2][TJ + 3];
     __shared__ int P[TJ + 2][TJ + 2];
-    __shared__ int RCs[4][TJ][TJ];
+    __shared__ int4 RC4[TJ][TJ];  // reduced costs of the in-arcs: from above, below, left, right
+    __shared__ int wchg[3][4];    // per-iteration "a label changed" flag of each wave's band
     __shared__ int flags[4];  // changed border: top, bottom, left, right
     __shared__ int sh_any;
     __shared__ unsigned long long sh_gcand, sh_rej;
@@ -375,50 +394,63 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                     ru = max(ru, 0); rd = max(rd, 0); rl = max(rl, 0); rr = max(rr, 0);
                 }
             }
-            RCs[0][li][lj] = ru;
-            RCs[1][li][lj] = rd;
-            RCs[2][li][lj] = rl;
-            RCs[3][li][lj] = rr;
+            RC4[li][lj] = make_int4(ru, rd, rl, rr);
         }
         __syncthreads();
         const unsigned long long t_staged = stats ? wall_clock64() : 0ull;
-        // owned nodes: column lj, rows 4*q .. 4*q+3
-        const int lj = threadIdx.x % TJ, q = threadIdx.x / TJ;
-        unsigned long long init[4];
+        // Each thread owns a column segment of 4 nodes (column lj, rows
+        // 4q..4q+3): their labels and in-arc reduced costs stay in registers,
+        // and every iteration sweeps down the segment and back up.  The left,
+        // right and end neighbours are re-read from LDS at every step, so a
+        // label written by the neighbouring lane of the same wave one step
+        // earlier is already seen (labels only decrease, so any value read is
+        // a valid label).  Wave w owns rows 8w..8w+7; it skips an iteration
+        // when no label changed in its band or the two adjacent bands during
+        // the previous one.
+        const int lj = threadIdx.x % TJ, q = threadIdx.x / TJ, wv = threadIdx.x >> 6;
+        const int r0 = q * 4;
+        unsigned long long init[4], y[4];
+        int4 rc[4];
+        bool ok[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) init[k] = L[q * 4 + k + 1][lj + 1];
-        unsigned long long rej = LINF;  // smallest candidate beyond the window
+        for (int k = 0; k < 4; ++k) {
+            init[k] = L[r0 + k + 1][lj + 1];
+            y[k] = init[k];
+            rc[k] = RC4[r0 + k][lj];
+            ok[k] = r0 + k < rows && lj < cols;
+        }
+        if (threadIdx.x < 12) wchg[threadIdx.x / 4][threadIdx.x % 4] = threadIdx.x < 8 ? 0 : 1;
+        __syncthreads();
+        unsigned long long rej = LINF;  // smallest useful candidate beyond the window
         for (int it = 0; it < MAX_ITERS; ++it) {
+            const int rd = (it + 2) % 3, wr = it % 3;
+            const bool live = wchg[rd][wv] || (wv > 0 && wchg[rd][wv - 1]) || (wv < 3 && wchg[rd][wv + 1]);
             int changed = 0;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int k = s < 4 ? s : 7 - s;  // down then up
-                const int li = q * 4 + k;
-                if (li >= rows || lj >= cols) continue;
-                const unsigned long long cur_l = L[li + 1][lj + 1];
-                unsigned long long bestl = cur_l;
-                const unsigned long long nb[4] = {L[li][lj + 1], L[li + 2][lj + 1], L[li + 1][lj],
-                                                  L[li + 1][lj + 2]};
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const int rc = RCs[d][li][lj];
-                    const unsigned long long u = nb[d];
-                    if (rc == RC_INF || u == LINF) continue;
-                    const unsigned long long nd = (unsigned long long)ldist(u) + (unsigned)rc;
-                    if (nd > 0xffffffffull) continue;
-                    const unsigned long long cand =
-                        (nd << 32) | ((unsigned long long)(lhops(u) + 1) << 3) | (unsigned)(d + 1);
-                    if (cand > lb) {
-                        if (cand < rej) rej = cand;
-                        continue;
-                    }
-                    if (cand < bestl) bestl = cand;
-                }
-                if (bestl < cur_l) {
-                    L[li + 1][lj + 1] = bestl;
-                    changed = 1;
-                }
+            if (live) {
+#define WW_RELAX_NODE(k, PREV, NEXT)                                                  \
+    if (ok[k]) {                                                                      \
+        unsigned long long best = y[k];                                               \
+        relax_one(best, PREV, rc[k].x, 1u, lb, rej);                                  \
+        relax_one(best, NEXT, rc[k].y, 2u, lb, rej);                                  \
+        relax_one(best, L[r0 + k + 1][lj], rc[k].z, 3u, lb, rej);                     \
+        relax_one(best, L[r0 + k + 1][lj + 2], rc[k].w, 4u, lb, rej);                 \
+        if (best < y[k]) {                                                            \
+            y[k] = best;                                                              \
+            L[r0 + k + 1][lj + 1] = best;                                             \
+            changed = 1;                                                              \
+        }                                                                             \
+    }
+                WW_RELAX_NODE(0, L[r0][lj + 1], y[1])
+                WW_RELAX_NODE(1, y[0], y[2])
+                WW_RELAX_NODE(2, y[1], y[3])
+                WW_RELAX_NODE(3, y[2], L[r0 + 5][lj + 1])
+                WW_RELAX_NODE(2, y[1], y[3])
+                WW_RELAX_NODE(1, y[0], y[2])
+                WW_RELAX_NODE(0, L[r0][lj + 1], y[1])
+#undef WW_RELAX_NODE
+                if (changed) wchg[wr][wv] = 1;
             }
+            if (threadIdx.x < 4) wchg[(it + 1) % 3][threadIdx.x] = 0;
             if (!__syncthreads_or(changed)) {
                 if (stats && threadIdx.x == 0) atomicAdd(&ctl->iters, (unsigned long long)(it + 1));
                 break;
@@ -479,7 +511,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 if (nd > 0xffffffffull) continue;
                 const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
                 if (cand > lb) {
-                    if (cand < rej) rej = cand;
+                    if (glab == LINF && cand < rej) rej = cand;
                     continue;
                 }
                 if (cand < gc) gc = cand;
