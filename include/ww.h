@@ -184,6 +184,73 @@ ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, in
                     int32_t n, int32_t looks, const ww_cost_params *cp, int32_t *K, float *phi,
                     int64_t *total_cost_host, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Many interferograms: a job server and a batch call.
+ *
+ * A server runs `slots` workers on the current device.  Each worker owns a
+ * HIP stream (default priority) and a private workspace, so jobs on
+ * different workers overlap on the GPU.  A submitted job waits in a queue
+ * until a worker is free and its device footprint fits the server's HBM
+ * budget beside the jobs already running; the first queued job that fits
+ * is taken, and a job that has waited longer than one second blocks the
+ * jobs behind it until it fits (no job starves).  A job larger than the
+ * budget runs alone.  Each job computes exactly what ww_unwrap computes on
+ * the same inputs (default cost rules), byte for byte.
+ * ------------------------------------------------------------------- */
+
+/* One unwrap request.  The caller fills the inputs and keeps the struct
+ * (and its arrays) alive until the server hands it back. */
+typedef struct {
+    int32_t m, n, looks;
+    int32_t host_io;         /* 0: the five arrays are device pointers;
+                                1: host pointers (pinned for full copy
+                                speed); the worker copies in and out    */
+    const float *psi;        /* [m*n] wrapped phase                      */
+    const float *coh;        /* [m*n] sample coherence                   */
+    const uint8_t *valid;    /* [m*n] mask, NULL = all valid             */
+    int32_t *K;              /* [m*n] out                                */
+    float *phi;              /* [m*n] out                                */
+    int64_t tag;             /* caller's, not touched                    */
+    /* outputs */
+    ww_status status;
+    int64_t total_cost;
+    double t_submit, t_start, t_end;  /* seconds on ww_clock()          */
+    int64_t footprint_bytes;          /* device bytes reserved for it   */
+    char error[160];                  /* message when status != WW_OK  */
+} ww_job;
+
+typedef struct ww_server ww_server;
+
+/* Seconds on the monotonic clock the server stamps jobs with. */
+double ww_clock(void);
+
+/* Starts `slots` workers (1..64) on the current device with an HBM budget
+ * in bytes for the jobs in flight (<= 0: 3/4 of the device memory that is
+ * free at creation).  Errors: WW_E_INVALID_ARG, WW_E_DEVICE. */
+ww_status ww_server_create(int32_t slots, int64_t hbm_budget_bytes, ww_server **out);
+
+/* Queues a job (stamps t_submit).  Errors: WW_E_INVALID_ARG (NULL job or
+ * server, stopped server). */
+ww_status ww_server_submit(ww_server *s, ww_job *job);
+
+/* Hands back up to max_done finished jobs in completion order, waiting up
+ * to wait_ms (< 0: until at least one finishes or nothing is in flight).
+ * Returns the number written to done[]. */
+int32_t ww_server_poll(ww_server *s, ww_job **done, int32_t max_done, int32_t wait_ms);
+
+/* Jobs submitted but not yet handed back by ww_server_poll. */
+int64_t ww_server_in_flight(ww_server *s);
+
+/* Waits for the queued and running jobs, stops the workers and frees the
+ * server (finished jobs not yet polled keep their outputs). */
+ww_status ww_server_destroy(ww_server *s);
+
+/* Unwraps njobs jobs on a temporary server with `slots` workers, largest
+ * first, and returns when all have finished; per-job results are in the
+ * structs.  Returns WW_OK if every job succeeded, else the first failure's
+ * status. */
+ww_status ww_unwrap_batch(ww_job *jobs, int32_t njobs, int32_t slots);
+
 #ifdef __cplusplus
 }
 #endif

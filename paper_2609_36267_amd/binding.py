@@ -25,7 +25,8 @@ _NAMES = {E_INVALID_ARG: "WW_E_INVALID_ARG", E_OOM: "WW_E_OOM", E_INFEASIBLE: "W
 
 EXPORTS = ["ww_last_error", "ww_version", "ww_last_mcf_stats", "ww_default_lut_params", "ww_default_cost_params",
            "ww_residues", "ww_build_cost_lut", "ww_edge_costs", "ww_mcf_solve", "ww_integrate",
-           "ww_unwrap"]
+           "ww_unwrap", "ww_clock", "ww_server_create", "ww_server_submit", "ww_server_poll",
+           "ww_server_in_flight", "ww_server_destroy", "ww_unwrap_batch"]
 
 
 class WWError(RuntimeError):
@@ -93,6 +94,20 @@ def _declare(L):
     for f in ("ww_residues", "ww_build_cost_lut", "ww_edge_costs", "ww_mcf_solve",
               "ww_integrate", "ww_unwrap"):
         getattr(L, f).restype = C.c_int32
+    L.ww_clock.restype = C.c_double
+    L.ww_clock.argtypes = []
+    L.ww_server_create.argtypes = [I32, I64, P]
+    L.ww_server_create.restype = C.c_int32
+    L.ww_server_submit.argtypes = [P, P]
+    L.ww_server_submit.restype = C.c_int32
+    L.ww_server_poll.argtypes = [P, P, I32, I32]
+    L.ww_server_poll.restype = C.c_int32
+    L.ww_server_in_flight.argtypes = [P]
+    L.ww_server_in_flight.restype = C.c_int64
+    L.ww_server_destroy.argtypes = [P]
+    L.ww_server_destroy.restype = C.c_int32
+    L.ww_unwrap_batch.argtypes = [P, I32, I32]
+    L.ww_unwrap_batch.restype = C.c_int32
 
 
 def _check(rc):
@@ -248,3 +263,132 @@ def unwrap(psi, coh, valid, looks, params: CostParams | None = None, out=None):
     _check(load().ww_unwrap(_ptr(psi), _ptr(coh), _ptr(valid), m, n, int(looks), C.byref(cp),
                             _ptr(K), _ptr(phi), C.byref(tot), _stream()))
     return K, phi, int(tot.value)
+
+
+# ------------------------------------------------- many interferograms ---
+
+class Job(C.Structure):
+    """Mirror of ww_job (include/ww.h)."""
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("looks", C.c_int32), ("host_io", C.c_int32),
+                ("psi", C.c_void_p), ("coh", C.c_void_p), ("valid", C.c_void_p),
+                ("K", C.c_void_p), ("phi", C.c_void_p), ("tag", C.c_int64),
+                ("status", C.c_int32), ("total_cost", C.c_int64), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_end", C.c_double), ("footprint_bytes", C.c_int64),
+                ("error", C.c_char * 160)]
+
+
+def clock() -> float:
+    """Seconds on the monotonic clock the job server stamps jobs with."""
+    return float(load().ww_clock())
+
+
+def _host_ptr(a, dtype):
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        if a.dtype != dtype or not a.flags.c_contiguous:
+            raise ValueError(f"host arrays must be C-contiguous {np.dtype(dtype).name}")
+        return C.c_void_p(a.ctypes.data), a
+    # a (pinned) host torch tensor
+    if a.is_cuda or not a.is_contiguous():
+        raise ValueError("host tensors must be contiguous CPU tensors")
+    return C.c_void_p(a.data_ptr()), a
+
+
+def make_job(psi, coh, valid, looks, K=None, phi=None, tag=0):
+    """A Job over device tensors (host_io = 0) or host arrays / pinned CPU
+    tensors (host_io = 1; the worker copies in and out).  Outputs are
+    allocated beside the inputs when not given.  Returns (job, keep) where
+    keep holds every array the job points to."""
+    on_device = not isinstance(psi, np.ndarray) and psi.is_cuda
+    m, n = psi.shape
+    j = Job()
+    j.m, j.n, j.looks, j.tag = m, n, int(looks), int(tag)
+    if on_device:
+        torch = _torch()
+        if K is None:
+            K = torch.empty((m, n), dtype=torch.int32, device=psi.device)
+        if phi is None:
+            phi = torch.empty((m, n), dtype=torch.float32, device=psi.device)
+        j.host_io = 0
+        j.psi, j.coh, j.valid, j.K, j.phi = (_ptr(psi), _ptr(coh), _ptr(valid), _ptr(K), _ptr(phi))
+        keep = (psi, coh, valid, K, phi)
+    else:
+        if K is None:
+            K = np.empty((m, n), np.int32)
+        if phi is None:
+            phi = np.empty((m, n), np.float32)
+        ptrs = [_host_ptr(psi, np.float32), _host_ptr(coh, np.float32), _host_ptr(valid, np.uint8),
+                _host_ptr(K, np.int32), _host_ptr(phi, np.float32)]
+        j.host_io = 1
+        j.psi, j.coh, j.valid, j.K, j.phi = [p for p, _ in ptrs]
+        keep = tuple(a for _, a in ptrs)
+    return j, keep
+
+
+class Server:
+    """Continuous-batching unwrap server (ww_server_*): `slots` workers, each
+    with its own stream and workspace, admitting queued jobs as slots and the
+    HBM budget free up.  Results come back through poll() in completion
+    order as (job, K, phi)."""
+
+    def __init__(self, slots: int = 4, hbm_budget_bytes: int = 0):
+        _torch()
+        self._h = C.c_void_p()
+        _check(load().ww_server_create(int(slots), int(hbm_budget_bytes), C.byref(self._h)))
+        self._live = {}
+
+    def submit(self, psi, coh, valid, looks, K=None, phi=None, tag=0) -> Job:
+        j, keep = make_job(psi, coh, valid, looks, K, phi, tag)
+        self._live[C.addressof(j)] = (j, keep)
+        rc = load().ww_server_submit(self._h, C.byref(j))
+        if rc != OK:
+            del self._live[C.addressof(j)]
+            _check(rc)
+        return j
+
+    def poll(self, wait_ms: int = 0, max_done: int = 256):
+        buf = (C.c_void_p * max_done)()
+        k = load().ww_server_poll(self._h, buf, max_done, int(wait_ms))
+        out = []
+        for a in buf[:k]:
+            j, keep = self._live.pop(a)
+            out.append((j, keep[3], keep[4]))
+        return out
+
+    def in_flight(self) -> int:
+        return int(load().ww_server_in_flight(self._h))
+
+    def drain(self):
+        out = []
+        while self.in_flight():
+            out += self.poll(wait_ms=-1)
+        return out
+
+    def close(self):
+        if self._h:
+            _check(load().ww_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def unwrap_batch(jobs, slots: int = 4):
+    """jobs: list of (psi, coh, valid, looks) device tensors.  Runs them on a
+    temporary server (ww_unwrap_batch) and returns [(K, phi, total_cost)]
+    in the input order."""
+    arr = (Job * len(jobs))()
+    keep = []
+    for k, (psi, coh, valid, looks) in enumerate(jobs):
+        j, kp = make_job(psi, coh, valid, looks, tag=k)
+        arr[k] = j
+        keep.append(kp)
+    rc = load().ww_unwrap_batch(arr, len(jobs), int(slots))
+    if rc != OK:
+        bad = [a for a in arr if a.status != OK]
+        raise WWError(rc, bad[0].error.decode() if bad else load().ww_last_error().decode())
+    return [(kp[3], kp[4], int(a.total_cost)) for a, kp in zip(arr, keep)], arr

@@ -34,21 +34,66 @@ int current_device() {
     return d;
 }
 
-struct DeviceBuffers {
+struct Workspace {
+    int device = 0;
     Buffer slot[SLOT_COUNT];
+    void *host = nullptr;
+    size_t host_bytes = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ww_mcf_stats stats{};
 };
 
-static std::map<int, DeviceBuffers> &buffers() {
-    static std::map<int, DeviceBuffers> b;
-    return b;
+static thread_local Workspace *t_ws = nullptr;
+
+void set_thread_workspace(Workspace *ws) { t_ws = ws; }
+
+Workspace *workspace_create(int device) {
+    Workspace *ws = new Workspace();
+    ws->device = device;
+    return ws;
 }
+
+void workspace_destroy(Workspace *ws) {
+    if (!ws) return;
+    for (auto &b : ws->slot)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (ws->host) (void)hipHostFree(ws->host);
+    for (auto &e : ws->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ws;
+}
+
+size_t workspace_bytes(const Workspace *ws) {
+    size_t s = 0;
+    for (auto &b : ws->slot) s += b.bytes;
+    return s;
+}
+
+Workspace *current_workspace() {
+    if (t_ws) return t_ws;
+    static std::map<int, Workspace *> per_device;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    const int d = current_device();
+    Workspace *&w = per_device[d];
+    if (!w) w = workspace_create(d);
+    return w;
+}
+
+std::mutex &lut_lock() {
+    static std::mutex mu;
+    return mu;
+}
+
+ww_mcf_stats &last_mcf_stats() { return current_workspace()->stats; }
 
 ww_status scratch(int slot, size_t bytes, void **out) {
     if (bytes == 0) bytes = 256;
-    Buffer &b = buffers()[current_device()].slot[slot];
+    Workspace *ws = current_workspace();
+    Buffer &b = ws->slot[slot];
     if (b.bytes < bytes) {
         if (b.ptr) {
-            // the buffer may still be read by queued work on any stream
+            // the buffer may still be read by work queued on any stream
             WW_HIP(hipDeviceSynchronize());
             WW_HIP(hipFree(b.ptr));
             b.ptr = nullptr;
@@ -68,19 +113,29 @@ ww_status scratch(int slot, size_t bytes, void **out) {
 }
 
 ww_status host_scratch(size_t bytes, void **out) {
-    static void *p = nullptr;
-    static size_t have = 0;
-    if (have < bytes) {
-        if (p) WW_HIP(hipHostFree(p));
-        p = nullptr;
-        have = 0;
-        if (hipHostMalloc(&p, bytes) != hipSuccess) {
+    Workspace *ws = current_workspace();
+    if (ws->host_bytes < bytes) {
+        if (ws->host) WW_HIP(hipHostFree(ws->host));
+        ws->host = nullptr;
+        ws->host_bytes = 0;
+        if (hipHostMalloc(&ws->host, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return fail(WW_E_OOM, "pinned host allocation of %zu bytes failed", bytes);
         }
-        have = bytes;
+        ws->host_bytes = bytes;
     }
-    *out = p;
+    *out = ws->host;
+    return WW_OK;
+}
+
+ww_status workspace_events(hipEvent_t *ev0, hipEvent_t *ev1) {
+    Workspace *ws = current_workspace();
+    if (!ws->ev[0]) {
+        WW_HIP(hipEventCreate(&ws->ev[0]));
+        WW_HIP(hipEventCreate(&ws->ev[1]));
+    }
+    *ev0 = ws->ev[0];
+    *ev1 = ws->ev[1];
     return WW_OK;
 }
 
@@ -119,6 +174,7 @@ struct LutKey {
 };
 
 ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, const int16_t **out) {
+    std::lock_guard<std::mutex> g(lut_lock());
     static std::map<LutKey, int16_t *> cache;
     LutKey key;
     memset(&key, 0, sizeof(key));
@@ -137,12 +193,56 @@ ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, cons
         return fail(WW_E_OOM, "cost-table allocation failed");
     }
     ww_status s = build_lut_impl(looks, p, d, stream);
+    // other streams may use the table as soon as it is in the cache
+    if (s == WW_OK && hipStreamSynchronize(stream) != hipSuccess)
+        s = fail(WW_E_DEVICE, "cost-table build failed: %s", hipGetErrorString(hipGetLastError()));
     if (s != WW_OK) {
         (void)hipFree(d);
         return s;
     }
     cache[key] = d;
     *out = d;
+    return WW_OK;
+}
+
+ww_status check_unwrap_args(const float *psi, const float *coh, int m, int n, int looks,
+                            const int32_t *K, const float *phi, const ww_cost_params &cp) {
+    WW_TRY(check_shape(m, n));
+    if (looks < 2 || looks > 64) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
+    if (!psi || !coh || !K || !phi) return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    WW_TRY(check_cost_params(cp));
+    if (cp.ref_i >= 0 && (cp.ref_i >= m || cp.ref_j < 0 || cp.ref_j >= n))
+        return fail(WW_E_INVALID_ARG, "reference pixel outside the image");
+    return WW_OK;
+}
+
+ww_status unwrap_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
+                      int looks, const ww_cost_params &cp, int32_t *K, float *phi,
+                      int64_t *total_out, hipStream_t st) {
+    ww_lut_params lp;
+    ww_default_lut_params(&lp);
+    const int16_t *lut = nullptr;
+    WW_TRY(lut_device(looks, lp, st, &lut));
+    int64_t nl = (int64_t)(m - 1) * (n - 1), nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
+    int8_t *res, *dkx, *dky;
+    int16_t *cxp, *cxn, *cyp, *cyn;
+    int64_t *gdev;
+    WW_TRY(scratch(SLOT_RES, nl, (void **)&res));
+    WW_TRY(scratch(SLOT_CXP, 2 * nx, (void **)&cxp));
+    WW_TRY(scratch(SLOT_CXN, 2 * nx, (void **)&cxn));
+    WW_TRY(scratch(SLOT_CYP, 2 * ny, (void **)&cyp));
+    WW_TRY(scratch(SLOT_CYN, 2 * ny, (void **)&cyn));
+    WW_TRY(scratch(SLOT_DKX, nx, (void **)&dkx));
+    WW_TRY(scratch(SLOT_DKY, ny, (void **)&dky));
+    WW_TRY(scratch(SLOT_COUNTERS, 64, (void **)&gdev));
+    WW_TRY(residues_impl(psi, valid, m, n, res, nullptr, gdev, st));
+    WW_TRY(edge_costs_impl(psi, coh, valid, m, n, lut, lp.n_alpha, lp.n_gamma, cp, cxp, cxn, cyp,
+                           cyn, st));
+    int64_t total = 0;
+    WW_TRY(mcf_impl(res, m, n, cxp, cxn, cyp, cyn, dkx, dky, nullptr, &total, nullptr, st));
+    WW_TRY(integrate_impl(psi, valid, dkx, dky, m, n, cp, K, phi, st));
+    WW_HIP(hipStreamSynchronize(st));
+    *total_out = total;
     return WW_OK;
 }
 
@@ -277,39 +377,12 @@ ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, in
                     int64_t *total_cost_host, void *stream) {
     std::lock_guard<std::mutex> g(lock());
     clear_error();
-    WW_TRY(check_shape(m, n));
-    if (looks < 2 || looks > 64) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
-    if (!psi || !coh || !K || !phi) return fail(WW_E_INVALID_ARG, "input or output array is NULL");
     ww_cost_params cp;
     if (cpin) cp = *cpin;
     else ww_default_cost_params(&cp);
-    WW_TRY(check_cost_params(cp));
-    if (cp.ref_i >= 0 && (cp.ref_i >= m || cp.ref_j < 0 || cp.ref_j >= n))
-        return fail(WW_E_INVALID_ARG, "reference pixel outside the image");
-    hipStream_t st = (hipStream_t)stream;
-    ww_lut_params lp;
-    ww_default_lut_params(&lp);
-    const int16_t *lut = nullptr;
-    WW_TRY(lut_device(looks, lp, st, &lut));
-    int64_t nl = (int64_t)(m - 1) * (n - 1), nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
-    int8_t *res, *dkx, *dky;
-    int16_t *cxp, *cxn, *cyp, *cyn;
-    int64_t *gdev;
-    WW_TRY(scratch(SLOT_RES, nl, (void **)&res));
-    WW_TRY(scratch(SLOT_CXP, 2 * nx, (void **)&cxp));
-    WW_TRY(scratch(SLOT_CXN, 2 * nx, (void **)&cxn));
-    WW_TRY(scratch(SLOT_CYP, 2 * ny, (void **)&cyp));
-    WW_TRY(scratch(SLOT_CYN, 2 * ny, (void **)&cyn));
-    WW_TRY(scratch(SLOT_DKX, nx, (void **)&dkx));
-    WW_TRY(scratch(SLOT_DKY, ny, (void **)&dky));
-    WW_TRY(scratch(SLOT_COUNTERS, 64, (void **)&gdev));
-    WW_TRY(residues_impl(psi, valid, m, n, res, nullptr, gdev, st));
-    WW_TRY(edge_costs_impl(psi, coh, valid, m, n, lut, lp.n_alpha, lp.n_gamma, cp, cxp, cxn, cyp,
-                           cyn, st));
+    WW_TRY(check_unwrap_args(psi, coh, m, n, looks, K, phi, cp));
     int64_t total = 0;
-    WW_TRY(mcf_impl(res, m, n, cxp, cxn, cyp, cyn, dkx, dky, nullptr, &total, nullptr, st));
-    WW_TRY(integrate_impl(psi, valid, dkx, dky, m, n, cp, K, phi, st));
-    WW_HIP(hipStreamSynchronize(st));
+    WW_TRY(unwrap_impl(psi, coh, valid, m, n, looks, cp, K, phi, &total, (hipStream_t)stream));
     if (total_cost_host) *total_cost_host = total;
     return WW_OK;
 }

@@ -975,11 +975,6 @@ __global__ void k_export_pot(const int *pot, const Ctl *ctl, long long N, int64_
 
 // ------------------------------------------------------------------ host ---
 
-ww_mcf_stats &last_mcf_stats() {
-    static ww_mcf_stats s;
-    return s;
-}
-
 constexpr unsigned int H0 = 64;        // hop limit of a pass's first window
 constexpr unsigned int DSTEP0 = 1024;  // first distance increment
 constexpr unsigned int HMAX = 0x1fffffffu;
@@ -1014,11 +1009,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         if (stats) *stats = S;
         return WW_OK;
     }
-    static hipEvent_t ev[2] = {nullptr, nullptr};
-    if (!ev[0]) {
-        WW_HIP(hipEventCreate(&ev[0]));
-        WW_HIP(hipEventCreate(&ev[1]));
-    }
+    hipEvent_t ev[2];
+    WW_TRY(workspace_events(&ev[0], &ev[1]));
     const long long N = (long long)R * C;
     if (N >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
     Graph g;

@@ -36,21 +36,38 @@ void clear_error();
 
 // ------------------------------------------------------------- workspace ---
 
-// Grow-only device buffers owned by the library, one set per device.  All
-// entry points serialise on `lock()`, so a buffer is never shared by two
-// calls at once.
+// Grow-only device buffers owned by the library.  A workspace holds one
+// buffer per slot, a pinned host staging area, timing events and the
+// statistics of its last solve.  The plain entry points use one workspace
+// per device and serialise on `lock()`; each worker of the job server owns a
+// workspace of its own (installed for its thread with set_thread_workspace),
+// so that concurrent jobs never share a buffer.
 struct Buffer {
     void *ptr = nullptr;
     size_t bytes = 0;
 };
 
+struct Workspace;
+
 std::mutex &lock();
 int current_device();
-// Returns a device buffer of at least `bytes` for (device, slot); contents
-// are unspecified.
+// Workspace used by the calling thread: its installed one, else the
+// per-device default.
+Workspace *current_workspace();
+void set_thread_workspace(Workspace *ws);
+Workspace *workspace_create(int device);
+void workspace_destroy(Workspace *ws);
+// Device bytes held by a workspace.
+size_t workspace_bytes(const Workspace *ws);
+// Returns a device buffer of at least `bytes` for (workspace, slot);
+// contents are unspecified.
 ww_status scratch(int slot, size_t bytes, void **out);
 // Pinned host staging area (for counters read back by the solver loop).
 ww_status host_scratch(size_t bytes, void **out);
+// Two timing events of the current workspace.
+ww_status workspace_events(hipEvent_t *ev0, hipEvent_t *ev1);
+// Serialises construction of the shared cost-table cache.
+std::mutex &lut_lock();
 
 enum Slot {
     SLOT_RES = 0, SLOT_CXP, SLOT_CXN, SLOT_CYP, SLOT_CYN, SLOT_DKX, SLOT_DKY, SLOT_LUT,
@@ -99,7 +116,15 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
                          float *phi, hipStream_t stream);
 ww_status build_lut_impl(int looks, const ww_lut_params &p, int16_t *lut_dev, hipStream_t stream);
 
-ww_mcf_stats &last_mcf_stats();
+ww_mcf_stats &last_mcf_stats();  // of the current workspace
+
+// Whole unwrap (residues, costs, solve, integration) on `stream`, using the
+// current workspace; the cost table comes from the shared cache.
+ww_status unwrap_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
+                      int looks, const ww_cost_params &cp, int32_t *K, float *phi,
+                      int64_t *total, hipStream_t stream);
+ww_status check_unwrap_args(const float *psi, const float *coh, int m, int n, int looks,
+                            const int32_t *K, const float *phi, const ww_cost_params &cp);
 
 ww_status check_lut_params(const ww_lut_params &p);
 ww_status check_cost_params(const ww_cost_params &p);

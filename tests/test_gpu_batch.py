@@ -1,0 +1,132 @@
+"""Many interferograms through the job server (ww_server_*, ww_unwrap_batch):
+every job's K, phi and cost must be byte-identical to the plain one-job
+ww_unwrap on the same inputs, alone or in a mix, with host or device arrays,
+and its cost must equal the CPU oracle's optimum."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_36267_amd import binding as ww
+from paper_2609_36267_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# (m, n, looks, seed): several tiles and ragged tails, three looks values
+JOBS = [(96, 130, 9, 11), (200, 150, 5, 12), (64, 300, 15, 13), (257, 129, 9, 14),
+        (33, 45, 5, 15), (150, 150, 15, 16), (2, 300, 9, 17), (300, 2, 5, 18)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    ww.load()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    out = []
+    for m, n, L, seed in JOBS:
+        sc = synth.make(m, n, looks=L, seed=seed, mask_frac=0.05, disks=1,
+                        disk_radius=(8, 20), keep_truth=False, workers=1)
+        out.append(sc)
+    return out
+
+
+@pytest.fixture(scope="module")
+def plain(torch_cuda, scenes):
+    """Plain path results: (K, phi, cost) as numpy."""
+    res = []
+    for sc in scenes:
+        K, phi, tot = ww.unwrap(sc.psi, sc.coh, sc.valid, sc.looks)
+        res.append((K.cpu().numpy(), phi.cpu().numpy(), tot))
+    return res
+
+
+def same_phi(a, b):
+    return np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_plain_costs_equal_oracle(plain, scenes):
+    for sc, (_, _, tot) in zip(scenes, plain):
+        _, _, total = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks)
+        assert tot == total, (sc.psi.shape, sc.looks)
+
+
+@pytest.mark.parametrize("slots", [1, 3, 8])
+def test_batch_matches_plain(torch_cuda, scenes, plain, slots):
+    torch = torch_cuda
+    jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+             torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes]
+    results, arr = ww.unwrap_batch(jobs, slots=slots)
+    for (K, phi, tot), (Kp, phip, totp), j in zip(results, plain, arr):
+        assert j.status == 0
+        assert tot == totp
+        assert np.array_equal(K.cpu().numpy(), Kp)
+        assert same_phi(phi.cpu().numpy(), phip)
+        assert j.t_submit <= j.t_start <= j.t_end
+
+
+def test_server_host_arrays_in_a_mix(torch_cuda, scenes, plain):
+    """Jobs arrive while others run; host arrays are copied in and out."""
+    with ww.Server(slots=3) as srv:
+        jobs = []
+        for k, sc in enumerate(scenes * 2):
+            jobs.append(srv.submit(sc.psi, sc.coh, sc.valid, sc.looks, tag=k))
+            if k % 3 == 2:
+                time.sleep(0.002)
+        done = srv.drain()
+    assert len(done) == 2 * len(scenes)
+    for j, K, phi in done:
+        assert j.status == 0, j.error
+        Kp, phip, totp = plain[j.tag % len(scenes)]
+        assert j.total_cost == totp
+        assert np.array_equal(K, Kp)
+        assert same_phi(phi, phip)
+
+
+def test_server_device_arrays_and_poll(torch_cuda, scenes, plain):
+    torch = torch_cuda
+    with ww.Server(slots=2) as srv:
+        for k, sc in enumerate(scenes):
+            srv.submit(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+                       torch.from_numpy(sc.valid).cuda(), sc.looks, tag=k)
+        got = []
+        t0 = time.time()
+        while len(got) < len(scenes) and time.time() - t0 < 60:
+            got += srv.poll(wait_ms=100)
+        assert srv.in_flight() == 0
+    assert sorted(j.tag for j, _, _ in got) == list(range(len(scenes)))
+    for j, K, phi in got:
+        Kp, phip, totp = plain[j.tag]
+        assert j.total_cost == totp
+        assert np.array_equal(K.cpu().numpy(), Kp)
+        assert same_phi(phi.cpu().numpy(), phip)
+
+
+def test_tiny_budget_runs_jobs_one_at_a_time(torch_cuda, scenes, plain):
+    """With a budget below any job's footprint each job runs alone."""
+    with ww.Server(slots=4, hbm_budget_bytes=1) as srv:
+        for k, sc in enumerate(scenes):
+            srv.submit(sc.psi, sc.coh, sc.valid, sc.looks, tag=k)
+        done = srv.drain()
+    spans = sorted((j.t_start, j.t_end) for j, _, _ in done)
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0
+    for j, K, phi in done:
+        assert j.total_cost == plain[j.tag][2]
+        assert j.footprint_bytes > 1
+
+
+def test_bad_job_fails_alone(torch_cuda, scenes, plain):
+    sc = scenes[0]
+    with ww.Server(slots=2) as srv:
+        good = srv.submit(sc.psi, sc.coh, sc.valid, sc.looks, tag=0)
+        bad = srv.submit(sc.psi, sc.coh, sc.valid, 1, tag=1)  # L = 1 is outside [2, 64]
+        done = {j.tag: j for j, _, _ in srv.drain()}
+    assert done[1].status == ww.E_INVALID_ARG and b"looks" in done[1].error
+    assert done[0].status == 0 and done[0].total_cost == plain[0][2]
+    assert good.tag == 0 and bad.tag == 1
