@@ -38,12 +38,19 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="rows of the full-width strip the oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slots", type=int, default=8, help="job-server workers for the stack and serving legs")
+    ap.add_argument("--stack-jobs", type=int, default=64, help="interferograms in the stack leg (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-pool", type=int, default=24, help="distinct pre-generated requests")
+    ap.add_argument("--serve-oracle", type=int, default=4,
+                    help="pool entries (smallest used first) whose cost the oracle checks")
     return ap.parse_args()
 
 
@@ -69,6 +76,119 @@ def cpu_baseline(sc, rows):
                       f"({px / 1e6:.2f} Mpixel, crosses the fault), {dt:.2f} s single-threaded; "
                       "cost table excluded (cached on both paths)",
             "host": _cpu_model()}
+
+
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def stack_scenes(args, synth):
+    t0 = time.time()
+    scs = [synth.stack_job(k) for k in range(args.stack_jobs)]
+    return scs, time.time() - t0
+
+
+def serve_pool(args, synth):
+    t0 = time.time()
+    pool = [synth.serve_request(k) for k in range(args.serve_pool)]
+    return pool, time.time() - t0
+
+
+def stack_leg(args, ww, torch, scs, gen_s):
+    """64 interferograms of mixed size and L: one job server with
+    ``--slots`` workers against 64 sequential plain ww_unwrap calls, all on
+    device-resident inputs, at identical exact costs."""
+    dev = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+            torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scs]
+    outs = [(torch.empty(sc.psi.shape, dtype=torch.int32, device="cuda"),
+             torch.empty(sc.psi.shape, dtype=torch.float32, device="cuda")) for sc in scs]
+    px = sum(sc.psi.size for sc in scs)
+    for L in sorted({sc.looks for sc in scs}):
+        ww.build_cost_lut(L)
+    # warm both paths (workspaces grow to the largest job)
+    ww.unwrap(*dev[0][:3], dev[0][3], out=outs[0])
+    ww.unwrap_batch(dev[:args.slots], slots=args.slots)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [ww.unwrap(*d[:3], d[3], out=o)[2] for d, o in zip(dev, outs)]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    t = time.perf_counter()
+    res, arr = ww.unwrap_batch(dev, slots=args.slots)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t
+    batch = [r[2] for r in res]
+    return {"workload": f"stack of {len(scs)} interferograms, rows logU[512,2048] x cols logU[512,4096], "
+                        "L in {5,9,15}, bump 5-80 rad (seeds 1000+k)",
+            "pixels": px, "generated_s": round(gen_s, 1), "slots": args.slots,
+            "batched_mpix_s": round(px / 1e6 / batch_s, 2), "plain_mpix_s": round(px / 1e6 / plain_s, 2),
+            "batched_s": round(batch_s, 3), "plain_s": round(plain_s, 3),
+            "speedup": round(plain_s / batch_s, 3), "identical_costs": plain == batch,
+            "total_cost_sum": int(sum(batch))}
+
+
+def serve_leg(args, ww, torch, pool, gen_s):
+    """Poisson stream of unwrap requests (c1 recipe, sizes logU[256, 8192]^2)
+    from a pool of pre-generated requests in pinned host memory; latency runs
+    from arrival to results back in host memory (copies included).  The job
+    server with ``--slots`` workers against the plain path (one request at a
+    time, same copies)."""
+    import numpy as np
+    pin = []
+    for sc in pool:
+        pin.append(tuple(torch.from_numpy(a).pin_memory() for a in (sc.psi, sc.coh, sc.valid))
+                   + (torch.empty(sc.psi.shape, dtype=torch.int32).pin_memory(),
+                      torch.empty(sc.psi.shape, dtype=torch.float32).pin_memory()))
+    ww.build_cost_lut(9)
+    rng = np.random.default_rng(42)
+    n_req = max(1, int(args.serve_rate * args.serve_seconds))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, n_req))
+    picks = rng.integers(0, len(pool), n_req)
+    alone = {}
+    # costs alone (plain path, one at a time)
+    for k in sorted(set(picks.tolist())):
+        p = pin[k]
+        alone[k] = ww.unwrap(p[0].cuda(), p[1].cuda(), p[2].cuda(), 9)[2]
+    torch.cuda.synchronize()
+
+    def run(slots):
+        with ww.Server(slots=slots) as srv:
+            t_start = ww.clock()
+            lat, costs, done = [], [], 0
+            for a, k in zip(arrivals, picks):
+                while ww.clock() - t_start < a:
+                    for j, _, _ in srv.poll(wait_ms=1):
+                        lat.append(j.t_end - j.t_submit)
+                        costs.append((int(j.tag), int(j.total_cost), int(j.status)))
+                p = pin[k]
+                srv.submit(p[0], p[1], p[2], 9, K=p[3], phi=p[4], tag=int(k))
+            for j, _, _ in srv.drain():
+                lat.append(j.t_end - j.t_submit)
+                costs.append((int(j.tag), int(j.total_cost), int(j.status)))
+            span = ww.clock() - t_start
+        px = sum(pool[k].psi.size for k in picks)
+        ok = all(st == 0 and c == alone[k] for k, c, st in costs)
+        return {"mpix_s": round(px / 1e6 / span, 2), "p50_ms": round(_pct(lat, 50) * 1e3, 2),
+                "p99_ms": round(_pct(lat, 99) * 1e3, 2), "makespan_s": round(span, 2),
+                "requests": len(costs), "same_cost_as_alone": ok}
+
+    served = run(args.slots)
+    plain = run(1)
+    # exact oracle cost on the smallest pool entries used
+    checked = []
+    if args.serve_oracle > 0:
+        import oracle
+        used = sorted(set(picks.tolist()), key=lambda k: pool[k].psi.size)[:args.serve_oracle]
+        for k in used:
+            sc = pool[k]
+            checked.append({"request": int(k), "shape": list(sc.psi.shape),
+                            "equal": int(oracle.unwrap(sc.psi, sc.coh, sc.valid, 9)[2]) == alone[k]})
+    offered = sum(pool[k].psi.size for k in picks) / 1e6 / float(arrivals[-1])
+    return {"workload": f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, "
+                        f"pool of {len(pool)} requests, rows/cols logU[256,8192], c1 recipe (seeds 2000+k)",
+            "offered_mpix_s": round(offered, 2), "generated_s": round(gen_s, 1), "slots": args.slots,
+            "server": served, "plain": plain, "oracle_checked": checked}
 
 
 def _cpu_model():
@@ -98,6 +218,9 @@ def main():
     sc = synth.config(args.workload)
     m, n = sc.psi.shape
     print(f"# generated {args.workload} {m}x{n} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    stack = stack_scenes(args, synth) if args.stack_jobs > 0 else None
+    pool = serve_pool(args, synth) if args.serve_seconds > 0 else None
+    print(f"# generated stack/pool in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     assert torch.cuda.is_available(), "no GPU visible"
     psi = torch.from_numpy(sc.psi).cuda()
     coh = torch.from_numpy(sc.coh).cuda()
@@ -171,6 +294,12 @@ def main():
         "paper_context": {"whirlwind_74mpix_s": 209, "derived_mpix_s": 0.356,
                           "note": "unstated CPU, real Sentinel-1 scene; context, not the target"},
     }
+    if args.stack_jobs > 0:
+        out["stack"] = stack_leg(args, ww, torch, *stack)
+        print(f"# stack: {out['stack']}", file=sys.stderr, flush=True)
+    if args.serve_seconds > 0:
+        out["serve"] = serve_leg(args, ww, torch, *pool)
+        print(f"# serve: {out['serve']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, min(args.cpu_rows, m))
     print(json.dumps(out), flush=True)
