@@ -33,6 +33,11 @@ TILE_NODES = 32 * 32
 BYTES_PER_NODE_VISIT = 8 + 8 + 4 + 10
 BYTES_PER_TILE_VISIT = TILE_NODES * BYTES_PER_NODE_VISIT
 GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
+# HBM bytes per k_sssp_round launch on the fault scene from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
+# (fetch x 2.0, write x 1.0), valid for the solver source of that hash only.
+TRAFFIC_SOURCE_SHA = "aeabe916eb98f34a"
+TRAFFIC_BYTES_PER_LAUNCH = 33.09e6
 
 
 def parse():
@@ -49,6 +54,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-pool", type=int, default=24, help="distinct pre-generated requests")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes (to scale HBM byte counters) and exit")
     ap.add_argument("--serve-oracle", type=int, default=4,
                     help="pool entries (smallest used first) whose cost the oracle checks")
     return ap.parse_args()
@@ -212,6 +219,17 @@ def main():
     from paper_2609_36267_amd import binding as ww
     from paper_2609_36267_amd import synth
 
+    if args.copy_calibration > 0:
+        # a plain copy of known size: reads and writes exactly MIB MiB each
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 3}), flush=True)
+        return
+
     ww.load()
     # generate (forked worker processes) before the GPU is initialised
     t0 = time.time()
@@ -264,6 +282,11 @@ def main():
     exact = bool(len(set(totals)) == 1 and (golden is None or totals[0] == golden))
 
     achieved = visits * BYTES_PER_TILE_VISIT / (relax_ms / 1e3) / 1e9 if relax_ms > 0 else 0.0
+    import hashlib
+    src = os.path.join(ROOT, "paper_2609_36267_amd", "csrc", "mcf.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = TRAFFIC_BYTES_PER_LAUNCH if (sha == TRAFFIC_SOURCE_SHA and args.workload == "c2") else None
+    rounds = sum(st["rounds"] for st in stats)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -286,7 +309,9 @@ def main():
         "oracle_cost": golden,
         "roofline": {"bound": "hbm", "kernel": "k_sssp_round",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": round(visits * BYTES_PER_TILE_VISIT / max(1, rounds)),
                      "relax_ms_per_step": round(relax_ms / args.steps, 3),
                      "tile_visits_per_step": visits // args.steps,
                      "bytes_per_tile_visit": BYTES_PER_TILE_VISIT},
