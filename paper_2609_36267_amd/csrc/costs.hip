@@ -1,6 +1,9 @@
 // Per-edge integer arc costs (Section II-B).
 //
-// k_edge_costs: one workgroup per 16 x 64 pixel tile.  The tile's wrapped
+// k_edge_costs_stream (box half-width h <= 4, table of at most 8192
+// entries): waves stream down column strips (described at the kernel).
+// k_edge_costs (any h up to 8, any table): one workgroup per 16 x 64 pixel
+// tile.  The tile's wrapped
 // phase and mask, plus a halo of h+1, are staged in LDS; each x- and y-edge
 // sample gets its wrapped gradient in 2^-20 rad fixed point; separable
 // integer box sums give the clipped (2h+1)^2 mean slope of every output edge,
@@ -249,6 +252,282 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
     }
 }
 
+// ------------------------------------------------ streaming variant (h <= 4)
+//
+// One wave per strip of CS_OW = 63 - 2H output columns, walking down a
+// segment of CS_ROWS output rows.  Lane l holds sample column
+// c = js - H + l; every pixel row is loaded once (coalesced, the next row
+// prefetched), the horizontal window sums come from wave shuffles and the
+// vertical ones from shift registers of the last 2H+1 sample rows, so the
+// only re-read data are the 2H halo columns of a strip and the 2H halo rows
+// of a segment.  Steep candidates are buffered per wave in LDS and appended
+// with one atomic reservation per CS_CB entries.  Same arithmetic as
+// k_edge_costs, so the outputs are identical.
+constexpr int CS_ROWS = 128;
+constexpr int CS_CB = 256;
+constexpr int CS_WAVES = 4;
+constexpr int CS_LUT_MAX = 8192;  // table entries staged in LDS (16 KB)
+
+struct CandBuf {
+    unsigned long long key[CS_CB];
+    unsigned int id[CS_CB];
+};
+
+__device__ __forceinline__ void cand_flush(CandBuf &b, int &cnt, int lane,
+                                           unsigned long long *__restrict__ cand_key,
+                                           unsigned int *__restrict__ cand_id, SteepState *st) {
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0 && cnt) base = atomicAdd(&st->ncand, (unsigned long long)cnt);
+    base = __shfl(base, 0, 64);
+    for (int k = lane; k < cnt; k += 64) {
+        cand_key[base + k] = b.key[k];
+        cand_id[base + k] = b.id[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    cnt = 0;
+}
+
+__device__ __forceinline__ void cand_push(CandBuf &b, int &cnt, int lane, bool has,
+                                          unsigned long long key, unsigned int id,
+                                          unsigned long long *__restrict__ cand_key,
+                                          unsigned int *__restrict__ cand_id, SteepState *st) {
+    const unsigned long long bal = __ballot(has);
+    if (!bal) return;
+    if (cnt + 64 > CS_CB) cand_flush(b, cnt, lane, cand_key, cand_id, st);
+    if (has) {
+        const int off = __popcll(bal & ((1ull << lane) - 1ull));
+        b.key[cnt + off] = key;
+        b.id[cnt + off] = id;
+    }
+    cnt += __popcll(bal);
+}
+
+// Slope bin floor((S + K P) NA / (2 K P)) clamped to [0, NA-1], P = PI_FIX,
+// for K >= 1 samples of sum S: a float estimate of the quotient (error far
+// below one) and one exact integer correction step.
+__device__ __forceinline__ int slope_bin(int S, int K, int NA) {
+    const int64_t num = ((int64_t)S + (int64_t)K * PI_FIX) * NA;
+    const int64_t den = 2 * (int64_t)K * PI_FIX;
+    int t = (int)floorf(__fdividef((float)num, (float)den));
+    const int64_t e = num - (int64_t)t * den;
+    t += (e >= den) - (e < 0);
+    return t < 0 ? 0 : (t > NA - 1 ? NA - 1 : t);
+}
+
+template <int H>
+__global__ __launch_bounds__(64 * CS_WAVES) void k_edge_costs_stream(
+    const float *__restrict__ psi, const float *__restrict__ coh, const uint8_t *__restrict__ valid,
+    int m, int n, const int16_t *__restrict__ lut, int NA, int NG, double steep_thresh,
+    int steep_on, int16_t *__restrict__ cxp, int16_t *__restrict__ cxn, int16_t *__restrict__ cyp,
+    int16_t *__restrict__ cyn, unsigned long long *__restrict__ cand_key,
+    unsigned int *__restrict__ cand_id, SteepState *__restrict__ st, int nstrips, int nwaves) {
+    constexpr int OW = 63 - 2 * H;
+    __shared__ CandBuf cbuf[CS_WAVES];
+    __shared__ int16_t slut[CS_LUT_MAX];
+    for (int t = threadIdx.x; t < NA * NG; t += 64 * CS_WAVES) slut[t] = lut[t];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * CS_WAVES + wv;
+    if (gw >= nwaves) return;  // whole waves only: no workgroup barrier below
+    CandBuf &cb = cbuf[wv];
+    int ccnt = 0;
+    const int strip = gw % nstrips, seg = gw / nstrips;
+    const int js = strip * OW;
+    const int r0 = seg * CS_ROWS, r1 = min(r0 + CS_ROWS, m);
+    const int c = js - H + lane;  // sample / pixel column of this lane
+    const bool col_in = c >= 0 && c < n;
+    const int j = c;              // output column of an output lane
+    const bool out_lane = lane >= H && lane < H + OW;
+    const int nx_cols = n - 1;
+    const int64_t nx_total = (int64_t)m * (n - 1);
+
+    constexpr int W = 2 * H + 1;
+    int hxs[W], hxk[W], hys[W], hyk[W];  // index 0: newest sample row
+    double dx[H + 1], dy[H + 1];
+    bool okx_r[H + 1], oky_r[H + 1];
+    float ch[H + 2];
+#pragma unroll
+    for (int k = 0; k < W; ++k) hxs[k] = hxk[k] = hys[k] = hyk[k] = 0;
+#pragma unroll
+    for (int k = 0; k <= H; ++k) {
+        dx[k] = dy[k] = 0.0;
+        okx_r[k] = oky_r[k] = false;
+    }
+#pragma unroll
+    for (int k = 0; k < H + 2; ++k) ch[k] = 0.f;
+    double ph_prev = 0.0;
+    bool vd_prev = false;
+    int nvalid = 0;
+
+    const int i_start = max(0, r0 - H);
+    const int i_last = r1 + H;  // inclusive; rows >= m are absent (zero samples)
+    // two rows of loads in flight ahead of the row being processed
+    auto fetch = [&](int i, float &p, uint8_t &v, float &cc) {
+        if (i < m && i <= i_last && col_in) {
+            const int a = i * n + c;  // m * n < 2^31
+            v = valid ? valid[a] : 1;
+            p = psi[a];
+            cc = coh[a];
+        } else {
+            v = 0;
+            p = 0.f;
+            cc = 0.f;
+        }
+    };
+    float p_n1, c_n1, p_n2, c_n2;
+    uint8_t v_n1, v_n2;
+    fetch(i_start, p_n1, v_n1, c_n1);
+    fetch(i_start + 1, p_n2, v_n2, c_n2);
+    for (int i = i_start; i <= i_last; ++i) {
+        const bool row_in = i < m;
+        const float p = p_n1, cc = c_n1;
+        const uint8_t v = v_n1;
+        p_n1 = p_n2;
+        c_n1 = c_n2;
+        v_n1 = v_n2;
+        fetch(i + 2, p_n2, v_n2, c_n2);
+        const bool vd = row_in && col_in && v != 0;
+        const double ph = vd ? (double)p : 0.0;
+        // x-sample (i, c): pixels c and c+1 (lane 63's right neighbour lies
+        // outside every output window)
+        const double ph_r = __shfl_down(ph, 1, 64);
+        const int vd_r = __shfl_down((int)vd, 1, 64);
+        const bool okx = vd && vd_r && (c + 1 < n);
+        int qx = 0;
+        double dxv = 0.0;
+        if (okx) {
+            const double diff = ph_r - ph;
+            dxv = diff - TWO_PI_D * wrap_cycles(diff);
+            qx = (int)floor(dxv * 1048576.0);
+        }
+        // y-sample (i-1, c): pixels (i-1, c) and (i, c)
+        const bool oky = vd && vd_prev;
+        int qy = 0;
+        double dyv = 0.0;
+        if (oky) {
+            const double diff = ph - ph_prev;
+            dyv = diff - TWO_PI_D * wrap_cycles(diff);
+            qy = (int)floor(dyv * 1048576.0);
+        }
+        // horizontal window sums (meaningful on output lanes), packed as
+        // 16 q + ok: at most 2H+1 <= 9 samples, |q| <= P + 1, so the count
+        // stays in the low 4 bits and the packed sum within 31 bits
+        const int px = qx * 16 + (int)okx, py = qy * 16 + (int)oky;
+        int spx = px, spy = py;
+#pragma unroll
+        for (int d = 1; d <= H; ++d) {
+            spx += __shfl(px, lane - d, 64) + __shfl(px, lane + d, 64);
+            spy += __shfl(py, lane - d, 64) + __shfl(py, lane + d, 64);
+        }
+#pragma unroll
+        for (int k = W - 1; k > 0; --k) {
+            hxs[k] = hxs[k - 1];
+            hxk[k] = hxk[k - 1];
+            hys[k] = hys[k - 1];
+            hyk[k] = hyk[k - 1];
+        }
+        hxs[0] = spx >> 4;
+        hxk[0] = spx & 15;
+        hys[0] = spy >> 4;
+        hyk[0] = spy & 15;
+#pragma unroll
+        for (int k = H; k > 0; --k) {
+            dx[k] = dx[k - 1];
+            dy[k] = dy[k - 1];
+            okx_r[k] = okx_r[k - 1];
+            oky_r[k] = oky_r[k - 1];
+        }
+        dx[0] = dxv;
+        dy[0] = dyv;
+        okx_r[0] = okx;
+        oky_r[0] = oky;
+#pragma unroll
+        for (int k = H + 1; k > 0; --k) ch[k] = ch[k - 1];
+        ch[0] = (row_in && col_in) ? cc : 0.f;
+        ph_prev = ph;
+        vd_prev = vd;
+
+        // ---- x-edges of row r = i - H
+        {
+            const int r = i - H;
+            const float c_right = __shfl_down(ch[H], 1, 64);  // coh(r, j+1)
+            bool has = false;
+            unsigned long long key = 0;
+            unsigned int id = 0;
+            if (r >= r0 && r < r1 && out_lane && j < n - 1) {
+                const int idx_x = r * nx_cols + j;
+                int16_t cp = 0, cn = 0;
+                if (okx_r[H]) {
+                    ++nvalid;
+                    int S = 0, K = 0;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        S += hxs[k];
+                        K += hxk[k];
+                    }
+                    const int ba = slope_bin(S, K, NA);
+                    float c0 = ch[H], c1 = c_right;
+                    c0 = (c0 != c0) ? 0.f : c0;  // NaN reads as 0 (fminf would drop it)
+                    c1 = (c1 != c1) ? 0.f : c1;
+                    const int bg = coh_bin(fminf(c0, c1), NG);
+                    cp = slut[bg * NA + ba];
+                    cn = slut[bg * NA + (NA - 1 - ba)];
+                    const double dd = fabs(dx[H]);
+                    if (steep_on && dd > steep_thresh) {
+                        has = true;
+                        key = (unsigned long long)__double_as_longlong(dd);
+                        id = (unsigned int)idx_x;
+                    }
+                }
+                cxp[idx_x] = cp;
+                cxn[idx_x] = cn;
+            }
+            cand_push(cb, ccnt, lane, has, key, id, cand_key, cand_id, st);
+        }
+        // ---- y-edges of row r = i - 1 - H
+        {
+            const int r = i - 1 - H;
+            bool has = false;
+            unsigned long long key = 0;
+            unsigned int id = 0;
+            if (r >= r0 && r < r1 && r < m - 1 && out_lane && j < n) {
+                const int idx_y = r * n + j;
+                int16_t cp = 0, cn = 0;
+                if (oky_r[H]) {
+                    ++nvalid;
+                    int S = 0, K = 0;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        S += hys[k];
+                        K += hyk[k];
+                    }
+                    const int ba = slope_bin(S, K, NA);
+                    float c0 = ch[H + 1], c1 = ch[H];  // coh(r, j), coh(r+1, j)
+                    c0 = (c0 != c0) ? 0.f : c0;
+                    c1 = (c1 != c1) ? 0.f : c1;
+                    const int bg = coh_bin(fminf(c0, c1), NG);
+                    cp = slut[bg * NA + ba];
+                    cn = slut[bg * NA + (NA - 1 - ba)];
+                    const double dd = fabs(dy[H]);
+                    if (steep_on && dd > steep_thresh) {
+                        has = true;
+                        key = (unsigned long long)__double_as_longlong(dd);
+                        id = (unsigned int)nx_total + (unsigned int)idx_y;
+                    }
+                }
+                cyp[idx_y] = cp;
+                cyn[idx_y] = cn;
+            }
+            cand_push(cb, ccnt, lane, has, key, id, cand_key, cand_id, st);
+        }
+    }
+    if (ccnt) cand_flush(cb, ccnt, lane, cand_key, cand_id, st);
+    for (int off = 32; off > 0; off >>= 1) nvalid += __shfl_down(nvalid, off, 64);
+    if (lane == 0 && nvalid)
+        atomicAdd(&st->nvalid_part[gw % STRIPES], (unsigned long long)nvalid);
+}
+
 // cap = floor(pct * valid / 100); remaining = cap
 __global__ void k_steep_init(SteepState *st, int pct) {
     unsigned long long nv = 0;
@@ -360,15 +639,36 @@ ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *val
     ids = (unsigned int *)(kbuf + ((size_t)capn * 8 + 255) / 256 * 256);
     WW_HIP(hipMemsetAsync(st, 0, sizeof(SteepState), stream));
     const int h = cp.box_half;
-    const int PR = CT_H + 2 * h + 1, PC = CT_W + 2 * h + 1, ER = CT_H + 2 * h, EC = CT_W + 2 * h;
-    const size_t lds = (size_t)PR * PC * 4 + 2 * (size_t)ER * EC * 4 + 2 * (size_t)ER * CT_W * 4 +
-                       2 * (size_t)ER * CT_W * 2 + (size_t)PR * PC + 2 * (size_t)ER * EC;
-    if (lds > 64 * 1024) return fail(WW_E_INVALID_ARG, "box_half %d too large for the tile (max 8)", h);
-    dim3 grid(ceil_div(n, CT_W), ceil_div(m, CT_H));
-    hipLaunchKernelGGL(k_edge_costs, grid, dim3(CT_THREADS), lds, stream, psi, coh, valid, m, n,
-                       lut, NA, NG, h, cp.steep_thresh_rad, steep_on, cxp, cxn, cyp, cyn, keys, ids,
-                       st);
-    WW_LAUNCH_CHECK();
+    if (h <= 4 && NA * NG <= CS_LUT_MAX) {
+        const int OW = 63 - 2 * h;
+        const int nstrips = ceil_div(n, OW), nsegs = ceil_div(m, CS_ROWS);
+        const int nwaves = nstrips * nsegs;
+        const dim3 grid(ceil_div(nwaves, CS_WAVES));
+#define WW_STREAM(HH)                                                                          \
+    hipLaunchKernelGGL(k_edge_costs_stream<HH>, grid, dim3(64 * CS_WAVES), 0, stream, psi, coh, \
+                       valid, m, n, lut, NA, NG, cp.steep_thresh_rad, steep_on, cxp, cxn, cyp,  \
+                       cyn, keys, ids, st, nstrips, nwaves)
+        switch (h) {
+            case 0: WW_STREAM(0); break;
+            case 1: WW_STREAM(1); break;
+            case 2: WW_STREAM(2); break;
+            case 3: WW_STREAM(3); break;
+            default: WW_STREAM(4); break;
+        }
+#undef WW_STREAM
+        WW_LAUNCH_CHECK();
+    } else {
+        const int PR = CT_H + 2 * h + 1, PC = CT_W + 2 * h + 1, ER = CT_H + 2 * h, EC = CT_W + 2 * h;
+        const size_t lds = (size_t)PR * PC * 4 + 2 * (size_t)ER * EC * 4 + 2 * (size_t)ER * CT_W * 4 +
+                           2 * (size_t)ER * CT_W * 2 + (size_t)PR * PC + 2 * (size_t)ER * EC;
+        if (lds > 64 * 1024)
+            return fail(WW_E_INVALID_ARG, "box_half %d too large for the tile (max 8)", h);
+        dim3 grid(ceil_div(n, CT_W), ceil_div(m, CT_H));
+        hipLaunchKernelGGL(k_edge_costs, grid, dim3(CT_THREADS), lds, stream, psi, coh, valid, m,
+                           n, lut, NA, NG, h, cp.steep_thresh_rad, steep_on, cxp, cxn, cyp, cyn,
+                           keys, ids, st);
+        WW_LAUNCH_CHECK();
+    }
     if (steep_on) {
         hipLaunchKernelGGL(k_steep_init, dim3(1), dim3(1), 0, stream, st, cp.steep_cap_pct);
         WW_LAUNCH_CHECK();

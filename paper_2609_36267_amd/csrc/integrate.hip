@@ -8,8 +8,10 @@
 //   k_first_valid : reference pixel = first valid pixel, row-major (atomicMin)
 //   k_col0        : one workgroup; column-0 prefix sums K0[i] and K(ref)
 //   k_rows        : one workgroup per row; chunked workgroup scan of the
-//                   row's x-edge increments, then K and
-//                   phi = (float)((double)psi + 2 pi K) (nodata if invalid).
+//                   row's x-edge increments (8 pixels per thread, 16-byte
+//                   accesses where rows are 4-aligned, next chunk prefetched),
+//                   then K and phi = (float)((double)psi + 2 pi K) (nodata
+//                   if invalid).
 // Bytes per pixel: psi 4 + valid 1 + dk_x 1 read, K 4 + phi 4 written.
 #pragma clang fp contract(off)
 
@@ -18,8 +20,6 @@
 namespace ww {
 
 constexpr int IT_THREADS = 256;
-constexpr int IT_PER = 4;
-constexpr int IT_CHUNK = IT_THREADS * IT_PER;
 
 struct IntegState {
     long long first_valid;
@@ -80,6 +80,9 @@ __device__ __forceinline__ int gx_at(const float *psi, const uint8_t *valid, con
            wrap_cycles(phase_at(psi, valid, a + 1) - phase_at(psi, valid, a));
 }
 
+// Column 0 and K(ref), one workgroup.  Column-0 increments
+// g(i) = dk_y(i-1, 0) - w_y(i-1, 0) are scanned in chunks of 8 rows per
+// thread, each thread's 8 loads issued together.
 __global__ __launch_bounds__(IT_THREADS) void k_col0(const float *__restrict__ psi,
                                                     const uint8_t *__restrict__ valid,
                                                     const int8_t *__restrict__ dkx,
@@ -93,30 +96,92 @@ __global__ __launch_bounds__(IT_THREADS) void k_col0(const float *__restrict__ p
         ri = (int)(fv / n);
         rj = (int)(fv % n);
     }
-    // K0[i] = sum_{i' < i} (dk_y(i',0) - w_y(i',0))
+    auto g_col = [&](int i) -> int {  // increment from row i-1 to row i, i >= 1
+        const int64_t a = (int64_t)(i - 1) * n;
+        return (int)dky[a] - wrap_cycles(phase_at(psi, valid, a + n) - phase_at(psi, valid, a));
+    };
+    // K0[i] = sum_{1 <= i' <= i} g(i'), in chunks of IT_THREADS x 8 rows:
+    // thread t owns 8 consecutive rows of a chunk, all 8 loads in flight
+    constexpr int PER = 8;
     int carry = 0;
-    for (int base = 0; base < m; base += IT_THREADS) {
-        const int i = base + threadIdx.x;
-        int g = 0;
-        if (i >= 1 && i < m) {
-            const int64_t a = (int64_t)(i - 1) * n;
-            g = (int)dky[(int64_t)(i - 1) * n] -
-                wrap_cycles(phase_at(psi, valid, a + n) - phase_at(psi, valid, a));
+    for (int base = 0; base < m; base += IT_THREADS * PER) {
+        const int lo = base + threadIdx.x * PER;
+        int g[PER];
+        int local = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = lo + q;
+            g[q] = (i >= 1 && i < m) ? g_col(i) : 0;
+            local += g[q];
         }
         int tot;
-        int ex = block_exclusive_scan(g, &tot);
-        if (i < m) K0[i] = carry + ex + g;
+        int run = carry + block_exclusive_scan(local, &tot);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            run += g[q];
+            if (lo + q < m) K0[lo + q] = run;
+        }
         carry += tot;
     }
+    __syncthreads();
     // K(ref) = K0[ri] + sum_{j < rj} g_x(ri, j)
-    int part = 0;
+    int part = 0, tot;
     for (int j = threadIdx.x; j < rj; j += IT_THREADS) part += gx_at(psi, valid, dkx, n, ri, j);
-    int tot;
     (void)block_exclusive_scan(part, &tot);
     __syncthreads();
     if (threadIdx.x == 0) st->kref = K0[ri] + tot;
 }
 
+// Loads of one chunk of a row: elements j0 .. j0+RP-1 of psi/valid/dk_x and
+// the pixel after them (psi/valid), for a thread of k_rows.
+template <int VEC>
+struct RowChunk {
+    static constexpr int RP = 8;
+    float ps[RP + 1];
+    uint8_t vd[RP + 1];
+    int8_t dk[RP];
+
+    __device__ __forceinline__ void load(const float *__restrict__ psi,
+                                         const uint8_t *__restrict__ valid,
+                                         const int8_t *__restrict__ dkx, int n, int64_t row,
+                                         int64_t drow, int j0) {
+        if (VEC == 4 && j0 + RP < n) {
+            // 16-byte loads; rows are 4-aligned when VEC == 4
+            const float4 a = *reinterpret_cast<const float4 *>(psi + row + j0);
+            const float4 b = *reinterpret_cast<const float4 *>(psi + row + j0 + 4);
+            ps[0] = a.x; ps[1] = a.y; ps[2] = a.z; ps[3] = a.w;
+            ps[4] = b.x; ps[5] = b.y; ps[6] = b.z; ps[7] = b.w;
+            ps[RP] = psi[row + j0 + RP];
+            if (valid) {
+                const uchar4 u = *reinterpret_cast<const uchar4 *>(valid + row + j0);
+                const uchar4 w = *reinterpret_cast<const uchar4 *>(valid + row + j0 + 4);
+                vd[0] = u.x; vd[1] = u.y; vd[2] = u.z; vd[3] = u.w;
+                vd[4] = w.x; vd[5] = w.y; vd[6] = w.z; vd[7] = w.w;
+                vd[RP] = valid[row + j0 + RP];
+            } else {
+#pragma unroll
+                for (int q = 0; q <= RP; ++q) vd[q] = 1;
+            }
+#pragma unroll
+            for (int q = 0; q < RP; ++q) dk[q] = dkx[drow + j0 + q];
+        } else {
+#pragma unroll
+            for (int q = 0; q <= RP; ++q) {
+                const int j = j0 + q;
+                ps[q] = j < n ? psi[row + j] : 0.f;
+                vd[q] = j < n ? (valid ? valid[row + j] : 1) : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < RP; ++q) dk[q] = (j0 + q < n - 1) ? dkx[drow + j0 + q] : (int8_t)0;
+        }
+    }
+};
+
+// One workgroup per row: K along the row is the carried value plus the
+// exclusive scan of the x-edge increments g = dk - w.  Chunks of
+// IT_THREADS * 8 pixels; the next chunk's loads are issued before the
+// current chunk is scanned.
+template <int VEC>
 __global__ __launch_bounds__(IT_THREADS) void k_rows(const float *__restrict__ psi,
                                                     const uint8_t *__restrict__ valid,
                                                     const int8_t *__restrict__ dkx, int m, int n,
@@ -124,57 +189,56 @@ __global__ __launch_bounds__(IT_THREADS) void k_rows(const float *__restrict__ p
                                                     const int *__restrict__ K0, float nodata,
                                                     int32_t *__restrict__ K,
                                                     float *__restrict__ phi) {
+    constexpr int RP = RowChunk<VEC>::RP;
+    constexpr int CH = IT_THREADS * RP;
     const int i = blockIdx.x;
-    const int64_t row = (int64_t)i * n;
+    const int64_t row = (int64_t)i * n, drow = (int64_t)i * (n - 1);
     int carry = K0[i] - st->kref;
-    for (int base = 0; base < n; base += IT_CHUNK) {
-        const int j0 = base + threadIdx.x * IT_PER;
-        float ps[IT_PER + 1];
-        uint8_t vd[IT_PER + 1];
-        int8_t dk[IT_PER];
-#pragma unroll
-        for (int q = 0; q <= IT_PER; ++q) {
-            const int j = j0 + q;
-            if (j < n) {
-                vd[q] = valid ? valid[row + j] : 1;
-                ps[q] = psi[row + j];
-            } else {
-                vd[q] = 0;
-                ps[q] = 0.f;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < IT_PER; ++q) {
-            const int j = j0 + q;
-            dk[q] = (j < n - 1) ? dkx[(int64_t)i * (n - 1) + j] : (int8_t)0;
-        }
-        int g[IT_PER];
+    RowChunk<VEC> cur, nxt;
+    cur.load(psi, valid, dkx, n, row, drow, threadIdx.x * RP);
+    for (int base = 0; base < n; base += CH) {
+        const int j0 = base + threadIdx.x * RP;
+        if (base + CH < n) nxt.load(psi, valid, dkx, n, row, drow, j0 + CH);
+        int g[RP];
         int local = 0;
 #pragma unroll
-        for (int q = 0; q < IT_PER; ++q) {
+        for (int q = 0; q < RP; ++q) {
             const int j = j0 + q;
             int v = 0;
             if (j < n - 1) {
-                const double a = vd[q] ? (double)ps[q] : 0.0;
-                const double b = vd[q + 1] ? (double)ps[q + 1] : 0.0;
-                v = (int)dk[q] - wrap_cycles(b - a);
+                const double a = cur.vd[q] ? (double)cur.ps[q] : 0.0;
+                const double b = cur.vd[q + 1] ? (double)cur.ps[q + 1] : 0.0;
+                v = (int)cur.dk[q] - wrap_cycles(b - a);
             }
             g[q] = v;
             local += v;
         }
         int tot;
-        int ex = block_exclusive_scan(local, &tot);
+        const int ex = block_exclusive_scan(local, &tot);
         int k = carry + ex;
+        int kk[RP];
+        float ph[RP];
 #pragma unroll
-        for (int q = 0; q < IT_PER; ++q) {
-            const int j = j0 + q;
-            if (j < n) {
-                K[row + j] = k;
-                phi[row + j] = vd[q] ? (float)((double)ps[q] + TWO_PI_D * (double)k) : nodata;
-            }
+        for (int q = 0; q < RP; ++q) {
+            kk[q] = k;
+            ph[q] = cur.vd[q] ? (float)((double)cur.ps[q] + TWO_PI_D * (double)k) : nodata;
             k += g[q];
         }
+        if (VEC == 4 && j0 + RP <= n) {
+            *reinterpret_cast<int4 *>(K + row + j0) = make_int4(kk[0], kk[1], kk[2], kk[3]);
+            *reinterpret_cast<int4 *>(K + row + j0 + 4) = make_int4(kk[4], kk[5], kk[6], kk[7]);
+            *reinterpret_cast<float4 *>(phi + row + j0) = make_float4(ph[0], ph[1], ph[2], ph[3]);
+            *reinterpret_cast<float4 *>(phi + row + j0 + 4) = make_float4(ph[4], ph[5], ph[6], ph[7]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                if (j0 + q < n) {
+                    K[row + j0 + q] = kk[q];
+                    phi[row + j0 + q] = ph[q];
+                }
+        }
         carry += tot;
+        cur = nxt;
     }
 }
 
@@ -199,8 +263,15 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
     hipLaunchKernelGGL(k_col0, dim3(1), dim3(IT_THREADS), 0, stream, psi, valid, dkx, dky, m, n,
                        cp.ref_i, cp.ref_j, st, K0);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rows, dim3(m), dim3(IT_THREADS), 0, stream, psi, valid, dkx, m, n, st, K0,
-                       cp.nodata, K, phi);
+    // 16-byte accesses need 4-aligned rows and base pointers
+    const bool vec = (n % 4 == 0) && (uintptr_t)psi % 16 == 0 && (uintptr_t)K % 16 == 0 &&
+                     (uintptr_t)phi % 16 == 0 && (!valid || (uintptr_t)valid % 4 == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_rows<4>, dim3(m), dim3(IT_THREADS), 0, stream, psi, valid, dkx, m, n,
+                           st, K0, cp.nodata, K, phi);
+    else
+        hipLaunchKernelGGL(k_rows<1>, dim3(m), dim3(IT_THREADS), 0, stream, psi, valid, dkx, m, n,
+                           st, K0, cp.nodata, K, phi);
     WW_LAUNCH_CHECK();
     // the host-side init struct must outlive the async copy
     WW_HIP(hipStreamSynchronize(stream));
