@@ -304,13 +304,16 @@ __device__ __forceinline__ void cand_push(CandBuf &b, int &cnt, int lane, bool h
 }
 
 // Slope bin floor((S + K P) NA / (2 K P)) clamped to [0, NA-1], P = PI_FIX,
-// for K >= 1 samples of sum S: a float estimate of the quotient (error far
-// below one) and one exact integer correction step.
+// for 1 <= K <= 81 samples of sum S (every sample lies in [-P, P), so
+// 0 <= u = S + K P < 2 K P < 2^30): a float estimate of u NA / (2 K P) from
+// the hardware reciprocal (relative error near 2^-22, far below one unit of
+// a quotient under 4096) and one exact integer correction step.
 __device__ __forceinline__ int slope_bin(int S, int K, int NA) {
-    const int64_t num = ((int64_t)S + (int64_t)K * PI_FIX) * NA;
-    const int64_t den = 2 * (int64_t)K * PI_FIX;
-    int t = (int)floorf(__fdividef((float)num, (float)den));
-    const int64_t e = num - (int64_t)t * den;
+    const int u = S + K * (int)PI_FIX;
+    const int den = 2 * K * (int)PI_FIX;
+    const float est = (float)u * ((float)NA * __builtin_amdgcn_rcpf((float)den));
+    int t = (int)floorf(est);
+    const int64_t e = (int64_t)u * NA - (int64_t)t * den;
     t += (e >= den) - (e < 0);
     return t < 0 ? 0 : (t > NA - 1 ? NA - 1 : t);
 }
