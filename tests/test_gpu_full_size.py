@@ -1,0 +1,114 @@
+"""Parity at the benchmark's own sizes, in the configuration bench.py times
+(one ww_unwrap on device-resident inputs).
+
+2048 x 2048 scene (ramp + bump, six low-coherence disks, 5 % nodata, L = 9):
+residues, cost planes, total cost, cycle differences on certified edges and
+K on certified pixels against the oracle, element by element.
+
+6912 x 10752 fault scene (74.3 Mpixel, L = 15, 3 % nodata): residues and the
+four cost planes byte-identical to the oracle's over the whole image; the
+GPU solve's own potentials certify optimality (reduced costs >= 0 and
+divergence = residues, checked by the oracle on the host); K is consistent
+with the GPU's cycle differences at every edge, phi within tolerance, and the
+total cost equals the oracle's stored optimum when it is present."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_36267_amd import binding as ww
+from paper_2609_36267_amd import synth
+from tests.helpers import (assert_same_on_certified_pixels, assert_same_on_fixed_edges, np_,
+                           phase_tolerance_ok)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "fault_6912x10752_L15_cost.json")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    ww.load()
+    return torch
+
+
+def wraps(psi, valid):
+    """Wrap counts of the x- and y-edges (double difference of the float32
+    phases, invalid pixels read as 0), as the paper's eq. 1 uses them."""
+    p = np.where(valid.astype(bool), psi.astype(np.float64), 0.0)
+    pi = np.float64(np.pi)
+    dx = p[:, 1:] - p[:, :-1]
+    dy = p[1:, :] - p[:-1, :]
+    w = lambda d: (d > pi).astype(np.int64) - (d <= -pi).astype(np.int64)  # noqa: E731
+    return w(dx), w(dy)
+
+
+def test_c1_full_size(torch_cuda):
+    torch = torch_cuda
+    sc = synth.config("c1")
+    m, n = sc.psi.shape
+    print(f"c1 {m}x{n}", flush=True)
+    out = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, want=True)
+    psi, coh, valid = (torch.from_numpy(a).cuda() for a in (sc.psi, sc.coh, sc.valid))
+    K, phi, tot = ww.unwrap(psi, coh, valid, sc.looks)
+    assert tot == out["total"]
+    res_g, _, g_g = ww.residues(psi, valid)
+    assert np.array_equal(np_(res_g), out["res"]) and g_g == out["ground"]
+    costs_g = ww.edge_costs(psi, coh, valid, ww.build_cost_lut(sc.looks))
+    for a, b in zip(costs_g, out["costs"]):
+        assert np.array_equal(np_(a), b)
+    r = ww.mcf_solve(out["res"], out["costs"], m, n, want_potentials=True)
+    assert r.total_cost == out["total"]
+    cert = oracle.check_optimal(out["res"], out["costs"], np_(r.dk_x), np_(r.dk_y), np_(r.potentials))
+    assert cert["ok"], cert
+    fx, fy = assert_same_on_fixed_edges(out["costs"], out["dkx"], out["dky"], out["pot"],
+                                        np_(r.dk_x), np_(r.dk_y))
+    share = assert_same_on_certified_pixels(np_(K), out["K"], fx, fy,
+                                            oracle.ref_index(sc.valid, m, n))
+    assert share > 0.5
+    ok, err = phase_tolerance_ok(np_(phi), sc.psi, np_(K), sc.valid)
+    assert ok, err
+
+
+def test_c2_full_size(torch_cuda):
+    torch = torch_cuda
+    sc = synth.config("c2")
+    m, n = sc.psi.shape
+    print(f"c2 {m}x{n}", flush=True)
+    psi, coh, valid = (torch.from_numpy(a).cuda() for a in (sc.psi, sc.coh, sc.valid))
+    # the timed configuration
+    K, phi, tot = ww.unwrap(psi, coh, valid, sc.looks)
+    K, phi = np_(K), np_(phi)
+    # residues and cost planes against the oracle, whole image
+    res_o, _, g_o = oracle.residues(sc.psi, sc.valid)
+    res_g, _, g_g = ww.residues(psi, valid)
+    assert np.array_equal(np_(res_g), res_o) and g_g == g_o
+    lut = oracle.build_lut(sc.looks)
+    assert np.array_equal(ww.build_cost_lut(sc.looks), lut)
+    costs_o = oracle.edge_costs(sc.psi, sc.coh, sc.valid, lut)
+    costs_g = [np_(c) for c in ww.edge_costs(psi, coh, valid, lut)]
+    del psi, coh, valid
+    for a, b in zip(costs_g, costs_o):
+        assert np.array_equal(a, b)
+    # the GPU optimum certified by its own potentials
+    r = ww.mcf_solve(res_o, costs_o, m, n, want_potentials=True)
+    assert r.total_cost == tot
+    dkx, dky = np_(r.dk_x), np_(r.dk_y)
+    cert = oracle.check_optimal(res_o, costs_o, dkx, dky, np_(r.potentials))
+    assert cert["ok"], cert
+    if os.path.exists(GOLDEN):
+        assert tot == json.load(open(GOLDEN))["total_cost"]
+    # K from ww_unwrap follows the same cycle differences at every edge
+    wx, wy = wraps(sc.psi, sc.valid)
+    Kl = K.astype(np.int64)
+    assert np.array_equal(Kl[:, 1:] - Kl[:, :-1], dkx.astype(np.int64) - wx)
+    assert np.array_equal(Kl[1:, :] - Kl[:-1, :], dky.astype(np.int64) - wy)
+    ref = oracle.ref_index(sc.valid, m, n)
+    assert K.reshape(-1)[ref] == 0
+    ok, err = phase_tolerance_ok(phi, sc.psi, K, sc.valid)
+    assert ok, err
