@@ -89,6 +89,26 @@ typedef struct {
     double solve_ms;         /* wall time of the whole solve                */
 } ww_mcf_stats;
 
+/* Schedule of the shortest-path windows of every pass of the min-cost-flow
+ * solve (Section II-C replaces Dial's unit buckets by windows; any
+ * increasing sequence of windows gives the same exact labels, so these only
+ * trade relaxation rounds against windows).
+ *   first_hop_window     hop limit of a pass's first, zero-distance window
+ *                        (1 .. 2^29-2; later zero-distance windows double)
+ *   first_distance_step  first increment of the distance bound (1 .. 2^30;
+ *                        later increments double)
+ * Process-wide; applies to solves that start after the call. */
+typedef struct {
+    int32_t first_hop_window;
+    int32_t first_distance_step;
+} ww_mcf_params;
+
+/* Defaults: first_hop_window 64, first_distance_step 256. */
+void ww_default_mcf_params(ww_mcf_params *p);
+/* Errors: WW_E_INVALID_ARG (NULL or out of range). */
+ww_status ww_set_mcf_params(const ww_mcf_params *p);
+void ww_get_mcf_params(ww_mcf_params *p);
+
 /* Counters of the most recent min-cost-flow solve made by this process
  * (through ww_mcf_solve or ww_unwrap).  Writes zeros before the first. */
 void ww_last_mcf_stats(ww_mcf_stats *out);

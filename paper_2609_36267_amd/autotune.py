@@ -1,0 +1,57 @@
+"""Autotuner for the window schedule of the min-cost-flow passes.
+
+Every increasing sequence of shortest-path windows yields the same exact
+labels and the same optimal flow (Section II-C's bucket order only decides
+which equal-cost optimum the paper's solver reaches first), so the schedule
+is a pure speed knob. Its best value depends on the scene: broad
+zero-distance plateaus favour few hop windows, long fault-crossing paths
+favour many. tune_schedule() times candidate schedules on sample jobs of a
+workload through the C ABI and installs the fastest process-wide (ties keep
+the earlier candidate, the default first).
+"""
+from __future__ import annotations
+
+import time
+
+from . import binding as ww
+
+# (first_hop_window, first_distance_step)
+CANDIDATES = [(64, 256), (16, 256), (512, 256), (64, 64), (16, 64), (512, 64), (64, 1024),
+              (16, 1024), (512, 1024)]
+
+
+def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
+    """jobs: list of (psi, coh, valid, looks) device tensors.  Times each
+    candidate on all jobs (sequential plain calls, or ww_unwrap_batch with
+    `slots` workers when slots > 0), keeps the fastest and returns
+    (best (h0, dstep0), {candidate: seconds}).  Costs must agree across
+    candidates (they are exact); a disagreement raises."""
+    import torch
+    cands = list(candidates or CANDIDATES)
+    old = ww.get_mcf_params()
+    timings, costs = {}, None
+    try:
+        for h0, ds in cands:
+            ww.set_mcf_params(h0, ds)
+            best = float("inf")
+            for _ in range(max(1, reps)):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                if slots > 0:
+                    res, _ = ww.unwrap_batch(jobs, slots=slots)
+                    got = [r[2] for r in res]
+                else:
+                    got = [ww.unwrap(*j[:3], j[3])[2] for j in jobs]
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t)
+            if costs is None:
+                costs = got
+            elif got != costs:
+                raise RuntimeError(f"schedule {(h0, ds)} changed an optimal cost: {got} vs {costs}")
+            timings[(h0, ds)] = best
+    except BaseException:
+        ww.set_mcf_params(old.first_hop_window, old.first_distance_step)
+        raise
+    choice = min(cands, key=lambda c: timings[c])
+    ww.set_mcf_params(*choice)
+    return choice, timings

@@ -26,7 +26,8 @@ _NAMES = {E_INVALID_ARG: "WW_E_INVALID_ARG", E_OOM: "WW_E_OOM", E_INFEASIBLE: "W
 EXPORTS = ["ww_last_error", "ww_version", "ww_last_mcf_stats", "ww_default_lut_params", "ww_default_cost_params",
            "ww_residues", "ww_build_cost_lut", "ww_edge_costs", "ww_mcf_solve", "ww_integrate",
            "ww_unwrap", "ww_clock", "ww_server_create", "ww_server_submit", "ww_server_poll",
-           "ww_server_in_flight", "ww_server_destroy", "ww_unwrap_batch"]
+           "ww_server_in_flight", "ww_server_destroy", "ww_unwrap_batch", "ww_default_mcf_params",
+           "ww_set_mcf_params", "ww_get_mcf_params"]
 
 
 class WWError(RuntimeError):
@@ -56,6 +57,30 @@ class McfStats(C.Structure):
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
                 for k, t in self._fields_}
+
+
+class McfParams(C.Structure):
+    """Window schedule of the shortest-path passes (ww_mcf_params)."""
+    _fields_ = [("first_hop_window", C.c_int32), ("first_distance_step", C.c_int32)]
+
+
+def get_mcf_params() -> McfParams:
+    p = McfParams()
+    load().ww_get_mcf_params(C.byref(p))
+    return p
+
+
+def set_mcf_params(first_hop_window=None, first_distance_step=None) -> McfParams:
+    """Set the process-wide window schedule (None keeps a field); returns the
+    previous schedule."""
+    old = get_mcf_params()
+    p = McfParams(old.first_hop_window, old.first_distance_step)
+    if first_hop_window is not None:
+        p.first_hop_window = int(first_hop_window)
+    if first_distance_step is not None:
+        p.first_distance_step = int(first_distance_step)
+    _check(load().ww_set_mcf_params(C.byref(p)))
+    return old
 
 
 def last_mcf_stats() -> dict:
@@ -108,6 +133,10 @@ def _declare(L):
     L.ww_server_destroy.restype = C.c_int32
     L.ww_unwrap_batch.argtypes = [P, I32, I32]
     L.ww_unwrap_batch.restype = C.c_int32
+    L.ww_default_mcf_params.argtypes = [P]
+    L.ww_get_mcf_params.argtypes = [P]
+    L.ww_set_mcf_params.argtypes = [P]
+    L.ww_set_mcf_params.restype = C.c_int32
 
 
 def _check(rc):

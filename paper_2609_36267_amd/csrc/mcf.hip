@@ -40,6 +40,7 @@
 #include <cstdlib>
 #include <string>
 #include <cstring>
+#include <atomic>
 #include <vector>
 
 #include "ww_internal.h"
@@ -975,9 +976,11 @@ __global__ void k_export_pot(const int *pot, const Ctl *ctl, long long N, int64_
 
 // ------------------------------------------------------------------ host ---
 
-constexpr unsigned int H0 = 64;        // hop limit of a pass's first window
-constexpr unsigned int DSTEP0 = 1024;  // first distance increment
 constexpr unsigned int HMAX = 0x1fffffffu;
+
+// window schedule (ww_set_mcf_params), read once per solve
+std::atomic<int> g_first_hops{64};
+std::atomic<int> g_first_dstep{256};
 
 static unsigned long long mk_label(unsigned int d, unsigned int h) {
     return ((unsigned long long)d << 32) | ((unsigned long long)h << 3) | 7ull;
@@ -1085,7 +1088,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     S.supplies = (long long)h->nsrc + std::max<long long>(h->gex, 0);
 
     const char *trace_env = getenv("WW_MCF_TRACE");
-    const bool trace = trace_env && trace_env[0] == '1';
+    const bool trace = trace_env && (trace_env[0] == '1' || trace_env[0] == '2');
     const char *check_env = getenv("WW_MCF_CHECK");
     const bool check = check_env && check_env[0] == '1';
     unsigned long long *lab_copy = nullptr;
@@ -1096,6 +1099,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         WW_HIP(hipHostMalloc(&hcrec, sizeof(CheckRec)));
     }
     const int rounds_per_sync = 4;
+    const unsigned int h0 = (unsigned int)g_first_hops.load(), dstep0 = (unsigned int)g_first_dstep.load();
+    const bool trace_windows = trace_env && trace_env[0] == '2';
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
     const unsigned int bound_cap = 0xffff0000u;
     unsigned int rr = 1, pass = 0;  // next round, current pass
@@ -1125,12 +1130,13 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         WW_LAUNCH_CHECK();
         // Windows in lexicographic (distance, hops) order: every label <= lb
         // is exact at the end of a window.  The first window admits only
-        // zero-distance labels within H0 hops; later windows jump to the
+        // zero-distance labels within h0 hops; later windows jump to the
         // smallest rejected candidate and grow the hop or distance limit.
-        unsigned long long lb = mk_label(0, H0);
-        unsigned int dstep = DSTEP0;
+        unsigned long long lb = mk_label(0, h0);
+        unsigned int dstep = dstep0;
         for (;;) {  // windows
             ++S.windows;
+            const long long rw0 = S.rounds;
             for (;;) {  // rounds
                 WW_HIP(hipEventRecord(ev[0], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
@@ -1154,6 +1160,10 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             hipLaunchKernelGGL(k_count_settled, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, lb);
             WW_LAUNCH_CHECK();
             WW_TRY(sync_ctl());
+            if (trace_windows)
+                fprintf(stderr, "[ww-mcf]   window %u/%u rounds %lld settled %u\n",
+                        (unsigned)(lb >> 32), (unsigned)((lb >> 3) & 0x1fffffffu), S.rounds - rw0,
+                        h->settled);
             const long long units = (long long)h->nsrc + std::max<long long>(h->gex, 0);
             const long long need = std::max<long long>(1, (units + 1) / 2);
             if ((long long)h->settled >= need) break;
@@ -1268,3 +1278,29 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
 }
 
 }  // namespace ww
+
+extern "C" {
+
+void ww_default_mcf_params(ww_mcf_params *p) {
+    if (!p) return;
+    p->first_hop_window = 64;
+    p->first_distance_step = 256;
+}
+
+ww_status ww_set_mcf_params(const ww_mcf_params *p) {
+    ww::clear_error();
+    if (!p || p->first_hop_window < 1 || p->first_hop_window > (int32_t)ww::HMAX - 1 ||
+        p->first_distance_step < 1 || p->first_distance_step > (1 << 30))
+        return ww::fail(WW_E_INVALID_ARG, "window schedule out of range");
+    ww::g_first_hops.store(p->first_hop_window);
+    ww::g_first_dstep.store(p->first_distance_step);
+    return WW_OK;
+}
+
+void ww_get_mcf_params(ww_mcf_params *p) {
+    if (!p) return;
+    p->first_hop_window = ww::g_first_hops.load();
+    p->first_distance_step = ww::g_first_dstep.load();
+}
+
+}  // extern "C"

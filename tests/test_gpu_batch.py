@@ -130,3 +130,34 @@ def test_bad_job_fails_alone(torch_cuda, scenes, plain):
     assert done[1].status == ww.E_INVALID_ARG and b"looks" in done[1].error
     assert done[0].status == 0 and done[0].total_cost == plain[0][2]
     assert good.tag == 0 and bad.tag == 1
+
+
+def test_window_schedule_keeps_the_optimum(torch_cuda, scenes, plain):
+    """Any window schedule reaches the same optimal cost, and K agrees with
+    the oracle wherever the optimum is unique; the autotuner installs one of
+    its candidates."""
+    from paper_2609_36267_amd import autotune
+    from tests.helpers import assert_same_on_certified_pixels, assert_same_on_fixed_edges
+    torch = torch_cuda
+    old = ww.get_mcf_params()
+    try:
+        for k in (0, 1, 3):
+            sc = scenes[k]
+            m, n = sc.psi.shape
+            out = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, want=True)
+            for h0, ds in ((1, 1), (16, 64), (1 << 28, 1 << 20)):
+                ww.set_mcf_params(h0, ds)
+                K, phi, tot = ww.unwrap(sc.psi, sc.coh, sc.valid, sc.looks)
+                assert tot == out["total"] == plain[k][2]
+                r = ww.mcf_solve(out["res"], out["costs"], m, n)
+                fx, fy = assert_same_on_fixed_edges(out["costs"], out["dkx"], out["dky"], out["pot"],
+                                                    r.dk_x.cpu().numpy(), r.dk_y.cpu().numpy())
+                assert_same_on_certified_pixels(K.cpu().numpy(), out["K"], fx, fy,
+                                                oracle.ref_index(sc.valid, m, n))
+        jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+                 torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes[:3]]
+        choice, table = autotune.tune_schedule(jobs, candidates=[(64, 256), (16, 64)])
+        p = ww.get_mcf_params()
+        assert choice in table and (p.first_hop_window, p.first_distance_step) == choice
+    finally:
+        ww.set_mcf_params(old.first_hop_window, old.first_distance_step)
