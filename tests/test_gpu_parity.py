@@ -65,6 +65,30 @@ def test_residues_parity(torch_cuda, shape):
         assert g_g == g_o
 
 
+@pytest.mark.parametrize("shape", [(40, 64), (33, 71)])  # 4-aligned rows and not
+def test_residues_parity_near_pi(torch_cuda, shape):
+    """Neighbour differences at and within float32 ulps of +-pi, out-of-range
+    and huge phases: the float decision's exact fallback must keep residues
+    identical to the oracle's double arithmetic."""
+    m, n = shape
+    rng = np.random.default_rng(m * 7 + n)
+    pf = np.float32(np.pi)
+    vals = np.array([pf, -pf, 0.0, np.nextafter(pf, np.float32(0)), np.nextafter(-pf, np.float32(0)),
+                     np.nextafter(pf, np.float32(4)), 1e-30, -1e-30, pf / 2, -pf / 2, 3.5, -3.5,
+                     1e30, -1e30, 7.0], np.float32)
+    psi = rng.choice(vals, size=(m, n)).astype(np.float32)
+    # long runs of near-pi steps so that whole waves take the float path or
+    # the fallback
+    psi[::3, :] = np.where(np.arange(n) % 2 == 0, pf, np.float32(0.0))[None, :]
+    psi[1::3, :] = np.where(np.arange(n) % 2 == 0, np.float32(0.5), np.float32(-0.5))[None, :]
+    valid = (rng.random((m, n)) > 0.1).astype(np.uint8)
+    for v in (valid, None):
+        res_g, perim_g, g_g = ww.residues(psi, v)
+        res_o, perim_o, g_o = oracle.residues(psi, v)
+        assert np.array_equal(np_(res_g), res_o)
+        assert np.array_equal(np_(perim_g), perim_o) and g_g == g_o
+
+
 def test_residues_parity_c0(torch_cuda, c0):
     res_g, perim_g, g_g = ww.residues(c0.psi, c0.valid)
     res_o, perim_o, g_o = oracle.residues(c0.psi, c0.valid)
