@@ -15,6 +15,8 @@ Parity status by function (the pins live in ``tests/test_oracle_*.py``):
   edge_costs       pinned (independent numpy recomputation, mirror, mask, cap)
   mcf              pinned (brute force, LP optimum, network simplex, certificate)
   integrate        pinned (path independence, congruence, exact recovery)
+  connected_components  pinned (graph connected components of a library
+                   routine, invariants, special cases)
 """
 from __future__ import annotations
 
@@ -91,6 +93,7 @@ def _declare(L):
     L.wwo_integrate.argtypes = [P, P, P, P, I32, I32, I32, I32, C.c_float, P, P]
     L.wwo_certified_pixels.argtypes = [I32, I32, P, P, I64, P, P]
     L.wwo_bruteforce.argtypes = [I32, I32, P, P, P, P, P, P, P, P]
+    L.wwo_connected_components.argtypes = [P, P, P, P, P, P, P, I32, I32, I32, I64, P, P]
 
 
 def _p(a):
@@ -333,3 +336,27 @@ def unwrap(psi, coh, valid, looks, lut=None, box_half=2, steep_rule=1, want=Fals
         return dict(res=res, perim=perim, ground=ground, costs=costs, dkx=dkx, dky=dky, pot=pot,
                     total=total, K=K, phi=phi, lut=lut)
     return K, phi, total
+
+
+def cc_min_size(valid, m, n, min_size_frac):
+    """Smallest labelled component: max(1, ceil(frac * valid pixels))."""
+    import math
+    nv = int(m) * int(n) if valid is None else int(np.count_nonzero(valid))
+    return max(1, int(math.ceil(float(min_size_frac) * nv)))
+
+
+def connected_components(dkx, dky, costs, valid, threshold=300, min_size_frac=0.001):
+    """Labels (uint32 [m, n]) of components of reliably unwrapped pixels and
+    their number (Section II-D)."""
+    dkx = _c(dkx, np.int8)
+    dky = _c(dky, np.int8)
+    cxp, cxn, cyp, cyn = [_c(c, np.int16) for c in costs]
+    m, n = dkx.shape[0], dky.shape[1]
+    valid = _c(valid, np.uint8)
+    labels = np.zeros((m, n), np.uint32)
+    nc = C.c_int64(0)
+    _chk(lib().wwo_connected_components(_p(dkx), _p(dky), _p(cxp), _p(cxn), _p(cyp), _p(cyn),
+                                        _p(valid), m, n, int(threshold),
+                                        C.c_int64(cc_min_size(valid, m, n, min_size_frac)),
+                                        _p(labels), C.byref(nc)), "connected_components")
+    return labels, int(nc.value)

@@ -1165,3 +1165,87 @@ int wwo_bruteforce(int m, int n, const int8_t *wxa, const int8_t *wya, const int
     *count = s.count;
     return s.count > 0 ? WWO_OK : WWO_E_INFEASIBLE;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Connected components of reliably unwrapped pixels (Section II-D)         */
+/* ------------------------------------------------------------------------ */
+
+/* An edge is reliable when both of its pixels are valid and changing its
+ * cycle difference dk by +1 or by -1 would each raise that edge's cost by
+ * more than `threshold`: with dk = 0 this means c+ > threshold and
+ * c- > threshold; with dk = +-1 one of the two changes would refund the
+ * edge's cost (never a rise), so such an edge is not reliable. */
+static int cc_reliable(int8_t dk, int16_t cp, int16_t cn, int threshold) {
+    return dk == 0 && cp > threshold && cn > threshold;
+}
+
+/* Grows components over reliable edges by breadth-first search from every
+ * not yet labelled valid pixel in row-major order, so components are
+ * discovered in the order of their first pixel.  Components with fewer than
+ * min_size pixels, and invalid pixels, get label 0; the others are numbered
+ * 1, 2, ... in discovery order.  labels uint32 [m*n]; *ncomp = number of
+ * labelled components.  valid NULL = all valid. */
+int wwo_connected_components(const int8_t *dk_x, const int8_t *dk_y, const int16_t *cxp,
+                             const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
+                             const uint8_t *valid, int m, int n, int threshold, int64_t min_size,
+                             uint32_t *labels, int64_t *ncomp) {
+    if (m < 1 || n < 1 || min_size < 1) return WWO_E_INVALID_ARG;
+    const int64_t N = (int64_t)m * n;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    int64_t *comp = (int64_t *)malloc(sizeof(int64_t) * (size_t)N); /* discovery index */
+    int64_t *size = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    if (!queue || !comp || !size) {
+        free(queue); free(comp); free(size);
+        return WWO_E_OOM;
+    }
+    for (int64_t p = 0; p < N; p++) comp[p] = -1;
+    int64_t ncomp_all = 0;
+    for (int64_t s = 0; s < N; s++) {
+        if (comp[s] >= 0 || (valid && !valid[s])) continue;
+        const int64_t c = ncomp_all++;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        comp[s] = c;
+        while (head < tail) {
+            const int64_t p = queue[head++];
+            const int i = (int)(p / n), j = (int)(p % n);
+            /* the four edges of pixel p and the pixel across each */
+            for (int d = 0; d < 4; d++) {
+                int64_t q, e;
+                int rel;
+                if (d == 0) {        /* right: hx(i, j) */
+                    if (j + 1 >= n) continue;
+                    q = p + 1;
+                    e = (int64_t)i * (n - 1) + j;
+                    rel = cc_reliable(dk_x[e], cxp[e], cxn[e], threshold);
+                } else if (d == 1) { /* left: hx(i, j-1) */
+                    if (j == 0) continue;
+                    q = p - 1;
+                    e = (int64_t)i * (n - 1) + j - 1;
+                    rel = cc_reliable(dk_x[e], cxp[e], cxn[e], threshold);
+                } else if (d == 2) { /* down: vy(i, j) */
+                    if (i + 1 >= m) continue;
+                    q = p + n;
+                    e = (int64_t)i * n + j;
+                    rel = cc_reliable(dk_y[e], cyp[e], cyn[e], threshold);
+                } else {             /* up: vy(i-1, j) */
+                    if (i == 0) continue;
+                    q = p - n;
+                    e = (int64_t)(i - 1) * n + j;
+                    rel = cc_reliable(dk_y[e], cyp[e], cyn[e], threshold);
+                }
+                if (!rel || comp[q] >= 0 || (valid && !valid[q])) continue;
+                comp[q] = c;
+                queue[tail++] = q;
+            }
+        }
+        size[c] = tail;
+    }
+    /* number the components that are large enough, in discovery order */
+    int64_t next = 0;
+    for (int64_t c = 0; c < ncomp_all; c++) size[c] = size[c] >= min_size ? ++next : 0;
+    for (int64_t p = 0; p < N; p++) labels[p] = comp[p] >= 0 ? (uint32_t)size[comp[p]] : 0u;
+    *ncomp = next;
+    free(queue); free(comp); free(size);
+    return WWO_OK;
+}
