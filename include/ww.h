@@ -204,6 +204,36 @@ ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, in
                     int32_t n, int32_t looks, const ww_cost_params *cp, int32_t *K, float *phi,
                     int64_t *total_cost_host, void *stream);
 
+/* Connected components of reliably unwrapped pixels (Section II-D).  An
+ * edge is reliable when both pixels are valid and changing its cycle
+ * difference by +1 or by -1 would each raise its cost by more than
+ * `threshold` cost units: dk = 0, c+ > threshold and c- > threshold (an
+ * edge with dk = +-1 could be changed back for a refund, so it is never
+ * reliable).  Components are grown over reliable edges; those with at
+ * least max(1, ceil(min_size_frac * valid pixels)) pixels are numbered
+ * 1, 2, ... in row-major order of their first pixel, all other pixels and
+ * every invalid pixel get 0.
+ *   threshold      >= 0, cost units of ww_edge_costs (default 300)
+ *   min_size_frac  in [0, 1] (default 0.001)                            */
+typedef struct {
+    int32_t threshold;
+    double min_size_frac;
+} ww_cc_params;
+
+void ww_default_cc_params(ww_cc_params *p);
+
+/*   dk_x, dk_y     the cycle differences of ww_mcf_solve.
+ *   cx_*, cy_*     the cost planes of ww_edge_costs.
+ *   valid          uint8 [m*n], NULL = all valid.
+ *   labels         uint32 [m*n] out.
+ *   ncomp_host     int64 out: number of labelled components (synchronises).
+ * Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
+ww_status ww_connected_components(const int8_t *dk_x, const int8_t *dk_y, const int16_t *cx_pos,
+                                  const int16_t *cx_neg, const int16_t *cy_pos,
+                                  const int16_t *cy_neg, const uint8_t *valid, int32_t m,
+                                  int32_t n, const ww_cc_params *p, uint32_t *labels,
+                                  int64_t *ncomp_host, void *stream);
+
 /* ---------------------------------------------------------------------
  * Many interferograms: a job server and a batch call.
  *

@@ -27,7 +27,8 @@ EXPORTS = ["ww_last_error", "ww_version", "ww_last_mcf_stats", "ww_default_lut_p
            "ww_residues", "ww_build_cost_lut", "ww_edge_costs", "ww_mcf_solve", "ww_integrate",
            "ww_unwrap", "ww_clock", "ww_server_create", "ww_server_submit", "ww_server_poll",
            "ww_server_in_flight", "ww_server_destroy", "ww_unwrap_batch", "ww_default_mcf_params",
-           "ww_set_mcf_params", "ww_get_mcf_params"]
+           "ww_set_mcf_params", "ww_get_mcf_params", "ww_default_cc_params",
+           "ww_connected_components"]
 
 
 class WWError(RuntimeError):
@@ -57,6 +58,37 @@ class McfStats(C.Structure):
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
                 for k, t in self._fields_}
+
+
+class CcParams(C.Structure):
+    """Reliability threshold and minimum component size (ww_cc_params)."""
+    _fields_ = [("threshold", C.c_int32), ("min_size_frac", C.c_double)]
+
+
+def default_cc_params(**kw) -> CcParams:
+    p = CcParams()
+    load().ww_default_cc_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def connected_components(dkx, dky, costs, valid, params: CcParams | None = None):
+    """(labels uint32 [m, n] device tensor, number of labelled components)."""
+    torch = _torch()
+    dkx = _dev(dkx, torch.int8)
+    dky = _dev(dky, torch.int8)
+    cxp, cxn, cyp, cyn = [_dev(c, torch.int16) for c in costs]
+    valid = _dev(valid, torch.uint8)
+    m, n = dkx.shape[0], dky.shape[1]
+    labels = torch.empty((m, n), dtype=torch.int32, device="cuda")  # uint32 bits
+    nc = C.c_int64(0)
+    p = params or default_cc_params()
+    nz = lambda t: _ptr(t) if (t is not None and t.numel()) else None  # noqa: E731
+    _check(load().ww_connected_components(nz(dkx), nz(dky), nz(cxp), nz(cxn), nz(cyp), nz(cyn),
+                                          _ptr(valid), m, n, C.byref(p), _ptr(labels),
+                                          C.byref(nc), _stream()))
+    return labels, int(nc.value)
 
 
 class McfParams(C.Structure):
@@ -137,6 +169,9 @@ def _declare(L):
     L.ww_get_mcf_params.argtypes = [P]
     L.ww_set_mcf_params.argtypes = [P]
     L.ww_set_mcf_params.restype = C.c_int32
+    L.ww_default_cc_params.argtypes = [P]
+    L.ww_connected_components.argtypes = [P, P, P, P, P, P, P, I32, I32, P, P, P, P]
+    L.ww_connected_components.restype = C.c_int32
 
 
 def _check(rc):

@@ -372,6 +372,32 @@ ww_status ww_integrate(const float *psi, const uint8_t *valid, const int8_t *dk_
     return integrate_impl(psi, valid, dk_x, dk_y, m, n, cp, K, phi, (hipStream_t)stream);
 }
 
+void ww_default_cc_params(ww_cc_params *p) {
+    if (!p) return;
+    p->threshold = 300;
+    p->min_size_frac = 0.001;
+}
+
+ww_status ww_connected_components(const int8_t *dk_x, const int8_t *dk_y, const int16_t *cx_pos,
+                                  const int16_t *cx_neg, const int16_t *cy_pos,
+                                  const int16_t *cy_neg, const uint8_t *valid, int32_t m,
+                                  int32_t n, const ww_cc_params *pin, uint32_t *labels,
+                                  int64_t *ncomp_host, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    ww_cc_params p;
+    if (pin) p = *pin;
+    else ww_default_cc_params(&p);
+    if (p.threshold < 0 || !(p.min_size_frac >= 0.0 && p.min_size_frac <= 1.0))
+        return fail(WW_E_INVALID_ARG, "threshold must be >= 0 and min_size_frac in [0, 1]");
+    if (!labels || !ncomp_host || (n > 1 && (!dk_x || !cx_pos || !cx_neg)) ||
+        (m > 1 && (!dk_y || !cy_pos || !cy_neg)))
+        return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    return components_impl(dk_x, dk_y, cx_pos, cx_neg, cy_pos, cy_neg, valid, m, n, p.threshold,
+                           p.min_size_frac, labels, ncomp_host, (hipStream_t)stream);
+}
+
 ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
                     int32_t n, int32_t looks, const ww_cost_params *cpin, int32_t *K, float *phi,
                     int64_t *total_cost_host, void *stream) {

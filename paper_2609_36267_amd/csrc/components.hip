@@ -1,0 +1,269 @@
+// Connected components of reliably unwrapped pixels (Section II-D).
+//
+// An edge is reliable when both pixels are valid, its cycle difference is 0
+// and changing it by +1 or -1 would each raise its cost by more than the
+// threshold (c+ > T and c- > T); a corrected edge (dk = +-1) could be
+// changed back for a refund, so it is never reliable.  Components over the
+// reliable edges are found by union-find rounds on the device:
+//
+//   k_cc_hook  every reliable edge links the roots of its two pixels: the
+//              larger root index is lowered to the smaller by atomicMin;
+//   k_cc_jump  full path compression: every pixel points at its root.
+//
+// Pointers only ever decrease, so every root ends as the smallest pixel
+// index of its component, whatever the order of the atomics; the rounds
+// repeat until a hook round changes nothing.  Sizes are counted with
+// wave-aggregated atomics; components with at least min_size pixels are
+// numbered 1, 2, ... in row-major order of their smallest pixel by a
+// two-level scan, all others and invalid pixels get 0.
+#include <cmath>
+
+#include "ww_internal.h"
+
+namespace ww {
+
+namespace {
+
+constexpr uint32_t CC_NONE = 0xffffffffu;  // invalid pixel
+constexpr int CC_THREADS = 256;
+constexpr int CC_PER = 16;                 // pixels per thread in the scan kernels
+constexpr int CC_CHUNK = CC_THREADS * CC_PER;
+
+struct CcState {
+    unsigned int changed;
+    unsigned int pad;
+    unsigned long long nvalid;
+    unsigned long long ncomp;
+};
+
+__device__ __forceinline__ bool cc_reliable(int8_t dk, int16_t cp, int16_t cn, int T) {
+    return dk == 0 && cp > T && cn > T;
+}
+
+__device__ __forceinline__ uint32_t cc_find(const uint32_t *L, uint32_t x) {
+    // pointers decrease along every chain, so the walk ends at a root
+    uint32_t y = L[x];
+    while (y != x) {
+        x = y;
+        y = L[x];
+    }
+    return x;
+}
+
+__global__ void k_cc_init(const uint8_t *__restrict__ valid, int64_t N, uint32_t *__restrict__ L,
+                          CcState *st) {
+    unsigned long long nv = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const bool v = !valid || valid[p];
+        L[p] = v ? (uint32_t)p : CC_NONE;
+        nv += v;
+    }
+    for (int off = 32; off > 0; off >>= 1) nv += __shfl_down(nv, off, 64);
+    if ((threadIdx.x & 63) == 0 && nv) atomicAdd(&st->nvalid, nv);
+}
+
+__global__ void k_cc_hook(const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
+                          const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
+                          const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn, int m,
+                          int n, int T, uint32_t *L, CcState *st) {
+    const int64_t N = (int64_t)m * n;
+    int changed = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (L[p] == CC_NONE) continue;
+        const int i = (int)(p / n), j = (int)(p % n);
+        for (int d = 0; d < 2; ++d) {
+            int64_t q, e;
+            bool rel;
+            if (d == 0) {  // right: hx(i, j)
+                if (j + 1 >= n) continue;
+                q = p + 1;
+                e = (int64_t)i * (n - 1) + j;
+                rel = cc_reliable(dkx[e], cxp[e], cxn[e], T);
+            } else {  // down: vy(i, j)
+                if (i + 1 >= m) continue;
+                q = p + n;
+                e = p;
+                rel = cc_reliable(dky[e], cyp[e], cyn[e], T);
+            }
+            if (!rel || L[q] == CC_NONE) continue;
+            const uint32_t a = cc_find(L, (uint32_t)p), b = cc_find(L, (uint32_t)q);
+            if (a != b) {
+                atomicMin(&L[a > b ? a : b], a > b ? b : a);
+                changed = 1;
+            }
+        }
+    }
+    if (__any(changed) && (threadIdx.x & 63) == 0) st->changed = 1;
+}
+
+__global__ void k_cc_jump(int64_t N, uint32_t *L) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t l = L[p];
+        if (l == CC_NONE || l == (uint32_t)p) continue;
+        L[p] = cc_find(L, l);
+    }
+}
+
+// Component sizes at the roots: lanes of a wave holding the same root add
+// their count with one atomic.
+__global__ void k_cc_size(const uint32_t *__restrict__ L, int64_t N, uint32_t *S) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = base + threadIdx.x;
+        uint32_t l = p < N ? L[p] : CC_NONE;
+        bool todo = l != CC_NONE;
+        for (;;) {
+            const unsigned long long pending = __ballot(todo);
+            if (!pending) break;
+            const int leader = __ffsll((long long)pending) - 1;
+            const uint32_t root = __shfl(l, leader, 64);
+            const unsigned long long same = __ballot(todo && l == root);
+            if (lane == leader) atomicAdd(&S[root], (uint32_t)__popcll(same));
+            if (todo && l == root) todo = false;
+        }
+    }
+}
+
+// qualifying roots: L[p] == p and size >= min_size
+__device__ __forceinline__ int cc_flag(const uint32_t *L, const uint32_t *S, int64_t p, int64_t N,
+                                       uint32_t min_size) {
+    return p < N && L[p] == (uint32_t)p && S[p] >= min_size;
+}
+
+__device__ int cc_block_scan(int v, int *total) {
+    __shared__ int wsum[CC_THREADS / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < CC_THREADS / 64; ++w) {
+        if (w < wid) before += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+// per chunk of CC_CHUNK pixels: number of qualifying roots
+__global__ __launch_bounds__(CC_THREADS) void k_cc_count(const uint32_t *__restrict__ L,
+                                                         const uint32_t *__restrict__ S, int64_t N,
+                                                         uint32_t min_size, uint32_t *chunk_sum) {
+    const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
+    int c = 0;
+    for (int k = 0; k < CC_PER; ++k) c += cc_flag(L, S, p0 + k, N, min_size);
+    int tot;
+    (void)cc_block_scan(c, &tot);
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = (uint32_t)tot;
+}
+
+// exclusive scan of the chunk sums (one workgroup) and the total
+__global__ __launch_bounds__(CC_THREADS) void k_cc_scan(uint32_t *chunk_sum, int nchunks,
+                                                        CcState *st) {
+    unsigned long long carry = 0;
+    for (int base = 0; base < nchunks; base += CC_THREADS) {
+        const int k = base + threadIdx.x;
+        const int v = k < nchunks ? (int)chunk_sum[k] : 0;
+        int tot;
+        const int ex = cc_block_scan(v, &tot);
+        if (k < nchunks) chunk_sum[k] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) st->ncomp = carry;
+}
+
+// every root gets its label (rank + 1, or 0 when too small) in S
+__global__ __launch_bounds__(CC_THREADS) void k_cc_rank(const uint32_t *__restrict__ L, uint32_t *S,
+                                                        int64_t N, uint32_t min_size,
+                                                        const uint32_t *__restrict__ chunk_off) {
+    const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
+    int f[CC_PER];
+    int c = 0;
+    for (int k = 0; k < CC_PER; ++k) {
+        f[k] = cc_flag(L, S, p0 + k, N, min_size);
+        c += f[k];
+    }
+    int tot;
+    uint32_t r = chunk_off[blockIdx.x] + (uint32_t)cc_block_scan(c, &tot);
+    for (int k = 0; k < CC_PER; ++k) {
+        const int64_t p = p0 + k;
+        if (p < N && L[p] == (uint32_t)p) {
+            // roots are written only by the thread that owns them
+            S[p] = f[k] ? ++r : 0u;
+        }
+    }
+}
+
+__global__ void k_cc_label(const uint32_t *__restrict__ L, const uint32_t *__restrict__ S,
+                           int64_t N, uint32_t *__restrict__ labels) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t l = L[p];
+        labels[p] = l == CC_NONE ? 0u : S[l];
+    }
+}
+
+}  // namespace
+
+ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *cxp,
+                          const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
+                          const uint8_t *valid, int m, int n, int threshold, double min_size_frac,
+                          uint32_t *labels, int64_t *ncomp, hipStream_t st) {
+    const int64_t N = (int64_t)m * n;
+    uint32_t *L = nullptr, *S = nullptr, *chunk = nullptr;
+    CcState *cs = nullptr, *hcs = nullptr;
+    const int nchunks = (int)((N + CC_CHUNK - 1) / CC_CHUNK);
+    WW_TRY(scratch(SLOT_CC_LABEL, sizeof(uint32_t) * (size_t)N, (void **)&L));
+    WW_TRY(scratch(SLOT_CC_SIZE, sizeof(uint32_t) * (size_t)N, (void **)&S));
+    char *small = nullptr;
+    WW_TRY(scratch(SLOT_CC_SMALL, 256 + sizeof(uint32_t) * (size_t)nchunks, (void **)&small));
+    cs = (CcState *)small;
+    chunk = (uint32_t *)(small + 256);
+    WW_TRY(host_scratch(sizeof(CcState), (void **)&hcs));
+    const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (N + 255) / 256));
+    WW_HIP(hipMemsetAsync(cs, 0, sizeof(CcState), st));
+    WW_HIP(hipMemsetAsync(S, 0, sizeof(uint32_t) * (size_t)N, st));
+    hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(256), 0, st, valid, N, L, cs);
+    WW_LAUNCH_CHECK();
+    // union-find rounds until a hook round changes nothing (each round that
+    // changes something merges at least two components, so at most N rounds)
+    for (int64_t round = 0;; ++round) {
+        if (round > N + 1) return fail(WW_E_DEVICE, "connected components did not converge");
+        WW_HIP(hipMemsetAsync(&cs->changed, 0, sizeof(unsigned int), st));
+        hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn,
+                           m, n, threshold, L, cs);
+        WW_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(256), 0, st, N, L);
+        WW_LAUNCH_CHECK();
+        WW_HIP(hipMemcpyAsync(hcs, cs, sizeof(CcState), hipMemcpyDeviceToHost, st));
+        WW_HIP(hipStreamSynchronize(st));
+        if (!hcs->changed) break;
+    }
+    const double want = std::ceil(min_size_frac * (double)hcs->nvalid);
+    const uint32_t min_size = want < 1.0 ? 1u : (want > 4294967295.0 ? 0xffffffffu : (uint32_t)want);
+    hipLaunchKernelGGL(k_cc_size, dim3(grid), dim3(256), 0, st, L, N, S);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_count, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, min_size, chunk);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_scan, dim3(1), dim3(CC_THREADS), 0, st, chunk, nchunks, cs);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_rank, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, min_size, chunk);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_label, dim3(grid), dim3(256), 0, st, L, S, N, labels);
+    WW_LAUNCH_CHECK();
+    WW_HIP(hipMemcpyAsync(hcs, cs, sizeof(CcState), hipMemcpyDeviceToHost, st));
+    WW_HIP(hipStreamSynchronize(st));
+    *ncomp = (int64_t)hcs->ncomp;
+    return WW_OK;
+}
+
+}  // namespace ww

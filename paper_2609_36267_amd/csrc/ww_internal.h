@@ -74,7 +74,7 @@ enum Slot {
     SLOT_COUNTERS, SLOT_STEEP, SLOT_STEEP_KEYS,
     SLOT_MCF_LAB, SLOT_MCF_POT, SLOT_MCF_EX, SLOT_MCF_BEST, SLOT_MCF_TILES,
     SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_MCF_PART, SLOT_INTEG,
-    SLOT_LUT_WORK,
+    SLOT_LUT_WORK, SLOT_CC_LABEL, SLOT_CC_SIZE, SLOT_CC_SMALL,
     SLOT_COUNT
 };
 
@@ -115,6 +115,10 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
                          const int8_t *dky, int m, int n, const ww_cost_params &cp, int32_t *K,
                          float *phi, hipStream_t stream);
 ww_status build_lut_impl(int looks, const ww_lut_params &p, int16_t *lut_dev, hipStream_t stream);
+ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *cxp,
+                          const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
+                          const uint8_t *valid, int m, int n, int threshold, double min_size_frac,
+                          uint32_t *labels, int64_t *ncomp, hipStream_t stream);
 
 ww_mcf_stats &last_mcf_stats();  // of the current workspace
 

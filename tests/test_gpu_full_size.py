@@ -10,7 +10,8 @@ four cost planes byte-identical to the oracle's over the whole image; the
 GPU solve's own potentials certify optimality (reduced costs >= 0 and
 divergence = residues, checked by the oracle on the host); K is consistent
 with the GPU's cycle differences at every edge, phi within tolerance, and the
-total cost equals the oracle's stored optimum when it is present."""
+total cost equals the oracle's stored optimum when it is present; connected
+components over the oracle's cost planes equal the oracle's labels."""
 import json
 import os
 
@@ -112,3 +113,12 @@ def test_c2_full_size(torch_cuda):
     assert K.reshape(-1)[ref] == 0
     ok, err = phase_tolerance_ok(phi, sc.psi, K, sc.valid)
     assert ok, err
+    # connected components at full size: the oracle's cost planes with a
+    # seeded pattern of corrections (no input from the GPU side)
+    rng = np.random.default_rng(5)
+    dkx_s = np.where(rng.random(costs_o[0].shape) < 0.02, 1, 0).astype(np.int8)
+    dky_s = np.where(rng.random(costs_o[2].shape) < 0.02, -1, 0).astype(np.int8)
+    lab_o, nc_o = oracle.connected_components(dkx_s, dky_s, costs_o, sc.valid)
+    lab_g, nc_g = ww.connected_components(dkx_s, dky_s, costs_o, sc.valid)
+    assert nc_g == nc_o and nc_o > 0
+    assert np.array_equal(np_(lab_g).view(np.uint32), lab_o)
