@@ -599,9 +599,10 @@ __global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsi
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&ctl->settled, c);
+    // a settled ground absorbs all of its deficit units
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
-        if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->settled, 1u);
+        if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->settled, (unsigned int)(-ctl->gex));
     }
 }
 
