@@ -86,7 +86,8 @@ def _declare(L):
     L.wwo_sigma_alpha.argtypes = [D, I32, I32]
     L.wwo_sigma_alpha.restype = D
     L.wwo_build_lut.argtypes = [I32, P, P, P, P, P]
-    L.wwo_edge_costs.argtypes = [P, P, P, I32, I32, P, I32, I32, I32, I32, D, I32, P, P, P, P, P]
+    L.wwo_edge_costs.argtypes = [P, P, P, I32, I32, P, I32, I32, I32, I32, D, I32, I32, P, P, P, P, P]
+    L.wwo_lut_pair.argtypes = [P, I32, I32, I64, I64, D, I32, P, P]
     L.wwo_mcf.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P, P]
     L.wwo_check_optimal.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P]
     L.wwo_fixed_edges.argtypes = [I32, I32, P, P, P, P, P, P, P, P, P]
@@ -201,7 +202,7 @@ def build_lut(L, params=None, want_probs=False):
 # ------------------------------------------------------------------- costs ---
 
 def edge_costs(psi, coh, valid, lut, box_half=2, steep_rule=1, steep_thresh=1.0, steep_cap_pct=3,
-               want_stats=False):
+               want_stats=False, interp=0):
     psi = _c(psi, np.float32)
     coh = _c(coh, np.float32)
     valid = _c(valid, np.uint8)
@@ -214,12 +215,24 @@ def edge_costs(psi, coh, valid, lut, box_half=2, steep_rule=1, steep_thresh=1.0,
     cyn = np.zeros_like(cyp)
     st = np.zeros(3, np.int64)
     _chk(lib().wwo_edge_costs(_p(psi), _p(coh), _p(valid), m, n, _p(lut), na, ng, box_half,
-                              steep_rule, float(steep_thresh), steep_cap_pct,
+                              steep_rule, float(steep_thresh), steep_cap_pct, int(interp),
                               _p(cxp), _p(cxn), _p(cyp), _p(cyn), _p(st)), "edge_costs")
     out = (cxp, cxn, cyp, cyn)
     if want_stats:
         return out, dict(valid_edges=int(st[0]), steep_candidates=int(st[1]), steep_zeroed=int(st[2]))
     return out
+
+
+def lut_pair(lut, S, K, g, interp=1):
+    """(c+, c-) of one edge from the table: slope sum S (2^-20 rad fixed point)
+    over K valid samples, edge coherence g (Section II-B lookup, nearest bin
+    when interp is 0, bilinear between bin centres otherwise)."""
+    lut = _c(lut, np.int16)
+    ng, na = lut.shape
+    cp, cn = C.c_int16(0), C.c_int16(0)
+    lib().wwo_lut_pair(_p(lut), na, ng, int(S), int(K), float(g), int(interp),
+                       C.byref(cp), C.byref(cn))
+    return int(cp.value), int(cn.value)
 
 
 # --------------------------------------------------------------------- MCF ---
@@ -324,12 +337,13 @@ def bruteforce(wx, wy, costs):
 
 # ------------------------------------------------------------ whole path ----
 
-def unwrap(psi, coh, valid, looks, lut=None, box_half=2, steep_rule=1, want=False):
+def unwrap(psi, coh, valid, looks, lut=None, box_half=2, steep_rule=1, want=False, interp=0):
     """Residues -> LUT -> costs -> SSP -> integration, all on the CPU."""
     if lut is None:
         lut = build_lut(looks)
     res, perim, ground = residues(psi, valid)
-    costs = edge_costs(psi, coh, valid, lut, box_half=box_half, steep_rule=steep_rule)
+    costs = edge_costs(psi, coh, valid, lut, box_half=box_half, steep_rule=steep_rule,
+                       interp=interp)
     dkx, dky, pot, total = mcf(res, costs, m=psi.shape[0], n=psi.shape[1])
     K, phi = integrate(psi, valid, dkx, dky)
     if want:

@@ -455,6 +455,49 @@ static double coh_eff(const float *coh, int64_t k) {
     return c;
 }
 
+/* The cost pair (c+, c-) of an edge from the table T[N_gamma][N_alpha].
+ * The slope position of the box mean is s = (S + K P) N_alpha / (2 K P)
+ * (bin b spans [b, b+1)); the coherence position is g N_gamma.
+ * interp == 0 (nearest bin, Section II-B read as the table's own bins):
+ *   c+ = T[floor(g N_gamma)][floor(s)], c- = T[..][N_alpha - 1 - floor(s)].
+ * interp == 1 (the table interpolated at run time, Section II-B): positions
+ *   relative to the bin centres, t = s - 1/2 and u = g N_gamma - 1/2, in
+ *   2^-16 fixed point (t16 = floor(s 2^16) - 2^15, likewise u16), split into
+ *   a cell index and a fraction, clamped to the outermost centres; the
+ *   bilinear blend of the four surrounding entries is rounded down.  c-
+ *   uses the mirrored position (N_alpha - 1) 2^16 - t16. */
+static int16_t lut_blend(const int16_t *T, int NA, int NG, int64_t t16, int64_t u16) {
+    int64_t ia = t16 >> 16, fa = t16 - (ia << 16);
+    int64_t ig = u16 >> 16, fg = u16 - (ig << 16);
+    if (ia < 0) { ia = 0; fa = 0; }
+    if (ia >= NA - 1) { ia = NA - 1; fa = 0; }
+    if (ig < 0) { ig = 0; fg = 0; }
+    if (ig >= NG - 1) { ig = NG - 1; fg = 0; }
+    const int64_t ib = ia + 1 < NA ? ia + 1 : ia, jg = ig + 1 < NG ? ig + 1 : ig;
+    const int64_t r0 = (int64_t)T[ig * NA + ia] * (65536 - fa) + (int64_t)T[ig * NA + ib] * fa;
+    const int64_t r1 = (int64_t)T[jg * NA + ia] * (65536 - fa) + (int64_t)T[jg * NA + ib] * fa;
+    return (int16_t)((r0 * (65536 - fg) + r1 * fg) >> 32);
+}
+
+void wwo_lut_pair(const int16_t *T, int NA, int NG, int64_t S, int64_t K, double g, int interp,
+                  int16_t *cp, int16_t *cn) {
+    const int64_t num = (S + K * PFIX) * NA, den = 2 * K * PFIX;
+    if (!interp) {
+        int64_t ba = num / den;
+        if (ba < 0) ba = 0;
+        if (ba > NA - 1) ba = NA - 1;
+        int64_t bg = (int64_t)floor(g * NG);
+        if (bg > NG - 1) bg = NG - 1;
+        *cp = T[bg * NA + ba];
+        *cn = T[bg * NA + (NA - 1 - ba)];
+        return;
+    }
+    const int64_t t16 = (num * 65536) / den - 32768;
+    const int64_t u16 = (int64_t)floor(g * NG * 65536.0) - 32768;
+    *cp = lut_blend(T, NA, NG, t16, u16);
+    *cn = lut_blend(T, NA, NG, (int64_t)(NA - 1) * 65536 - t16, u16);
+}
+
 /* Edge costs c+ (the arc that raises the edge's cycle difference by one) and
  * c- (lowers it): c+ = T[bg][ba], c- = T[bg][N_alpha-1-ba].  ba is the bin of
  * the box-filtered (side 2h+1, clipped, valid samples only) wrapped gradient in
@@ -462,12 +505,13 @@ static double coh_eff(const float *coh, int64_t k) {
  * invalid endpoint cost 0.  Steep rule: valid edges with |d| > thresh get cost
  * 0, at most floor(cap_pct * valid_edges / 100) of them, largest |d| first,
  * ties by edge id (x-edges row-major, then y-edges row-major).
+ * interp selects the table lookup of wwo_lut_pair.
  * stats (nullable): [0]=valid edges, [1]=steep candidates, [2]=zeroed.
  * Pinned by mirror symmetry, mask, steep count and an independent numpy
  * recomputation. */
 int wwo_edge_costs(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
                    const int16_t *T, int n_alpha, int n_gamma, int box_half,
-                   int steep_rule, double steep_thresh, int steep_cap_pct,
+                   int steep_rule, double steep_thresh, int steep_cap_pct, int interp,
                    int16_t *cxp, int16_t *cxn, int16_t *cyp, int16_t *cyn, int64_t *stats) {
     if (m < 1 || n < 1 || box_half < 0) return WWO_E_INVALID_ARG;
     int64_t nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
@@ -518,15 +562,9 @@ int wwo_edge_costs(const float *psi, const float *coh, const uint8_t *valid, int
                     cnt++;
                 }
             }
-            int64_t ba = ((S + cnt * PFIX) * n_alpha) / (2 * cnt * PFIX);
-            if (ba < 0) ba = 0;
-            if (ba > n_alpha - 1) ba = n_alpha - 1;
             int64_t a = (int64_t)i * n + j;
             double g = fmin(coh_eff(coh, a), coh_eff(coh, a + 1));
-            int64_t bg = (int64_t)floor(g * n_gamma);
-            if (bg > n_gamma - 1) bg = n_gamma - 1;
-            cxp[e] = T[bg * n_alpha + ba];
-            cxn[e] = T[bg * n_alpha + (n_alpha - 1 - ba)];
+            wwo_lut_pair(T, n_alpha, n_gamma, S, cnt, g, interp, &cxp[e], &cxn[e]);
         }
     /* y-edges: array (m-1) x n */
     for (int i = 0; i + 1 < m; i++)
@@ -544,15 +582,9 @@ int wwo_edge_costs(const float *psi, const float *coh, const uint8_t *valid, int
                     cnt++;
                 }
             }
-            int64_t ba = ((S + cnt * PFIX) * n_alpha) / (2 * cnt * PFIX);
-            if (ba < 0) ba = 0;
-            if (ba > n_alpha - 1) ba = n_alpha - 1;
             int64_t a = (int64_t)i * n + j;
             double g = fmin(coh_eff(coh, a), coh_eff(coh, a + n));
-            int64_t bg = (int64_t)floor(g * n_gamma);
-            if (bg > n_gamma - 1) bg = n_gamma - 1;
-            cyp[e] = T[bg * n_alpha + ba];
-            cyn[e] = T[bg * n_alpha + (n_alpha - 1 - ba)];
+            wwo_lut_pair(T, n_alpha, n_gamma, S, cnt, g, interp, &cyp[e], &cyn[e]);
         }
     /* steep-gradient rule */
     int64_t nvalid = 0, ncand = 0, nzero = 0;

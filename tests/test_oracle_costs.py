@@ -157,3 +157,114 @@ def test_reverse_arc_uses_mirrored_slope(lut9):
     assert cxp[8, 8] == lut9[bg, b]
     assert cxn[8, 8] == lut9[bg, NA - 1 - b]
     assert cxp[8, 8] < cxn[8, 8]  # slope towards +pi: a +1 correction is cheaper
+
+
+# ------------------------------------------------- interpolated table lookup --
+
+def _interp_costs(psi, coh, valid, T, h=2):
+    """Edge costs with the table interpolated at run time, recomputed in
+    float64 with scipy's linear grid interpolator over the bin centres
+    (positions clamped to the outermost centres, the result rounded down)."""
+    from scipy.interpolate import RegularGridInterpolator
+    NG, NA = T.shape
+    F = RegularGridInterpolator((np.arange(NG) + 0.5, np.arange(NA) + 0.5), T.astype(np.float64))
+    p = psi.astype(np.float64).copy()
+    v = np.ones(psi.shape, bool) if valid is None else valid.astype(bool)
+    p[~v] = 0.0
+    c = coh.astype(np.float64)
+    c = np.where(np.isnan(c) | (c < 0), 0.0, np.minimum(c, 1.0))
+    out = []
+    for axis in (1, 0):
+        if axis == 1:
+            diff, ve, g = p[:, 1:] - p[:, :-1], v[:, 1:] & v[:, :-1], np.minimum(c[:, 1:], c[:, :-1])
+        else:
+            diff, ve, g = p[1:, :] - p[:-1, :], v[1:, :] & v[:-1, :], np.minimum(c[1:, :], c[:-1, :])
+        w = (diff > PI_D).astype(int) - (diff <= -PI_D).astype(int)
+        q = np.floor((diff - 2 * PI_D * w) * 2.0 ** 20).astype(np.int64)
+        S = _box(np.where(ve, q, 0), h)
+        cnt = np.maximum(_box(ve.astype(np.int64), h), 1)
+        s = (S + cnt * PFIX) * NA / (2.0 * cnt * PFIX)
+        gp = np.clip(g * NG, 0.5, NG - 0.5)
+        for pos in (s, NA - s):
+            val = F(np.stack([gp.ravel(), np.clip(pos, 0.5, NA - 0.5).ravel()], 1)).reshape(s.shape)
+            out.append(np.where(ve, np.floor(val), 0).astype(np.int64))
+    return out
+
+
+def test_interp_at_bin_centres_is_the_table(lut9):
+    """With K = N_alpha samples and S = ((2b+1) - N_alpha) P the slope position
+    is exactly the centre of bin b; a power-of-two N_gamma puts g = (k+1/2)/N_gamma
+    on a coherence centre: the interpolated pair is then the table's entries."""
+    NG, NA = lut9.shape
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        b, k = int(rng.integers(NA)), int(rng.integers(NG))
+        S = ((2 * b + 1) - NA) * PFIX
+        g = (k + 0.5) / NG
+        cp, cn = oracle.lut_pair(lut9, S, NA, g, interp=1)
+        assert (cp, cn) == (int(lut9[k, b]), int(lut9[k, NA - 1 - b]))
+        assert oracle.lut_pair(lut9, S, NA, g, interp=0) == (cp, cn)
+
+
+def test_interp_lies_between_neighbours(lut9):
+    """Halfway between two slope centres the blend is the floor of their
+    mean; anywhere it stays within the four surrounding entries."""
+    NG, NA = lut9.shape
+    k = NG // 2
+    g = (k + 0.5) / NG
+    for b in range(NA - 1):
+        S = (2 * (b + 1) - NA) * PFIX  # s = b + 1: the edge between bins b and b+1
+        cp, _ = oracle.lut_pair(lut9, S, NA, g, interp=1)
+        assert cp == (int(lut9[k, b]) + int(lut9[k, b + 1])) // 2
+    rng = np.random.default_rng(4)
+    for _ in range(500):
+        K = int(rng.integers(1, 26))
+        S = int(rng.integers(-K * PFIX, K * PFIX))
+        g = float(rng.random())
+        cp, cn = oracle.lut_pair(lut9, S, K, g, interp=1)
+        assert lut9.min() <= cp <= lut9.max() and lut9.min() <= cn <= lut9.max()
+
+
+@pytest.mark.parametrize("h", [0, 2])
+def test_interp_costs_match_float_interpolation(h, lut9):
+    """The fixed-point blend agrees with float64 bilinear interpolation over
+    the bin centres within one cost unit at every edge (masked edges are 0
+    on both sides), and differs from the nearest-bin lookup somewhere."""
+    rng = np.random.default_rng(20 + h)
+    m, n = 33, 41
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    coh = rng.uniform(-0.1, 1.1, (m, n)).astype(np.float32)
+    valid = (rng.random((m, n)) > 0.1).astype(np.uint8)
+    got = oracle.edge_costs(psi, coh, valid, lut9, box_half=h, steep_rule=0, interp=1)
+    want = _interp_costs(psi, coh, valid, lut9, h=h)
+    near = oracle.edge_costs(psi, coh, valid, lut9, box_half=h, steep_rule=0, interp=0)
+    for g, w in zip(got, want):
+        assert np.abs(g.astype(np.int64) - w).max() <= 1
+    assert any(not np.array_equal(g, nb) for g, nb in zip(got, near))
+
+
+def test_interp_keeps_steep_and_mask_rules(lut9):
+    """The steep-gradient and mask rules act on the same edges whichever
+    lookup is used."""
+    rng = np.random.default_rng(11)
+    m, n = 40, 50
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    coh = np.full((m, n), 0.9, np.float32)
+    valid = (rng.random((m, n)) > 0.1).astype(np.uint8)
+    vx = (valid[:, 1:] & valid[:, :-1]).astype(bool)
+    vy = (valid[1:, :] & valid[:-1, :]).astype(bool)
+    runs = []
+    for interp in (0, 1):
+        full, st = oracle.edge_costs(psi, coh, valid, lut9, want_stats=True, interp=interp)
+        free = oracle.edge_costs(psi, coh, valid, lut9, steep_rule=0, interp=interp)
+        for c, ve in zip(free, (vx, vx, vy, vy)):
+            assert np.all(c[~ve] == 0)
+        runs.append((full, free, st))
+    assert runs[0][2] == runs[1][2] and runs[0][2]["steep_zeroed"] > 0
+    # one set of edges zeroed by the steep rule, the same for both lookups
+    hit = [(a != b) | (c != d) for a, b, c, d in zip(runs[0][0], runs[0][1], runs[1][0], runs[1][1])]
+    # (each zeroed edge clears both of its arcs)
+    assert 0 < sum(int((x | y).sum()) for x, y in (hit[0:2], hit[2:4])) <= runs[0][2]["steep_zeroed"]
+    for full, free, _ in runs:
+        for f, c, x in zip(full, free, hit):
+            assert np.array_equal(f, np.where(x, 0, c))
