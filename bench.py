@@ -37,7 +37,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash only (see round_kernel_sha).
 TRAFFIC_SOURCE_SHA = "710003f3884eb60b"
-TRAFFIC_BYTES_PER_LAUNCH = 33.09e6
+TRAFFIC_BYTES_PER_LAUNCH = 8.37e6
 
 
 def round_kernel_sha() -> str:

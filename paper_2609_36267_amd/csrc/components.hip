@@ -12,8 +12,9 @@
 //
 // Pointers only ever decrease, so every root ends as the smallest pixel
 // index of its component, whatever the order of the atomics; the rounds
-// repeat until a hook round changes nothing.  Sizes are counted with
-// wave-aggregated atomics; components with at least min_size pixels are
+// repeat until a hook round changes nothing.  Sizes are counted per wave and
+// per workgroup before the global atomics; components with at least
+// min_size pixels are
 // numbered 1, 2, ... in row-major order of their smallest pixel by a
 // two-level scan, all others and invalid pixels get 0.
 #include <cmath>
@@ -107,14 +108,28 @@ __global__ void k_cc_jump(int64_t N, uint32_t *L) {
     }
 }
 
-// Component sizes at the roots: lanes of a wave holding the same root add
-// their count with one atomic.
-__global__ void k_cc_size(const uint32_t *__restrict__ L, int64_t N, uint32_t *S) {
+// Component sizes at the roots.  Lanes of a wave holding the same root are
+// counted together (ballot), the wave's leader adds the count into a small
+// per-workgroup table in LDS (open addressing on the root index), and the
+// table is flushed to the global counters once at the end; a root that
+// finds no free slot is added to its global counter directly.
+constexpr int CC_SLOTS = 128;
+constexpr int CC_PROBES = 8;
+
+__global__ __launch_bounds__(256) void k_cc_size(const uint32_t *__restrict__ L, int64_t N,
+                                                 uint32_t *S) {
+    __shared__ uint32_t keys[CC_SLOTS];
+    __shared__ uint32_t cnts[CC_SLOTS];
+    for (int t = threadIdx.x; t < CC_SLOTS; t += blockDim.x) {
+        keys[t] = CC_NONE;
+        cnts[t] = 0;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N;
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p = base + threadIdx.x;
-        uint32_t l = p < N ? L[p] : CC_NONE;
+        const uint32_t l = p < N ? L[p] : CC_NONE;
         bool todo = l != CC_NONE;
         for (;;) {
             const unsigned long long pending = __ballot(todo);
@@ -122,10 +137,27 @@ __global__ void k_cc_size(const uint32_t *__restrict__ L, int64_t N, uint32_t *S
             const int leader = __ffsll((long long)pending) - 1;
             const uint32_t root = __shfl(l, leader, 64);
             const unsigned long long same = __ballot(todo && l == root);
-            if (lane == leader) atomicAdd(&S[root], (uint32_t)__popcll(same));
+            if (lane == leader) {
+                const uint32_t c = (uint32_t)__popcll(same);
+                uint32_t slot = (root * 2654435761u) % CC_SLOTS;
+                bool done = false;
+                for (int probe = 0; probe < CC_PROBES && !done; ++probe) {
+                    const uint32_t k = atomicCAS(&keys[slot], CC_NONE, root);
+                    if (k == CC_NONE || k == root) {
+                        atomicAdd(&cnts[slot], c);
+                        done = true;
+                    } else {
+                        slot = (slot + 1) % CC_SLOTS;
+                    }
+                }
+                if (!done) atomicAdd(&S[root], c);
+            }
             if (todo && l == root) todo = false;
         }
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < CC_SLOTS; t += blockDim.x)
+        if (keys[t] != CC_NONE) atomicAdd(&S[keys[t]], cnts[t]);
 }
 
 // qualifying roots: L[p] == p and size >= min_size
