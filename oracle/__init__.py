@@ -17,6 +17,9 @@ Parity status by function (the pins live in ``tests/test_oracle_*.py``):
   integrate        pinned (path independence, congruence, exact recovery)
   connected_components  pinned (graph connected components of a library
                    routine, invariants, special cases)
+  goldstein        pinned (identity at alpha = 0, plane waves on the DFT grid,
+                   explicit DFT sums on tiny patches, conjugation symmetry)
+  transfer_ambiguity  pinned (congruence, nearest value, brute force)
 """
 from __future__ import annotations
 
@@ -374,3 +377,94 @@ def connected_components(dkx, dky, costs, valid, threshold=300, min_size_frac=0.
                                         C.c_int64(cc_min_size(valid, m, n, min_size_frac)),
                                         _p(labels), C.byref(nc)), "connected_components")
     return labels, int(nc.value)
+
+
+# ------------------------------------------------ Goldstein preprocessing ---
+
+def triangle_taper(N):
+    """Patch taper w(i) = 1 - |2i + 1 - N| / N, i = 0..N-1: positive, and two
+    copies offset by N/2 sum to 1."""
+    i = np.arange(N, dtype=np.float64)
+    return 1.0 - np.abs(2.0 * i + 1.0 - N) / N
+
+
+def goldstein(psi, valid=None, alpha=0.5, patch=32, smooth=3, want_sum=False):
+    """Adaptive power-spectrum ("Goldstein") filter of the wrapped phase, the
+    optional preprocessing of Section II-D, in float64.
+
+    Unit phasors exp(i psi) at valid pixels, 0 elsewhere and outside the
+    image.  Patches of N x N pixels (N = patch) sit on a grid of step N/2
+    whose first patch starts N/2 rows above and N/2 columns left of the
+    image, so that every pixel lies in four patches.  For each patch: the
+    2-D DFT Z; B = the circular smooth x smooth mean of |Z|; Z is multiplied
+    by H = (B / max B)^alpha (an all-zero patch contributes nothing); the
+    inverse DFT is tapered by w(r) w(c) (triangle_taper) and added to the
+    sum.  The filtered phase is the argument of the sum at valid pixels;
+    invalid pixels keep psi.  Returns float32 [m, n] (and the complex sum
+    when want_sum)."""
+    psi = np.asarray(psi, np.float32)
+    m, n = psi.shape
+    v = np.ones((m, n), bool) if valid is None else np.asarray(valid).astype(bool)
+    N = int(patch)
+    S = N // 2
+    z = np.where(v, np.exp(1j * psi.astype(np.float64)), 0.0)
+    w = triangle_taper(N)
+    w2 = np.outer(w, w)
+    h = smooth // 2
+    acc = np.zeros((m, n), np.complex128)
+    for pi in range((m + S - 1) // S + 1):
+        for pj in range((n + S - 1) // S + 1):
+            r0, c0 = pi * S - S, pj * S - S
+            blk = np.zeros((N, N), np.complex128)
+            ra, rb = max(r0, 0), min(r0 + N, m)
+            ca, cb = max(c0, 0), min(c0 + N, n)
+            if ra >= rb or ca >= cb:
+                continue
+            blk[ra - r0:rb - r0, ca - c0:cb - c0] = z[ra:rb, ca:cb]
+            Z = np.fft.fft2(blk)
+            A = np.abs(Z)
+            B = np.zeros_like(A)
+            for du in range(-h, h + 1):
+                for dv in range(-h, h + 1):
+                    B += np.roll(np.roll(A, du, axis=0), dv, axis=1)
+            B /= float(smooth * smooth)
+            mx = B.max()
+            if not mx > 0.0:
+                continue
+            H = (B / mx) ** float(alpha)
+            zf = np.fft.ifft2(Z * H) * w2
+            acc[ra:rb, ca:cb] += zf[ra - r0:rb - r0, ca - c0:cb - c0]
+    out = np.where(v, np.arctan2(acc.imag, acc.real), psi.astype(np.float64)).astype(np.float32)
+    if want_sum:
+        return out, acc
+    return out
+
+
+def transfer_ambiguity(psi, valid, psi_f, K_f, nodata=float("nan")):
+    """Cycle counts on the original phase from those found on a filtered
+    copy (Section II-D: the modified phase only estimates K).  At a valid
+    pixel K = K_f + k with k the integer that puts psi + 2 pi K within
+    (-pi, pi] of psi_f + 2 pi K_f, i.e. k = -wrap(psi - psi_f), wrap(x) =
+    [x > pi] - [x <= -pi] in float64; elsewhere K = K_f.  phi = float32 of
+    psi + 2 pi K (float64) at valid pixels, nodata elsewhere."""
+    psi = np.asarray(psi, np.float32).astype(np.float64)
+    psi_f = np.asarray(psi_f, np.float32).astype(np.float64)
+    K_f = np.asarray(K_f, np.int64)
+    v = np.ones(psi.shape, bool) if valid is None else np.asarray(valid).astype(bool)
+    x = psi - psi_f
+    wrap = (x > np.pi).astype(np.int64) - (x <= -np.pi).astype(np.int64)
+    K = np.where(v, K_f - wrap, K_f).astype(np.int32)
+    phi = np.where(v, psi + 2.0 * np.pi * K.astype(np.float64), nodata).astype(np.float32)
+    return K, phi
+
+
+def unwrap_filtered(psi, coh, valid, looks, alpha=0.5, patch=32, smooth=3, lut=None, want=False):
+    """Goldstein-filtered phase -> the whole path -> cycle counts moved back
+    onto the original phase (Section II-D)."""
+    psi_f = goldstein(psi, valid, alpha=alpha, patch=patch, smooth=smooth)
+    out = unwrap(psi_f, coh, valid, looks, lut=lut, want=True)
+    K, phi = transfer_ambiguity(psi, valid, psi_f, out["K"])
+    if want:
+        out.update(psi_f=psi_f, K_f=out["K"], K=K, phi=phi)
+        return out
+    return K, phi, out["total"]
