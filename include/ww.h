@@ -65,7 +65,15 @@ typedef struct {
  *   steep_rule    1: edges with |wrapped gradient| > steep_thresh_rad cost 0,
  *                 at most floor(steep_cap_pct * valid_edges / 100) of them
  *   ref_i, ref_j  pixel with K = 0 (-1: first valid pixel, row-major)
- *   nodata        phi written at invalid pixels                           */
+ *   nodata        phi written at invalid pixels
+ *   lut_interp    0 (default): nearest table bin; 1: the table interpolated
+ *                 at run time (Section II-B), bilinear between bin centres:
+ *                 slope position t16 = floor((S+K P) n_alpha 2^16/(2 K P)) - 2^15,
+ *                 coherence position u16 = floor(g n_gamma 2^16) - 2^15 (FP64),
+ *                 each split into a cell and a 16-bit fraction and clamped to
+ *                 the outermost centres; the int64 blend of the four entries
+ *                 is shifted right by 32; the reverse arc uses
+ *                 (n_alpha-1) 2^16 - t16.                                 */
 typedef struct {
     int32_t box_half;
     int32_t steep_rule;
@@ -73,6 +81,7 @@ typedef struct {
     int32_t steep_cap_pct;
     int32_t ref_i, ref_j;
     float nodata;
+    int32_t lut_interp;
 } ww_cost_params;
 
 /* Solver counters (all optional outputs). */
@@ -149,6 +158,7 @@ ww_status ww_build_cost_lut(int32_t looks, const ww_lut_params *p, int16_t *lut_
  *                  gradient (fixed point 2^-20 rad, clipped window, samples
  *                  with two valid endpoints), bg = bin of min(coh_u, coh_v);
  *   cx_neg/cy_neg  the reverse correction: T[bg][n_alpha-1-ba];
+ *   (with cp->lut_interp = 1 both are the interpolated lookups instead)
  * 0 for edges with an invalid endpoint and for the steep edges.
  *   psi, coh  float32 [m*n]; coh is clamped to [0,1], NaN read as 0.
  *   valid     uint8 [m*n], NULL = all valid.

@@ -46,7 +46,8 @@ class LutParams(C.Structure):
 class CostParams(C.Structure):
     _fields_ = [("box_half", C.c_int32), ("steep_rule", C.c_int32),
                 ("steep_thresh_rad", C.c_double), ("steep_cap_pct", C.c_int32),
-                ("ref_i", C.c_int32), ("ref_j", C.c_int32), ("nodata", C.c_float)]
+                ("ref_i", C.c_int32), ("ref_j", C.c_int32), ("nodata", C.c_float),
+                ("lut_interp", C.c_int32)]
 
 
 class McfStats(C.Structure):

@@ -153,6 +153,8 @@ ww_status check_cost_params(const ww_cost_params &p) {
         return fail(WW_E_INVALID_ARG, "box_half must lie in [0, 16]");
     if (p.steep_cap_pct < 0 || p.steep_cap_pct > 100 || !(p.steep_thresh_rad >= 0.0))
         return fail(WW_E_INVALID_ARG, "steep-rule parameters out of range");
+    if (p.lut_interp != 0 && p.lut_interp != 1)
+        return fail(WW_E_INVALID_ARG, "lut_interp must be 0 or 1");
     return WW_OK;
 }
 
@@ -282,6 +284,7 @@ void ww_default_cost_params(ww_cost_params *p) {
     p->ref_i = -1;
     p->ref_j = -1;
     p->nodata = std::nanf("");
+    p->lut_interp = 0;
 }
 
 ww_status ww_residues(const float *psi, const uint8_t *valid, int32_t m, int32_t n, int8_t *res,

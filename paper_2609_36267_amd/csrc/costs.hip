@@ -45,10 +45,55 @@ __device__ __forceinline__ int coh_bin(float c, int NG) {
     return b > NG - 1 ? NG - 1 : b;
 }
 
+// Interpolated lookup (Section II-B, the table read between its entries):
+// positions relative to the bin centres in 2^-16 bin units, a cell index and
+// a 16-bit fraction per axis, clamped to the outermost centres, and the
+// bilinear blend of the four surrounding entries rounded down.
+__device__ __forceinline__ int64_t coh_pos16(float c, int NG) {
+    double g = (double)c;
+    if (!(g > 0.0)) g = 0.0;
+    if (g > 1.0) g = 1.0;
+    return (int64_t)floor(g * (double)NG * 65536.0) - 32768;
+}
+
+template <typename TP>
+__device__ __forceinline__ int16_t lut_blend(TP T, int NA, int NG, int64_t t16, int64_t u16) {
+    int64_t ia = t16 >> 16, ig = u16 >> 16;
+    int64_t fa = t16 - (ia << 16), fg = u16 - (ig << 16);
+    if (ia < 0) { ia = 0; fa = 0; }
+    if (ia >= NA - 1) { ia = NA - 1; fa = 0; }
+    if (ig < 0) { ig = 0; fg = 0; }
+    if (ig >= NG - 1) { ig = NG - 1; fg = 0; }
+    const int a0 = (int)ia, a1 = a0 + 1 < NA ? a0 + 1 : a0;
+    const int g0 = (int)ig * NA, g1 = ((int)ig + 1 < NG ? (int)ig + 1 : (int)ig) * NA;
+    const int64_t r0 = (int64_t)T[g0 + a0] * (65536 - fa) + (int64_t)T[g0 + a1] * fa;
+    const int64_t r1 = (int64_t)T[g1 + a0] * (65536 - fa) + (int64_t)T[g1 + a1] * fa;
+    return (int16_t)((r0 * (65536 - fg) + r1 * fg) >> 32);
+}
+
+// Table lookup of the tile kernel: num / den is the slope position
+// (S + K P) NA / (2 K P) with num >= 0 for phases in [-pi, pi].
+__device__ __forceinline__ void tile_lookup(const int16_t *__restrict__ lut, int NA, int NG,
+                                            int64_t num, int64_t den, float g, int interp,
+                                            int16_t &cp, int16_t &cn) {
+    if (interp) {
+        const int64_t t16 = (num * 65536) / den - 32768;
+        const int64_t u16 = coh_pos16(g, NG);
+        cp = lut_blend(lut, NA, NG, t16, u16);
+        cn = lut_blend(lut, NA, NG, (int64_t)(NA - 1) * 65536 - t16, u16);
+        return;
+    }
+    int ba = (int)floor((double)num / (double)den);
+    ba = ba < 0 ? 0 : (ba > NA - 1 ? NA - 1 : ba);
+    const int bg = coh_bin(g, NG);
+    cp = lut[bg * NA + ba];
+    cn = lut[bg * NA + (NA - 1 - ba)];
+}
+
 __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
     const float *__restrict__ psi, const float *__restrict__ coh, const uint8_t *__restrict__ valid,
     int m, int n, const int16_t *__restrict__ lut, int NA, int NG, int h, double steep_thresh,
-    int steep_on, int16_t *__restrict__ cxp, int16_t *__restrict__ cxn, int16_t *__restrict__ cyp,
+    int steep_on, int interp, int16_t *__restrict__ cxp, int16_t *__restrict__ cxn, int16_t *__restrict__ cyp,
     int16_t *__restrict__ cyn, unsigned long long *__restrict__ cand_key,
     unsigned int *__restrict__ cand_id, SteepState *__restrict__ st) {
     extern __shared__ unsigned char smem[];
@@ -161,15 +206,11 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
                 ++nvalid;
                 const int64_t num = (S1 + (int64_t)K1 * PI_FIX) * NA;
                 const int64_t den = 2 * (int64_t)K1 * PI_FIX;
-                int ba = (int)floor((double)num / (double)den);
-                ba = ba < 0 ? 0 : (ba > NA - 1 ? NA - 1 : ba);
                 const int64_t a = (int64_t)i * n + j;
                 float c0 = coh[a], c1 = coh[a + 1];
                 c0 = (c0 != c0) ? 0.f : c0;  // NaN reads as 0 (fminf would drop it)
                 c1 = (c1 != c1) ? 0.f : c1;
-                const int bg = coh_bin(fminf(c0, c1), NG);
-                cp = lut[bg * NA + ba];
-                cn = lut[bg * NA + (NA - 1 - ba)];
+                tile_lookup(lut, NA, NG, num, den, fminf(c0, c1), interp, cp, cn);
                 const int p = (r + h) * PC + (c + h);
                 double diff = (double)ph[p + 1] - (double)ph[p];
                 double dd = fabs(diff - TWO_PI_D * wrap_cycles(diff));
@@ -190,15 +231,11 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
                 ++nvalid;
                 const int64_t num = (S2 + (int64_t)K2 * PI_FIX) * NA;
                 const int64_t den = 2 * (int64_t)K2 * PI_FIX;
-                int ba = (int)floor((double)num / (double)den);
-                ba = ba < 0 ? 0 : (ba > NA - 1 ? NA - 1 : ba);
                 const int64_t a = (int64_t)i * n + j;
                 float c0 = coh[a], c1 = coh[a + n];
                 c0 = (c0 != c0) ? 0.f : c0;
                 c1 = (c1 != c1) ? 0.f : c1;
-                const int bg = coh_bin(fminf(c0, c1), NG);
-                cp = lut[bg * NA + ba];
-                cn = lut[bg * NA + (NA - 1 - ba)];
+                tile_lookup(lut, NA, NG, num, den, fminf(c0, c1), interp, cp, cn);
                 const int p = (r + h) * PC + (c + h);
                 double diff = (double)ph[p + PC] - (double)ph[p];
                 double dd = fabs(diff - TWO_PI_D * wrap_cycles(diff));
@@ -318,7 +355,42 @@ __device__ __forceinline__ int slope_bin(int S, int K, int NA) {
     return t < 0 ? 0 : (t > NA - 1 ? NA - 1 : t);
 }
 
-template <int H>
+// Slope position of the interpolated lookup, floor((S + K P) NA 2^16 /
+// (2 K P)) - 2^15: the quotient q and remainder e of u NA / (2 K P) as in
+// slope_bin (unclamped), then floor(e 2^16 / (2 K P)) < 2^16 by the same
+// float estimate and exact correction.
+__device__ __forceinline__ int64_t slope_pos16(int S, int K, int NA) {
+    const int u = S + K * (int)PI_FIX;
+    const int den = 2 * K * (int)PI_FIX;
+    const float rden = __builtin_amdgcn_rcpf((float)den);
+    int q = (int)floorf((float)u * ((float)NA * rden));
+    int64_t e = (int64_t)u * NA - (int64_t)q * den;
+    const int c = (e >= den) - (e < 0);
+    q += c;
+    e -= (int64_t)c * den;
+    int f = (int)floorf((float)e * (65536.f * rden));
+    const int64_t e2 = e * 65536 - (int64_t)f * den;
+    f += (e2 >= den) - (e2 < 0);
+    return (int64_t)q * 65536 + f - 32768;
+}
+
+template <bool INTERP>
+__device__ __forceinline__ void stream_lookup(const int16_t *slut, int NA, int NG, int S, int K,
+                                              float g, int16_t &cp, int16_t &cn) {
+    if constexpr (INTERP) {
+        const int64_t t16 = slope_pos16(S, K, NA);
+        const int64_t u16 = coh_pos16(g, NG);
+        cp = lut_blend(slut, NA, NG, t16, u16);
+        cn = lut_blend(slut, NA, NG, (int64_t)(NA - 1) * 65536 - t16, u16);
+    } else {
+        const int ba = slope_bin(S, K, NA);
+        const int bg = coh_bin(g, NG);
+        cp = slut[bg * NA + ba];
+        cn = slut[bg * NA + (NA - 1 - ba)];
+    }
+}
+
+template <int H, bool INTERP>
 __global__ __launch_bounds__(64 * CS_WAVES) void k_edge_costs_stream(
     const float *__restrict__ psi, const float *__restrict__ coh, const uint8_t *__restrict__ valid,
     int m, int n, const int16_t *__restrict__ lut, int NA, int NG, double steep_thresh,
@@ -469,13 +541,10 @@ __global__ __launch_bounds__(64 * CS_WAVES) void k_edge_costs_stream(
                         S += hxs[k];
                         K += hxk[k];
                     }
-                    const int ba = slope_bin(S, K, NA);
                     float c0 = ch[H], c1 = c_right;
                     c0 = (c0 != c0) ? 0.f : c0;  // NaN reads as 0 (fminf would drop it)
                     c1 = (c1 != c1) ? 0.f : c1;
-                    const int bg = coh_bin(fminf(c0, c1), NG);
-                    cp = slut[bg * NA + ba];
-                    cn = slut[bg * NA + (NA - 1 - ba)];
+                    stream_lookup<INTERP>(slut, NA, NG, S, K, fminf(c0, c1), cp, cn);
                     const double dd = fabs(dx[H]);
                     if (steep_on && dd > steep_thresh) {
                         has = true;
@@ -505,13 +574,10 @@ __global__ __launch_bounds__(64 * CS_WAVES) void k_edge_costs_stream(
                         S += hys[k];
                         K += hyk[k];
                     }
-                    const int ba = slope_bin(S, K, NA);
                     float c0 = ch[H + 1], c1 = ch[H];  // coh(r, j), coh(r+1, j)
                     c0 = (c0 != c0) ? 0.f : c0;
                     c1 = (c1 != c1) ? 0.f : c1;
-                    const int bg = coh_bin(fminf(c0, c1), NG);
-                    cp = slut[bg * NA + ba];
-                    cn = slut[bg * NA + (NA - 1 - ba)];
+                    stream_lookup<INTERP>(slut, NA, NG, S, K, fminf(c0, c1), cp, cn);
                     const double dd = fabs(dy[H]);
                     if (steep_on && dd > steep_thresh) {
                         has = true;
@@ -647,17 +713,24 @@ ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *val
         const int nstrips = ceil_div(n, OW), nsegs = ceil_div(m, CS_ROWS);
         const int nwaves = nstrips * nsegs;
         const dim3 grid(ceil_div(nwaves, CS_WAVES));
-#define WW_STREAM(HH)                                                                          \
-    hipLaunchKernelGGL(k_edge_costs_stream<HH>, grid, dim3(64 * CS_WAVES), 0, stream, psi, coh, \
-                       valid, m, n, lut, NA, NG, cp.steep_thresh_rad, steep_on, cxp, cxn, cyp,  \
-                       cyn, keys, ids, st, nstrips, nwaves)
-        switch (h) {
-            case 0: WW_STREAM(0); break;
-            case 1: WW_STREAM(1); break;
-            case 2: WW_STREAM(2); break;
-            case 3: WW_STREAM(3); break;
-            default: WW_STREAM(4); break;
+#define WW_STREAM(HH, IP)                                                                   \
+    hipLaunchKernelGGL((k_edge_costs_stream<HH, IP>), grid, dim3(64 * CS_WAVES), 0, stream, psi, \
+                       coh, valid, m, n, lut, NA, NG, cp.steep_thresh_rad, steep_on, cxp, cxn,   \
+                       cyp, cyn, keys, ids, st, nstrips, nwaves)
+#define WW_STREAM_H(IP)                   \
+    switch (h) {                          \
+        case 0: WW_STREAM(0, IP); break;  \
+        case 1: WW_STREAM(1, IP); break;  \
+        case 2: WW_STREAM(2, IP); break;  \
+        case 3: WW_STREAM(3, IP); break;  \
+        default: WW_STREAM(4, IP); break; \
+    }
+        if (cp.lut_interp) {
+            WW_STREAM_H(true)
+        } else {
+            WW_STREAM_H(false)
         }
+#undef WW_STREAM_H
 #undef WW_STREAM
         WW_LAUNCH_CHECK();
     } else {
@@ -668,7 +741,8 @@ ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *val
             return fail(WW_E_INVALID_ARG, "box_half %d too large for the tile (max 8)", h);
         dim3 grid(ceil_div(n, CT_W), ceil_div(m, CT_H));
         hipLaunchKernelGGL(k_edge_costs, grid, dim3(CT_THREADS), lds, stream, psi, coh, valid, m,
-                           n, lut, NA, NG, h, cp.steep_thresh_rad, steep_on, cxp, cxn, cyp, cyn,
+                           n, lut, NA, NG, h, cp.steep_thresh_rad, steep_on, cp.lut_interp, cxp,
+                           cxn, cyp, cyn,
                            keys, ids, st);
         WW_LAUNCH_CHECK();
     }

@@ -44,6 +44,7 @@ def test_defaults_and_version_without_gpu():
     assert (lp.n_alpha, lp.n_gamma, lp.n_eta, lp.n_aquad) == (128, 64, 2048, 513)
     cp = binding.default_cost_params()
     assert cp.box_half == 2 and cp.steep_cap_pct == 3 and cp.ref_i == -1
+    assert cp.lut_interp == 0  # nearest table bin unless asked
     assert binding.load().ww_version().startswith(b"ww-gfx950")
 
 
@@ -55,6 +56,10 @@ def test_argument_errors_are_reported_without_touching_the_gpu():
     assert b"shape" in L.ww_last_error()
     assert L.ww_build_cost_lut(1, None, None) == binding.E_INVALID_ARG
     assert L.ww_unwrap(None, None, None, 4, 4, 9, None, None, None, None, None) == binding.E_INVALID_ARG
+    bad = binding.default_cost_params(lut_interp=2)
+    assert L.ww_edge_costs(None, None, None, 4, 4, None, None, ctypes.byref(bad),
+                           None, None, None, None, None) == binding.E_INVALID_ARG
+    assert b"lut_interp" in L.ww_last_error()
 
 
 def test_product_path_has_no_oracle_dependency():
