@@ -133,6 +133,54 @@ def components_leg(ww, torch, psi, coh, valid, looks, m, n, reps=3):
             "threshold": 300, "min_size_frac": 0.001}
 
 
+# FP32 operations of one complex radix-2 N-point transform: (N/2) log2 N
+# butterflies of one complex multiply (6) and two complex adds (4).
+def _fft_flops(N):
+    import math
+    return (N // 2) * int(math.log2(N)) * 10
+
+
+def goldstein_leg(ww, torch, psi, coh, valid, looks, m, n, reps=5):
+    """The optional Goldstein preprocessing (Section II-D) on the same scene:
+    device time of ww_goldstein_filter (default 32 x 32 patches, 3 x 3
+    spectrum smoothing, alpha 0.5), its roofline, and one whole
+    ww_unwrap_filtered call."""
+    p = ww.default_filter_params()
+    N = p.patch
+    out = ww.goldstein_filter(psi, valid, p)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ww.goldstein_filter(psi, valid, p, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    S = N // 2
+    patches = ((m + S - 1) // S + 1) * ((n + S - 1) // S + 1)
+    # forward and inverse 2-D transforms: 2 x 2N one-dimensional transforms
+    flops = patches * 4 * N * _fft_flops(N)
+    alg_bytes = m * n * (4 + 1 + 4)  # psi + mask in, filtered psi out
+    r_raw = int(ww.residues(psi, valid)[0].abs().sum())
+    r_f = int(ww.residues(out, valid)[0].abs().sum())
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, _, tot = ww.unwrap_filtered(psi, coh, valid, looks)
+    torch.cuda.synchronize()
+    uw_ms = (time.perf_counter() - t) * 1e3
+    return {"filter_ms": round(ms, 3), "filter_mpix_s": round(m * n / 1e3 / ms, 1),
+            "patch": N, "smooth": p.smooth, "alpha": round(p.alpha, 3),
+            "fft_gflop": round(flops / 1e9, 2),
+            "fp32_tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+            "fp32_frac": round(flops / (ms * 1e-3) / 157.3e12, 4),
+            "alg_bytes_gbs": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "residues_raw": r_raw, "residues_filtered": r_f,
+            "unwrap_filtered_ms": round(uw_ms, 1), "unwrap_filtered_cost": tot}
+
+
 def stack_leg(args, ww, torch, scs, gen_s):
     """64 interferograms of mixed size and L: one job server with
     ``--slots`` workers against 64 sequential plain ww_unwrap calls, all on
@@ -370,6 +418,8 @@ def main():
     }
     out["components"] = components_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
     print(f"# components: {out['components']}", file=sys.stderr, flush=True)
+    out["goldstein"] = goldstein_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
+    print(f"# goldstein: {out['goldstein']}", file=sys.stderr, flush=True)
     if args.stack_jobs > 0:
         out["stack"] = stack_leg(args, ww, torch, *stack)
         print(f"# stack: {out['stack']}", file=sys.stderr, flush=True)

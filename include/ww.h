@@ -244,6 +244,59 @@ ww_status ww_connected_components(const int8_t *dk_x, const int8_t *dk_y, const 
                                   int32_t n, const ww_cc_params *p, uint32_t *labels,
                                   int64_t *ncomp_host, void *stream);
 
+/* Goldstein adaptive power-spectrum filter (the optional preprocessing of
+ * Section II-D).  Unit phasors exp(i psi) at valid pixels, 0 elsewhere and
+ * outside the image, in patch x patch windows on a grid of step patch/2
+ * whose first window starts patch/2 rows above and columns left of the
+ * image (every pixel lies in four windows).  Per window: the 2-D DFT Z is
+ * multiplied by (B / max B)^alpha, B the circular smooth x smooth mean of
+ * |Z| (an all-zero window contributes 0); the inverse DFT is tapered by
+ * w(r) w(c), w(i) = 1 - |2i + 1 - patch| / patch; the filtered phase is the
+ * argument of the sum of the tapered windows at each valid pixel, and
+ * invalid pixels keep psi.  FP32 arithmetic.
+ *   patch   16, 32 or 64 (default 32)
+ *   smooth  1, 3 or 5 (default 3)
+ *   alpha   exponent in [0, 4] (default 0.5)                            */
+typedef struct {
+    int32_t patch;
+    int32_t smooth;
+    float alpha;
+} ww_filter_params;
+
+void ww_default_filter_params(ww_filter_params *p);
+
+/*   psi, valid  as ww_residues (device).
+ *   p           NULL = defaults.
+ *   psi_out     float32 [m*n] out (device), may equal psi.
+ * Uses 32 bytes per pixel of library workspace.
+ * Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
+ww_status ww_goldstein_filter(const float *psi, const uint8_t *valid, int32_t m, int32_t n,
+                              const ww_filter_params *p, float *psi_out, void *stream);
+
+/* Cycle counts found on a filtered copy psi_f moved onto the original phase
+ * psi (Section II-D: the modified phase only estimates K).  At a valid pixel
+ * K = K_f + k, k the integer that puts psi + 2 pi K within (-pi, pi] of
+ * psi_f + 2 pi K_f: k = -([x > pi] - [x <= -pi]), x = psi - psi_f in FP64;
+ * at an invalid pixel K = K_f.  With ref_i >= 0 every K is then shifted so
+ * that K(ref_i, ref_j) = 0.  phi = (float)((double)psi + 2 pi K) at valid
+ * pixels, nodata elsewhere.
+ *   K_f    int32 [m*n] (device); K may equal K_f.
+ *   K, phi int32 / float32 [m*n] out (device).
+ * Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
+ww_status ww_transfer_ambiguity(const float *psi, const uint8_t *valid, const float *psi_f,
+                                const int32_t *K_f, int32_t m, int32_t n, int32_t ref_i,
+                                int32_t ref_j, float nodata, int32_t *K, float *phi,
+                                void *stream);
+
+/* ww_unwrap on the Goldstein-filtered phase, then ww_transfer_ambiguity
+ * onto psi with the reference pixel of the integration (K = 0 there).
+ * total_cost_host is the optimum of the filtered problem.
+ * Errors: as ww_unwrap and ww_goldstein_filter. */
+ww_status ww_unwrap_filtered(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
+                             int32_t n, int32_t looks, const ww_cost_params *cp,
+                             const ww_filter_params *fp, int32_t *K, float *phi,
+                             int64_t *total_cost_host, void *stream);
+
 /* ---------------------------------------------------------------------
  * Many interferograms: a job server and a batch call.
  *

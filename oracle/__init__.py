@@ -440,12 +440,13 @@ def goldstein(psi, valid=None, alpha=0.5, patch=32, smooth=3, want_sum=False):
     return out
 
 
-def transfer_ambiguity(psi, valid, psi_f, K_f, nodata=float("nan")):
+def transfer_ambiguity(psi, valid, psi_f, K_f, ref=None, nodata=float("nan")):
     """Cycle counts on the original phase from those found on a filtered
     copy (Section II-D: the modified phase only estimates K).  At a valid
     pixel K = K_f + k with k the integer that puts psi + 2 pi K within
     (-pi, pi] of psi_f + 2 pi K_f, i.e. k = -wrap(psi - psi_f), wrap(x) =
-    [x > pi] - [x <= -pi] in float64; elsewhere K = K_f.  phi = float32 of
+    [x > pi] - [x <= -pi] in float64; elsewhere K = K_f.  With ref = (i, j)
+    every K is then shifted so that K(i, j) = 0.  phi = float32 of
     psi + 2 pi K (float64) at valid pixels, nodata elsewhere."""
     psi = np.asarray(psi, np.float32).astype(np.float64)
     psi_f = np.asarray(psi_f, np.float32).astype(np.float64)
@@ -453,7 +454,10 @@ def transfer_ambiguity(psi, valid, psi_f, K_f, nodata=float("nan")):
     v = np.ones(psi.shape, bool) if valid is None else np.asarray(valid).astype(bool)
     x = psi - psi_f
     wrap = (x > np.pi).astype(np.int64) - (x <= -np.pi).astype(np.int64)
-    K = np.where(v, K_f - wrap, K_f).astype(np.int32)
+    K = np.where(v, K_f - wrap, K_f)
+    if ref is not None:
+        K = K - K[ref[0], ref[1]]
+    K = K.astype(np.int32)
     phi = np.where(v, psi + 2.0 * np.pi * K.astype(np.float64), nodata).astype(np.float32)
     return K, phi
 
@@ -463,7 +467,10 @@ def unwrap_filtered(psi, coh, valid, looks, alpha=0.5, patch=32, smooth=3, lut=N
     onto the original phase (Section II-D)."""
     psi_f = goldstein(psi, valid, alpha=alpha, patch=patch, smooth=smooth)
     out = unwrap(psi_f, coh, valid, looks, lut=lut, want=True)
-    K, phi = transfer_ambiguity(psi, valid, psi_f, out["K"])
+    m, n = np.shape(psi)
+    r = ref_index(valid, m, n)
+    ref = divmod(int(r), n) if 0 <= r < m * n else None
+    K, phi = transfer_ambiguity(psi, valid, psi_f, out["K"], ref=ref)
     if want:
         out.update(psi_f=psi_f, K_f=out["K"], K=K, phi=phi)
         return out

@@ -28,7 +28,8 @@ EXPORTS = ["ww_last_error", "ww_version", "ww_last_mcf_stats", "ww_default_lut_p
            "ww_unwrap", "ww_clock", "ww_server_create", "ww_server_submit", "ww_server_poll",
            "ww_server_in_flight", "ww_server_destroy", "ww_unwrap_batch", "ww_default_mcf_params",
            "ww_set_mcf_params", "ww_get_mcf_params", "ww_default_cc_params",
-           "ww_connected_components"]
+           "ww_connected_components", "ww_default_filter_params", "ww_goldstein_filter",
+           "ww_transfer_ambiguity", "ww_unwrap_filtered"]
 
 
 class WWError(RuntimeError):
@@ -90,6 +91,73 @@ def connected_components(dkx, dky, costs, valid, params: CcParams | None = None)
                                           _ptr(valid), m, n, C.byref(p), _ptr(labels),
                                           C.byref(nc), _stream()))
     return labels, int(nc.value)
+
+
+class FilterParams(C.Structure):
+    """Goldstein filter parameters (ww_filter_params)."""
+    _fields_ = [("patch", C.c_int32), ("smooth", C.c_int32), ("alpha", C.c_float)]
+
+
+def default_filter_params(**kw) -> FilterParams:
+    p = FilterParams()
+    load().ww_default_filter_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def goldstein_filter(psi, valid, params: FilterParams | None = None, out=None):
+    """Filtered wrapped phase (float32 [m, n] device tensor)."""
+    torch = _torch()
+    psi = _dev(psi, torch.float32)
+    valid = _dev(valid, torch.uint8)
+    m, n = psi.shape
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    p = params or default_filter_params()
+    _check(load().ww_goldstein_filter(_ptr(psi), _ptr(valid), m, n, C.byref(p), _ptr(out),
+                                      _stream()))
+    return out
+
+
+def transfer_ambiguity(psi, valid, psi_f, K_f, ref=None, nodata=math.nan):
+    """(K, phi): cycle counts of a filtered phase moved onto psi."""
+    torch = _torch()
+    psi = _dev(psi, torch.float32)
+    valid = _dev(valid, torch.uint8)
+    psi_f = _dev(psi_f, torch.float32)
+    K_f = _dev(K_f, torch.int32)
+    m, n = psi.shape
+    K = torch.empty((m, n), dtype=torch.int32, device="cuda")
+    phi = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    ri, rj = ref if ref is not None else (-1, -1)
+    _check(load().ww_transfer_ambiguity(_ptr(psi), _ptr(valid), _ptr(psi_f), _ptr(K_f), m, n,
+                                        int(ri), int(rj), float(nodata), _ptr(K), _ptr(phi),
+                                        _stream()))
+    return K, phi
+
+
+def unwrap_filtered(psi, coh, valid, looks, params: CostParams | None = None,
+                    filter_params: FilterParams | None = None, out=None):
+    """The whole path on the Goldstein-filtered phase, cycle counts moved
+    back onto psi.  Returns (K, phi, total_cost of the filtered problem)."""
+    torch = _torch()
+    psi = _dev(psi, torch.float32)
+    coh = _dev(coh, torch.float32)
+    valid = _dev(valid, torch.uint8)
+    m, n = psi.shape
+    if out is None:
+        K = torch.empty((m, n), dtype=torch.int32, device="cuda")
+        phi = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    else:
+        K, phi = out
+    tot = C.c_int64(0)
+    cp = params or default_cost_params()
+    fp = filter_params or default_filter_params()
+    _check(load().ww_unwrap_filtered(_ptr(psi), _ptr(coh), _ptr(valid), m, n, int(looks),
+                                     C.byref(cp), C.byref(fp), _ptr(K), _ptr(phi), C.byref(tot),
+                                     _stream()))
+    return K, phi, int(tot.value)
 
 
 class McfParams(C.Structure):
@@ -173,6 +241,12 @@ def _declare(L):
     L.ww_default_cc_params.argtypes = [P]
     L.ww_connected_components.argtypes = [P, P, P, P, P, P, P, I32, I32, P, P, P, P]
     L.ww_connected_components.restype = C.c_int32
+    L.ww_default_filter_params.argtypes = [P]
+    L.ww_goldstein_filter.argtypes = [P, P, I32, I32, P, P, P]
+    L.ww_transfer_ambiguity.argtypes = [P, P, P, P, I32, I32, I32, I32, C.c_float, P, P, P]
+    L.ww_unwrap_filtered.argtypes = [P, P, P, I32, I32, I32, P, P, P, P, P, P]
+    for f in ("ww_goldstein_filter", "ww_transfer_ambiguity", "ww_unwrap_filtered"):
+        getattr(L, f).restype = C.c_int32
 
 
 def _check(rc):

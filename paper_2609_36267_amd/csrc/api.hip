@@ -416,4 +416,78 @@ ww_status ww_unwrap(const float *psi, const float *coh, const uint8_t *valid, in
     return WW_OK;
 }
 
+void ww_default_filter_params(ww_filter_params *p) {
+    if (!p) return;
+    p->patch = 32;
+    p->smooth = 3;
+    p->alpha = 0.5f;
+}
+
+static ww_status check_filter_params(const ww_filter_params &p) {
+    if (p.patch != 16 && p.patch != 32 && p.patch != 64)
+        return fail(WW_E_INVALID_ARG, "patch must be 16, 32 or 64");
+    if (p.smooth != 1 && p.smooth != 3 && p.smooth != 5)
+        return fail(WW_E_INVALID_ARG, "smooth must be 1, 3 or 5");
+    if (!(p.alpha >= 0.f && p.alpha <= 4.f)) return fail(WW_E_INVALID_ARG, "alpha must lie in [0, 4]");
+    return WW_OK;
+}
+
+ww_status ww_goldstein_filter(const float *psi, const uint8_t *valid, int32_t m, int32_t n,
+                              const ww_filter_params *pin, float *psi_out, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    ww_filter_params p;
+    if (pin) p = *pin;
+    else ww_default_filter_params(&p);
+    WW_TRY(check_filter_params(p));
+    if (!psi || !psi_out) return fail(WW_E_INVALID_ARG, "psi and psi_out must be non-NULL");
+    return goldstein_impl(psi, valid, m, n, p, psi_out, (hipStream_t)stream);
+}
+
+ww_status ww_transfer_ambiguity(const float *psi, const uint8_t *valid, const float *psi_f,
+                                const int32_t *K_f, int32_t m, int32_t n, int32_t ref_i,
+                                int32_t ref_j, float nodata, int32_t *K, float *phi,
+                                void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    if (!psi || !psi_f || !K_f || !K || !phi)
+        return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    if (ref_i >= 0 && (ref_i >= m || ref_j < 0 || ref_j >= n))
+        return fail(WW_E_INVALID_ARG, "reference pixel outside the image");
+    const int64_t ref = ref_i >= 0 ? (int64_t)ref_i * n + ref_j : -1;
+    return transfer_impl(psi, valid, psi_f, K_f, m, n, ref, nullptr, nodata, K, phi,
+                         (hipStream_t)stream);
+}
+
+ww_status ww_unwrap_filtered(const float *psi, const float *coh, const uint8_t *valid, int32_t m,
+                             int32_t n, int32_t looks, const ww_cost_params *cpin,
+                             const ww_filter_params *fpin, int32_t *K, float *phi,
+                             int64_t *total_cost_host, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    ww_cost_params cp;
+    if (cpin) cp = *cpin;
+    else ww_default_cost_params(&cp);
+    WW_TRY(check_unwrap_args(psi, coh, m, n, looks, K, phi, cp));
+    ww_filter_params fp;
+    if (fpin) fp = *fpin;
+    else ww_default_filter_params(&fp);
+    WW_TRY(check_filter_params(fp));
+    const hipStream_t st = (hipStream_t)stream;
+    float *psi_f = nullptr;
+    WW_TRY(scratch(SLOT_GS_PSI, sizeof(float) * (size_t)m * n, (void **)&psi_f));
+    WW_TRY(goldstein_impl(psi, valid, m, n, fp, psi_f, st));
+    int64_t total = 0;
+    WW_TRY(unwrap_impl(psi_f, coh, valid, m, n, looks, cp, K, phi, &total, st));
+    const int64_t ref = cp.ref_i >= 0 ? (int64_t)cp.ref_i * n + cp.ref_j : -1;
+    const long long *ref_dev = cp.ref_i >= 0 ? nullptr : integrate_ref_index();
+    if (cp.ref_i < 0 && !ref_dev) return fail(WW_E_DEVICE, "integration state unavailable");
+    WW_TRY(transfer_impl(psi, valid, psi_f, K, m, n, ref, ref_dev, cp.nodata, K, phi, st));
+    WW_HIP(hipStreamSynchronize(st));
+    if (total_cost_host) *total_cost_host = total;
+    return WW_OK;
+}
+
 }  // extern "C"

@@ -278,4 +278,10 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
     return WW_OK;
 }
 
+const long long *integrate_ref_index() {
+    char *buf = nullptr;
+    if (scratch(SLOT_INTEG, sizeof(IntegState), (void **)&buf) != WW_OK) return nullptr;
+    return &((IntegState *)buf)->first_valid;
+}
+
 }  // namespace ww

@@ -75,6 +75,7 @@ enum Slot {
     SLOT_MCF_LAB, SLOT_MCF_POT, SLOT_MCF_EX, SLOT_MCF_BEST, SLOT_MCF_TILES,
     SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_MCF_PART, SLOT_INTEG,
     SLOT_LUT_WORK, SLOT_CC_LABEL, SLOT_CC_SIZE, SLOT_CC_SMALL,
+    SLOT_GS_PLANES, SLOT_GS_SHIFT, SLOT_GS_PSI,
     SLOT_COUNT
 };
 
@@ -131,6 +132,20 @@ ww_status check_unwrap_args(const float *psi, const float *coh, int m, int n, in
                             const int32_t *K, const float *phi, const ww_cost_params &cp);
 
 ww_status check_lut_params(const ww_lut_params &p);
+// Goldstein filter of the wrapped phase (out may alias psi) and the transfer
+// of cycle counts found on a filtered phase back onto psi; K may alias K_f.
+// The reference pixel is *ref_dev when ref_dev is non-NULL, else ref_host;
+// outside [0, m n) there is none.
+ww_status goldstein_impl(const float *psi, const uint8_t *valid, int m, int n,
+                         const ww_filter_params &fp, float *out, hipStream_t stream);
+ww_status transfer_impl(const float *psi, const uint8_t *valid, const float *psi_f,
+                        const int32_t *K_f, int m, int n, int64_t ref_host,
+                        const long long *ref_dev, float nodata, int32_t *K, float *phi,
+                        hipStream_t stream);
+// Device address of the reference pixel index found by the last integration
+// on the current workspace (first valid pixel, or m n when there is none).
+const long long *integrate_ref_index();
+
 ww_status check_cost_params(const ww_cost_params &p);
 
 }  // namespace ww

@@ -172,3 +172,17 @@ def test_unwrap_filtered_keeps_the_original_phase():
     cyc = (out["phi"].astype(np.float64) - psi) / (2 * np.pi)
     assert np.abs(cyc - np.round(cyc)).max() < 1e-4
     assert np.abs(out["res"]).sum() * 5 < np.abs(oracle.residues(psi)[0]).sum()
+
+
+def test_transfer_reference_shift_is_a_constant():
+    rng = np.random.default_rng(6)
+    m, n = 25, 31
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    psi_f = np.angle(np.exp(1j * (psi + rng.normal(0, 2.0, (m, n))))).astype(np.float32)
+    K_f = rng.integers(-4, 5, (m, n)).astype(np.int32)
+    K0, _ = oracle.transfer_ambiguity(psi, None, psi_f, K_f)
+    for ref in ((0, 0), (7, 19), (24, 30)):
+        K, phi = oracle.transfer_ambiguity(psi, None, psi_f, K_f, ref=ref)
+        assert K[ref] == 0
+        d = K.astype(np.int64) - K0
+        assert np.all(d == d[0, 0])
