@@ -20,6 +20,9 @@ Parity status by function (the pins live in ``tests/test_oracle_*.py``):
   goldstein        pinned (identity at alpha = 0, plane waves on the DFT grid,
                    explicit DFT sums on tiny patches, conjugation symmetry)
   transfer_ambiguity  pinned (congruence, nearest value, brute force)
+  regions, bridge  pinned (scipy labelling and exact distance transform,
+                   offset recovery on smooth fields, closed-form medians,
+                   ranking, invariants)
 """
 from __future__ import annotations
 
@@ -475,3 +478,101 @@ def unwrap_filtered(psi, coh, valid, looks, alpha=0.5, patch=32, smooth=3, lut=N
         out.update(psi_f=psi_f, K_f=out["K"], K=K, phi=phi)
         return out
     return K, phi, out["total"]
+
+
+# ----------------------------------------------------------------- bridging ---
+
+def regions(valid):
+    """4-connected regions of valid pixels, numbered 1, 2, ... in row-major
+    order of their first pixel (0 = invalid): the component labelling of
+    Section II-D with every edge between two valid pixels taken as reliable
+    and no size cut.  Returns (labels uint32 [m, n], R)."""
+    valid = np.ascontiguousarray(np.asarray(valid, np.uint8))
+    m, n = valid.shape
+    zx = np.zeros((m, max(n - 1, 0)), np.int8)
+    zy = np.zeros((max(m - 1, 0), n), np.int8)
+    big = [np.full(zx.shape, 32767, np.int16), np.full(zx.shape, 32767, np.int16),
+           np.full(zy.shape, 32767, np.int16), np.full(zy.shape, 32767, np.int16)]
+    return connected_components(zx, zy, big, valid, threshold=0, min_size_frac=0.0)
+
+
+def _boundary(lab, r):
+    """Pixels of region r with a 4-neighbour inside the image outside r: the
+    only pixels that can be closest to anything outside r."""
+    m, n = lab.shape
+    own = lab == r
+    out = np.zeros_like(own)
+    out[:, 1:] |= own[:, 1:] & ~own[:, :-1]
+    out[:, :-1] |= own[:, :-1] & ~own[:, 1:]
+    out[1:, :] |= own[1:, :] & ~own[:-1, :]
+    out[:-1, :] |= own[:-1, :] & ~own[1:, :]
+    return np.flatnonzero(out)
+
+
+def bridge(psi, valid, K, half_window=32, nodata=float("nan"), want=False):
+    """Bridging of mask-separated regions (Section II-D), exact and slow.
+
+    Regions (see regions()) are ranked by decreasing size, ties by label.
+    Region k >= 1 attaches to the region of rank < k holding the pixel
+    closest to it: the pair (p in region k, q of lower rank) minimising
+    (|p - q|^2, index p, index q), indices row-major.  For each such edge the
+    lower medians of phi = psi + 2 pi K (float64) over the pixels of the same
+    region in the (2 half_window + 1)^2 square windows centred on q and on p
+    give the offset d = floor((med_q - med_p) / 2 pi + 1/2); the region's
+    shift is its parent's shift plus d, the largest region keeps 0.
+    Returns (K + shift at valid pixels, phi, R) and, when want, the edges as
+    a list of (rank, p, q, parent rank, d, shift)."""
+    psi = np.asarray(psi, np.float32)
+    m, n = psi.shape
+    K = np.asarray(K, np.int64)
+    lab, R = regions(valid)
+    lab = lab.astype(np.int64)
+    v = lab > 0
+    Kout = K.copy()
+    edges = []
+    if R > 0:
+        sizes = np.bincount(lab.ravel(), minlength=R + 1)[1:]
+        order = sorted(range(1, R + 1), key=lambda r: (-int(sizes[r - 1]), r))
+        rank_of = np.empty(R + 1, np.int64)
+        for k, r in enumerate(order):
+            rank_of[r] = k
+        rank = np.where(v, rank_of[lab], -1)
+        phi64 = psi.astype(np.float64) + 2.0 * np.pi * K.astype(np.float64)
+        bnd = {r: _boundary(lab, r) for r in range(1, R + 1)}
+        shift = np.zeros(R, np.int64)
+        lower = np.zeros(0, np.int64)
+
+        def lower_median(c, rr):
+            i, j = divmod(int(c), n)
+            sl = (slice(max(0, i - half_window), i + half_window + 1),
+                  slice(max(0, j - half_window), j + half_window + 1))
+            vals = np.sort(phi64[sl][lab[sl] == rr])
+            return vals[(vals.size - 1) // 2]
+
+        for k, r in enumerate(order):
+            if k > 0:
+                P = bnd[r]
+                best = None
+                for c0 in range(0, P.size, 256):
+                    pp = P[c0:c0 + 256]
+                    di = (pp[:, None] // n) - (lower[None, :] // n)
+                    dj = (pp[:, None] % n) - (lower[None, :] % n)
+                    d2 = di * di + dj * dj
+                    a = np.lexsort((np.broadcast_to(lower[None, :], d2.shape).ravel(),
+                                    np.broadcast_to(pp[:, None], d2.shape).ravel(), d2.ravel()))[0]
+                    cand = (int(d2.ravel()[a]), int(pp[a // lower.size]), int(lower[a % lower.size]))
+                    if best is None or cand < best:
+                        best = cand
+                _, p, q = best
+                rq = int(lab.ravel()[q])
+                d = int(np.floor((lower_median(q, rq) - lower_median(p, r)) / (2.0 * np.pi) + 0.5))
+                shift[k] = shift[rank_of[rq]] + d
+                edges.append((k, p, q, int(rank_of[rq]), d, int(shift[k])))
+            lower = np.sort(np.concatenate([lower, bnd[r]]))
+        Kout = np.where(v, K + shift[np.maximum(rank, 0)], K)
+    Kout = Kout.astype(np.int32)
+    phi = np.where(v, psi.astype(np.float64) + 2.0 * np.pi * Kout.astype(np.float64),
+                   nodata).astype(np.float32)
+    if want:
+        return Kout, phi, int(R), edges
+    return Kout, phi, int(R)
