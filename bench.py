@@ -181,6 +181,34 @@ def goldstein_leg(ww, torch, psi, coh, valid, looks, m, n, reps=5):
             "unwrap_filtered_ms": round(uw_ms, 1), "unwrap_filtered_cost": tot}
 
 
+def bridge_leg(ww, torch, synth, psi, coh, valid, looks, m, n, reps=3):
+    """Bridging of mask-separated regions (Section II-D) on the same scene
+    with a river, a canal and 30 lakes with islands added to its mask
+    (synth.river_mask, width 40 px): ww_unwrap on that mask, then the device
+    time of ww_bridge on its cycle counts."""
+    import numpy as np
+    river = synth.river_mask(m, n, np.random.default_rng(7), width=40, lakes=30)
+    vr = valid & torch.from_numpy(river).cuda()
+    K, _, tot = ww.unwrap(psi, coh, vr, looks)
+    Kb = torch.empty_like(K)
+    phib = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    _, _, R = ww.bridge(psi, vr, K, out=(Kb, phib))
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ww.bridge(psi, vr, K, out=(Kb, phib))
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    moved = int((Kb != K).sum())
+    alg = m * n * (4 + 1 + 4 + 4 + 4)  # psi, mask, K in; K, phi out
+    return {"ms": round(best * 1e3, 3), "mpix_s": round(m * n / 1e6 / best, 1), "regions": R,
+            "pixels_shifted": moved, "unwrap_cost": tot,
+            "alg_bytes_gbs": round(alg / best / 1e9, 1),
+            "hbm_frac": round(alg / best / 1e9 / HBM_PEAK_GBS, 4),
+            "mask": "scene mask + river (40 px) + canal + 30 lakes with islands"}
+
+
 def stack_leg(args, ww, torch, scs, gen_s):
     """64 interferograms of mixed size and L: one job server with
     ``--slots`` workers against 64 sequential plain ww_unwrap calls, all on
@@ -420,6 +448,8 @@ def main():
     print(f"# components: {out['components']}", file=sys.stderr, flush=True)
     out["goldstein"] = goldstein_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
     print(f"# goldstein: {out['goldstein']}", file=sys.stderr, flush=True)
+    out["bridge"] = bridge_leg(ww, torch, synth, psi, coh, valid, sc.looks, m, n)
+    print(f"# bridge: {out['bridge']}", file=sys.stderr, flush=True)
     if args.stack_jobs > 0:
         out["stack"] = stack_leg(args, ww, torch, *stack)
         print(f"# stack: {out['stack']}", file=sys.stderr, flush=True)

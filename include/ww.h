@@ -297,6 +297,40 @@ ww_status ww_unwrap_filtered(const float *psi, const float *coh, const uint8_t *
                              const ww_filter_params *fp, int32_t *K, float *phi,
                              int64_t *total_cost_host, void *stream);
 
+/* Bridging of mask-separated regions (Section II-D post-processing).  The
+ * wrapped phase carries no information about the relative cycle levels of
+ * regions the mask separates; this call sets them.  Regions are the
+ * 4-connected components of valid pixels, numbered 1, 2, ... in row-major
+ * order of their first pixel, and ranked by decreasing size (ties by
+ * number).  Each region of rank k >= 1 attaches to the region of smaller
+ * rank holding the pixel closest to it: the pair (p in the region, q of
+ * smaller rank) minimising (|p - q|^2, index p, index q), indices
+ * row-major.  With phi = psi + 2 pi K in FP64, the lower medians of phi
+ * over the pixels of the same region in the (2 half_window + 1)^2 windows
+ * centred on q and on p give d = floor((med_q - med_p) / 2 pi + 1/2); the
+ * region's shift is its parent's shift plus d, and the largest region keeps
+ * its cycle counts.
+ *   half_window  0..32 (default 32: 65 x 65 windows)                      */
+typedef struct {
+    int32_t half_window;
+} ww_bridge_params;
+
+void ww_default_bridge_params(ww_bridge_params *p);
+
+/*   psi, valid   as ww_residues (device); m, n <= 46000.
+ *   K_in         int32 [m*n] cycle counts (device), e.g. from ww_unwrap.
+ *   K_out, phi   int32 / float32 [m*n] out (device): K_in + shift at valid
+ *                pixels, K_in elsewhere; phi = (float)((double)psi +
+ *                2 pi K_out), nodata at invalid pixels.  K_out may equal
+ *                K_in.
+ *   regions      uint32 [m*n] out (device), nullable: region numbers
+ *                (0 = invalid).
+ *   nregions_host  int64 out: number of regions.
+ * Synchronous.  Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
+ww_status ww_bridge(const float *psi, const uint8_t *valid, const int32_t *K_in, int32_t m,
+                    int32_t n, const ww_bridge_params *p, float nodata, int32_t *K_out,
+                    float *phi, uint32_t *regions, int64_t *nregions_host, void *stream);
+
 /* ---------------------------------------------------------------------
  * Many interferograms: a job server and a batch call.
  *

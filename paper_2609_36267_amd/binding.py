@@ -29,7 +29,8 @@ EXPORTS = ["ww_last_error", "ww_version", "ww_last_mcf_stats", "ww_default_lut_p
            "ww_server_in_flight", "ww_server_destroy", "ww_unwrap_batch", "ww_default_mcf_params",
            "ww_set_mcf_params", "ww_get_mcf_params", "ww_default_cc_params",
            "ww_connected_components", "ww_default_filter_params", "ww_goldstein_filter",
-           "ww_transfer_ambiguity", "ww_unwrap_filtered"]
+           "ww_transfer_ambiguity", "ww_unwrap_filtered", "ww_default_bridge_params",
+           "ww_bridge"]
 
 
 class WWError(RuntimeError):
@@ -160,6 +161,43 @@ def unwrap_filtered(psi, coh, valid, looks, params: CostParams | None = None,
     return K, phi, int(tot.value)
 
 
+class BridgeParams(C.Structure):
+    """Bridging parameters (ww_bridge_params)."""
+    _fields_ = [("half_window", C.c_int32)]
+
+
+def default_bridge_params(**kw) -> BridgeParams:
+    p = BridgeParams()
+    load().ww_default_bridge_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def bridge(psi, valid, K, params: BridgeParams | None = None, nodata=math.nan, out=None,
+           want_regions=False):
+    """Bridging of mask-separated regions.  Returns (K_out, phi, nregions)
+    and the region numbers (uint32 bits in an int32 tensor) when asked."""
+    torch = _torch()
+    psi = _dev(psi, torch.float32)
+    valid = _dev(valid, torch.uint8)
+    K = _dev(K, torch.int32)
+    m, n = psi.shape
+    if out is None:
+        K_out = torch.empty((m, n), dtype=torch.int32, device="cuda")
+        phi = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    else:
+        K_out, phi = out
+    reg = torch.empty((m, n), dtype=torch.int32, device="cuda") if want_regions else None
+    nr = C.c_int64(0)
+    p = params or default_bridge_params()
+    _check(load().ww_bridge(_ptr(psi), _ptr(valid), _ptr(K), m, n, C.byref(p), float(nodata),
+                            _ptr(K_out), _ptr(phi), _ptr(reg), C.byref(nr), _stream()))
+    if want_regions:
+        return K_out, phi, int(nr.value), reg
+    return K_out, phi, int(nr.value)
+
+
 class McfParams(C.Structure):
     """Window schedule of the shortest-path passes (ww_mcf_params)."""
     _fields_ = [("first_hop_window", C.c_int32), ("first_distance_step", C.c_int32)]
@@ -247,6 +285,9 @@ def _declare(L):
     L.ww_unwrap_filtered.argtypes = [P, P, P, I32, I32, I32, P, P, P, P, P, P]
     for f in ("ww_goldstein_filter", "ww_transfer_ambiguity", "ww_unwrap_filtered"):
         getattr(L, f).restype = C.c_int32
+    L.ww_default_bridge_params.argtypes = [P]
+    L.ww_bridge.argtypes = [P, P, P, I32, I32, P, C.c_float, P, P, P, P, P]
+    L.ww_bridge.restype = C.c_int32
 
 
 def _check(rc):

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libww.so")
 SOURCES = ["api.hip", "residues.hip", "lut.hip", "costs.hip", "mcf.hip", "integrate.hip",
-           "server.hip", "components.hip", "goldstein.hip"]
+           "server.hip", "components.hip", "goldstein.hip",
+           "bridge.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -490,4 +490,24 @@ ww_status ww_unwrap_filtered(const float *psi, const float *coh, const uint8_t *
     return WW_OK;
 }
 
+void ww_default_bridge_params(ww_bridge_params *p) {
+    if (!p) return;
+    p->half_window = 32;
+}
+
+ww_status ww_bridge(const float *psi, const uint8_t *valid, const int32_t *K_in, int32_t m,
+                    int32_t n, const ww_bridge_params *pin, float nodata, int32_t *K_out,
+                    float *phi, uint32_t *regions, int64_t *nregions_host, void *stream) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    WW_TRY(check_shape(m, n));
+    ww_bridge_params p;
+    if (pin) p = *pin;
+    else ww_default_bridge_params(&p);
+    if (!psi || !K_in || !K_out || !phi || !nregions_host)
+        return fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    return bridge_impl(psi, valid, K_in, m, n, p.half_window, nodata, K_out, phi, regions,
+                       nregions_host, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -67,7 +67,7 @@ __global__ void k_cc_init(const uint8_t *__restrict__ valid, int64_t N, uint32_t
 __global__ void k_cc_hook(const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
                           const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
                           const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn, int m,
-                          int n, int T, uint32_t *L, CcState *st) {
+                          int n, int T, int all_edges, uint32_t *L, CcState *st) {
     const int64_t N = (int64_t)m * n;
     int changed = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
@@ -81,12 +81,12 @@ __global__ void k_cc_hook(const int8_t *__restrict__ dkx, const int8_t *__restri
                 if (j + 1 >= n) continue;
                 q = p + 1;
                 e = (int64_t)i * (n - 1) + j;
-                rel = cc_reliable(dkx[e], cxp[e], cxn[e], T);
+                rel = all_edges || cc_reliable(dkx[e], cxp[e], cxn[e], T);
             } else {  // down: vy(i, j)
                 if (i + 1 >= m) continue;
                 q = p + n;
                 e = p;
-                rel = cc_reliable(dky[e], cyp[e], cyn[e], T);
+                rel = all_edges || cc_reliable(dky[e], cyp[e], cyn[e], T);
             }
             if (!rel || L[q] == CC_NONE) continue;
             const uint32_t a = cc_find(L, (uint32_t)p), b = cc_find(L, (uint32_t)q);
@@ -216,7 +216,8 @@ __global__ __launch_bounds__(CC_THREADS) void k_cc_scan(uint32_t *chunk_sum, int
 // every root gets its label (rank + 1, or 0 when too small) in S
 __global__ __launch_bounds__(CC_THREADS) void k_cc_rank(const uint32_t *__restrict__ L, uint32_t *S,
                                                         int64_t N, uint32_t min_size,
-                                                        const uint32_t *__restrict__ chunk_off) {
+                                                        const uint32_t *__restrict__ chunk_off,
+                                                        uint32_t *__restrict__ sizes_out) {
     const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
     int f[CC_PER];
     int c = 0;
@@ -230,7 +231,13 @@ __global__ __launch_bounds__(CC_THREADS) void k_cc_rank(const uint32_t *__restri
         const int64_t p = p0 + k;
         if (p < N && L[p] == (uint32_t)p) {
             // roots are written only by the thread that owns them
-            S[p] = f[k] ? ++r : 0u;
+            if (f[k]) {
+                ++r;
+                if (sizes_out) sizes_out[r - 1] = S[p];
+                S[p] = r;
+            } else {
+                S[p] = 0u;
+            }
         }
     }
 }
@@ -249,7 +256,8 @@ __global__ void k_cc_label(const uint32_t *__restrict__ L, const uint32_t *__res
 ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *cxp,
                           const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
                           const uint8_t *valid, int m, int n, int threshold, double min_size_frac,
-                          uint32_t *labels, int64_t *ncomp, hipStream_t st) {
+                          uint32_t *labels, int64_t *ncomp, hipStream_t st, int all_edges,
+                          uint32_t *sizes_out) {
     const int64_t N = (int64_t)m * n;
     uint32_t *L = nullptr, *S = nullptr, *chunk = nullptr;
     CcState *cs = nullptr, *hcs = nullptr;
@@ -272,7 +280,7 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
         if (round > N + 1) return fail(WW_E_DEVICE, "connected components did not converge");
         WW_HIP(hipMemsetAsync(&cs->changed, 0, sizeof(unsigned int), st));
         hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn,
-                           m, n, threshold, L, cs);
+                           m, n, threshold, all_edges, L, cs);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(256), 0, st, N, L);
         WW_LAUNCH_CHECK();
@@ -288,7 +296,8 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_scan, dim3(1), dim3(CC_THREADS), 0, st, chunk, nchunks, cs);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cc_rank, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, min_size, chunk);
+    hipLaunchKernelGGL(k_cc_rank, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, min_size, chunk,
+                       sizes_out);
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_label, dim3(grid), dim3(256), 0, st, L, S, N, labels);
     WW_LAUNCH_CHECK();

@@ -76,6 +76,7 @@ enum Slot {
     SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_MCF_PART, SLOT_INTEG,
     SLOT_LUT_WORK, SLOT_CC_LABEL, SLOT_CC_SIZE, SLOT_CC_SMALL,
     SLOT_GS_PLANES, SLOT_GS_SHIFT, SLOT_GS_PSI,
+    SLOT_BR_LABEL, SLOT_BR_RANK, SLOT_BR_SMALL, SLOT_BR_SIZES,
     SLOT_COUNT
 };
 
@@ -119,7 +120,12 @@ ww_status build_lut_impl(int looks, const ww_lut_params &p, int16_t *lut_dev, hi
 ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *cxp,
                           const int16_t *cxn, const int16_t *cyp, const int16_t *cyn,
                           const uint8_t *valid, int m, int n, int threshold, double min_size_frac,
-                          uint32_t *labels, int64_t *ncomp, hipStream_t stream);
+                          uint32_t *labels, int64_t *ncomp, hipStream_t stream,
+                          int all_edges = 0, uint32_t *sizes_out = nullptr);
+// Bridging of mask-separated regions.
+ww_status bridge_impl(const float *psi, const uint8_t *valid, const int32_t *K_in, int m, int n,
+                      int half_window, float nodata, int32_t *K_out, float *phi,
+                      uint32_t *regions, int64_t *nregions, hipStream_t stream);
 
 ww_mcf_stats &last_mcf_stats();  // of the current workspace
 

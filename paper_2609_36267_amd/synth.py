@@ -31,6 +31,13 @@ Workloads (sizes, phase fields, coherence fields, masks and seeds):
   * ``serve``  request pool, rows/cols log-uniform in [256, 8192], c1 recipe,
     seed 2000 + k.
 
+  * ``river`` masks (bridging inputs, :func:`river_mask`): a meandering
+    river of width w (centre column n/2 + (n/8) sin(2 pi i / (m/2))) cuts the
+    scene in two; a canal of width w/2 runs from the left edge to the river
+    at one third of the height; lakes (squares of side U[4w, 8w]) each hold a
+    square island of half the lake's side.  Several regions of very
+    different sizes, the structure rivers, coastlines and lakes give.
+
 Any other size can be produced with :func:`make` for tests.
 """
 from __future__ import annotations
@@ -149,6 +156,28 @@ def rect_mask(m, n, frac, rng, side_lo=16, side_hi=256):
         blk = valid[i0:i0 + h, j0:j0 + w]
         covered += int(blk.sum())
         blk[...] = 0
+    return valid
+
+
+def river_mask(m, n, rng, width=6, lakes=6):
+    """Mask (uint8, 1 = valid) of a meandering river, a canal and lakes with
+    islands: several regions separated by invalid pixels."""
+    valid = np.ones((m, n), np.uint8)
+    i = np.arange(m)
+    centre = n / 2.0 + (n / 8.0) * np.sin(2.0 * np.pi * i / max(m / 2.0, 1.0))
+    j = np.arange(n)[None, :]
+    valid[np.abs(j - centre[:, None]) < width / 2.0] = 0
+    c0 = m // 3
+    lim = int(max(0, centre[c0] - width / 2.0))
+    valid[c0:c0 + max(1, width // 2), :lim] = 0
+    for _ in range(lakes):
+        side = int(rng.integers(4 * width, 8 * width + 1))
+        side = max(3, min(side, m - 1, n - 1))
+        a = int(rng.integers(0, max(1, m - side)))
+        b = int(rng.integers(0, max(1, n - side)))
+        valid[a:a + side, b:b + side] = 0
+        k = side // 4
+        valid[a + k:a + side - k, b + k:b + side - k] = 1
     return valid
 
 
