@@ -22,9 +22,8 @@
 //                  64-bit atomicMin.  Only boundary pixels (a 4-neighbour
 //                  inside the image outside the region) can be closest, so
 //                  no other pixel searches.
-//   k_br_pair      the winning pixel of each region searches once more
-//                  without pruning for its partner q (smallest index at the
-//                  winning distance)
+//   k_br_pair      the winning pixel's partner q (smallest index at the
+//                  winning distance), kept per boundary pixel by the search
 //   k_br_median    one workgroup per tree edge: both windows' values
 //                  gathered into LDS and sorted (bitonic), lower medians, d
 //   host           shifts in rank order (each parent ranks before its child)
@@ -81,15 +80,14 @@ __device__ void nearest_lower(const uint32_t *__restrict__ rankpix,
     best_q = -1;
     const int bi = i / BR_B, bj = j / BR_B;
     const int rho_max = max(max(bi, nbi - 1 - bi), max(bj, nbj - 1 - bj));
+    unsigned long long rbd2 = ~0ull;  // region's best squared distance so far
     for (int rho = 0; rho <= rho_max; ++rho) {
+        if (region_best)
+            rbd2 = __hip_atomic_load(region_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32;
+        const unsigned long long bound = best_d2 < rbd2 ? best_d2 : rbd2;
         if (rho >= 1) {
             const unsigned long long lb = (unsigned long long)((rho - 1) * BR_B + 1);
-            if (lb * lb > best_d2) break;
-            if (region_best) {
-                const unsigned long long rb =
-                    __hip_atomic_load(region_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (lb * lb > (rb >> 32)) break;
-            }
+            if (lb * lb > bound) break;
         }
         for (int di = -rho; di <= rho; ++di) {
             const int ci = bi + di;
@@ -98,9 +96,21 @@ __device__ void nearest_lower(const uint32_t *__restrict__ rankpix,
             for (int dj = -rho; dj <= rho; dj += edge_row ? 1 : 2 * rho) {
                 const int cj = bj + dj;
                 if (cj >= 0 && cj < nbj && blockmin[(int64_t)ci * nbj + cj] < r) {
-                    for (int y = ci * BR_B; y < min(m, ci * BR_B + BR_B); ++y) {
+                    // nearest point of the block: skip it when even that is too far
+                    const int y0 = ci * BR_B, y1 = min(m, y0 + BR_B) - 1;
+                    const int x0 = cj * BR_B, x1 = min(n, x0 + BR_B) - 1;
+                    const long long gy = i < y0 ? y0 - i : (i > y1 ? i - y1 : 0);
+                    const long long gx = j < x0 ? x0 - j : (j > x1 ? j - x1 : 0);
+                    const unsigned long long lbb = (unsigned long long)(gy * gy + gx * gx);
+                    const unsigned long long lim = best_d2 < rbd2 ? best_d2 : rbd2;
+                    if (lbb > lim) {
+                        if (rho == 0) break;
+                        continue;
+                    }
+                    for (int y = y0; y <= y1; ++y) {
                         const long long dy = y - i;
-                        for (int x = cj * BR_B; x < min(n, cj * BR_B + BR_B); ++x) {
+                        if ((unsigned long long)(dy * dy) > best_d2) continue;
+                        for (int x = x0; x <= x1; ++x) {
                             const int64_t q = (int64_t)y * n + x;
                             if (rankpix[q] >= r) continue;
                             const long long dx = x - j;
@@ -126,7 +136,7 @@ __device__ __forceinline__ bool is_boundary(const uint32_t *rankpix, int m, int 
 
 __global__ void k_br_search(const uint32_t *__restrict__ rankpix,
                             const uint32_t *__restrict__ blockmin, int m, int n, int nbi, int nbj,
-                            unsigned long long *region_best) {
+                            unsigned long long *region_best, uint32_t *__restrict__ partner) {
     const int64_t N = (int64_t)m * n;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x) {
@@ -137,7 +147,12 @@ __global__ void k_br_search(const uint32_t *__restrict__ rankpix,
         unsigned long long d2;
         long long q;
         nearest_lower(rankpix, blockmin, m, n, nbi, nbj, i, j, r, &region_best[r], d2, q);
-        if (q >= 0) atomicMin(&region_best[r], (d2 << 32) | (unsigned long long)p);
+        if (q >= 0) {
+            // exact for every pixel that can win: a search cut short by the
+            // region's best already lost to it
+            partner[p] = (uint32_t)q;
+            atomicMin(&region_best[r], (d2 << 32) | (unsigned long long)p);
+        }
     }
 }
 
@@ -148,7 +163,7 @@ struct BrEdge {
 };
 
 __global__ void k_br_pair(const uint32_t *__restrict__ rankpix,
-                          const uint32_t *__restrict__ blockmin, int m, int n, int nbi, int nbj,
+                          const uint32_t *__restrict__ partner,
                           const unsigned long long *__restrict__ region_best, uint32_t R,
                           BrEdge *__restrict__ edges) {
     for (uint32_t r = 1 + blockIdx.x * blockDim.x + threadIdx.x; r < R;
@@ -161,13 +176,10 @@ __global__ void k_br_pair(const uint32_t *__restrict__ rankpix,
             continue;
         }
         const long long p = (long long)(key & 0xffffffffull);
-        unsigned long long d2;
-        long long q;
-        nearest_lower(rankpix, blockmin, m, n, nbi, nbj, (int)(p / n), (int)(p % n), r, nullptr,
-                      d2, q);
+        const long long q = (long long)partner[p];
         edges[r].p = p;
         edges[r].q = q;
-        edges[r].parent = q >= 0 ? rankpix[q] : 0u;
+        edges[r].parent = rankpix[q];
     }
 }
 
@@ -317,12 +329,13 @@ ww_status bridge_impl(const float *psi, const uint8_t *valid, const int32_t *K_i
         hipLaunchKernelGGL(k_br_fill64, dim3((unsigned)std::min<int64_t>(1024, (R + 255) / 256)),
                            dim3(256), 0, st, best, R, ~0ull);
         WW_LAUNCH_CHECK();
+        uint32_t *partner = nullptr;
+        WW_TRY(scratch(SLOT_BR_Q, sizeof(uint32_t) * (size_t)N, (void **)&partner));
         hipLaunchKernelGGL(k_br_search, dim3(grid), dim3(256), 0, st, rankpix, blockmin, m, n, nbi,
-                           nbj, best);
+                           nbj, best, partner);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_br_pair, dim3((unsigned)std::min<int64_t>(1024, (R + 255) / 256)),
-                           dim3(256), 0, st, rankpix, blockmin, m, n, nbi, nbj, best,
-                           (uint32_t)R, edges);
+                           dim3(256), 0, st, rankpix, partner, best, (uint32_t)R, edges);
         WW_LAUNCH_CHECK();
         if (R - 1 >= ((int64_t)1 << 31)) return fail(WW_E_INVALID_ARG, "too many regions");
         hipLaunchKernelGGL(k_br_median, dim3((unsigned)(R - 1)), dim3(BR_MED_THREADS), 0, st, psi,

@@ -110,10 +110,18 @@ __device__ __forceinline__ void dft_dif(float (&re)[N], float (&im)[N]) {
                 im[i] = ai + bi;
                 const float dr = ar - br, di = ai - bi;
                 const int k = t * (N / (2 * h));
-                const float c = tw.c[k], s = tw.s[k];
-                // (dr + i di)(c - i s)
-                re[j] = dr * c + di * s;
-                im[j] = di * c - dr * s;
+                if (k == 0) {  // W = 1
+                    re[j] = dr;
+                    im[j] = di;
+                } else if (4 * k == N) {  // W = -i
+                    re[j] = di;
+                    im[j] = -dr;
+                } else {
+                    const float c = tw.c[k], s = tw.s[k];
+                    // (dr + i di)(c - i s)
+                    re[j] = dr * c + di * s;
+                    im[j] = di * c - dr * s;
+                }
             }
         }
     }
@@ -132,9 +140,19 @@ __device__ __forceinline__ void idft_dit(float (&re)[N], float (&im)[N]) {
             for (int t = 0; t < h; ++t) {
                 const int i = b0 + t, j = i + h;
                 const int k = t * (N / (2 * h));
-                const float c = tw.c[k], s = tw.s[k];
-                // x_j (c + i s)
-                const float tr = re[j] * c - im[j] * s, ti = im[j] * c + re[j] * s;
+                float tr, ti;
+                if (k == 0) {  // W = 1
+                    tr = re[j];
+                    ti = im[j];
+                } else if (4 * k == N) {  // W = +i
+                    tr = -im[j];
+                    ti = re[j];
+                } else {
+                    const float c = tw.c[k], s = tw.s[k];
+                    // x_j (c + i s)
+                    tr = re[j] * c - im[j] * s;
+                    ti = im[j] * c + re[j] * s;
+                }
                 const float ar = re[i], ai = im[i];
                 re[i] = ar + tr;
                 im[i] = ai + ti;
@@ -156,7 +174,7 @@ constexpr float taper(int i) {
 constexpr int GS_PLANES = 4;
 
 template <int N, int SH>
-__global__ __launch_bounds__(64) void k_gs_patch(const float *__restrict__ psi,
+__global__ __launch_bounds__(64, (N == 32 ? 3 : 1)) void k_gs_patch(const float *__restrict__ psi,
                                                  const uint8_t *__restrict__ valid, int m, int n,
                                                  int PJ, int64_t npatch, float alpha,
                                                  float2 *__restrict__ planes, int64_t pstride) {
@@ -175,13 +193,18 @@ __global__ __launch_bounds__(64) void k_gs_patch(const float *__restrict__ psi,
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         const int r = r0 + a;
-        float sv = 0.f, cv = 0.f;
-        if (cin && r >= 0 && r < m) {
+        float x = 0.f;
+        bool on = cin && r >= 0 && r < m;
+        if (on) {
             const int64_t idx = (int64_t)r * n + c;
-            if (!valid || valid[idx]) sincosf(psi[idx], &sv, &cv);
+            x = psi[idx];
+            if (valid) on = valid[idx] != 0;
         }
-        re[a] = cv;
-        im[a] = sv;
+        // exp(i x) through sinpi/cospi of x / pi: a short reduction for any x
+        float sv, cv;
+        sincospif(x * (float)(1.0 / PI_D), &sv, &cv);
+        re[a] = on ? cv : 0.f;
+        im[a] = on ? sv : 0.f;
     }
     // DFT over rows: lane k holds column k, register j = row frequency bitrev(j)
     dft_dif<N>(re, im);
@@ -205,7 +228,7 @@ __global__ __launch_bounds__(64) void k_gs_patch(const float *__restrict__ psi,
     {
         float A[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) A[j] = sqrtf(re[j] * re[j] + im[j] * im[j]);
+        for (int j = 0; j < N; ++j) A[j] = __builtin_amdgcn_sqrtf(re[j] * re[j] + im[j] * im[j]);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             float s = 0.f;
@@ -229,13 +252,16 @@ __global__ __launch_bounds__(64) void k_gs_patch(const float *__restrict__ psi,
     }
 #pragma unroll
     for (int off = N / 2; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    const float inv = mx > 0.f ? 1.f / mx : 0.f;
+    // H = (B / max B)^alpha by the hardware base-2 logarithm and exponential
+    // (B = 0 gives log2 = -inf and H = 0); alpha = 0 leaves Z unchanged
+    if (alpha != 0.f) {
+        const float inv = mx > 0.f ? 1.f / mx : 0.f;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const float r = R[j] * inv;
-        const float H = alpha == 0.f ? 1.f : (r > 0.f ? exp2f(alpha * log2f(r)) : 0.f);
-        re[j] *= H;
-        im[j] *= H;
+        for (int j = 0; j < N; ++j) {
+            const float H = __builtin_amdgcn_exp2f(alpha * __builtin_amdgcn_logf(R[j] * inv));
+            re[j] *= H;
+            im[j] *= H;
+        }
     }
 
     // inverse over columns: register j (= bitrev column) in, natural column out

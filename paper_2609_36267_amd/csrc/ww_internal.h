@@ -76,7 +76,7 @@ enum Slot {
     SLOT_MCF_LISTS, SLOT_MCF_NODES, SLOT_MCF_PART, SLOT_INTEG,
     SLOT_LUT_WORK, SLOT_CC_LABEL, SLOT_CC_SIZE, SLOT_CC_SMALL,
     SLOT_GS_PLANES, SLOT_GS_SHIFT, SLOT_GS_PSI,
-    SLOT_BR_LABEL, SLOT_BR_RANK, SLOT_BR_SMALL, SLOT_BR_SIZES,
+    SLOT_BR_LABEL, SLOT_BR_RANK, SLOT_BR_SMALL, SLOT_BR_SIZES, SLOT_BR_Q,
     SLOT_COUNT
 };
 
