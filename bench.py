@@ -35,9 +35,11 @@ BYTES_PER_TILE_VISIT = TILE_NODES * BYTES_PER_NODE_VISIT
 GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # HBM bytes per k_sssp_round launch on the fault scene from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
-# (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash only (see round_kernel_sha).
+# (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
+# (see round_kernel_sha) and the solve schedule they were taken with only.
 TRAFFIC_SOURCE_SHA = "710003f3884eb60b"
-TRAFFIC_BYTES_PER_LAUNCH = 8.37e6
+TRAFFIC_SCHEDULE = (64, 256, 2, 0)
+TRAFFIC_BYTES_PER_LAUNCH = 11.80e6
 
 
 def round_kernel_sha() -> str:
@@ -60,6 +62,13 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="rows of the full-width strip the oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the components, Goldstein and bridging legs (for counter runs)")
+    ap.add_argument("--schedule", default=None, metavar="H0,DSTEP,FULL,FIRSTDEF",
+                    help="solve schedule to time (skips tuning), e.g. 64,256,2,0")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the library's default solve schedule instead of tuning it on a "
+                         "sibling scene first")
     ap.add_argument("--slots", type=int, default=8, help="job-server workers for the stack and serving legs")
     ap.add_argument("--stack-jobs", type=int, default=64, help="interferograms in the stack leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of the serving leg (0: skip)")
@@ -99,6 +108,13 @@ def cpu_baseline(sc, rows):
 def _pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def _sched_dict(sched):
+    """A solve schedule (2 or 4 fields) as a dict."""
+    full = tuple(sched) + (0, 0)[len(sched) - 2:]
+    return {"first_hop_window": full[0], "first_distance_step": full[1], "full_passes": full[2],
+            "first_deficit_after": full[3]}
 
 
 def stack_scenes(args, synth):
@@ -246,7 +262,7 @@ def stack_leg(args, ww, torch, scs, gen_s):
             "batched_s": round(batch_s, 3), "plain_s": round(plain_s, 3),
             "speedup": round(plain_s / batch_s, 3), "identical_costs": plain == batch,
             "total_cost_sum": int(sum(batch)),
-            "schedule": {"first_hop_window": sched[0], "first_distance_step": sched[1],
+            "schedule": {**_sched_dict(sched),
                          "tuned_on": f"{len(dev[::8])} of the {len(dev)} jobs, {len(table)} candidates",
                          "tuning_s": round(tune_s, 2)}}
 
@@ -316,8 +332,7 @@ def serve_leg(args, ww, torch, pool, gen_s):
     return {"workload": f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, "
                         f"pool of {len(pool)} requests, rows/cols logU[256,8192], c1 recipe (seeds 2000+k)",
             "offered_mpix_s": round(offered, 2), "generated_s": round(gen_s, 1), "slots": args.slots,
-            "schedule": {"first_hop_window": sched[0], "first_distance_step": sched[1],
-                         "tuned_on": "4 pool requests"},
+            "schedule": {**_sched_dict(sched), "tuned_on": "4 pool requests"},
             "server": served, "plain": plain, "oracle_checked": checked}
 
 
@@ -359,6 +374,12 @@ def main():
     sc = synth.config(args.workload)
     m, n = sc.psi.shape
     print(f"# generated {args.workload} {m}x{n} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    # a sibling of the timed scene (same recipe, half the size, another
+    # seed) on which the solve schedule is tuned: the timed scene is never
+    # used for tuning
+    sib = None
+    if not args.no_tune and args.schedule is None and args.workload == "c2":
+        sib = synth.make_fault(m // 2, n // 2, looks=sc.looks, seed=3, mask_frac=0.03)
     stack = stack_scenes(args, synth) if args.stack_jobs > 0 else None
     pool = serve_pool(args, synth) if args.serve_seconds > 0 else None
     print(f"# generated stack/pool in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -370,6 +391,20 @@ def main():
     phi = torch.empty((m, n), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
 
+    tuned_on = "library default (not tuned)"
+    if args.schedule:
+        ww.set_mcf_params(*[int(x) for x in args.schedule.split(",")])
+        tuned_on = "given on the command line"
+    if sib is not None:
+        from paper_2609_36267_amd import autotune
+        sjob = [(torch.from_numpy(sib.psi).cuda(), torch.from_numpy(sib.coh).cuda(),
+                 torch.from_numpy(sib.valid).cuda(), sib.looks)]
+        t = time.perf_counter()
+        choice, table = autotune.tune_schedule(sjob, reps=2)
+        tuned_on = (f"fault recipe {sib.psi.shape[0]}x{sib.psi.shape[1]} seed 3 (not the timed "
+                    f"scene), {len(table)} candidates, {time.perf_counter() - t:.1f} s")
+        del sjob, sib
+        print(f"# schedule {choice} tuned on the sibling scene", file=sys.stderr, flush=True)
     sched_main = ww.get_mcf_params()
     totals = []
     for w in range(args.warmup):
@@ -407,7 +442,8 @@ def main():
 
     achieved = visits * BYTES_PER_TILE_VISIT / (relax_ms / 1e3) / 1e9 if relax_ms > 0 else 0.0
     sha = round_kernel_sha()
-    traffic = TRAFFIC_BYTES_PER_LAUNCH if (sha == TRAFFIC_SOURCE_SHA and args.workload == "c2") else None
+    traffic = (TRAFFIC_BYTES_PER_LAUNCH if (sha == TRAFFIC_SOURCE_SHA and args.workload == "c2" and
+                                            sched_main.as_tuple() == TRAFFIC_SCHEDULE) else None)
     rounds = sum(st["rounds"] for st in stats)
     out = {
         "metric": METRIC,
@@ -438,18 +474,17 @@ def main():
                      "tile_visits_per_step": visits // args.steps,
                      "bytes_per_tile_visit": BYTES_PER_TILE_VISIT},
         "mcf": stats[-1],
-        "schedule": {"first_hop_window": sched_main.first_hop_window,
-                     "first_distance_step": sched_main.first_distance_step,
-                     "tuned_on": "library default (not tuned on this scene)"},
+        "schedule": {**_sched_dict(sched_main.as_tuple()), "tuned_on": tuned_on},
         "paper_context": {"whirlwind_74mpix_s": 209, "derived_mpix_s": 0.356,
                           "note": "unstated CPU, real Sentinel-1 scene; context, not the target"},
     }
-    out["components"] = components_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
-    print(f"# components: {out['components']}", file=sys.stderr, flush=True)
-    out["goldstein"] = goldstein_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
-    print(f"# goldstein: {out['goldstein']}", file=sys.stderr, flush=True)
-    out["bridge"] = bridge_leg(ww, torch, synth, psi, coh, valid, sc.looks, m, n)
-    print(f"# bridge: {out['bridge']}", file=sys.stderr, flush=True)
+    if not args.no_legs:
+        out["components"] = components_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
+        print(f"# components: {out['components']}", file=sys.stderr, flush=True)
+        out["goldstein"] = goldstein_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
+        print(f"# goldstein: {out['goldstein']}", file=sys.stderr, flush=True)
+        out["bridge"] = bridge_leg(ww, torch, synth, psi, coh, valid, sc.looks, m, n)
+        print(f"# bridge: {out['bridge']}", file=sys.stderr, flush=True)
     if args.stack_jobs > 0:
         out["stack"] = stack_leg(args, ww, torch, *stack)
         print(f"# stack: {out['stack']}", file=sys.stderr, flush=True)

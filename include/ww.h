@@ -98,21 +98,34 @@ typedef struct {
     double solve_ms;         /* wall time of the whole solve                */
 } ww_mcf_stats;
 
-/* Schedule of the shortest-path windows of every pass of the min-cost-flow
- * solve (Section II-C replaces Dial's unit buckets by windows; any
- * increasing sequence of windows gives the same exact labels, so these only
- * trade relaxation rounds against windows).
+/* Schedule of the min-cost-flow solve: the shortest-path windows of every
+ * pass (Section II-C replaces Dial's unit buckets by windows; any increasing
+ * sequence of windows gives the same exact labels, so these only trade
+ * relaxation rounds against windows) and when a pass stops searching.  Every
+ * schedule reaches an optimum of the same cost.
  *   first_hop_window     hop limit of a pass's first, zero-distance window
  *                        (1 .. 2^29-2; later zero-distance windows double)
  *   first_distance_step  first increment of the distance bound (1 .. 2^30;
  *                        later increments double)
+ *   full_passes          number of first passes that search until every
+ *                        reachable deficit is settled (0 .. 2^20)
+ *   first_deficit_after  0: every later pass stops once half of the
+ *                        remaining units have a settled deficit; 1: every
+ *                        later pass stops at the first window that settles a
+ *                        deficit.  full_passes = 8 with first_deficit_after = 1
+ *                        is the paper's schedule of Section II-C (eight full
+ *                        multi-source passes, then searches that stop at the
+ *                        first deficit).
  * Process-wide; applies to solves that start after the call. */
 typedef struct {
     int32_t first_hop_window;
     int32_t first_distance_step;
+    int32_t full_passes;
+    int32_t first_deficit_after;
 } ww_mcf_params;
 
-/* Defaults: first_hop_window 64, first_distance_step 256. */
+/* Defaults: first_hop_window 64, first_distance_step 256, full_passes 0,
+ * first_deficit_after 0. */
 void ww_default_mcf_params(ww_mcf_params *p);
 /* Errors: WW_E_INVALID_ARG (NULL or out of range). */
 ww_status ww_set_mcf_params(const ww_mcf_params *p);

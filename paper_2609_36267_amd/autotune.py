@@ -1,11 +1,14 @@
-"""Autotuner for the window schedule of the min-cost-flow passes.
+"""Autotuner for the schedule of the min-cost-flow passes.
 
 Every increasing sequence of shortest-path windows yields the same exact
 labels and the same optimal flow (Section II-C's bucket order only decides
-which equal-cost optimum the paper's solver reaches first), so the schedule
-is a pure speed knob. Its best value depends on the scene: broad
-zero-distance plateaus favour few hop windows, long fault-crossing paths
-favour many. tune_schedule() times candidate schedules on sample jobs of a
+which equal-cost optimum the paper's solver reaches first), and every stop
+rule of a pass keeps successive shortest paths exact, so the schedule is a
+pure speed knob. Its best value depends on the scene: broad zero-distance
+plateaus favour few hop windows, long fault-crossing paths favour many, and
+a few passes that settle every deficit first pay off where most residues
+pair up over short distances (the fault scene) but not where low-coherence
+patches hold long paths. tune_schedule() times candidate schedules on sample jobs of a
 workload through the C ABI and installs the fastest process-wide (ties keep
 the earlier candidate, the default first).
 """
@@ -15,24 +18,28 @@ import time
 
 from . import binding as ww
 
-# (first_hop_window, first_distance_step)
+# (first_hop_window, first_distance_step[, full_passes, first_deficit_after]);
+# the last one is the paper's pass schedule (Section II-C: eight full
+# multi-source passes, then searches that stop at the first deficit)
+PAPER_SCHEDULE = (64, 256, 8, 1)
 CANDIDATES = [(64, 256), (16, 256), (512, 256), (64, 64), (16, 64), (512, 64), (64, 1024),
-              (16, 1024), (512, 1024)]
+              (16, 1024), (512, 1024), (64, 256, 2, 0), (64, 256, 4, 0), PAPER_SCHEDULE]
 
 
 def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
     """jobs: list of (psi, coh, valid, looks) device tensors.  Times each
     candidate on all jobs (sequential plain calls, or ww_unwrap_batch with
     `slots` workers when slots > 0), keeps the fastest and returns
-    (best (h0, dstep0), {candidate: seconds}).  Costs must agree across
-    candidates (they are exact); a disagreement raises."""
+    (best candidate, {candidate: seconds}).  A two-field candidate keeps
+    the default stop rule.  Costs must agree across candidates (they are
+    exact); a disagreement raises."""
     import torch
     cands = list(candidates or CANDIDATES)
     old = ww.get_mcf_params()
     timings, costs = {}, None
     try:
-        for h0, ds in cands:
-            ww.set_mcf_params(h0, ds)
+        for c in cands:
+            ww.set_mcf_params(*(tuple(c) + (0, 0)[len(c) - 2:]))
             best = float("inf")
             for _ in range(max(1, reps)):
                 torch.cuda.synchronize()
@@ -47,11 +54,11 @@ def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
             if costs is None:
                 costs = got
             elif got != costs:
-                raise RuntimeError(f"schedule {(h0, ds)} changed an optimal cost: {got} vs {costs}")
-            timings[(h0, ds)] = best
+                raise RuntimeError(f"schedule {c} changed an optimal cost: {got} vs {costs}")
+            timings[tuple(c)] = best
     except BaseException:
-        ww.set_mcf_params(old.first_hop_window, old.first_distance_step)
+        ww.set_mcf_params(*old.as_tuple())
         raise
-    choice = min(cands, key=lambda c: timings[c])
-    ww.set_mcf_params(*choice)
+    choice = min(cands, key=lambda c: timings[tuple(c)])
+    ww.set_mcf_params(*(tuple(choice) + (0, 0)[len(choice) - 2:]))
     return choice, timings

@@ -199,8 +199,13 @@ def bridge(psi, valid, K, params: BridgeParams | None = None, nodata=math.nan, o
 
 
 class McfParams(C.Structure):
-    """Window schedule of the shortest-path passes (ww_mcf_params)."""
-    _fields_ = [("first_hop_window", C.c_int32), ("first_distance_step", C.c_int32)]
+    """Schedule of the min-cost-flow passes (ww_mcf_params)."""
+    _fields_ = [("first_hop_window", C.c_int32), ("first_distance_step", C.c_int32),
+                ("full_passes", C.c_int32), ("first_deficit_after", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.first_hop_window, self.first_distance_step, self.full_passes,
+                self.first_deficit_after)
 
 
 def get_mcf_params() -> McfParams:
@@ -209,15 +214,16 @@ def get_mcf_params() -> McfParams:
     return p
 
 
-def set_mcf_params(first_hop_window=None, first_distance_step=None) -> McfParams:
-    """Set the process-wide window schedule (None keeps a field); returns the
+def set_mcf_params(first_hop_window=None, first_distance_step=None, full_passes=None,
+                   first_deficit_after=None) -> McfParams:
+    """Set the process-wide solve schedule (None keeps a field); returns the
     previous schedule."""
     old = get_mcf_params()
-    p = McfParams(old.first_hop_window, old.first_distance_step)
-    if first_hop_window is not None:
-        p.first_hop_window = int(first_hop_window)
-    if first_distance_step is not None:
-        p.first_distance_step = int(first_distance_step)
+    p = McfParams(*old.as_tuple())
+    for k, v in (("first_hop_window", first_hop_window), ("first_distance_step", first_distance_step),
+                 ("full_passes", full_passes), ("first_deficit_after", first_deficit_after)):
+        if v is not None:
+            setattr(p, k, int(v))
     _check(load().ww_set_mcf_params(C.byref(p)))
     return old
 

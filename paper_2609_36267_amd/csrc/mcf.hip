@@ -982,6 +982,8 @@ constexpr unsigned int HMAX = 0x1fffffffu;
 // window schedule (ww_set_mcf_params), read once per solve
 std::atomic<int> g_first_hops{64};
 std::atomic<int> g_first_dstep{256};
+std::atomic<int> g_full_passes{0};
+std::atomic<int> g_first_deficit{0};
 
 static unsigned long long mk_label(unsigned int d, unsigned int h) {
     return ((unsigned long long)d << 32) | ((unsigned long long)h << 3) | 7ull;
@@ -1101,6 +1103,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     }
     const int rounds_per_sync = 4;
     const unsigned int h0 = (unsigned int)g_first_hops.load(), dstep0 = (unsigned int)g_first_dstep.load();
+    const unsigned int full_passes = (unsigned int)g_full_passes.load();
+    const bool first_deficit = g_first_deficit.load() != 0;
     const bool trace_windows = trace_env && trace_env[0] == '2';
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
     const unsigned int bound_cap = 0xffff0000u;
@@ -1165,8 +1169,12 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 fprintf(stderr, "[ww-mcf]   window %u/%u rounds %lld settled %u\n",
                         (unsigned)(lb >> 32), (unsigned)((lb >> 3) & 0x1fffffffu), S.rounds - rw0,
                         h->settled);
+            // stop rule: all units in a full pass, else the first deficit or
+            // half of the units
             const long long units = (long long)h->nsrc + std::max<long long>(h->gex, 0);
-            const long long need = std::max<long long>(1, (units + 1) / 2);
+            const long long need = pass <= full_passes ? std::max<long long>(1, units)
+                                   : first_deficit    ? 1
+                                                      : std::max<long long>(1, (units + 1) / 2);
             if ((long long)h->settled >= need) break;
             hipLaunchKernelGGL(k_clear_minrej, dim3(1), dim3(1), 0, st, ctl);
             WW_LAUNCH_CHECK();
@@ -1286,6 +1294,8 @@ void ww_default_mcf_params(ww_mcf_params *p) {
     if (!p) return;
     p->first_hop_window = 64;
     p->first_distance_step = 256;
+    p->full_passes = 0;
+    p->first_deficit_after = 0;
 }
 
 ww_status ww_set_mcf_params(const ww_mcf_params *p) {
@@ -1293,8 +1303,13 @@ ww_status ww_set_mcf_params(const ww_mcf_params *p) {
     if (!p || p->first_hop_window < 1 || p->first_hop_window > (int32_t)ww::HMAX - 1 ||
         p->first_distance_step < 1 || p->first_distance_step > (1 << 30))
         return ww::fail(WW_E_INVALID_ARG, "window schedule out of range");
+    if (p->full_passes < 0 || p->full_passes > (1 << 20) ||
+        (p->first_deficit_after != 0 && p->first_deficit_after != 1))
+        return ww::fail(WW_E_INVALID_ARG, "pass schedule out of range");
     ww::g_first_hops.store(p->first_hop_window);
     ww::g_first_dstep.store(p->first_distance_step);
+    ww::g_full_passes.store(p->full_passes);
+    ww::g_first_deficit.store(p->first_deficit_after);
     return WW_OK;
 }
 
@@ -1302,6 +1317,8 @@ void ww_get_mcf_params(ww_mcf_params *p) {
     if (!p) return;
     p->first_hop_window = ww::g_first_hops.load();
     p->first_distance_step = ww::g_first_dstep.load();
+    p->full_passes = ww::g_full_passes.load();
+    p->first_deficit_after = ww::g_first_deficit.load();
 }
 
 }  // extern "C"

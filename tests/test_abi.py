@@ -73,20 +73,22 @@ def test_product_path_has_no_oracle_dependency():
 
 
 def test_mcf_schedule_round_trip_and_range():
-    """The window schedule is host state: settable without a GPU."""
+    """The solve schedule is host state: settable without a GPU."""
     from paper_2609_36267_amd import binding as ww
     old = ww.get_mcf_params()
     try:
         ww.set_mcf_params(16, 4096)
         p = ww.get_mcf_params()
         assert (p.first_hop_window, p.first_distance_step) == (16, 4096)
-        for bad in ((0, 256), (64, 0), (64, (1 << 30) + 1), (1 << 29, 256)):
+        ww.set_mcf_params(full_passes=8, first_deficit_after=1)
+        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1)
+        for bad in ((0, 256), (64, 0), (64, (1 << 30) + 1), (1 << 29, 256), (64, 256, -1, 0),
+                    (64, 256, (1 << 20) + 1, 0), (64, 256, 0, 2)):
             with pytest.raises(ww.WWError):
                 ww.set_mcf_params(*bad)
-        p = ww.get_mcf_params()
-        assert (p.first_hop_window, p.first_distance_step) == (16, 4096)
+        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1)
         d = ww.McfParams()
         ww.load().ww_default_mcf_params(ctypes.byref(d))
-        assert (d.first_hop_window, d.first_distance_step) == (64, 256)
+        assert d.as_tuple() == (64, 256, 0, 0)
     finally:
-        ww.set_mcf_params(old.first_hop_window, old.first_distance_step)
+        ww.set_mcf_params(*old.as_tuple())

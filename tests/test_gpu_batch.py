@@ -145,8 +145,11 @@ def test_window_schedule_keeps_the_optimum(torch_cuda, scenes, plain):
             sc = scenes[k]
             m, n = sc.psi.shape
             out = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, want=True)
-            for h0, ds in ((1, 1), (16, 64), (1 << 28, 1 << 20)):
-                ww.set_mcf_params(h0, ds)
+            # windows, and the pass schedules: the paper's (eight full passes,
+            # then first-deficit passes), full passes only, first-deficit only
+            for sched in ((1, 1, 0, 0), (16, 64, 0, 0), (1 << 28, 1 << 20, 0, 0), (64, 256, 8, 1),
+                          (16, 64, 1000, 0), (64, 256, 0, 1)):
+                ww.set_mcf_params(*sched)
                 K, phi, tot = ww.unwrap(sc.psi, sc.coh, sc.valid, sc.looks)
                 assert tot == out["total"] == plain[k][2]
                 r = ww.mcf_solve(out["res"], out["costs"], m, n)
@@ -156,8 +159,10 @@ def test_window_schedule_keeps_the_optimum(torch_cuda, scenes, plain):
                                                 oracle.ref_index(sc.valid, m, n))
         jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
                  torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes[:3]]
-        choice, table = autotune.tune_schedule(jobs, candidates=[(64, 256), (16, 64)])
+        choice, table = autotune.tune_schedule(jobs, candidates=[(64, 256), (16, 64),
+                                                                 autotune.PAPER_SCHEDULE])
         p = ww.get_mcf_params()
-        assert choice in table and (p.first_hop_window, p.first_distance_step) == choice
+        assert choice in table
+        assert p.as_tuple() == tuple(choice) + (0, 0)[len(choice) - 2:]
     finally:
-        ww.set_mcf_params(old.first_hop_window, old.first_distance_step)
+        ww.set_mcf_params(*old.as_tuple())
