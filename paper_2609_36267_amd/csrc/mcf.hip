@@ -53,7 +53,6 @@ constexpr unsigned long long LINF = ~0ull;
 constexpr int RC_INF = 0x7fffffff;
 constexpr int DIR_NONE = 0, DIR_UP = 1, DIR_DOWN = 2, DIR_LEFT = 3, DIR_RIGHT = 4;
 constexpr int POT_LIMIT = 1 << 30;
-constexpr int MAX_ITERS = 1 << 16;
 
 enum : int { ERR_NEG_RC = 1, ERR_POT = 2, ERR_WALK = 4, ERR_ITERS = 8 };
 
@@ -316,6 +315,13 @@ __device__ __forceinline__ void relax_one(unsigned long long &best, unsigned lon
     best = (ok && !beyond && cand < best) ? cand : best;
 }
 
+// Sweeps per tile visit at most (a speed knob: the labels are the same for
+// any value).
+#ifndef WW_VISIT_ITERS
+#define WW_VISIT_ITERS 8
+#endif
+constexpr int VISIT_ITERS = WW_VISIT_ITERS;  // sweeps per tile visit at most
+
 __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
                                                    unsigned int round, unsigned int pass_stamp,
                                                    unsigned long long lb, int stats) {
@@ -349,47 +355,75 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             sh_rej = LINF;
             sh_gcand = LINF;
         }
-        // stage labels and potentials with a one-node halo; outside = ground
-        for (int t = threadIdx.x; t < (TJ + 2) * (TJ + 2); t += 256) {
-            const int r = t / (TJ + 2), c = t % (TJ + 2);
-            const int i = i0 - 1 + r, j = j0 - 1 + c;
-            unsigned long long l = LINF;
-            int p = 0;
-            if (r <= rows + 1 && c <= cols + 1) {
-                if (i >= 0 && i < R && j >= 0 && j < C) {
-                    const long long v = (long long)i * C + j;
-                    l = g.lab[v];
-                    p = g.pot[v];
-                } else {
-                    l = glab;
-                    p = gpot;
+        // stage labels and potentials with a one-node halo; outside = ground.
+        // All loads of a thread are issued before any LDS store, so that
+        // their latencies overlap.
+        constexpr int NSTAGE = ((TJ + 2) * (TJ + 2) + 255) / 256;
+        {
+            unsigned long long lv[NSTAGE];
+            int pv[NSTAGE];
+#pragma unroll
+            for (int s = 0; s < NSTAGE; ++s) {
+                const int t = threadIdx.x + 256 * s;
+                const int r = t / (TJ + 2), c = t % (TJ + 2);
+                const int i = i0 - 1 + r, j = j0 - 1 + c;
+                lv[s] = LINF;
+                pv[s] = 0;
+                if (t < (TJ + 2) * (TJ + 2) && r <= rows + 1 && c <= cols + 1) {
+                    if (i >= 0 && i < R && j >= 0 && j < C) {
+                        const long long v = (long long)i * C + j;
+                        lv[s] = g.lab[v];
+                        pv[s] = g.pot[v];
+                    } else {
+                        lv[s] = glab;
+                        pv[s] = gpot;
+                    }
                 }
             }
-            L[r][c] = l;
-            P[r][c] = p;
+#pragma unroll
+            for (int s = 0; s < NSTAGE; ++s) {
+                const int t = threadIdx.x + 256 * s;
+                if (t < (TJ + 2) * (TJ + 2)) {
+                    L[t / (TJ + 2)][t % (TJ + 2)] = lv[s];
+                    P[t / (TJ + 2)][t % (TJ + 2)] = pv[s];
+                }
+            }
+        }
+        // arc costs and flows of the four in-arcs of every node, loaded
+        // before the potentials are needed
+        constexpr int NRC = TJ * TJ / 256;
+        int cst[NRC][4];
+#pragma unroll
+        for (int s = 0; s < NRC; ++s) {
+            const int t = threadIdx.x + 256 * s;
+            const int li = t / TJ, lj = t % TJ;
+            cst[s][0] = cst[s][1] = cst[s][2] = cst[s][3] = RC_INF;
+            if (li < rows && lj < cols) {
+                const int i = i0 + li, j = j0 + lj;
+                long long e;
+                e = (long long)i * C + j;  // hx(i,j): from above, +1
+                cst[s][0] = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
+                e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
+                cst[s][1] = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
+                e = (long long)i * g.n + j;  // vy(i,j): from the left, -1
+                cst[s][2] = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
+                e = (long long)i * g.n + j + 1;  // vy(i,j+1): from the right, +1
+                cst[s][3] = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
+            }
         }
         __syncthreads();
         // reduced costs of the four in-arcs of every node
-        for (int t = threadIdx.x; t < TJ * TJ; t += 256) {
+#pragma unroll
+        for (int s = 0; s < NRC; ++s) {
+            const int t = threadIdx.x + 256 * s;
             const int li = t / TJ, lj = t % TJ;
             int ru = RC_INF, rd = RC_INF, rl = RC_INF, rr = RC_INF;
             if (li < rows && lj < cols) {
-                const int i = i0 + li, j = j0 + lj;
                 const int pv = P[li + 1][lj + 1];
-                long long e;
-                int c;
-                e = (long long)i * C + j;  // hx(i,j): from above, +1
-                c = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
-                if (c != RC_INF) ru = c - P[li][lj + 1] + pv;
-                e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
-                c = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
-                if (c != RC_INF) rd = c - P[li + 2][lj + 1] + pv;
-                e = (long long)i * g.n + j;  // vy(i,j): from the left, -1
-                c = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
-                if (c != RC_INF) rl = c - P[li + 1][lj] + pv;
-                e = (long long)i * g.n + j + 1;  // vy(i,j+1): from the right, +1
-                c = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
-                if (c != RC_INF) rr = c - P[li + 1][lj + 2] + pv;
+                if (cst[s][0] != RC_INF) ru = cst[s][0] - P[li][lj + 1] + pv;
+                if (cst[s][1] != RC_INF) rd = cst[s][1] - P[li + 2][lj + 1] + pv;
+                if (cst[s][2] != RC_INF) rl = cst[s][2] - P[li + 1][lj] + pv;
+                if (cst[s][3] != RC_INF) rr = cst[s][3] - P[li + 1][lj + 2] + pv;
                 if (ru < 0 || rd < 0 || rl < 0 || rr < 0) {
                     atomicOr(&ctl->error, ERR_NEG_RC);
                     ru = max(ru, 0); rd = max(rd, 0); rl = max(rl, 0); rr = max(rr, 0);
@@ -423,7 +457,12 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         if (threadIdx.x < 12) wchg[threadIdx.x / 4][threadIdx.x % 4] = threadIdx.x < 8 ? 0 : 1;
         __syncthreads();
         unsigned long long rej = LINF;  // smallest useful candidate beyond the window
-        for (int it = 0; it < MAX_ITERS; ++it) {
+        // A visit stops after VISIT_ITERS sweeps even when labels still
+        // change: it writes back what it has (labels only decrease, so every
+        // label is valid) and lists the tile again for the next round, so
+        // that one slow tile does not hold up the whole round.
+        bool unconverged = true;
+        for (int it = 0; it < VISIT_ITERS; ++it) {
             const int rd = (it + 2) % 3, wr = it % 3;
             const bool live = wchg[rd][wv] || (wv > 0 && wchg[rd][wv - 1]) || (wv < 3 && wchg[rd][wv + 1]);
             int changed = 0;
@@ -454,10 +493,12 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             if (threadIdx.x < 4) wchg[(it + 1) % 3][threadIdx.x] = 0;
             if (!__syncthreads_or(changed)) {
                 if (stats && threadIdx.x == 0) atomicAdd(&ctl->iters, (unsigned long long)(it + 1));
+                unconverged = false;
                 break;
             }
-            if (it == MAX_ITERS - 1 && threadIdx.x == 0) atomicOr(&ctl->error, ERR_ITERS);
         }
+        if (unconverged && stats && threadIdx.x == 0)
+            atomicAdd(&ctl->iters, (unsigned long long)VISIT_ITERS);
         // write back, note changed borders
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -521,33 +562,46 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         if (gc != LINF) atomicMin(&sh_gcand, gc);
         if (rej != LINF) atomicMin(&sh_rej, rej & ~7ull);
         __syncthreads();
-        // activations for the next round, stamps for this pass
-        if (threadIdx.x == 0) {
+        // activations for the next round (lanes 0-3, one neighbour each, so
+        // that the atomics' round trips overlap), stamps for this pass
+        // (lane 4) and the ground label (lane 5), all in wave 0
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
             const unsigned int nr = round + 1;
-            unsigned int nb[4];
-            int k = 0;
-            if (flags[0] && ti > 0) nb[k++] = tile - g.TC;
-            if (flags[1] && ti < g.TR - 1) nb[k++] = tile + g.TC;
-            if (flags[2] && tj > 0) nb[k++] = tile - 1;
-            if (flags[3] && tj < g.TC - 1) nb[k++] = tile + 1;
-            int fresh = 0;
-            for (int q = 0; q < k; ++q)
-                if (atomicExch(&ra.act[nb[q]], nr) != nr) nb[fresh++] = nb[q];
-            if (fresh) {
-                const unsigned int pos = atomicAdd(&ctl->count[nr % 3][0], (unsigned int)fresh);
-                unsigned int *dst = ra.lists + (size_t)(nr % 3) * NT + pos;
-                for (int q = 0; q < fresh; ++q) dst[q] = nb[q];
+            unsigned int nb = 0;
+            bool want = false;
+            if (lane == 0) { want = flags[0] && ti > 0; nb = tile - g.TC; }
+            if (lane == 1) { want = flags[1] && ti < g.TR - 1; nb = tile + g.TC; }
+            if (lane == 2) { want = flags[2] && tj > 0; nb = tile - 1; }
+            if (lane == 3) { want = flags[3] && tj < g.TC - 1; nb = tile + 1; }
+            if (lane == 7) { want = unconverged; nb = tile; }
+            const bool fresh = want && atomicExch(&ra.act[nb], nr) != nr;
+            const unsigned long long fm = __ballot(fresh);
+            if (fm) {
+                const int leader = __ffsll((long long)fm) - 1;
+                unsigned int pos = 0;
+                if (lane == leader) pos = atomicAdd(&ctl->count[nr % 3][0], (unsigned int)__popcll(fm));
+                pos = __shfl(pos, leader, 64);
+                if (fresh) {
+                    const unsigned int rank = (unsigned int)__popcll(fm & ((1ull << lane) - 1ull));
+                    ra.lists[(size_t)(nr % 3) * NT + pos + rank] = nb;
+                }
             }
-            // the tile's parked candidates (recomputed in full at every visit)
-            ra.tile_rej[tile] = sh_rej;
-            if (sh_rej != LINF) ra.pstamp[tile] = pass_stamp;
-            ra.tstamp[tile] = pass_stamp;
-            sh_any = 0;
-            if (sh_gcand != LINF && sh_gcand < ctl->glab) {
-                unsigned long long old = atomicMin(&ctl->glab, sh_gcand);
-                if (sh_gcand < old) sh_any = 1;
+            if (lane == 4) {
+                // the tile's parked candidates (recomputed in full at every visit)
+                ra.tile_rej[tile] = sh_rej;
+                if (sh_rej != LINF) ra.pstamp[tile] = pass_stamp;
+                ra.tstamp[tile] = pass_stamp;
             }
-            if (stats) {
+            if (lane == 5) {
+                int any = 0;
+                if (sh_gcand != LINF && sh_gcand < ctl->glab) {
+                    unsigned long long old = atomicMin(&ctl->glab, sh_gcand);
+                    if (sh_gcand < old) any = 1;
+                }
+                sh_any = any;
+            }
+            if (stats && lane == 6) {
                 const unsigned long long t_end = wall_clock64();
                 atomicAdd(&ctl->vt_sum, t_end - t_start);
                 atomicAdd(&ctl->vt_stage, t_staged - t_start);
