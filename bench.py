@@ -37,9 +37,9 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
-TRAFFIC_SOURCE_SHA = "710003f3884eb60b"
+TRAFFIC_SOURCE_SHA = "13277593c7988297"
 TRAFFIC_SCHEDULE = (64, 256, 2, 0)
-TRAFFIC_BYTES_PER_LAUNCH = 11.80e6
+TRAFFIC_BYTES_PER_LAUNCH = 14.14e6
 
 
 def round_kernel_sha() -> str:
