@@ -116,16 +116,22 @@ typedef struct {
  *                        is the paper's schedule of Section II-C (eight full
  *                        multi-source passes, then searches that stop at the
  *                        first deficit).
+ *   reverse_below        0: every pass searches from the supplies; n > 0:
+ *                        once at most n units are left, passes search from
+ *                        the demands instead (the same successive shortest
+ *                        paths on the reversed problem: arcs turned round,
+ *                        supplies and demands exchanged, potentials negated)
  * Process-wide; applies to solves that start after the call. */
 typedef struct {
     int32_t first_hop_window;
     int32_t first_distance_step;
     int32_t full_passes;
     int32_t first_deficit_after;
+    int32_t reverse_below;
 } ww_mcf_params;
 
 /* Defaults: first_hop_window 64, first_distance_step 256, full_passes 0,
- * first_deficit_after 0. */
+ * first_deficit_after 0, reverse_below 0. */
 void ww_default_mcf_params(ww_mcf_params *p);
 /* Errors: WW_E_INVALID_ARG (NULL or out of range). */
 ww_status ww_set_mcf_params(const ww_mcf_params *p);

@@ -5,10 +5,12 @@ labels and the same optimal flow (Section II-C's bucket order only decides
 which equal-cost optimum the paper's solver reaches first), and every stop
 rule of a pass keeps successive shortest paths exact, so the schedule is a
 pure speed knob. Its best value depends on the scene: broad zero-distance
-plateaus favour few hop windows, long fault-crossing paths favour many, and
-a few passes that settle every deficit first pay off where most residues
-pair up over short distances (the fault scene) but not where low-coherence
-patches hold long paths. tune_schedule() times candidate schedules on sample jobs of a
+plateaus favour few hop windows, long fault-crossing paths favour many, a
+few passes that settle every deficit first pay off where most residues pair
+up over short distances (the fault scene) but not where low-coherence
+patches hold long paths, and searching from the demands once few units are
+left avoids the plateaus that the earlier passes made tight around the
+supplies. tune_schedule() times candidate schedules on sample jobs of a
 workload through the C ABI and installs the fastest process-wide (ties keep
 the earlier candidate, the default first).
 """
@@ -18,12 +20,20 @@ import time
 
 from . import binding as ww
 
-# (first_hop_window, first_distance_step[, full_passes, first_deficit_after]);
+# (first_hop_window, first_distance_step[, full_passes, first_deficit_after
+# [, reverse_below]]), missing fields 0;
 # the last one is the paper's pass schedule (Section II-C: eight full
 # multi-source passes, then searches that stop at the first deficit)
 PAPER_SCHEDULE = (64, 256, 8, 1)
 CANDIDATES = [(64, 256), (16, 256), (512, 256), (64, 64), (16, 64), (512, 64), (64, 1024),
-              (16, 1024), (512, 1024), (64, 256, 2, 0), (64, 256, 4, 0), PAPER_SCHEDULE]
+              (16, 1024), (512, 1024), (64, 256, 2, 0), (64, 256, 4, 0), PAPER_SCHEDULE,
+              (64, 256, 0, 0, 1024), (64, 256, 2, 0, 1024), (64, 256, 4, 0, 1024),
+              (64, 256, 8, 0, 1024), (512, 64, 0, 0, 1024)]
+
+
+def pad(c):
+    """A candidate with its missing trailing fields set to 0."""
+    return tuple(c) + (0,) * (5 - len(c))
 
 
 def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
@@ -39,7 +49,7 @@ def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
     timings, costs = {}, None
     try:
         for c in cands:
-            ww.set_mcf_params(*(tuple(c) + (0, 0)[len(c) - 2:]))
+            ww.set_mcf_params(*pad(c))
             best = float("inf")
             for _ in range(max(1, reps)):
                 torch.cuda.synchronize()
@@ -60,5 +70,5 @@ def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
         ww.set_mcf_params(*old.as_tuple())
         raise
     choice = min(cands, key=lambda c: timings[tuple(c)])
-    ww.set_mcf_params(*(tuple(choice) + (0, 0)[len(choice) - 2:]))
+    ww.set_mcf_params(*pad(choice))
     return choice, timings

@@ -993,6 +993,33 @@ __global__ void k_swap_lists(Ctl *ctl) {
     ctl->ndef = ctl->ndef2;
 }
 
+// The reversed problem: every arc turned round, supplies and demands
+// exchanged.  Its residual arc v -> u across an edge has the cost of the
+// original residual arc u -> v when the net flows are negated and the two
+// cost planes of every edge exchanged (the host swaps the plane pointers);
+// with potentials negated its reduced costs equal the original ones, so a
+// forward search in the reversed frame is a search towards the demands in
+// the original one.  Applying the map twice restores the original state.
+__global__ void k_reverse_frame(Graph g, Ctl *ctl, long long nx, long long ny, long long N) {
+    const long long total = max(nx + ny, N);
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < nx) g.fx[t] = (int8_t)-g.fx[t];
+        else if (t < nx + ny) g.fy[t - nx] = (int8_t)-g.fy[t - nx];
+        if (t < N) {
+            g.pot[t] = -g.pot[t];
+            g.ex[t] = (int8_t)-g.ex[t];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned int ns = ctl->nsrc;
+        ctl->nsrc = ctl->ndef;
+        ctl->ndef = ns;
+        ctl->gex = -ctl->gex;
+        ctl->gpot = -ctl->gpot;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_total_cost(const int8_t *fx, const int8_t *fy,
                                                    const int16_t *cxp, const int16_t *cxn,
                                                    const int16_t *cyp, const int16_t *cyn,
@@ -1038,6 +1065,7 @@ std::atomic<int> g_first_hops{64};
 std::atomic<int> g_first_dstep{256};
 std::atomic<int> g_full_passes{0};
 std::atomic<int> g_first_deficit{0};
+std::atomic<int> g_reverse_below{0};
 
 static unsigned long long mk_label(unsigned int d, unsigned int h) {
     return ((unsigned long long)d << 32) | ((unsigned long long)h << 3) | 7ull;
@@ -1159,6 +1187,19 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const unsigned int h0 = (unsigned int)g_first_hops.load(), dstep0 = (unsigned int)g_first_dstep.load();
     const unsigned int full_passes = (unsigned int)g_full_passes.load();
     const bool first_deficit = g_first_deficit.load() != 0;
+    const long long reverse_below = g_reverse_below.load();
+    bool reversed = false;
+    const int rev_grid = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx + ny, N), 256)));
+    auto flip_frame = [&]() -> ww_status {
+        hipLaunchKernelGGL(k_reverse_frame, dim3(rev_grid), dim3(256), 0, st, g, ctl, nx, ny, N);
+        WW_LAUNCH_CHECK();
+        std::swap(g.cxp, g.cxn);
+        std::swap(g.cyp, g.cyn);
+        std::swap(src, def);
+        std::swap(src2, def2);
+        reversed = !reversed;
+        return sync_ctl();
+    };
     const bool trace_windows = trace_env && trace_env[0] == '2';
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
     const unsigned int bound_cap = 0xffff0000u;
@@ -1174,6 +1215,12 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     };
     for (;;) {
         if (h->nsrc == 0 && h->gex <= 0) break;
+        // few units left: search from the demands instead (in the reversed
+        // frame), where the plateaus that earlier passes made tight around
+        // the supplies do not lie
+        if (!reversed && reverse_below > 0 &&
+            (long long)h->nsrc + std::max<long long>(h->gex, 0) <= reverse_below)
+            WW_TRY(flip_frame());
         const int gsrc = h->gex > 0;
         const auto tp0 = std::chrono::steady_clock::now();
         const long long r0 = S.rounds, w0 = S.windows;
@@ -1319,6 +1366,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         if (h->naug == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
     }
+    if (reversed) WW_TRY(flip_frame());
     const int cg = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(nx + ny, 256 * 8)));
     long long *part = (long long *)bc;
     hipLaunchKernelGGL(k_total_cost, dim3(cg), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn, nx,
@@ -1350,6 +1398,7 @@ void ww_default_mcf_params(ww_mcf_params *p) {
     p->first_distance_step = 256;
     p->full_passes = 0;
     p->first_deficit_after = 0;
+    p->reverse_below = 0;
 }
 
 ww_status ww_set_mcf_params(const ww_mcf_params *p) {
@@ -1358,12 +1407,13 @@ ww_status ww_set_mcf_params(const ww_mcf_params *p) {
         p->first_distance_step < 1 || p->first_distance_step > (1 << 30))
         return ww::fail(WW_E_INVALID_ARG, "window schedule out of range");
     if (p->full_passes < 0 || p->full_passes > (1 << 20) ||
-        (p->first_deficit_after != 0 && p->first_deficit_after != 1))
+        (p->first_deficit_after != 0 && p->first_deficit_after != 1) || p->reverse_below < 0)
         return ww::fail(WW_E_INVALID_ARG, "pass schedule out of range");
     ww::g_first_hops.store(p->first_hop_window);
     ww::g_first_dstep.store(p->first_distance_step);
     ww::g_full_passes.store(p->full_passes);
     ww::g_first_deficit.store(p->first_deficit_after);
+    ww::g_reverse_below.store(p->reverse_below);
     return WW_OK;
 }
 
@@ -1373,6 +1423,7 @@ void ww_get_mcf_params(ww_mcf_params *p) {
     p->first_distance_step = ww::g_first_dstep.load();
     p->full_passes = ww::g_full_passes.load();
     p->first_deficit_after = ww::g_first_deficit.load();
+    p->reverse_below = ww::g_reverse_below.load();
 }
 
 }  // extern "C"

@@ -148,7 +148,8 @@ def test_window_schedule_keeps_the_optimum(torch_cuda, scenes, plain):
             # windows, and the pass schedules: the paper's (eight full passes,
             # then first-deficit passes), full passes only, first-deficit only
             for sched in ((1, 1, 0, 0), (16, 64, 0, 0), (1 << 28, 1 << 20, 0, 0), (64, 256, 8, 1),
-                          (16, 64, 1000, 0), (64, 256, 0, 1)):
+                          (16, 64, 1000, 0), (64, 256, 0, 1), (64, 256, 2, 0, 1), (64, 256, 0, 0, 64),
+                          (64, 256, 0, 0, 1 << 30)):
                 ww.set_mcf_params(*sched)
                 K, phi, tot = ww.unwrap(sc.psi, sc.coh, sc.valid, sc.looks)
                 assert tot == out["total"] == plain[k][2]
@@ -163,6 +164,6 @@ def test_window_schedule_keeps_the_optimum(torch_cuda, scenes, plain):
                                                                  autotune.PAPER_SCHEDULE])
         p = ww.get_mcf_params()
         assert choice in table
-        assert p.as_tuple() == tuple(choice) + (0, 0)[len(choice) - 2:]
+        assert p.as_tuple() == autotune.pad(choice)
     finally:
         ww.set_mcf_params(*old.as_tuple())
