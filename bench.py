@@ -225,6 +225,60 @@ def bridge_leg(ww, torch, synth, psi, coh, valid, looks, m, n, reps=3):
             "mask": "scene mask + river (40 px) + canal + 30 lakes with islands"}
 
 
+def streaming_leg(ww, torch, psi, coh, valid, looks, m, n, reps=7):
+    """The three streaming steps of the path timed alone on the scene
+    (HIP events on the library's stream, median of `reps`), with their
+    algorithmic bytes per pixel, beside two measured ceilings: a plain 1 GiB
+    device copy, and random 64-bit atomicMin (the SSSP labels' update) by
+    torch's scatter_reduce."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return sorted(ts)[len(ts) // 2]
+    lut = torch.from_numpy(ww.build_cost_lut(looks)).cuda()
+    res = torch.empty((m - 1, n - 1), dtype=torch.int8, device="cuda")
+    dkx = torch.zeros((m, n - 1), dtype=torch.int8, device="cuda")
+    dky = torch.zeros((m - 1, n), dtype=torch.int8, device="cuda")
+    px = m * n
+    out = {}
+    for name, bpp, fn in (
+            ("residues", 6, lambda: ww.load().ww_residues(ww._ptr(psi), ww._ptr(valid), m, n,
+                                                          ww._ptr(res), None, None, ww._stream())),
+            ("edge_costs", 17, lambda: ww.edge_costs(psi, coh, valid, lut)),
+            ("integrate", 15, lambda: ww.integrate(psi, valid, dkx, dky))):
+        ms = timed(fn)
+        gbs = bpp * px / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "bytes_per_px": bpp, "gbs": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del res, dkx, dky
+    src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src))
+    out["copy_ceiling"] = {"gbs": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(2 * (1 << 30) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "what": "torch copy of 1 GiB (read + write)"}
+    del src, dst
+    # 2^26 random 64-bit atomicMin updates onto as many labels
+    nupd = 1 << 26
+    g = torch.Generator(device="cuda").manual_seed(7)
+    idx = torch.randint(0, nupd, (nupd,), device="cuda", generator=g)
+    val = torch.randint(0, 1 << 62, (nupd,), device="cuda", generator=g)
+    lab = torch.full((nupd,), (1 << 62), dtype=torch.int64, device="cuda")
+    ms = timed(lambda: lab.scatter_reduce_(0, idx, val, reduce="amin"))
+    out["atomic_min_ceiling"] = {"gupd_s": round(nupd / (ms * 1e-3) / 1e9, 2),
+                                 "what": "torch scatter_reduce amin, 2^26 random int64 updates"}
+    return out
+
+
 def stack_leg(args, ww, torch, scs, gen_s):
     """64 interferograms of mixed size and L: one job server with
     ``--slots`` workers against 64 sequential plain ww_unwrap calls, all on
@@ -485,6 +539,8 @@ def main():
         print(f"# goldstein: {out['goldstein']}", file=sys.stderr, flush=True)
         out["bridge"] = bridge_leg(ww, torch, synth, psi, coh, valid, sc.looks, m, n)
         print(f"# bridge: {out['bridge']}", file=sys.stderr, flush=True)
+        out["streaming"] = streaming_leg(ww, torch, psi, coh, valid, sc.looks, m, n)
+        print(f"# streaming: {out['streaming']}", file=sys.stderr, flush=True)
     if args.stack_jobs > 0:
         out["stack"] = stack_leg(args, ww, torch, *stack)
         print(f"# stack: {out['stack']}", file=sys.stderr, flush=True)

@@ -300,7 +300,14 @@ __global__ __launch_bounds__(CT_THREADS) void k_edge_costs(
 // of a segment.  Steep candidates are buffered per wave in LDS and appended
 // with one atomic reservation per CS_CB entries.  Same arithmetic as
 // k_edge_costs, so the outputs are identical.
-constexpr int CS_ROWS = 128;
+#ifndef WW_CS_ROWS
+#define WW_CS_ROWS 64
+#endif
+#ifndef WW_CS_PF
+#define WW_CS_PF 4
+#endif
+constexpr int CS_ROWS = WW_CS_ROWS;  // output rows per wave
+constexpr int CS_PF = WW_CS_PF;      // pixel rows loaded ahead
 constexpr int CS_CB = 256;
 constexpr int CS_WAVES = 4;
 constexpr int CS_LUT_MAX = 8192;  // table entries staged in LDS (16 KB)
@@ -437,7 +444,7 @@ __global__ __launch_bounds__(64 * CS_WAVES) void k_edge_costs_stream(
 
     const int i_start = max(0, r0 - H);
     const int i_last = r1 + H;  // inclusive; rows >= m are absent (zero samples)
-    // two rows of loads in flight ahead of the row being processed
+    // CS_PF rows of loads in flight ahead of the row being processed
     auto fetch = [&](int i, float &p, uint8_t &v, float &cc) {
         if (i < m && i <= i_last && col_in) {
             const int a = i * n + c;  // m * n < 2^31
@@ -450,18 +457,21 @@ __global__ __launch_bounds__(64 * CS_WAVES) void k_edge_costs_stream(
             cc = 0.f;
         }
     };
-    float p_n1, c_n1, p_n2, c_n2;
-    uint8_t v_n1, v_n2;
-    fetch(i_start, p_n1, v_n1, c_n1);
-    fetch(i_start + 1, p_n2, v_n2, c_n2);
+    float p_q[CS_PF], c_q[CS_PF];
+    uint8_t v_q[CS_PF];
+#pragma unroll
+    for (int k = 0; k < CS_PF; ++k) fetch(i_start + k, p_q[k], v_q[k], c_q[k]);
     for (int i = i_start; i <= i_last; ++i) {
         const bool row_in = i < m;
-        const float p = p_n1, cc = c_n1;
-        const uint8_t v = v_n1;
-        p_n1 = p_n2;
-        c_n1 = c_n2;
-        v_n1 = v_n2;
-        fetch(i + 2, p_n2, v_n2, c_n2);
+        const float p = p_q[0], cc = c_q[0];
+        const uint8_t v = v_q[0];
+#pragma unroll
+        for (int k = 0; k + 1 < CS_PF; ++k) {
+            p_q[k] = p_q[k + 1];
+            c_q[k] = c_q[k + 1];
+            v_q[k] = v_q[k + 1];
+        }
+        fetch(i + CS_PF, p_q[CS_PF - 1], v_q[CS_PF - 1], c_q[CS_PF - 1]);
         const bool vd = row_in && col_in && v != 0;
         const double ph = vd ? (double)p : 0.0;
         // x-sample (i, c): pixels c and c+1 (lane 63's right neighbour lies
