@@ -39,7 +39,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # (see round_kernel_sha) and the solve schedule they were taken with only.
 TRAFFIC_SOURCE_SHA = "13277593c7988297"
 TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024)
-TRAFFIC_BYTES_PER_LAUNCH = 12.42e6
+TRAFFIC_BYTES_PER_LAUNCH = 10.22e6
 
 
 def round_kernel_sha() -> str:

@@ -1183,7 +1183,12 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         WW_HIP(hipMalloc(&crec, sizeof(CheckRec)));
         WW_HIP(hipHostMalloc(&hcrec, sizeof(CheckRec)));
     }
-    const int rounds_per_sync = 4;
+#ifndef WW_ROUNDS_PER_SYNC
+#define WW_ROUNDS_PER_SYNC 8
+#endif
+    // relaxation rounds launched between two host checks of the list
+    // lengths (a round whose list is empty returns at once)
+    const int rounds_per_sync = WW_ROUNDS_PER_SYNC;
     const unsigned int h0 = (unsigned int)g_first_hops.load(), dstep0 = (unsigned int)g_first_dstep.load();
     const unsigned int full_passes = (unsigned int)g_full_passes.load();
     const bool first_deficit = g_first_deficit.load() != 0;
