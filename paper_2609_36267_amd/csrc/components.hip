@@ -4,15 +4,18 @@
 // and changing it by +1 or -1 would each raise its cost by more than the
 // threshold (c+ > T and c- > T); a corrected edge (dk = +-1) could be
 // changed back for a refund, so it is never reliable.  Components over the
-// reliable edges are found by union-find rounds on the device:
+// reliable edges are found by union-find on the device:
 //
-//   k_cc_hook  every reliable edge links the roots of its two pixels: the
-//              larger root index is lowered to the smaller by atomicMin;
-//   k_cc_jump  full path compression: every pixel points at its root.
+//   k_cc_local        every 32 x 32 tile joins its own pixels in LDS (hooks
+//                     and pointer jumping until nothing changes) and points
+//                     them at the smallest pixel of their tile-local part;
+//   k_cc_hook_border  rounds over the edges that cross tile borders: the
+//                     larger root is lowered to the smaller by atomicMin;
+//   k_cc_jump         full path compression: every pixel points at its root.
 //
 // Pointers only ever decrease, so every root ends as the smallest pixel
-// index of its component, whatever the order of the atomics; the rounds
-// repeat until a hook round changes nothing.  Sizes are counted per wave and
+// index of its component, whatever the order of the atomics; the border
+// rounds repeat until one changes nothing.  Sizes are counted per wave and
 // per workgroup before the global atomics; components with at least
 // min_size pixels are
 // numbered 1, 2, ... in row-major order of their smallest pixel by a
@@ -51,49 +54,151 @@ __device__ __forceinline__ uint32_t cc_find(const uint32_t *L, uint32_t x) {
     return x;
 }
 
-__global__ void k_cc_init(const uint8_t *__restrict__ valid, int64_t N, uint32_t *__restrict__ L,
-                          CcState *st) {
+// Reliability of the edge to the right of pixel (i, j) / below it (both
+// pixels valid is checked by the caller).
+__device__ __forceinline__ bool cc_right_ok(const int8_t *dkx, const int16_t *cxp,
+                                            const int16_t *cxn, int n, int i, int j, int T,
+                                            int all_edges) {
+    if (all_edges) return true;
+    const int64_t e = (int64_t)i * (n - 1) + j;
+    return cc_reliable(dkx[e], cxp[e], cxn[e], T);
+}
+
+__device__ __forceinline__ bool cc_down_ok(const int8_t *dky, const int16_t *cyp,
+                                           const int16_t *cyn, int n, int i, int j, int T,
+                                           int all_edges) {
+    if (all_edges) return true;
+    const int64_t e = (int64_t)i * n + j;
+    return cc_reliable(dky[e], cyp[e], cyn[e], T);
+}
+
+// Components inside one CC_TH x CC_TW tile, by union-find in LDS (hooks by
+// atomicMin towards the smaller local index, then pointer jumping, until no
+// hook changes anything).  Every pixel's global pointer is set to the
+// smallest pixel of its tile-local component: local indices run row-major
+// inside the tile like the global ones, so that pixel is the smallest
+// global index too, and the global rounds that follow only have to join
+// components across tile borders.  Also counts the valid pixels.
+constexpr int CC_TH = 32, CC_TW = 32, CC_PX = CC_TH * CC_TW / 256;
+
+__global__ __launch_bounds__(256) void k_cc_local(
+    const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
+    const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
+    const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn,
+    const uint8_t *__restrict__ valid, int m, int n, int T, int all_edges, int ntx,
+    uint32_t *__restrict__ L, CcState *st) {
+    __shared__ int lab[CC_TH * CC_TW];
+    __shared__ unsigned char rel[CC_TH * CC_TW];  // bit 0: right edge, bit 1: edge below
+    const int ti = blockIdx.x / ntx, tj = blockIdx.x % ntx;
+    const int i0 = ti * CC_TH, j0 = tj * CC_TW;
     unsigned long long nv = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const bool v = !valid || valid[p];
-        L[p] = v ? (uint32_t)p : CC_NONE;
+#pragma unroll
+    for (int k = 0; k < CC_PX; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int r = t / CC_TW, c = t % CC_TW, i = i0 + r, j = j0 + c;
+        const bool in = i < m && j < n;
+        const int64_t p = (int64_t)i * n + j;
+        const bool v = in && (!valid || valid[p]);
+        lab[t] = v ? t : -1;
         nv += v;
+        unsigned char b = 0;
+        if (v && c + 1 < CC_TW && j + 1 < n && (!valid || valid[p + 1]) &&
+            cc_right_ok(dkx, cxp, cxn, n, i, j, T, all_edges))
+            b |= 1;
+        if (v && r + 1 < CC_TH && i + 1 < m && (!valid || valid[p + n]) &&
+            cc_down_ok(dky, cyp, cyn, n, i, j, T, all_edges))
+            b |= 2;
+        rel[t] = b;
     }
     for (int off = 32; off > 0; off >>= 1) nv += __shfl_down(nv, off, 64);
     if ((threadIdx.x & 63) == 0 && nv) atomicAdd(&st->nvalid, nv);
+    __syncthreads();
+    auto find = [&](int x) {
+        int y = lab[x];
+        while (y != x) {
+            x = y;
+            y = lab[x];
+        }
+        return x;
+    };
+    // at most one hook round per pixel pair of the tile can change anything
+    for (int round = 0; round < CC_TH * CC_TW; ++round) {
+        int changed = 0;
+#pragma unroll
+        for (int k = 0; k < CC_PX; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            const unsigned char b = rel[t];
+            if (b & 1) {
+                const int a = find(t), q = find(t + 1);
+                if (a != q) {
+                    atomicMin(&lab[a > q ? a : q], a > q ? q : a);
+                    changed = 1;
+                }
+            }
+            if (b & 2) {
+                const int a = find(t), q = find(t + CC_TW);
+                if (a != q) {
+                    atomicMin(&lab[a > q ? a : q], a > q ? q : a);
+                    changed = 1;
+                }
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+#pragma unroll
+        for (int k = 0; k < CC_PX; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            if (lab[t] >= 0) lab[t] = find(t);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < CC_PX; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int r = t / CC_TW, c = t % CC_TW, i = i0 + r, j = j0 + c;
+        if (i >= m || j >= n) continue;
+        const int root = lab[t] >= 0 ? find(t) : -1;
+        L[(int64_t)i * n + j] =
+            root < 0 ? CC_NONE : (uint32_t)((int64_t)(i0 + root / CC_TW) * n + (j0 + root % CC_TW));
+    }
 }
 
-__global__ void k_cc_hook(const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
-                          const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
-                          const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn, int m,
-                          int n, int T, int all_edges, uint32_t *L, CcState *st) {
-    const int64_t N = (int64_t)m * n;
+// Hooks across tile borders only: the right edges of every tile's last
+// column and the edges below every tile's last row.
+__global__ void k_cc_hook_border(const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
+                                 const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
+                                 const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn,
+                                 int m, int n, int T, int all_edges, int ntx, int nty, uint32_t *L,
+                                 CcState *st) {
+    const int64_t nvb = (int64_t)m * (ntx - 1), nhb = (int64_t)(nty - 1) * n;
     int changed = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        if (L[p] == CC_NONE) continue;
-        const int i = (int)(p / n), j = (int)(p % n);
-        for (int d = 0; d < 2; ++d) {
-            int64_t q, e;
-            bool rel;
-            if (d == 0) {  // right: hx(i, j)
-                if (j + 1 >= n) continue;
-                q = p + 1;
-                e = (int64_t)i * (n - 1) + j;
-                rel = all_edges || cc_reliable(dkx[e], cxp[e], cxn[e], T);
-            } else {  // down: vy(i, j)
-                if (i + 1 >= m) continue;
-                q = p + n;
-                e = p;
-                rel = all_edges || cc_reliable(dky[e], cyp[e], cyn[e], T);
-            }
-            if (!rel || L[q] == CC_NONE) continue;
-            const uint32_t a = cc_find(L, (uint32_t)p), b = cc_find(L, (uint32_t)q);
-            if (a != b) {
-                atomicMin(&L[a > b ? a : b], a > b ? b : a);
-                changed = 1;
-            }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvb + nhb;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int i, j;
+        bool ok;
+        int64_t p, q;
+        if (k < nvb) {  // right edge of column (b + 1) CC_TW - 1
+            i = (int)(k / (ntx - 1));
+            j = (int)(k % (ntx - 1) + 1) * CC_TW - 1;
+            if (j + 1 >= n) continue;
+            p = (int64_t)i * n + j;
+            q = p + 1;
+            if (L[p] == CC_NONE || L[q] == CC_NONE) continue;
+            ok = cc_right_ok(dkx, cxp, cxn, n, i, j, T, all_edges);
+        } else {  // edge below row (b + 1) CC_TH - 1
+            const int64_t k2 = k - nvb;
+            i = (int)(k2 / n + 1) * CC_TH - 1;
+            j = (int)(k2 % n);
+            if (i + 1 >= m) continue;
+            p = (int64_t)i * n + j;
+            q = p + n;
+            if (L[p] == CC_NONE || L[q] == CC_NONE) continue;
+            ok = cc_down_ok(dky, cyp, cyn, n, i, j, T, all_edges);
+        }
+        if (!ok) continue;
+        const uint32_t a = cc_find(L, (uint32_t)p), b = cc_find(L, (uint32_t)q);
+        if (a != b) {
+            atomicMin(&L[a > b ? a : b], a > b ? b : a);
+            changed = 1;
         }
     }
     if (__any(changed) && (threadIdx.x & 63) == 0) st->changed = 1;
@@ -272,15 +377,21 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
     const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (N + 255) / 256));
     WW_HIP(hipMemsetAsync(cs, 0, sizeof(CcState), st));
     WW_HIP(hipMemsetAsync(S, 0, sizeof(uint32_t) * (size_t)N, st));
-    hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(256), 0, st, valid, N, L, cs);
+    // components inside tiles first, then joins across tile borders
+    const int ntx = (n + CC_TW - 1) / CC_TW, nty = (m + CC_TH - 1) / CC_TH;
+    if ((int64_t)ntx * nty >= ((int64_t)1 << 31)) return fail(WW_E_INVALID_ARG, "image too large");
+    hipLaunchKernelGGL(k_cc_local, dim3((unsigned)(ntx * nty)), dim3(256), 0, st, dkx, dky, cxp,
+                       cxn, cyp, cyn, valid, m, n, threshold, all_edges, ntx, L, cs);
     WW_LAUNCH_CHECK();
+    const int64_t nborder = (int64_t)m * (ntx - 1) + (int64_t)(nty - 1) * n;
+    const int bgrid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (nborder + 255) / 256));
     // union-find rounds until a hook round changes nothing (each round that
     // changes something merges at least two components, so at most N rounds)
     for (int64_t round = 0;; ++round) {
         if (round > N + 1) return fail(WW_E_DEVICE, "connected components did not converge");
         WW_HIP(hipMemsetAsync(&cs->changed, 0, sizeof(unsigned int), st));
-        hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn,
-                           m, n, threshold, all_edges, L, cs);
+        hipLaunchKernelGGL(k_cc_hook_border, dim3(bgrid), dim3(256), 0, st, dkx, dky, cxp, cxn,
+                           cyp, cyn, m, n, threshold, all_edges, ntx, nty, L, cs);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(256), 0, st, N, L);
         WW_LAUNCH_CHECK();

@@ -192,6 +192,34 @@ def test_mcf_parity_random(torch_cuda, shape, seed):
     _mcf_case(psi, tuple(costs), m, n)
 
 
+SCHEDULES = [(64, 256, 0, 0, 1 << 30),   # every pass from the demands (reversed problem)
+             (64, 256, 4, 0, 16),        # full passes, then reversal for the last units
+             (1, 1, 2, 1, 1),            # tiny windows, first-deficit passes, last unit reversed
+             (64, 256, 8, 1, 0)]         # the paper's pass schedule
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("shape,seed", [((33, 33), 0), ((65, 97), 1), ((130, 257), 0)])
+def test_mcf_parity_schedules(torch_cuda, sched, shape, seed):
+    """Every solve schedule, the reversed-problem passes included, reaches
+    the oracle's optimum with a valid certificate, and agrees with it on
+    every edge the optimum fixes."""
+    m, n = shape
+    rng = np.random.default_rng(seed * 31 + m + n)
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    costs = []
+    for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)):
+        c = rng.integers(0, [50, 3000][seed], sz).astype(np.int16)
+        c[rng.random(sz) < 0.1] = 0
+        costs.append(c)
+    old = ww.get_mcf_params()
+    try:
+        ww.set_mcf_params(*sched)
+        _mcf_case(psi, tuple(costs), m, n)
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
+
+
 def test_mcf_degenerate_shapes(torch_cuda):
     for m, n in ((1, 1), (1, 12), (12, 1)):
         costs = (np.ones((m, max(n - 1, 0)), np.int16), np.ones((m, max(n - 1, 0)), np.int16),
