@@ -10,8 +10,11 @@
 //                     and pointer jumping until nothing changes) and points
 //                     them at the smallest pixel of their tile-local part;
 //   k_cc_hook_border  rounds over the edges that cross tile borders: the
-//                     larger root is lowered to the smaller by atomicMin;
-//   k_cc_jump         full path compression: every pixel points at its root.
+//                     larger root is lowered to the smaller by atomicMin,
+//                     then the pixels of those edges are compressed
+//                     (k_cc_jump_border);
+//   k_cc_jump         full path compression once the rounds are done: every
+//                     pixel points at its root.
 //
 // Pointers only ever decrease, so every root ends as the smallest pixel
 // index of its component, whatever the order of the atomics; the border
@@ -35,7 +38,7 @@ constexpr int CC_CHUNK = CC_THREADS * CC_PER;
 
 struct CcState {
     unsigned int changed;
-    unsigned int pad;
+    unsigned int min_size;  // size threshold, set once the valid pixels are counted
     unsigned long long nvalid;
     unsigned long long ncomp;
 };
@@ -78,7 +81,7 @@ __device__ __forceinline__ bool cc_down_ok(const int8_t *dky, const int16_t *cyp
 // smallest pixel of its tile-local component: local indices run row-major
 // inside the tile like the global ones, so that pixel is the smallest
 // global index too, and the global rounds that follow only have to join
-// components across tile borders.  Also counts the valid pixels.
+// components across tile borders.
 constexpr int CC_TH = 32, CC_TW = 32, CC_PX = CC_TH * CC_TW / 256;
 
 __global__ __launch_bounds__(256) void k_cc_local(
@@ -86,12 +89,12 @@ __global__ __launch_bounds__(256) void k_cc_local(
     const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
     const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn,
     const uint8_t *__restrict__ valid, int m, int n, int T, int all_edges, int ntx,
-    uint32_t *__restrict__ L, CcState *st) {
+    uint32_t *__restrict__ L) {
     __shared__ int lab[CC_TH * CC_TW];
     __shared__ unsigned char rel[CC_TH * CC_TW];  // bit 0: right edge, bit 1: edge below
     const int ti = blockIdx.x / ntx, tj = blockIdx.x % ntx;
     const int i0 = ti * CC_TH, j0 = tj * CC_TW;
-    unsigned long long nv = 0;
+    int whole = 1;  // every in-image pixel valid and every in-tile edge reliable
 #pragma unroll
     for (int k = 0; k < CC_PX; ++k) {
         const int t = threadIdx.x + 256 * k;
@@ -100,19 +103,28 @@ __global__ __launch_bounds__(256) void k_cc_local(
         const int64_t p = (int64_t)i * n + j;
         const bool v = in && (!valid || valid[p]);
         lab[t] = v ? t : -1;
-        nv += v;
         unsigned char b = 0;
-        if (v && c + 1 < CC_TW && j + 1 < n && (!valid || valid[p + 1]) &&
+        const bool has_r = in && c + 1 < CC_TW && j + 1 < n;
+        const bool has_d = in && r + 1 < CC_TH && i + 1 < m;
+        if (v && has_r && (!valid || valid[p + 1]) &&
             cc_right_ok(dkx, cxp, cxn, n, i, j, T, all_edges))
             b |= 1;
-        if (v && r + 1 < CC_TH && i + 1 < m && (!valid || valid[p + n]) &&
+        if (v && has_d && (!valid || valid[p + n]) &&
             cc_down_ok(dky, cyp, cyn, n, i, j, T, all_edges))
             b |= 2;
         rel[t] = b;
+        if ((in && !v) || (has_r && !(b & 1)) || (has_d && !(b & 2))) whole = 0;
     }
-    for (int off = 32; off > 0; off >>= 1) nv += __shfl_down(nv, off, 64);
-    if ((threadIdx.x & 63) == 0 && nv) atomicAdd(&st->nvalid, nv);
-    __syncthreads();
+    if (__syncthreads_and(whole)) {
+        // one component: its smallest pixel is the tile's first
+#pragma unroll
+        for (int k = 0; k < CC_PX; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            const int i = i0 + t / CC_TW, j = j0 + t % CC_TW;
+            if (i < m && j < n) L[(int64_t)i * n + j] = (uint32_t)((int64_t)i0 * n + j0);
+        }
+        return;
+    }
     auto find = [&](int x) {
         int y = lab[x];
         while (y != x) {
@@ -204,12 +216,65 @@ __global__ void k_cc_hook_border(const int8_t *__restrict__ dkx, const int8_t *_
     if (__any(changed) && (threadIdx.x & 63) == 0) st->changed = 1;
 }
 
-__global__ void k_cc_jump(int64_t N, uint32_t *L) {
+// Path compression for the pixels on both sides of the tile-border edges
+// only (between border rounds; the full pass runs once at the end).
+__global__ void k_cc_jump_border(int m, int n, int ntx, int nty, uint32_t *L) {
+    const int64_t nvb = (int64_t)m * (ntx - 1), nhb = (int64_t)(nty - 1) * n;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvb + nhb;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t p, q;
+        if (k < nvb) {
+            const int i = (int)(k / (ntx - 1)), j = (int)(k % (ntx - 1) + 1) * CC_TW - 1;
+            if (j + 1 >= n) continue;
+            p = (int64_t)i * n + j;
+            q = p + 1;
+        } else {
+            const int64_t k2 = k - nvb;
+            const int i = (int)(k2 / n + 1) * CC_TH - 1, j = (int)(k2 % n);
+            if (i + 1 >= m) continue;
+            p = (int64_t)i * n + j;
+            q = p + n;
+        }
+        const uint32_t lp = L[p], lq = L[q];
+        if (lp != CC_NONE && lp != (uint32_t)p) L[p] = cc_find(L, lp);
+        if (lq != CC_NONE && lq != (uint32_t)q) L[q] = cc_find(L, lq);
+    }
+}
+
+// Also counts the valid pixels, one partial sum per workgroup (a single
+// global counter would serialise tens of thousands of atomics on one
+// address).
+__global__ __launch_bounds__(256) void k_cc_jump(int64_t N, uint32_t *L, uint32_t *vpart) {
+    __shared__ uint32_t wsum[4];
+    uint32_t nv = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t l = L[p];
+        nv += l != CC_NONE;
         if (l == CC_NONE || l == (uint32_t)p) continue;
         L[p] = cc_find(L, l);
+    }
+    for (int off = 32; off > 0; off >>= 1) nv += __shfl_down(nv, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nv;
+    __syncthreads();
+    if (threadIdx.x == 0) vpart[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Total of the valid pixels and the size threshold ceil(min_size_frac *
+// valid pixels), at least 1 (one workgroup).
+__global__ __launch_bounds__(256) void k_cc_total(const uint32_t *__restrict__ vpart, int nparts,
+                                                  double min_size_frac, CcState *st) {
+    __shared__ unsigned long long wsum[4];
+    unsigned long long nv = 0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) nv += vpart[k];
+    for (int off = 32; off > 0; off >>= 1) nv += __shfl_down(nv, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        const double want = ceil(min_size_frac * (double)tot);
+        st->nvalid = tot;
+        st->min_size = want < 1.0 ? 1u : (want > 4294967295.0 ? 0xffffffffu : (unsigned)want);
     }
 }
 
@@ -294,7 +359,8 @@ __device__ int cc_block_scan(int v, int *total) {
 // per chunk of CC_CHUNK pixels: number of qualifying roots
 __global__ __launch_bounds__(CC_THREADS) void k_cc_count(const uint32_t *__restrict__ L,
                                                          const uint32_t *__restrict__ S, int64_t N,
-                                                         uint32_t min_size, uint32_t *chunk_sum) {
+                                                         const CcState *st, uint32_t *chunk_sum) {
+    const uint32_t min_size = st->min_size;
     const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
     int c = 0;
     for (int k = 0; k < CC_PER; ++k) c += cc_flag(L, S, p0 + k, N, min_size);
@@ -320,9 +386,10 @@ __global__ __launch_bounds__(CC_THREADS) void k_cc_scan(uint32_t *chunk_sum, int
 
 // every root gets its label (rank + 1, or 0 when too small) in S
 __global__ __launch_bounds__(CC_THREADS) void k_cc_rank(const uint32_t *__restrict__ L, uint32_t *S,
-                                                        int64_t N, uint32_t min_size,
+                                                        int64_t N, const CcState *st,
                                                         const uint32_t *__restrict__ chunk_off,
                                                         uint32_t *__restrict__ sizes_out) {
+    const uint32_t min_size = st->min_size;
     const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
     int f[CC_PER];
     int c = 0;
@@ -370,18 +437,20 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
     WW_TRY(scratch(SLOT_CC_LABEL, sizeof(uint32_t) * (size_t)N, (void **)&L));
     WW_TRY(scratch(SLOT_CC_SIZE, sizeof(uint32_t) * (size_t)N, (void **)&S));
     char *small = nullptr;
-    WW_TRY(scratch(SLOT_CC_SMALL, 256 + sizeof(uint32_t) * (size_t)nchunks, (void **)&small));
+    const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (N + 255) / 256));
+    WW_TRY(scratch(SLOT_CC_SMALL, 256 + sizeof(uint32_t) * ((size_t)nchunks + (size_t)grid),
+                   (void **)&small));
     cs = (CcState *)small;
     chunk = (uint32_t *)(small + 256);
+    uint32_t *vpart = chunk + nchunks;
     WW_TRY(host_scratch(sizeof(CcState), (void **)&hcs));
-    const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (N + 255) / 256));
     WW_HIP(hipMemsetAsync(cs, 0, sizeof(CcState), st));
     WW_HIP(hipMemsetAsync(S, 0, sizeof(uint32_t) * (size_t)N, st));
     // components inside tiles first, then joins across tile borders
     const int ntx = (n + CC_TW - 1) / CC_TW, nty = (m + CC_TH - 1) / CC_TH;
     if ((int64_t)ntx * nty >= ((int64_t)1 << 31)) return fail(WW_E_INVALID_ARG, "image too large");
     hipLaunchKernelGGL(k_cc_local, dim3((unsigned)(ntx * nty)), dim3(256), 0, st, dkx, dky, cxp,
-                       cxn, cyp, cyn, valid, m, n, threshold, all_edges, ntx, L, cs);
+                       cxn, cyp, cyn, valid, m, n, threshold, all_edges, ntx, L);
     WW_LAUNCH_CHECK();
     const int64_t nborder = (int64_t)m * (ntx - 1) + (int64_t)(nty - 1) * n;
     const int bgrid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (nborder + 255) / 256));
@@ -393,21 +462,26 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
         hipLaunchKernelGGL(k_cc_hook_border, dim3(bgrid), dim3(256), 0, st, dkx, dky, cxp, cxn,
                            cyp, cyn, m, n, threshold, all_edges, ntx, nty, L, cs);
         WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(256), 0, st, N, L);
+        hipLaunchKernelGGL(k_cc_jump_border, dim3(bgrid), dim3(256), 0, st, m, n, ntx, nty, L);
         WW_LAUNCH_CHECK();
         WW_HIP(hipMemcpyAsync(hcs, cs, sizeof(CcState), hipMemcpyDeviceToHost, st));
         WW_HIP(hipStreamSynchronize(st));
         if (!hcs->changed) break;
     }
-    const double want = std::ceil(min_size_frac * (double)hcs->nvalid);
-    const uint32_t min_size = want < 1.0 ? 1u : (want > 4294967295.0 ? 0xffffffffu : (uint32_t)want);
-    hipLaunchKernelGGL(k_cc_size, dim3(grid), dim3(256), 0, st, L, N, S);
+    hipLaunchKernelGGL(k_cc_jump, dim3(grid), dim3(256), 0, st, N, L, vpart);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cc_count, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, min_size, chunk);
+    hipLaunchKernelGGL(k_cc_total, dim3(1), dim3(256), 0, st, vpart, grid, min_size_frac, cs);
+    WW_LAUNCH_CHECK();
+    // fewer workgroups for the sizes: each flushes its table of roots with
+    // global atomics, and a large component's root takes one from every one
+    const int sgrid = std::min(grid, 2048);
+    hipLaunchKernelGGL(k_cc_size, dim3(sgrid), dim3(256), 0, st, L, N, S);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_count, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, cs, chunk);
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_scan, dim3(1), dim3(CC_THREADS), 0, st, chunk, nchunks, cs);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cc_rank, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, min_size, chunk,
+    hipLaunchKernelGGL(k_cc_rank, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, cs, chunk,
                        sizes_out);
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_label, dim3(grid), dim3(256), 0, st, L, S, N, labels);
