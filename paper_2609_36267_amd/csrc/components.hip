@@ -6,23 +6,25 @@
 // changed back for a refund, so it is never reliable.  Components over the
 // reliable edges are found by union-find on the device:
 //
-//   k_cc_local        every 32 x 32 tile joins its own pixels in LDS (hooks
-//                     and pointer jumping until nothing changes) and points
-//                     them at the smallest pixel of their tile-local part;
-//   k_cc_hook_border  rounds over the edges that cross tile borders: the
-//                     larger root is lowered to the smaller by atomicMin,
-//                     then the pixels of those edges are compressed
-//                     (k_cc_jump_border);
+//   k_cc_local        every 32 x 32 tile joins its own pixels in LDS (runs
+//                     along the rows by ballot, then unions over the edges
+//                     below) and points them at the smallest pixel of their
+//                     tile-local part;
+//   k_cc_hook_border  unions over the edges that cross tile borders: the
+//                     larger root is hooked under the smaller by
+//                     compare-and-swap, retried until the two roots agree;
+//                     a union that gives up after a few attempts is finished
+//                     by another pass, after the pixels of the border edges
+//                     are compressed (k_cc_jump_border);
 //   k_cc_jump         full path compression once the rounds are done: every
 //                     pixel points at its root.
 //
-// Pointers only ever decrease, so every root ends as the smallest pixel
-// index of its component, whatever the order of the atomics; the border
-// rounds repeat until one changes nothing.  Sizes are counted per wave and
-// per workgroup before the global atomics; components with at least
-// min_size pixels are
-// numbered 1, 2, ... in row-major order of their smallest pixel by a
-// two-level scan, all others and invalid pixels get 0.
+// Pointers only ever decrease and only roots are hooked, so no union is
+// ever undone and every root ends as the smallest pixel index of its
+// component, whatever the order of the atomics.  Sizes are counted per wave
+// and per workgroup before the global atomics; components with at least
+// min_size pixels are numbered 1, 2, ... in row-major order of their
+// smallest pixel by a two-level scan, all others and invalid pixels get 0.
 #include <cmath>
 
 #include "ww_internal.h"
@@ -57,6 +59,21 @@ __device__ __forceinline__ uint32_t cc_find(const uint32_t *L, uint32_t x) {
     return x;
 }
 
+// Root of x with path halving: every visited pixel is pointed at its
+// grandparent.  The plain stores only ever replace a non-root's pointer by
+// another of its ancestors, and a root's pointer is only changed by
+// compare-and-swap, so racing finds and unions leave every pointer valid.
+__device__ __forceinline__ uint32_t cc_find_halve(uint32_t *L, uint32_t x) {
+    uint32_t y = L[x];
+    while (y != x) {
+        const uint32_t z = L[y];
+        if (z != y) L[x] = z;
+        x = y;
+        y = z;
+    }
+    return x;
+}
+
 // Reliability of the edge to the right of pixel (i, j) / below it (both
 // pixels valid is checked by the caller).
 __device__ __forceinline__ bool cc_right_ok(const int8_t *dkx, const int16_t *cxp,
@@ -75,21 +92,30 @@ __device__ __forceinline__ bool cc_down_ok(const int8_t *dky, const int16_t *cyp
     return cc_reliable(dky[e], cyp[e], cyn[e], T);
 }
 
-// Components inside one CC_TH x CC_TW tile, by union-find in LDS (hooks by
-// atomicMin towards the smaller local index, then pointer jumping, until no
-// hook changes anything).  Every pixel's global pointer is set to the
+// Components inside one CC_TH x CC_TW tile: every pixel first points at
+// the first pixel of its run of reliable edges along the row (one ballot per
+// wave), then the runs are joined by union-find in LDS over the edges below
+// (hooks by atomicMin towards the smaller local index, then pointer
+// jumping, until no hook changes anything).  Every pixel's global pointer is set to the
 // smallest pixel of its tile-local component: local indices run row-major
 // inside the tile like the global ones, so that pixel is the smallest
 // global index too, and the global rounds that follow only have to join
-// components across tile borders.
+// components across tile borders.  The reliability of the edges that leave
+// the tile to the right and downwards (both pixels valid included) is
+// stored as one byte per border edge in bb, so that the border rounds read
+// one coalesced byte instead of four strided cost planes:
+//   bb[b * m + i]             edge right of (i, (b + 1) CC_TW - 1), b < ntx - 1
+//   bb[nvb + b * n + j]       edge below ((b + 1) CC_TH - 1, j),    b < nty - 1
+// with nvb = m (ntx - 1).  Every entry is written.
 constexpr int CC_TH = 32, CC_TW = 32, CC_PX = CC_TH * CC_TW / 256;
+constexpr int CC_TRIES = 16;  // compare-and-swap attempts per union and pass
 
 __global__ __launch_bounds__(256) void k_cc_local(
     const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
     const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
     const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn,
-    const uint8_t *__restrict__ valid, int m, int n, int T, int all_edges, int ntx,
-    uint32_t *__restrict__ L) {
+    const uint8_t *__restrict__ valid, int m, int n, int T, int all_edges, int ntx, int64_t nvb,
+    uint32_t *__restrict__ L, uint8_t *__restrict__ bb) {
     __shared__ int lab[CC_TH * CC_TW];
     __shared__ unsigned char rel[CC_TH * CC_TW];  // bit 0: right edge, bit 1: edge below
     const int ti = blockIdx.x / ntx, tj = blockIdx.x % ntx;
@@ -102,7 +128,6 @@ __global__ __launch_bounds__(256) void k_cc_local(
         const bool in = i < m && j < n;
         const int64_t p = (int64_t)i * n + j;
         const bool v = in && (!valid || valid[p]);
-        lab[t] = v ? t : -1;
         unsigned char b = 0;
         const bool has_r = in && c + 1 < CC_TW && j + 1 < n;
         const bool has_d = in && r + 1 < CC_TH && i + 1 < m;
@@ -113,7 +138,21 @@ __global__ __launch_bounds__(256) void k_cc_local(
             cc_down_ok(dky, cyp, cyn, n, i, j, T, all_edges))
             b |= 2;
         rel[t] = b;
+        // runs along the row: a wave holds two tile rows (lanes 0-31 and
+        // 32-63), a pixel starts a run unless the edge from its left
+        // neighbour is reliable (never across the two rows: lane 31 has no
+        // right edge), and it points at the first pixel of its run
+        const int lane = threadIdx.x & 63;
+        const unsigned long long starts = ~(__ballot(b & 1) << 1);
+        const int head = 63 - __clzll(starts & (~0ull >> (63 - lane)));
+        lab[t] = v ? t - lane + head : -1;
         if ((in && !v) || (has_r && !(b & 1)) || (has_d && !(b & 2))) whole = 0;
+        if (in && c == CC_TW - 1 && j + 1 < n)
+            bb[(int64_t)tj * m + i] = v && (!valid || valid[p + 1]) &&
+                                      cc_right_ok(dkx, cxp, cxn, n, i, j, T, all_edges);
+        if (in && r == CC_TH - 1 && i + 1 < m)
+            bb[nvb + (int64_t)ti * n + j] = v && (!valid || valid[p + n]) &&
+                                            cc_down_ok(dky, cyp, cyn, n, i, j, T, all_edges);
     }
     if (__syncthreads_and(whole)) {
         // one component: its smallest pixel is the tile's first
@@ -125,43 +164,64 @@ __global__ __launch_bounds__(256) void k_cc_local(
         }
         return;
     }
+    // other lanes hook roots while a union is in progress: read through a
+    // volatile view
+    volatile int *vlab = lab;
     auto find = [&](int x) {
-        int y = lab[x];
+        int y = vlab[x];
         while (y != x) {
             x = y;
-            y = lab[x];
+            y = vlab[x];
         }
         return x;
     };
-    // at most one hook round per pixel pair of the tile can change anything
-    for (int round = 0; round < CC_TH * CC_TW; ++round) {
-        int changed = 0;
+    // The runs are joined over the edges below.  A union hooks the larger
+    // root under the smaller by compare-and-swap and retries from fresh
+    // roots when another lane hooked one of them first; a union still open
+    // after CC_TRIES attempts is left to another pass.  Every failed attempt
+    // means another union succeeded, so each pass joins at least two runs.
+    const int lane = threadIdx.x & 63;
+    for (int pass = 0; pass < CC_TH * CC_TW; ++pass) {
+        int open = 0;
 #pragma unroll
         for (int k = 0; k < CC_PX; ++k) {
             const int t = threadIdx.x + 256 * k;
-            const unsigned char b = rel[t];
-            if (b & 1) {
-                const int a = find(t), q = find(t + 1);
-                if (a != q) {
-                    atomicMin(&lab[a > q ? a : q], a > q ? q : a);
-                    changed = 1;
+            bool act = rel[t] & 2;
+            int x = 0, y = 0;
+            if (act) {
+                x = find(t);
+                y = find(t + CC_TW);
+                if (x > y) {
+                    const int z = x;
+                    x = y;
+                    y = z;
                 }
+                act = x != y;
             }
-            if (b & 2) {
-                const int a = find(t), q = find(t + CC_TW);
-                if (a != q) {
-                    atomicMin(&lab[a > q ? a : q], a > q ? q : a);
-                    changed = 1;
+            // a row of edges below mostly joins the same two runs: a lane
+            // whose pair equals the previous lane's leaves the union to it
+            const int px = __shfl_up(x, 1, 64), py = __shfl_up(y, 1, 64);
+            const int pact = __shfl_up((int)act, 1, 64);
+            if (act && lane > 0 && pact && px == x && py == y) act = false;
+            if (!act) continue;
+            for (int tries = 0;; ++tries) {
+                const int old = atomicCAS(&lab[y], y, x);
+                if (old == y) break;
+                if (tries == CC_TRIES) {
+                    open = 1;
+                    break;
+                }
+                x = find(x);
+                y = find(old);
+                if (x == y) break;
+                if (x > y) {
+                    const int z = x;
+                    x = y;
+                    y = z;
                 }
             }
         }
-        if (!__syncthreads_or(changed)) break;
-#pragma unroll
-        for (int k = 0; k < CC_PX; ++k) {
-            const int t = threadIdx.x + 256 * k;
-            if (lab[t] >= 0) lab[t] = find(t);
-        }
-        __syncthreads();
+        if (!__syncthreads_or(open)) break;
     }
 #pragma unroll
     for (int k = 0; k < CC_PX; ++k) {
@@ -174,70 +234,90 @@ __global__ __launch_bounds__(256) void k_cc_local(
     }
 }
 
-// Hooks across tile borders only: the right edges of every tile's last
-// column and the edges below every tile's last row.
-__global__ void k_cc_hook_border(const int8_t *__restrict__ dkx, const int8_t *__restrict__ dky,
-                                 const int16_t *__restrict__ cxp, const int16_t *__restrict__ cxn,
-                                 const int16_t *__restrict__ cyp, const int16_t *__restrict__ cyn,
-                                 int m, int n, int T, int all_edges, int ntx, int nty, uint32_t *L,
-                                 CcState *st) {
-    const int64_t nvb = (int64_t)m * (ntx - 1), nhb = (int64_t)(nty - 1) * n;
-    int changed = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvb + nhb;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int i, j;
-        bool ok;
-        int64_t p, q;
-        if (k < nvb) {  // right edge of column (b + 1) CC_TW - 1
-            i = (int)(k / (ntx - 1));
-            j = (int)(k % (ntx - 1) + 1) * CC_TW - 1;
-            if (j + 1 >= n) continue;
-            p = (int64_t)i * n + j;
-            q = p + 1;
-            if (L[p] == CC_NONE || L[q] == CC_NONE) continue;
-            ok = cc_right_ok(dkx, cxp, cxn, n, i, j, T, all_edges);
-        } else {  // edge below row (b + 1) CC_TH - 1
-            const int64_t k2 = k - nvb;
-            i = (int)(k2 / n + 1) * CC_TH - 1;
-            j = (int)(k2 % n);
-            if (i + 1 >= m) continue;
-            p = (int64_t)i * n + j;
-            q = p + n;
-            if (L[p] == CC_NONE || L[q] == CC_NONE) continue;
-            ok = cc_down_ok(dky, cyp, cyn, n, i, j, T, all_edges);
-        }
-        if (!ok) continue;
-        const uint32_t a = cc_find(L, (uint32_t)p), b = cc_find(L, (uint32_t)q);
-        if (a != b) {
-            atomicMin(&L[a > b ? a : b], a > b ? b : a);
-            changed = 1;
-        }
+// Pixels on both sides of border edge k (the numbering of bb above).
+__device__ __forceinline__ void cc_border_edge(int64_t k, int m, int n, int64_t nvb, int64_t &p,
+                                               int64_t &q) {
+    if (k < nvb) {
+        const int b = (int)(k / m), i = (int)(k % m);
+        p = (int64_t)i * n + (int64_t)b * CC_TW + CC_TW - 1;
+        q = p + 1;
+    } else {
+        const int64_t k2 = k - nvb;
+        const int b = (int)(k2 / n), j = (int)(k2 % n);
+        p = ((int64_t)b * CC_TH + CC_TH - 1) * n + j;
+        q = p + n;
     }
-    if (__any(changed) && (threadIdx.x & 63) == 0) st->changed = 1;
 }
 
-// Path compression for the pixels on both sides of the tile-border edges
-// only (between border rounds; the full pass runs once at the end).
-__global__ void k_cc_jump_border(int m, int n, int ntx, int nty, uint32_t *L) {
-    const int64_t nvb = (int64_t)m * (ntx - 1), nhb = (int64_t)(nty - 1) * n;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvb + nhb;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t p, q;
-        if (k < nvb) {
-            const int i = (int)(k / (ntx - 1)), j = (int)(k % (ntx - 1) + 1) * CC_TW - 1;
-            if (j + 1 >= n) continue;
-            p = (int64_t)i * n + j;
-            q = p + 1;
-        } else {
-            const int64_t k2 = k - nvb;
-            const int i = (int)(k2 / n + 1) * CC_TH - 1, j = (int)(k2 % n);
-            if (i + 1 >= m) continue;
-            p = (int64_t)i * n + j;
-            q = p + n;
+// Unions across tile borders, over the edges marked in bb, by the same
+// compare-and-swap hooks as inside the tiles.  A failed attempt returns the
+// root's current pointer, from which the next attempt continues.  Unions
+// still open after CC_TRIES attempts (another union won each time, or this
+// XCD's cache still held an older pointer) raise st->changed, and the host
+// runs another pass after compressing the border pixels.
+__global__ __launch_bounds__(256) void k_cc_hook_border(const uint8_t *__restrict__ bb, int m,
+                                                        int n, int64_t nvb, int64_t nb,
+                                                        uint32_t *L, CcState *st) {
+    const int lane = threadIdx.x & 63;
+    int open = 0;
+    // the loop bound is the same for the whole workgroup, so that every
+    // lane takes part in the shuffle below
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nb;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = base + threadIdx.x;
+        bool act = k < nb && bb[k];
+        uint32_t x = 0, y = 0;
+        if (act) {
+            int64_t p, q;
+            cc_border_edge(k, m, n, nvb, p, q);
+            x = cc_find_halve(L, (uint32_t)p);
+            y = cc_find_halve(L, (uint32_t)q);
+            if (x > y) {
+                const uint32_t z = x;
+                x = y;
+                y = z;
+            }
+            act = x != y;
         }
+        // neighbouring border edges mostly join the same two roots: a lane
+        // whose pair equals the previous lane's leaves the union to it (if
+        // that one gives up, the next pass sees this edge again)
+        const uint32_t px = __shfl_up(x, 1, 64), py = __shfl_up(y, 1, 64);
+        const int pact = __shfl_up((int)act, 1, 64);
+        if (act && lane > 0 && pact && px == x && py == y) act = false;
+        if (!act) continue;
+        for (int tries = 0;; ++tries) {
+            const uint32_t old = atomicCAS(&L[y], y, x);
+            if (old == y) break;
+            if (tries == CC_TRIES) {
+                open = 1;
+                break;
+            }
+            x = cc_find_halve(L, x);
+            y = cc_find_halve(L, old);
+            if (x == y) break;
+            if (x > y) {
+                const uint32_t z = x;
+                x = y;
+                y = z;
+            }
+        }
+    }
+    if (__any(open) && lane == 0) st->changed = 1;
+}
+
+// Path compression for the pixels on both sides of the marked border edges
+// only (between border rounds; the full pass runs once at the end).
+__global__ void k_cc_jump_border(const uint8_t *__restrict__ bb, int m, int n, int64_t nvb,
+                                 int64_t nb, uint32_t *L) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (!bb[k]) continue;
+        int64_t p, q;
+        cc_border_edge(k, m, n, nvb, p, q);
         const uint32_t lp = L[p], lq = L[q];
-        if (lp != CC_NONE && lp != (uint32_t)p) L[p] = cc_find(L, lp);
-        if (lq != CC_NONE && lq != (uint32_t)q) L[q] = cc_find(L, lq);
+        if (lp != (uint32_t)p) L[p] = cc_find(L, lp);
+        if (lq != (uint32_t)q) L[q] = cc_find(L, lq);
     }
 }
 
@@ -279,12 +359,34 @@ __global__ __launch_bounds__(256) void k_cc_total(const uint32_t *__restrict__ v
 }
 
 // Component sizes at the roots.  Lanes of a wave holding the same root are
-// counted together (ballot), the wave's leader adds the count into a small
-// per-workgroup table in LDS (open addressing on the root index), and the
-// table is flushed to the global counters once at the end; a root that
-// finds no free slot is added to its global counter directly.
+// counted together (ballot); a count of at least CC_TABLE_MIN goes into a
+// small per-workgroup table in LDS (open addressing on the root index),
+// flushed to the global counters once at the end, so that a large
+// component's root takes one global atomic per workgroup rather than one
+// per wave.  Smaller counts, and roots that find no free slot, are added to
+// their global counters directly: these are spread over many addresses.
 constexpr int CC_SLOTS = 128;
 constexpr int CC_PROBES = 8;
+
+__device__ __forceinline__ void cc_table_add(uint32_t *keys, uint32_t *cnts, uint32_t *S,
+                                             uint32_t root, uint32_t c) {
+    uint32_t slot = (root * 2654435761u) % CC_SLOTS;
+    for (int probe = 0; probe < CC_PROBES; ++probe) {
+        const uint32_t k = atomicCAS(&keys[slot], CC_NONE, root);
+        if (k == CC_NONE || k == root) {
+            atomicAdd(&cnts[slot], c);
+            return;
+        }
+        slot = (slot + 1) % CC_SLOTS;
+    }
+    atomicAdd(&S[root], c);
+}
+
+// Every thread takes CC_SZV consecutive pixels per step (two 16-byte
+// loads); a wave whose 64 x CC_SZV pixels all share one root adds them in
+// one go, which is the common case inside large components.
+constexpr int CC_SZV = 8;
+constexpr uint32_t CC_TABLE_MIN = 16;
 
 __global__ __launch_bounds__(256) void k_cc_size(const uint32_t *__restrict__ L, int64_t N,
                                                  uint32_t *S) {
@@ -296,33 +398,49 @@ __global__ __launch_bounds__(256) void k_cc_size(const uint32_t *__restrict__ L,
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = base + threadIdx.x;
-        const uint32_t l = p < N ? L[p] : CC_NONE;
-        bool todo = l != CC_NONE;
-        for (;;) {
-            const unsigned long long pending = __ballot(todo);
-            if (!pending) break;
-            const int leader = __ffsll((long long)pending) - 1;
-            const uint32_t root = __shfl(l, leader, 64);
-            const unsigned long long same = __ballot(todo && l == root);
-            if (lane == leader) {
-                const uint32_t c = (uint32_t)__popcll(same);
-                uint32_t slot = (root * 2654435761u) % CC_SLOTS;
-                bool done = false;
-                for (int probe = 0; probe < CC_PROBES && !done; ++probe) {
-                    const uint32_t k = atomicCAS(&keys[slot], CC_NONE, root);
-                    if (k == CC_NONE || k == root) {
-                        atomicAdd(&cnts[slot], c);
-                        done = true;
-                    } else {
-                        slot = (slot + 1) % CC_SLOTS;
-                    }
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * CC_SZV;
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x * CC_SZV; b0 < N; b0 += step) {
+        const int64_t p = b0 + (int64_t)threadIdx.x * CC_SZV;
+        uint32_t v[CC_SZV];
+        if (p + CC_SZV <= N) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(L + p);
+            const uint4 y = *reinterpret_cast<const uint4 *>(L + p + 4);
+            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+            v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < CC_SZV; ++k) v[k] = p + k < N ? L[p + k] : CC_NONE;
+        }
+        bool uni = v[0] != CC_NONE;
+#pragma unroll
+        for (int k = 1; k < CC_SZV; ++k) uni = uni && v[k] == v[0];
+        const uint32_t w0 = __shfl(v[0], 0, 64);
+        if (__all(uni && v[0] == w0)) {
+            if (lane == 0) cc_table_add(keys, cnts, S, w0, 64u * CC_SZV);
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < CC_SZV; ++k) {
+            const uint32_t l = v[k];
+            bool todo = l != CC_NONE;
+            for (;;) {
+                const unsigned long long pending = __ballot(todo);
+                if (!pending) break;
+                const int leader = __ffsll((long long)pending) - 1;
+                const uint32_t root = __shfl(l, leader, 64);
+                const unsigned long long same = __ballot(todo && l == root);
+                if (lane == leader) {
+                    // small counts (mostly the roots of one-pixel components)
+                    // go straight to their own global counters, which keeps
+                    // the table for the few large components
+                    const uint32_t c = (uint32_t)__popcll(same);
+                    if (c >= CC_TABLE_MIN)
+                        cc_table_add(keys, cnts, S, root, c);
+                    else
+                        atomicAdd(&S[root], c);
                 }
-                if (!done) atomicAdd(&S[root], c);
+                if (todo && l == root) todo = false;
             }
-            if (todo && l == root) todo = false;
         }
     }
     __syncthreads();
@@ -330,10 +448,22 @@ __global__ __launch_bounds__(256) void k_cc_size(const uint32_t *__restrict__ L,
         if (keys[t] != CC_NONE) atomicAdd(&S[keys[t]], cnts[t]);
 }
 
-// qualifying roots: L[p] == p and size >= min_size
-__device__ __forceinline__ int cc_flag(const uint32_t *L, const uint32_t *S, int64_t p, int64_t N,
-                                       uint32_t min_size) {
-    return p < N && L[p] == (uint32_t)p && S[p] >= min_size;
+// the CC_PER pointers of pixels p0 ... p0 + CC_PER - 1 (CC_NONE past N)
+__device__ __forceinline__ void cc_load_run(const uint32_t *__restrict__ L, int64_t p0, int64_t N,
+                                            uint32_t v[CC_PER]) {
+    if (p0 + CC_PER <= N) {
+#pragma unroll
+        for (int k = 0; k < CC_PER; k += 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(L + p0 + k);
+            v[k] = x.x;
+            v[k + 1] = x.y;
+            v[k + 2] = x.z;
+            v[k + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < CC_PER; ++k) v[k] = p0 + k < N ? L[p0 + k] : CC_NONE;
+    }
 }
 
 __device__ int cc_block_scan(int v, int *total) {
@@ -362,8 +492,12 @@ __global__ __launch_bounds__(CC_THREADS) void k_cc_count(const uint32_t *__restr
                                                          const CcState *st, uint32_t *chunk_sum) {
     const uint32_t min_size = st->min_size;
     const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
+    uint32_t v[CC_PER];
+    cc_load_run(L, p0, N, v);
     int c = 0;
-    for (int k = 0; k < CC_PER; ++k) c += cc_flag(L, S, p0 + k, N, min_size);
+#pragma unroll
+    for (int k = 0; k < CC_PER; ++k)
+        c += v[k] == (uint32_t)(p0 + k) && S[p0 + k] >= min_size;
     int tot;
     (void)cc_block_scan(c, &tot);
     if (threadIdx.x == 0) chunk_sum[blockIdx.x] = (uint32_t)tot;
@@ -391,17 +525,20 @@ __global__ __launch_bounds__(CC_THREADS) void k_cc_rank(const uint32_t *__restri
                                                         uint32_t *__restrict__ sizes_out) {
     const uint32_t min_size = st->min_size;
     const int64_t p0 = (int64_t)blockIdx.x * CC_CHUNK + (int64_t)threadIdx.x * CC_PER;
+    uint32_t v[CC_PER];
+    cc_load_run(L, p0, N, v);
     int f[CC_PER];
     int c = 0;
+#pragma unroll
     for (int k = 0; k < CC_PER; ++k) {
-        f[k] = cc_flag(L, S, p0 + k, N, min_size);
+        f[k] = v[k] == (uint32_t)(p0 + k) && S[p0 + k] >= min_size;
         c += f[k];
     }
     int tot;
     uint32_t r = chunk_off[blockIdx.x] + (uint32_t)cc_block_scan(c, &tot);
     for (int k = 0; k < CC_PER; ++k) {
         const int64_t p = p0 + k;
-        if (p < N && L[p] == (uint32_t)p) {
+        if (v[k] == (uint32_t)p) {
             // roots are written only by the thread that owns them
             if (f[k]) {
                 ++r;
@@ -445,24 +582,29 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
     uint32_t *vpart = chunk + nchunks;
     WW_TRY(host_scratch(sizeof(CcState), (void **)&hcs));
     WW_HIP(hipMemsetAsync(cs, 0, sizeof(CcState), st));
-    WW_HIP(hipMemsetAsync(S, 0, sizeof(uint32_t) * (size_t)N, st));
-    // components inside tiles first, then joins across tile borders
+    // components inside tiles first, then joins across tile borders; the
+    // border-edge bytes live in the size buffer until the sizes are counted
+    // (at most N / 16 bytes)
     const int ntx = (n + CC_TW - 1) / CC_TW, nty = (m + CC_TH - 1) / CC_TH;
     if ((int64_t)ntx * nty >= ((int64_t)1 << 31)) return fail(WW_E_INVALID_ARG, "image too large");
+    const int64_t nvb = (int64_t)m * (ntx - 1), nborder = nvb + (int64_t)(nty - 1) * n;
+    uint8_t *bb = reinterpret_cast<uint8_t *>(S);
     hipLaunchKernelGGL(k_cc_local, dim3((unsigned)(ntx * nty)), dim3(256), 0, st, dkx, dky, cxp,
-                       cxn, cyp, cyn, valid, m, n, threshold, all_edges, ntx, L);
+                       cxn, cyp, cyn, valid, m, n, threshold, all_edges, ntx, nvb, L, bb);
     WW_LAUNCH_CHECK();
-    const int64_t nborder = (int64_t)m * (ntx - 1) + (int64_t)(nty - 1) * n;
     const int bgrid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (nborder + 255) / 256));
-    // union-find rounds until a hook round changes nothing (each round that
-    // changes something merges at least two components, so at most N rounds)
-    for (int64_t round = 0;; ++round) {
-        if (round > N + 1) return fail(WW_E_DEVICE, "connected components did not converge");
+    // border passes until no union is left open (each pass with open unions
+    // completes at least one, so at most N passes)
+    for (int64_t pass = 0;; ++pass) {
+        if (pass > N + 1) return fail(WW_E_DEVICE, "connected components did not converge");
+        if (pass > 0) {
+            hipLaunchKernelGGL(k_cc_jump_border, dim3(bgrid), dim3(256), 0, st, bb, m, n, nvb,
+                               nborder, L);
+            WW_LAUNCH_CHECK();
+        }
         WW_HIP(hipMemsetAsync(&cs->changed, 0, sizeof(unsigned int), st));
-        hipLaunchKernelGGL(k_cc_hook_border, dim3(bgrid), dim3(256), 0, st, dkx, dky, cxp, cxn,
-                           cyp, cyn, m, n, threshold, all_edges, ntx, nty, L, cs);
-        WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cc_jump_border, dim3(bgrid), dim3(256), 0, st, m, n, ntx, nty, L);
+        hipLaunchKernelGGL(k_cc_hook_border, dim3(bgrid), dim3(256), 0, st, bb, m, n, nvb, nborder,
+                           L, cs);
         WW_LAUNCH_CHECK();
         WW_HIP(hipMemcpyAsync(hcs, cs, sizeof(CcState), hipMemcpyDeviceToHost, st));
         WW_HIP(hipStreamSynchronize(st));
@@ -472,9 +614,10 @@ ww_status components_impl(const int8_t *dkx, const int8_t *dky, const int16_t *c
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_total, dim3(1), dim3(256), 0, st, vpart, grid, min_size_frac, cs);
     WW_LAUNCH_CHECK();
-    // fewer workgroups for the sizes: each flushes its table of roots with
-    // global atomics, and a large component's root takes one from every one
-    const int sgrid = std::min(grid, 2048);
+    WW_HIP(hipMemsetAsync(S, 0, sizeof(uint32_t) * (size_t)N, st));
+    // each workgroup flushes its table of roots with global atomics, and a
+    // large component's root takes one from every workgroup: 4096 at most
+    const int sgrid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (N + 2047) / 2048));
     hipLaunchKernelGGL(k_cc_size, dim3(sgrid), dim3(256), 0, st, L, N, S);
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_count, dim3(nchunks), dim3(CC_THREADS), 0, st, L, S, N, cs, chunk);
