@@ -21,13 +21,13 @@ def torch_cuda():
     return torch
 
 
-def random_solution(seed, m, n, zero_frac=0.8, cmax=700):
+def random_solution(seed, m, n, zero_frac=0.8, cmax=700, invalid=0.1):
     rng = np.random.default_rng(seed)
     dkx = np.where(rng.random((m, n - 1)) < zero_frac, 0, rng.choice([-1, 1], (m, n - 1))).astype(np.int8)
     dky = np.where(rng.random((m - 1, n)) < zero_frac, 0, rng.choice([-1, 1], (m - 1, n))).astype(np.int8)
     costs = [rng.integers(0, cmax, s).astype(np.int16)
              for s in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n))]
-    valid = (rng.random((m, n)) > 0.1).astype(np.uint8)
+    valid = (rng.random((m, n)) > invalid).astype(np.uint8)
     return dkx, dky, costs, valid
 
 
@@ -59,6 +59,42 @@ def test_components_long_snakes(torch_cuda):
         dky[i, :] = 1
         dky[i, (n - 1) if i % 2 == 0 else 0] = 0
     check(dkx, dky, hi, None, 300, 0.0)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_components_snake_across_tiles(torch_cuda, transpose):
+    """One serpentine component over many tiles: every row (or column) is
+    joined to the next at alternating ends, so the unions form chains
+    across tile borders in both directions."""
+    m, n = (200, 333) if not transpose else (333, 200)
+    dkx = np.zeros((m, n - 1), np.int8)
+    dky = np.zeros((m - 1, n), np.int8)
+    hi = [np.full(s, 1000, np.int16) for s in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n))]
+    if not transpose:
+        for i in range(m - 1):
+            dky[i, :] = 1
+            dky[i, (n - 1) if i % 2 == 0 else 0] = 0
+    else:
+        for j in range(n - 1):
+            dkx[:, j] = 1
+            dkx[(m - 1) if j % 2 == 0 else 0, j] = 0
+    check(dkx, dky, hi, None, 300, 0.0)
+    lab, nc = ww.connected_components(dkx, dky, hi, np.ones((m, n), np.uint8),
+                                      ww.default_cc_params(threshold=300, min_size_frac=0.0))
+    assert nc == 1
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_components_large_with_holes(torch_cuda, seed):
+    """Few large components with scattered holes and single-pixel islands
+    over hundreds of tiles: many border edges join the same two roots."""
+    m, n = 701, 1103
+    dkx, dky, costs, valid = random_solution(seed, m, n, zero_frac=0.997, cmax=30000, invalid=0.02)
+    # T = 8000 leaves about 54 % of the edges reliable: near percolation,
+    # large fractal components
+    for T, frac in ((10, 0.0), (10, 0.001), (8000, 0.0), (20000, 0.0)):
+        check(dkx, dky, costs, valid, T, frac)
+    check(dkx, dky, costs, None, 10, 0.0)
 
 
 def test_components_of_the_oracle_solution(torch_cuda):
