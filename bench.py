@@ -49,7 +49,7 @@ def round_kernel_sha() -> str:
     import hashlib
     txt = open(os.path.join(ROOT, "paper_2609_36267_amd", "csrc", "mcf.hip")).read()
     a = txt.index("__device__ __forceinline__ void relax_one(")
-    b = txt.index("// smallest parked candidate over the tiles")
+    b = txt.index("__global__ void k_requeue_pending(")
     return hashlib.sha256(txt[a:b].encode()).hexdigest()[:16]
 
 

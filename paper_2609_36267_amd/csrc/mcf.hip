@@ -65,14 +65,14 @@ struct Ctl {
     unsigned int nsrc2, ndef2; // compaction targets
     unsigned int gsub_count;   // ground-rooted subtrees with a deficit
     unsigned int gpred;        // ground predecessor (perimeter arc index)
-    unsigned int settled;      // deficits reached in the window
+    unsigned int wsettled[2];  // deficits reached in the window (by window parity)
     unsigned int naug;         // augmentations in this pass
     unsigned long long arcs;   // arcs flipped in this pass
     int error;
     int max_pot;
     long long total_cost;
     long long sum_res;
-    unsigned long long min_rej; // smallest candidate label beyond the window
+    unsigned long long wminrej[2];  // smallest candidate beyond the window (by parity)
     unsigned long long iters;   // in-tile relaxation iterations, all visits
     unsigned long long vt_sum;  // visit durations (wall-clock ticks), all visits
     unsigned long long vt_max;  // longest visit
@@ -231,6 +231,7 @@ __global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict_
         ctl->gex = -sum;
         ctl->gpot = 0;
         ctl->glab = LINF;
+        ctl->wminrej[0] = ctl->wminrej[1] = LINF;
     }
 }
 
@@ -278,7 +279,16 @@ __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned
         for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x)
             activate(act, lists, NT, ctl, perim_tiles[k], rr);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->glab = ground_source ? 0ull : LINF;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->glab = ground_source ? 0ull : LINF;
+        // per-pass counters back to zero (none of them is read by this kernel)
+        ctl->naug = 0;
+        ctl->gsub_count = 0;
+        ctl->gpred = 0xffffffffu;
+        ctl->arcs = 0;
+        ctl->nsrc2 = 0;
+        ctl->ndef2 = 0;
+    }
 }
 
 // ------------------------------------------------------ relaxation round ---
@@ -619,23 +629,6 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         atomicAdd(&ra.vpart[(blockIdx.x % 64) * 16], (unsigned long long)my_visits);
 }
 
-// smallest parked candidate over the tiles that parked one in this pass
-__global__ void k_min_pending(Ctl *ctl, const unsigned int *pstamp, unsigned int pass,
-                              const unsigned long long *tile_rej, unsigned int NT) {
-    unsigned long long mn = LINF;
-    for (unsigned int t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x)
-        if (pstamp[t] == pass) {
-            const unsigned long long r = tile_rej[t];
-            mn = r < mn ? r : mn;
-        }
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_down(mn, off, 64);
-        mn = o < mn ? o : mn;
-    }
-    if ((threadIdx.x & 63) == 0 && mn != LINF) atomicMin(&ctl->min_rej, mn);
-}
-
-// activate, for round rr, the tiles whose parked candidates the window admits
 __global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pstamp, unsigned int pass,
                                   const unsigned long long *tile_rej, unsigned long long lb,
                                   unsigned int *act, unsigned int *lists, unsigned int NT,
@@ -644,19 +637,41 @@ __global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pstamp, unsigned
         if (pstamp[t] == pass && tile_rej[t] <= lb) activate(act, lists, NT, ctl, t, rr);
 }
 
-__global__ void k_count_settled(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb) {
+// End of a window, in one launch: the deficits settled in it (a settled
+// ground absorbs all of its deficit units) and the smallest candidate parked
+// by a tile in this pass, in the counters of window parity w; the other
+// parity's counters are cleared for the next window.
+__global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb,
+                             const unsigned int *pstamp, unsigned int pass,
+                             const unsigned long long *tile_rej, unsigned int NT, int w) {
     const unsigned int nd = ctl->ndef;
     unsigned int c = 0;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += gridDim.x * blockDim.x) {
         const unsigned long long l = g.lab[def[k]];
         if (l <= lb) ++c;
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&ctl->settled, c);
-    // a settled ground absorbs all of its deficit units
+    unsigned long long mn = LINF;
+    for (unsigned int t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x)
+        if (pstamp[t] == pass) {
+            const unsigned long long r = tile_rej[t];
+            mn = r < mn ? r : mn;
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        const unsigned long long o = __shfl_down(mn, off, 64);
+        mn = o < mn ? o : mn;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c) atomicAdd(&ctl->wsettled[w], c);
+        // only a wave that may lower the minimum takes the atomic
+        if (mn != LINF && mn < *(volatile unsigned long long *)&ctl->wminrej[w])
+            atomicMin(&ctl->wminrej[w], mn);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
-        if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->settled, (unsigned int)(-ctl->gex));
+        if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->wsettled[w], (unsigned int)(-ctl->gex));
+        ctl->wsettled[w ^ 1] = 0;
+        ctl->wminrej[w ^ 1] = LINF;
     }
 }
 
@@ -870,31 +885,61 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
     }
 }
 
-// pot(v) += B - d(v) on every reached node, labels back to infinity.
-__global__ void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp, unsigned int pass,
-                             unsigned int NT, unsigned long long lb) {
+// pot(v) += B - d(v) on every reached node, labels back to infinity.  Each
+// workgroup checks the stamps of POT_CHUNK tiles at once and then updates
+// only the tiles relaxed in this pass, so that a pass that reached a few
+// tiles costs little more than one read of the stamps.  The relaxed tiles
+// of a pass lie close together, so chunks are kept small: a workgroup
+// updates at most POT_CHUNK tiles one after another.
+constexpr int POT_CHUNK = 8;
+
+__global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
+                                                    unsigned int pass, unsigned int NT,
+                                                    unsigned long long lb) {
+    __shared__ unsigned int todo[POT_CHUNK];
+    __shared__ int ntodo;
     const unsigned int bound = ldist(lb);
     int mx = 0;
-    for (unsigned int tile = blockIdx.x; tile < NT; tile += gridDim.x) {
-        if (tstamp[tile] != pass) continue;
-        const int i0 = (tile / g.TC) * g.th, j0 = (tile % g.TC) * g.tw;
-        for (int t = threadIdx.x; t < g.th * g.tw; t += blockDim.x) {
-            const int i = i0 + t / g.tw, j = j0 + t % g.tw;
-            if (i >= g.R || j >= g.C) continue;
-            const long long v = (long long)i * g.C + j;
-            const unsigned long long l = g.lab[v];
-            if (l == LINF) continue;
-            g.lab[v] = LINF;
-            const unsigned int d = ldist(l);
-            if (l > lb) continue;
-            const long long np = (long long)g.pot[v] + (bound - d);
-            if (np > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
-            g.pot[v] = (int)min(np, (long long)POT_LIMIT);
-            mx = max(mx, (int)min(np, (long long)POT_LIMIT));
+    for (unsigned int base = blockIdx.x * POT_CHUNK; base < NT; base += gridDim.x * POT_CHUNK) {
+        if (threadIdx.x == 0) ntodo = 0;
+        __syncthreads();
+        if (threadIdx.x < POT_CHUNK) {
+            const unsigned int tile = base + threadIdx.x;
+            if (tile < NT && tstamp[tile] == pass) todo[atomicAdd(&ntodo, 1)] = tile;
         }
+        __syncthreads();
+        const int nt = ntodo;
+        for (int k = 0; k < nt; ++k) {
+            const unsigned int tile = todo[k];
+            const int i0 = (int)(tile / g.TC) * TJ, j0 = (int)(tile % g.TC) * TJ;
+            long long v[TJ * TJ / 256];
+            unsigned long long l[TJ * TJ / 256];
+#pragma unroll
+            for (int s = 0; s < TJ * TJ / 256; ++s) {
+                const int t = threadIdx.x + 256 * s;
+                const int i = i0 + t / TJ, j = j0 + t % TJ;
+                v[s] = (i < g.R && j < g.C) ? (long long)i * g.C + j : -1;
+                l[s] = v[s] >= 0 ? g.lab[v[s]] : LINF;
+            }
+#pragma unroll
+            for (int s = 0; s < TJ * TJ / 256; ++s) {
+                if (l[s] == LINF) continue;
+                g.lab[v[s]] = LINF;
+                if (l[s] > lb) continue;
+                const unsigned int d = ldist(l[s]);
+                const long long np = (long long)g.pot[v[s]] + (bound - d);
+                if (np > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
+                g.pot[v[s]] = (int)min(np, (long long)POT_LIMIT);
+                mx = max(mx, (int)min(np, (long long)POT_LIMIT));
+            }
+        }
+        __syncthreads();
     }
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_down(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(&ctl->max_pot, mx);
+    // only a wave that may raise the maximum takes the atomic: thousands of
+    // atomics on one address from every wave cost more than the updates
+    if ((threadIdx.x & 63) == 0 && mx > 0 && mx > *(volatile int *)&ctl->max_pot)
+        atomicMax(&ctl->max_pot, mx);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
         if (gl <= lb) {
@@ -957,36 +1002,34 @@ __global__ void k_check_rc(Graph g, const Ctl *ctl, const unsigned long long *la
     }
 }
 
-// keep supplies / demands that still carry excess
+// keep supplies / demands that still carry excess; one counter atomic per
+// wave and list (the lanes' slots follow from a ballot)
 __global__ void k_compact(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *def,
                           unsigned int *src2, unsigned int *def2) {
     const unsigned int ns = ctl->nsrc, nd = ctl->ndef;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns + nd;
-         k += gridDim.x * blockDim.x) {
-        if (k < ns) {
-            const unsigned int v = src[k];
-            if (g.ex[v] > 0) src2[atomicAdd(&ctl->nsrc2, 1u)] = v;
-        } else {
-            const unsigned int v = def[k - ns];
-            if (g.ex[v] < 0) def2[atomicAdd(&ctl->ndef2, 1u)] = v;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // the loop bound is the same for every lane of a wave (blockDim is a
+    // multiple of 64), so that all lanes take part in the ballots
+    for (unsigned int base = blockIdx.x * blockDim.x; base < ns + nd; base += gridDim.x * blockDim.x) {
+        const unsigned int k = base + threadIdx.x;
+        const bool in = k < ns + nd;
+        const bool is_src = in && k < ns;
+        const unsigned int v = !in ? 0u : (is_src ? src[k] : def[k - ns]);
+        const bool keep_s = is_src && g.ex[v] > 0;
+        const bool keep_d = in && !is_src && g.ex[v] < 0;
+        const unsigned long long ms = __ballot(keep_s), md = __ballot(keep_d);
+        unsigned int bs = 0, bd = 0;
+        if (lane == 0) {
+            if (ms) bs = atomicAdd(&ctl->nsrc2, (unsigned int)__popcll(ms));
+            if (md) bd = atomicAdd(&ctl->ndef2, (unsigned int)__popcll(md));
         }
+        bs = __shfl(bs, 0, 64);
+        bd = __shfl(bd, 0, 64);
+        if (keep_s) src2[bs + __popcll(ms & below)] = v;
+        if (keep_d) def2[bd + __popcll(md & below)] = v;
     }
 }
-
-// per-pass counters back to zero (node lists untouched)
-__global__ void k_pass_reset(Ctl *ctl) {
-    ctl->settled = 0;
-    ctl->naug = 0;
-    ctl->gsub_count = 0;
-    ctl->gpred = 0xffffffffu;
-    ctl->min_rej = LINF;
-    ctl->arcs = 0;
-    ctl->nsrc2 = 0;
-    ctl->ndef2 = 0;
-}
-
-__global__ void k_clear_settled(Ctl *ctl) { ctl->settled = 0; }
-__global__ void k_clear_minrej(Ctl *ctl) { ctl->min_rej = LINF; }
 
 __global__ void k_swap_lists(Ctl *ctl) {
     ctl->nsrc = ctl->nsrc2;
@@ -1207,6 +1250,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     };
     const bool trace_windows = trace_env && trace_env[0] == '2';
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
+    const int pot_grid = (int)std::min<unsigned int>((NT + POT_CHUNK - 1) / POT_CHUNK, 16384u);
     const unsigned int bound_cap = 0xffff0000u;
     unsigned int rr = 1, pass = 0;  // next round, current pass
     const int SB = 256;
@@ -1234,8 +1278,6 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         const unsigned int nsrc0 = h->nsrc;
         const long long gex0 = h->gex;
         ++pass;
-        hipLaunchKernelGGL(k_pass_reset, dim3(1), dim3(1), 0, st, ctl);
-        WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.act,
                            ra.lists, NT, rr, gsrc, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
@@ -1244,6 +1286,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         // zero-distance labels within h0 hops; later windows jump to the
         // smallest rejected candidate and grow the hop or distance limit.
         unsigned long long lb = mk_label(0, h0);
+        unsigned int settled = 0;  // deficits settled by the last window
         unsigned int dstep = dstep0;
         for (;;) {  // windows
             ++S.windows;
@@ -1266,30 +1309,28 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 S.relax_ms += ms;
                 if (h->count[rr % 3][0] == 0) break;
             }
-            hipLaunchKernelGGL(k_clear_settled, dim3(1), dim3(1), 0, st, ctl);
-            WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_count_settled, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, lb);
+            // settled deficits and the smallest parked candidate in one
+            // launch and one round trip (the candidate is only read when the
+            // window does not end the pass)
+            const int wpar = (int)(S.windows & 1);
+            const int tg = (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB);
+            hipLaunchKernelGGL(k_window_end, dim3(std::max(list_grid, tg)), dim3(SB), 0, st, g, ctl,
+                               def, lb, ra.pstamp, pass, ra.tile_rej, NT, wpar);
             WW_LAUNCH_CHECK();
             WW_TRY(sync_ctl());
+            settled = h->wsettled[wpar];
             if (trace_windows)
                 fprintf(stderr, "[ww-mcf]   window %u/%u rounds %lld settled %u\n",
                         (unsigned)(lb >> 32), (unsigned)((lb >> 3) & 0x1fffffffu), S.rounds - rw0,
-                        h->settled);
+                        settled);
             // stop rule: all units in a full pass, else the first deficit or
             // half of the units
             const long long units = (long long)h->nsrc + std::max<long long>(h->gex, 0);
             const long long need = pass <= full_passes ? std::max<long long>(1, units)
                                    : first_deficit    ? 1
                                                       : std::max<long long>(1, (units + 1) / 2);
-            if ((long long)h->settled >= need) break;
-            hipLaunchKernelGGL(k_clear_minrej, dim3(1), dim3(1), 0, st, ctl);
-            WW_LAUNCH_CHECK();
-            const int tg = (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB);
-            hipLaunchKernelGGL(k_min_pending, dim3(tg), dim3(SB), 0, st, ctl, ra.pstamp, pass,
-                               ra.tile_rej, NT);
-            WW_LAUNCH_CHECK();
-            WW_TRY(sync_ctl());
-            const unsigned long long mr = h->min_rej;
+            if ((long long)settled >= need) break;
+            const unsigned long long mr = h->wminrej[wpar];
             if (mr == LINF) break;  // every reachable node is settled
             const unsigned int d = (unsigned int)(lb >> 32), hcur = (unsigned int)((lb >> 3) & 0x1fffffffu);
             if ((unsigned int)(mr >> 32) == d && d == 0) {
@@ -1307,7 +1348,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                                ra.tile_rej, lb, ra.act, ra.lists, NT, rr);
             WW_LAUNCH_CHECK();
         }
-        if (h->settled == 0)
+        if (settled == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: %u supplies reach no demand", h->nsrc);
         const int pg = (int)std::min<long long>(1024, ceil_div(nperim_arcs, SB));
         hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, lb);
@@ -1321,7 +1362,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         if (check)
             WW_HIP(hipMemcpyAsync(lab_copy, g.lab, sizeof(unsigned long long) * N,
                                   hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_potentials, dim3(round_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass,
+        hipLaunchKernelGGL(k_potentials, dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass,
                            NT, lb);
         WW_LAUNCH_CHECK();
         if (check) {
