@@ -1251,10 +1251,13 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const bool trace_windows = trace_env && trace_env[0] == '2';
     const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
     const int pot_grid = (int)std::min<unsigned int>((NT + POT_CHUNK - 1) / POT_CHUNK, 16384u);
+    unsigned long long nbatch = 0;  // round batches so far (their parity picks the window-end slot)
+    int wslot = 0;
     const unsigned int bound_cap = 0xffff0000u;
     unsigned int rr = 1, pass = 0;  // next round, current pass
     const int SB = 256;
     const int list_grid = (int)std::min<long long>(4096, std::max<long long>(1, ceil_div(N, 256)));
+    const int we_grid = std::max(list_grid, (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB));
     std::vector<unsigned long long> hv(64 * 16);
     auto host_visits = [&]() -> unsigned long long {
         if (hipMemcpy(hv.data(), ra.vpart, 8192, hipMemcpyDeviceToHost) != hipSuccess) return 0;
@@ -1300,6 +1303,13 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                     ++rr;
                 }
                 WW_HIP(hipEventRecord(ev[1], st));
+                // the window-end counts after every batch, so that the batch
+                // that ends the window needs no further round trip (each run
+                // writes the slot of its batch parity and clears the other)
+                wslot = (int)(nbatch++ & 1);
+                hipLaunchKernelGGL(k_window_end, dim3(we_grid), dim3(SB), 0, st, g, ctl, def, lb,
+                                   ra.pstamp, pass, ra.tile_rej, NT, wslot);
+                WW_LAUNCH_CHECK();
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
                     return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
@@ -1309,16 +1319,10 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 S.relax_ms += ms;
                 if (h->count[rr % 3][0] == 0) break;
             }
-            // settled deficits and the smallest parked candidate in one
-            // launch and one round trip (the candidate is only read when the
-            // window does not end the pass)
-            const int wpar = (int)(S.windows & 1);
+            // settled deficits and the smallest parked candidate (the latter
+            // is only read when the window does not end the pass)
             const int tg = (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB);
-            hipLaunchKernelGGL(k_window_end, dim3(std::max(list_grid, tg)), dim3(SB), 0, st, g, ctl,
-                               def, lb, ra.pstamp, pass, ra.tile_rej, NT, wpar);
-            WW_LAUNCH_CHECK();
-            WW_TRY(sync_ctl());
-            settled = h->wsettled[wpar];
+            settled = h->wsettled[wslot];
             if (trace_windows)
                 fprintf(stderr, "[ww-mcf]   window %u/%u rounds %lld settled %u\n",
                         (unsigned)(lb >> 32), (unsigned)((lb >> 3) & 0x1fffffffu), S.rounds - rw0,
@@ -1330,7 +1334,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                                    : first_deficit    ? 1
                                                       : std::max<long long>(1, (units + 1) / 2);
             if ((long long)settled >= need) break;
-            const unsigned long long mr = h->wminrej[wpar];
+            const unsigned long long mr = h->wminrej[wslot];
             if (mr == LINF) break;  // every reachable node is settled
             const unsigned int d = (unsigned int)(lb >> 32), hcur = (unsigned int)((lb >> 3) & 0x1fffffffu);
             if ((unsigned int)(mr >> 32) == d && d == 0) {
