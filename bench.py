@@ -37,20 +37,24 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
-TRAFFIC_SOURCE_SHA = "13277593c7988297"
+TRAFFIC_SOURCE_SHA = "67ac132090b6030a"
 TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024)
-TRAFFIC_BYTES_PER_LAUNCH = 10.22e6
+TRAFFIC_BYTES_PER_LAUNCH = 10.91e6
 
 
 def round_kernel_sha() -> str:
     """Hash of the source text of the relaxation-round kernel and the device
     helpers it calls (csrc/mcf.hip, from relax_one to the end of
-    k_sssp_round): the measured traffic belongs to that code only."""
+    k_sssp_round) and of the number of rounds launched per host check (the
+    share of empty launches in the per-launch average): the measured traffic
+    belongs to that code only."""
     import hashlib
     txt = open(os.path.join(ROOT, "paper_2609_36267_amd", "csrc", "mcf.hip")).read()
     a = txt.index("__device__ __forceinline__ void relax_one(")
     b = txt.index("__global__ void k_requeue_pending(")
-    return hashlib.sha256(txt[a:b].encode()).hexdigest()[:16]
+    c = txt.index("#define WW_ROUNDS_PER_SYNC")
+    d = txt.index("\n", c)
+    return hashlib.sha256((txt[a:b] + txt[c:d]).encode()).hexdigest()[:16]
 
 
 def parse():

@@ -639,11 +639,19 @@ __global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pstamp, unsigned
 
 // End of a window, in one launch: the deficits settled in it (a settled
 // ground absorbs all of its deficit units) and the smallest candidate parked
-// by a tile in this pass, in the counters of window parity w; the other
-// parity's counters are cleared for the next window.
+// by a tile in this pass, in the counters of slot w; the other slot's
+// counters are cleared for the next launch.  The host launches it after
+// every batch of rounds; it counts only when the list of round rr is empty,
+// i.e. when the batch ended the window.
 __global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb,
                              const unsigned int *pstamp, unsigned int pass,
-                             const unsigned long long *tile_rej, unsigned int NT, int w) {
+                             const unsigned long long *tile_rej, unsigned int NT, int w,
+                             unsigned int rr) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->wsettled[w ^ 1] = 0;
+        ctl->wminrej[w ^ 1] = LINF;
+    }
+    if (ctl->count[rr % 3][0] != 0) return;
     const unsigned int nd = ctl->ndef;
     unsigned int c = 0;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += gridDim.x * blockDim.x) {
@@ -670,8 +678,6 @@ __global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigne
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
         if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->wsettled[w], (unsigned int)(-ctl->gex));
-        ctl->wsettled[w ^ 1] = 0;
-        ctl->wminrej[w ^ 1] = LINF;
     }
 }
 
@@ -1227,7 +1233,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         WW_HIP(hipHostMalloc(&hcrec, sizeof(CheckRec)));
     }
 #ifndef WW_ROUNDS_PER_SYNC
-#define WW_ROUNDS_PER_SYNC 8
+#define WW_ROUNDS_PER_SYNC 12
 #endif
     // relaxation rounds launched between two host checks of the list
     // lengths (a round whose list is empty returns at once)
@@ -1308,7 +1314,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 // writes the slot of its batch parity and clears the other)
                 wslot = (int)(nbatch++ & 1);
                 hipLaunchKernelGGL(k_window_end, dim3(we_grid), dim3(SB), 0, st, g, ctl, def, lb,
-                                   ra.pstamp, pass, ra.tile_rej, NT, wslot);
+                                   ra.pstamp, pass, ra.tile_rej, NT, wslot, rr);
                 WW_LAUNCH_CHECK();
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
