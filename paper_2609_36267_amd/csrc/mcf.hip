@@ -1042,6 +1042,34 @@ __global__ void k_swap_lists(Ctl *ctl) {
     ctl->ndef = ctl->ndef2;
 }
 
+// a[k] = -a[k] for k < n, 16 bytes per thread and step (SWAR negation of
+// the bytes, or of the words), with scalar head and tail where a is not
+// 16-byte aligned
+__device__ __forceinline__ unsigned int neg_bytes(unsigned int w) {
+    const unsigned int y = ~w;  // -x = ~x + 1 in every byte, no carry across bytes
+    return ((y & 0x7f7f7f7fu) + 0x01010101u) ^ (y & 0x80808080u);
+}
+
+template <typename T>
+__device__ __forceinline__ void negate_span(T *a, long long n, long long tid, long long stride) {
+    constexpr int V = 16 / (int)sizeof(T);
+    const long long head =
+        min(n, (long long)(((16u - ((unsigned int)(uintptr_t)a & 15u)) & 15u) / sizeof(T)));
+    for (long long k = tid; k < head; k += stride) a[k] = (T)-a[k];
+    const long long nvec = (n - head) / V;
+    uint4 *v = reinterpret_cast<uint4 *>(a + head);
+    for (long long k = tid; k < nvec; k += stride) {
+        uint4 x = v[k];
+        if (sizeof(T) == 1) {
+            x.x = neg_bytes(x.x); x.y = neg_bytes(x.y); x.z = neg_bytes(x.z); x.w = neg_bytes(x.w);
+        } else {
+            x.x = 0u - x.x; x.y = 0u - x.y; x.z = 0u - x.z; x.w = 0u - x.w;
+        }
+        v[k] = x;
+    }
+    for (long long k = head + nvec * V + tid; k < n; k += stride) a[k] = (T)-a[k];
+}
+
 // The reversed problem: every arc turned round, supplies and demands
 // exchanged.  Its residual arc v -> u across an edge has the cost of the
 // original residual arc u -> v when the net flows are negated and the two
@@ -1050,16 +1078,12 @@ __global__ void k_swap_lists(Ctl *ctl) {
 // forward search in the reversed frame is a search towards the demands in
 // the original one.  Applying the map twice restores the original state.
 __global__ void k_reverse_frame(Graph g, Ctl *ctl, long long nx, long long ny, long long N) {
-    const long long total = max(nx + ny, N);
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (long long)gridDim.x * blockDim.x) {
-        if (t < nx) g.fx[t] = (int8_t)-g.fx[t];
-        else if (t < nx + ny) g.fy[t - nx] = (int8_t)-g.fy[t - nx];
-        if (t < N) {
-            g.pot[t] = -g.pot[t];
-            g.ex[t] = (int8_t)-g.ex[t];
-        }
-    }
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    negate_span(g.fx, nx, tid, stride);
+    negate_span(g.fy, ny, tid, stride);
+    negate_span(g.ex, N, tid, stride);
+    negate_span(g.pot, N, tid, stride);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned int ns = ctl->nsrc;
         ctl->nsrc = ctl->ndef;
@@ -1243,7 +1267,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const bool first_deficit = g_first_deficit.load() != 0;
     const long long reverse_below = g_reverse_below.load();
     bool reversed = false;
-    const int rev_grid = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx + ny, N), 256)));
+    const int rev_grid = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx + ny, N), 256 * 16)));
     auto flip_frame = [&]() -> ww_status {
         hipLaunchKernelGGL(k_reverse_frame, dim3(rev_grid), dim3(256), 0, st, g, ctl, nx, ny, N);
         WW_LAUNCH_CHECK();
@@ -1255,7 +1279,17 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         return sync_ctl();
     };
     const bool trace_windows = trace_env && trace_env[0] == '2';
-    const int round_grid = (int)std::min<unsigned int>(NT, 2048u);
+    // one wave of resident workgroups: more would only add workgroups that
+    // find the round's list exhausted, which an empty round pays for too
+    int dev = 0, ncu = 256, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sssp_round, 256, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 4;
+    (void)hipGetLastError();
+    const int round_grid = (int)std::min<long long>(NT, (long long)ncu * per_cu);
     const int pot_grid = (int)std::min<unsigned int>((NT + POT_CHUNK - 1) / POT_CHUNK, 16384u);
     unsigned long long nbatch = 0;  // round batches so far (their parity picks the window-end slot)
     int wslot = 0;

@@ -302,3 +302,46 @@ def test_errors_raise(torch_cuda, c0):
     with pytest.raises(ww.WWError):
         ww.edge_costs(c0.psi, c0.coh, c0.valid, np.zeros((64, 128), np.int16),
                       ww.default_cost_params(box_half=40))
+
+
+def test_mcf_unaligned_outputs_reversed_frame(torch_cuda):
+    """Flow planes at odd byte offsets (the C ABI allows any pointer) through
+    a schedule that searches from the demands from the first pass on, so that
+    the frame reversal negates unaligned heads and tails as well as the
+    16-byte body; flows and cost equal those of aligned outputs."""
+    import ctypes as C
+    torch = torch_cuda
+    m, n = 45, 77
+    rng = np.random.default_rng(11)
+    res = np.zeros((m - 1, n - 1), np.int8)
+    idx = rng.choice((m - 1) * (n - 1), 60, replace=False)
+    res.flat[idx[:30]] = 1
+    res.flat[idx[30:]] = -1
+    costs = [rng.integers(1, 600, s).astype(np.int16)
+             for s in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n))]
+    old = ww.set_mcf_params(64, 256, 0, 0, 1 << 20)
+    try:
+        ref = ww.mcf_solve(res, costs, m, n)
+        r = torch.from_numpy(res).cuda()
+        cs = [torch.from_numpy(c).cuda() for c in costs]
+        nx, ny = m * (n - 1), (m - 1) * n
+        for off in (1, 3, 7):
+            bx = torch.full((nx + 32,), 99, dtype=torch.int8, device="cuda")
+            by = torch.full((ny + 32,), 99, dtype=torch.int8, device="cuda")
+            tot = C.c_int64(0)
+            st = ww.McfStats()
+            ww._check(ww.load().ww_mcf_solve(
+                C.c_void_p(r.data_ptr()), m, n, *[C.c_void_p(c.data_ptr()) for c in cs],
+                C.c_void_p(bx.data_ptr() + off), C.c_void_p(by.data_ptr() + off), None,
+                C.byref(tot), C.byref(st), ww._stream()))
+            torch.cuda.synchronize()
+            assert tot.value == ref.total_cost
+            assert st.as_dict()["passes"] >= 1
+            gx = bx[off:off + nx].cpu().numpy().reshape(m, n - 1)
+            gy = by[off:off + ny].cpu().numpy().reshape(m - 1, n)
+            assert np.array_equal(gx, np_(ref.dk_x)) and np.array_equal(gy, np_(ref.dk_y))
+            # nothing written outside the planes
+            assert (bx[:off] == 99).all() and (bx[off + nx:] == 99).all()
+            assert (by[:off] == 99).all() and (by[off + ny:] == 99).all()
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
