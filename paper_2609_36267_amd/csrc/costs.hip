@@ -34,6 +34,7 @@ struct SteepState {
     unsigned long long nvalid, ncand, cap, remaining;
     unsigned long long prefix_hi, mask_hi;
     unsigned int prefix_lo, mask_lo;
+    unsigned int done;  // the threshold is known before the last digit
     unsigned int hist[256];
 };
 
@@ -618,6 +619,7 @@ __global__ void k_steep_init(SteepState *st, int pct) {
     st->mask_hi = 0;
     st->prefix_lo = 0;
     st->mask_lo = 0;
+    st->done = 0;
 }
 
 __device__ __forceinline__ bool steep_selecting(const SteepState *st) {
@@ -626,7 +628,7 @@ __device__ __forceinline__ bool steep_selecting(const SteepState *st) {
 
 __global__ void k_steep_hist(const unsigned long long *key, const unsigned int *id, SteepState *st,
                              int pass) {
-    if (!steep_selecting(st)) return;
+    if (!steep_selecting(st) || st->done) return;
     __shared__ unsigned int h[256];
     for (int t = threadIdx.x; t < 256; t += blockDim.x) h[t] = 0;
     __syncthreads();
@@ -647,19 +649,35 @@ __global__ void k_steep_hist(const unsigned long long *key, const unsigned int *
         if (h[t]) atomicAdd(&st->hist[t], h[t]);
 }
 
-__global__ void k_steep_pick(SteepState *st, int pass) {
-    if (threadIdx.x != 0) return;
-    if (steep_selecting(st)) {
-        unsigned long long acc = 0;
-        int digit = 0;
-        for (int d = 255; d >= 0; --d) {
-            if (acc + st->hist[d] >= st->remaining) {
-                digit = d;
-                break;
-            }
-            acc += st->hist[d];
-        }
-        st->remaining -= acc;
+// The digit of this pass: the largest d whose candidates with digits >= d
+// (among those matching the prefix so far) number at least `remaining`,
+// from suffix sums of the histogram (256 threads, one bin each).  When
+// that bucket is taken whole, the digits below it are left at zero: the
+// threshold is then the smallest key of the bucket and selects the same
+// candidates, so the remaining passes are skipped.
+__global__ __launch_bounds__(256) void k_steep_pick(SteepState *st, int pass) {
+    __shared__ unsigned long long suf[256];
+    __shared__ int best;
+    const int d = threadIdx.x;
+    const bool active = steep_selecting(st) && !st->done;
+    const unsigned int hd = st->hist[d];
+    suf[d] = hd;
+    if (d == 0) best = -1;
+    __syncthreads();
+    // inclusive suffix sums: suf[d] = sum of hist[d'] for d' >= d
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned long long add = d + off < 256 ? suf[d + off] : 0ull;
+        __syncthreads();
+        suf[d] += add;
+        __syncthreads();
+    }
+    if (active && suf[d] >= st->remaining) atomicMax(&best, d);
+    __syncthreads();
+    if (active && d == 0) {
+        const int digit = best < 0 ? 0 : best;
+        const unsigned long long above = digit < 255 ? suf[digit + 1] : 0ull;
+        const unsigned long long take = st->remaining - above;
+        st->remaining = take;
         if (pass < 8) {
             const int sh = 8 * (7 - pass);
             st->prefix_hi |= (unsigned long long)digit << sh;
@@ -669,8 +687,10 @@ __global__ void k_steep_pick(SteepState *st, int pass) {
             st->prefix_lo |= (unsigned int)digit << sh;
             st->mask_lo |= 0xffu << sh;
         }
+        if (take == (unsigned long long)st->hist[digit]) st->done = 1;
     }
-    for (int d = 0; d < 256; ++d) st->hist[d] = 0;
+    __syncthreads();
+    st->hist[d] = 0;
 }
 
 // Zero the selected candidates: all of them when they fit under the cap,
@@ -763,7 +783,7 @@ ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *val
         for (int pass = 0; pass < 12; ++pass) {
             hipLaunchKernelGGL(k_steep_hist, dim3(hb), dim3(256), 0, stream, keys, ids, st, pass);
             WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_steep_pick, dim3(1), dim3(64), 0, stream, st, pass);
+            hipLaunchKernelGGL(k_steep_pick, dim3(1), dim3(256), 0, stream, st, pass);
             WW_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(k_steep_zero, dim3(hb), dim3(256), 0, stream, keys, ids, st,
