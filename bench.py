@@ -44,13 +44,13 @@ TRAFFIC_BYTES_PER_LAUNCH = 10.91e6
 
 def round_kernel_sha() -> str:
     """Hash of the source text of the relaxation-round kernel and the device
-    helpers it calls (csrc/mcf.hip, from relax_one to the end of
-    k_sssp_round) and of the number of rounds launched per host check (the
-    share of empty launches in the per-launch average): the measured traffic
-    belongs to that code only."""
+    helpers it calls (csrc/mcf.hip, from the staged reduced-cost encoding to
+    the end of k_sssp_round) and of the number of rounds launched per host
+    check (the share of empty launches in the per-launch average): the
+    measured traffic belongs to that code only."""
     import hashlib
     txt = open(os.path.join(ROOT, "paper_2609_36267_amd", "csrc", "mcf.hip")).read()
-    a = txt.index("__device__ __forceinline__ void relax_one(")
+    a = txt.index("// Reduced costs of the in-arcs are staged as unsigned words")
     b = txt.index("__global__ void k_requeue_pending(")
     c = txt.index("#define WW_ROUNDS_PER_SYNC")
     d = txt.index("\n", c)

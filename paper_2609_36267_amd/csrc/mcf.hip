@@ -77,6 +77,7 @@ struct Ctl {
     unsigned long long vt_sum;  // visit durations (wall-clock ticks), all visits
     unsigned long long vt_max;  // longest visit
     unsigned long long vt_stage;  // staging part of the visits
+    unsigned long long vt_sweep;  // staging and sweeps of the visits
 };
 
 struct Graph {
@@ -308,21 +309,39 @@ struct RoundArgs {
 // 32 x 32 loop tiles, 256 threads, 4 nodes per thread.
 constexpr int TJ = 32;
 
+// Reduced costs of the in-arcs are staged as unsigned words, RC_NONE where
+// there is no arc (a valid reduced cost is below 2^31).
+constexpr unsigned int RC_NONE = 0xffffffffu;
+
 // Candidate label of a node reached from neighbour label u over an arc of
-// reduced cost rc (direction code dir).  Candidates inside the window lower
-// best; one beyond it is kept in rej, but only for a node without a label:
-// every label is inside the window, so such a candidate can never lower one.
-__device__ __forceinline__ void relax_one(unsigned long long &best, unsigned long long u, int rc,
-                                          unsigned int dir, unsigned long long lb,
-                                          unsigned long long &rej) {
-    // branch-free, so that best and rej stay in registers
-    const unsigned long long nd = (u >> 32) + (unsigned long long)(unsigned)rc;
-    const bool ok = rc != RC_INF && u != LINF && nd <= 0xffffffffull;
-    const unsigned int lo = (((unsigned int)u | 7u) + 1u) | dir;  // hops + 1, direction
-    const unsigned long long cand = (nd << 32) | lo;
-    const bool beyond = cand > lb;
-    rej = (ok && beyond && best == LINF && cand < rej) ? cand : rej;
-    best = (ok && !beyond && cand < best) ? cand : best;
+// reduced cost rc (direction code dir): the distance in the high word, hops
+// + 1 and the direction in the low word.  A distance sum that carries out
+// of 32 bits (no arc, a neighbour without a label, or a distance of 2^32
+// or more) becomes 0xffffffff, above the distance of every window bound, so
+// such a candidate is never taken inside a window.
+__device__ __forceinline__ unsigned long long cand_of(unsigned long long u, unsigned int rc,
+                                                      unsigned int dir) {
+    unsigned int d;
+    const bool carry = __builtin_add_overflow((unsigned int)(u >> 32), rc, &d);
+    const unsigned int lo = (((unsigned int)u | 7u) + 1u) | dir;
+    return ((unsigned long long)(carry ? 0xffffffffu : d) << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+// A candidate beyond the window for a node without a label, kept in rej
+// (the smallest such over the tile parks the tile for a later window).
+// Every label lies inside the window, so a beyond-window candidate can
+// only ever matter to a node without one.
+__device__ __forceinline__ void rej_one(unsigned long long &rej, unsigned long long u,
+                                        unsigned int rc, unsigned int dir, unsigned long long lb) {
+    unsigned int d;
+    const bool carry = __builtin_add_overflow((unsigned int)(u >> 32), rc, &d);
+    const bool ok = rc != RC_NONE && u != LINF && !carry;
+    const unsigned long long cand = ((unsigned long long)d << 32) | ((((unsigned int)u | 7u) + 1u) | dir);
+    rej = (ok && cand > lb && cand < rej) ? cand : rej;
 }
 
 // Sweeps per tile visit at most (a speed knob: the labels are the same for
@@ -439,7 +458,8 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                     ru = max(ru, 0); rd = max(rd, 0); rl = max(rl, 0); rr = max(rr, 0);
                 }
             }
-            RC4[li][lj] = make_int4(ru, rd, rl, rr);
+            RC4[li][lj] = make_int4(ru == RC_INF ? (int)RC_NONE : ru, rd == RC_INF ? (int)RC_NONE : rd,
+                                    rl == RC_INF ? (int)RC_NONE : rl, rr == RC_INF ? (int)RC_NONE : rr);
         }
         __syncthreads();
         const unsigned long long t_staged = stats ? wall_clock64() : 0ull;
@@ -467,6 +487,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         if (threadIdx.x < 12) wchg[threadIdx.x / 4][threadIdx.x % 4] = threadIdx.x < 8 ? 0 : 1;
         __syncthreads();
         unsigned long long rej = LINF;  // smallest useful candidate beyond the window
+        const unsigned long long lb1 = lb + 1ull;  // lb < LINF: its hop field is at most HMAX
         // A visit stops after VISIT_ITERS sweeps even when labels still
         // change: it writes back what it has (labels only decrease, so every
         // label is valid) and lists the tile again for the next round, so
@@ -477,16 +498,17 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             const bool live = wchg[rd][wv] || (wv > 0 && wchg[rd][wv - 1]) || (wv < 3 && wchg[rd][wv + 1]);
             int changed = 0;
             if (live) {
+// the smallest of the four candidates is taken when it is inside the window
+// and below the node's label: one comparison with min(label, lb + 1)
 #define WW_RELAX_NODE(k, PREV, NEXT)                                                  \
     if (ok[k]) {                                                                      \
-        unsigned long long best = y[k];                                               \
-        relax_one(best, PREV, rc[k].x, 1u, lb, rej);                                  \
-        relax_one(best, NEXT, rc[k].y, 2u, lb, rej);                                  \
-        relax_one(best, L[r0 + k + 1][lj], rc[k].z, 3u, lb, rej);                     \
-        relax_one(best, L[r0 + k + 1][lj + 2], rc[k].w, 4u, lb, rej);                 \
-        if (best < y[k]) {                                                            \
-            y[k] = best;                                                              \
-            L[r0 + k + 1][lj + 1] = best;                                             \
+        const unsigned long long c = umin64(                                          \
+            umin64(cand_of(PREV, (unsigned)rc[k].x, 1u), cand_of(NEXT, (unsigned)rc[k].y, 2u)), \
+            umin64(cand_of(L[r0 + k + 1][lj], (unsigned)rc[k].z, 3u),                  \
+                   cand_of(L[r0 + k + 1][lj + 2], (unsigned)rc[k].w, 4u)));            \
+        if (c < umin64(y[k], lb1)) {                                                  \
+            y[k] = c;                                                                 \
+            L[r0 + k + 1][lj + 1] = c;                                                \
             changed = 1;                                                              \
         }                                                                             \
     }
@@ -509,6 +531,20 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         }
         if (unconverged && stats && threadIdx.x == 0)
             atomicAdd(&ctl->iters, (unsigned long long)VISIT_ITERS);
+        // beyond-window candidates of the nodes still without a label, from
+        // the final labels of the visit (all LDS writes are done: the loop
+        // above ends on a barrier)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!ok[k] || y[k] != LINF) continue;
+            const unsigned long long up = k == 0 ? L[r0][lj + 1] : y[k > 0 ? k - 1 : 0];
+            const unsigned long long dn = k == 3 ? L[r0 + 5][lj + 1] : y[k < 3 ? k + 1 : 3];
+            rej_one(rej, up, (unsigned)rc[k].x, 1u, lb);
+            rej_one(rej, dn, (unsigned)rc[k].y, 2u, lb);
+            rej_one(rej, L[r0 + k + 1][lj], (unsigned)rc[k].z, 3u, lb);
+            rej_one(rej, L[r0 + k + 1][lj + 2], (unsigned)rc[k].w, 4u, lb);
+        }
+        const unsigned long long t_swept = stats ? wall_clock64() : 0ull;
         // write back, note changed borders
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -615,6 +651,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 const unsigned long long t_end = wall_clock64();
                 atomicAdd(&ctl->vt_sum, t_end - t_start);
                 atomicAdd(&ctl->vt_stage, t_staged - t_start);
+                atomicAdd(&ctl->vt_sweep, t_swept - t_start);
                 atomicMax(&ctl->vt_max, t_end - t_start);
             }
         }
@@ -1317,7 +1354,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         const auto tp0 = std::chrono::steady_clock::now();
         const long long r0 = S.rounds, w0 = S.windows;
         const unsigned long long v0 = trace ? host_visits() : 0, it0 = h->iters, vs0 = h->vt_sum,
-                                 vst0 = h->vt_stage;
+                                 vst0 = h->vt_stage, vsw0 = h->vt_sweep;
         const unsigned int nsrc0 = h->nsrc;
         const long long gex0 = h->gex;
         ++pass;
@@ -1444,12 +1481,13 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             const unsigned long long v1 = host_visits();
             fprintf(stderr,
                     "[ww-mcf] pass %lld src %u gex %lld bound %u/%u windows %lld rounds %lld "
-                    "tile_visits %llu iters %llu visit_us %.2f stage_us %.2f maxvisit_us %.1f aug %u arcs %llu ms %.3f\n",
+                    "tile_visits %llu iters %llu visit_us %.2f stage_us %.2f swept_us %.2f maxvisit_us %.1f aug %u arcs %llu ms %.3f\n",
                     (long long)S.passes, nsrc0, gex0, (unsigned)(lb >> 32),
                     (unsigned)((lb >> 3) & 0x1fffffffu), S.windows - w0, S.rounds - r0,
                     v1 - v0, h->iters - it0,
                     (h->vt_sum - vs0) * 0.01 / std::max<double>(1.0, (double)(v1 - v0)),
                     (h->vt_stage - vst0) * 0.01 / std::max<double>(1.0, (double)(v1 - v0)),
+                    (h->vt_sweep - vsw0) * 0.01 / std::max<double>(1.0, (double)(v1 - v0)),
                     h->vt_max * 0.01, h->naug, (unsigned long long)h->arcs,
                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
         }
