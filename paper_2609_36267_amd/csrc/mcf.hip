@@ -385,9 +385,11 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             sh_gcand = LINF;
         }
         // stage labels and potentials with a one-node halo; outside = ground.
-        // All loads of a thread are issued before any LDS store, so that
-        // their latencies overlap.
+        // All loads of a thread (labels, potentials, arc costs and flows) are
+        // issued before any LDS store, so that their latencies overlap.
         constexpr int NSTAGE = ((TJ + 2) * (TJ + 2) + 255) / 256;
+        constexpr int NRC = TJ * TJ / 256;
+        int cst[NRC][4];
         {
             unsigned long long lv[NSTAGE];
             int pv[NSTAGE];
@@ -409,6 +411,26 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                     }
                 }
             }
+            // arc costs and flows of the four in-arcs of every node, issued
+            // with the label and potential loads (one memory latency for all)
+#pragma unroll
+            for (int s = 0; s < NRC; ++s) {
+                const int t = threadIdx.x + 256 * s;
+                const int li = t / TJ, lj = t % TJ;
+                cst[s][0] = cst[s][1] = cst[s][2] = cst[s][3] = RC_INF;
+                if (li < rows && lj < cols) {
+                    const int i = i0 + li, j = j0 + lj;
+                    long long e;
+                    e = (long long)i * C + j;  // hx(i,j): from above, +1
+                    cst[s][0] = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
+                    e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
+                    cst[s][1] = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
+                    e = (long long)i * g.n + j;  // vy(i,j): from the left, -1
+                    cst[s][2] = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
+                    e = (long long)i * g.n + j + 1;  // vy(i,j+1): from the right, +1
+                    cst[s][3] = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
+                }
+            }
 #pragma unroll
             for (int s = 0; s < NSTAGE; ++s) {
                 const int t = threadIdx.x + 256 * s;
@@ -416,28 +438,6 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                     L[t / (TJ + 2)][t % (TJ + 2)] = lv[s];
                     P[t / (TJ + 2)][t % (TJ + 2)] = pv[s];
                 }
-            }
-        }
-        // arc costs and flows of the four in-arcs of every node, loaded
-        // before the potentials are needed
-        constexpr int NRC = TJ * TJ / 256;
-        int cst[NRC][4];
-#pragma unroll
-        for (int s = 0; s < NRC; ++s) {
-            const int t = threadIdx.x + 256 * s;
-            const int li = t / TJ, lj = t % TJ;
-            cst[s][0] = cst[s][1] = cst[s][2] = cst[s][3] = RC_INF;
-            if (li < rows && lj < cols) {
-                const int i = i0 + li, j = j0 + lj;
-                long long e;
-                e = (long long)i * C + j;  // hx(i,j): from above, +1
-                cst[s][0] = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
-                e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
-                cst[s][1] = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
-                e = (long long)i * g.n + j;  // vy(i,j): from the left, -1
-                cst[s][2] = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
-                e = (long long)i * g.n + j + 1;  // vy(i,j+1): from the right, +1
-                cst[s][3] = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
             }
         }
         __syncthreads();
@@ -523,7 +523,11 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 if (changed) wchg[wr][wv] = 1;
             }
             if (threadIdx.x < 4) wchg[(it + 1) % 3][threadIdx.x] = 0;
-            if (!__syncthreads_or(changed)) {
+            // the waves' change flags of this sweep decide for the whole
+            // workgroup after one barrier (slot wr is next cleared two sweeps
+            // later, after another barrier)
+            __syncthreads();
+            if (!(wchg[wr][0] | wchg[wr][1] | wchg[wr][2] | wchg[wr][3])) {
                 if (stats && threadIdx.x == 0) atomicAdd(&ctl->iters, (unsigned long long)(it + 1));
                 unconverged = false;
                 break;
