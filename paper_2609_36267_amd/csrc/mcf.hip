@@ -710,11 +710,20 @@ __global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigne
         const unsigned long long o = __shfl_down(mn, off, 64);
         mn = o < mn ? o : mn;
     }
+    // one counter atomic per workgroup (thousands on one address cost more
+    // than the count itself)
+    __shared__ unsigned int wc[4];
     if ((threadIdx.x & 63) == 0) {
-        if (c) atomicAdd(&ctl->wsettled[w], c);
+        wc[threadIdx.x >> 6] = c;
         // only a wave that may lower the minimum takes the atomic
         if (mn != LINF && mn < *(volatile unsigned long long *)&ctl->wminrej[w])
             atomicMin(&ctl->wminrej[w], mn);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wc[k];
+        if (t) atomicAdd(&ctl->wsettled[w], t);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const unsigned long long gl = ctl->glab;
@@ -748,6 +757,16 @@ __global__ void k_ground_pred(Graph g, Ctl *ctl, unsigned long long lb) {
     }
 }
 
+// row and column of loop node v (v < 2^29, so 32-bit arithmetic suffices:
+// the walks below take one step per memory round trip, and a 64-bit
+// division would add to every step)
+__device__ __forceinline__ void node_rc(const Graph &g, long long v, int &i, int &j) {
+    const unsigned int u = (unsigned int)v, C = (unsigned int)g.C;
+    const unsigned int q = u / C;
+    i = (int)q;
+    j = (int)(u - q * C);
+}
+
 // predecessor of loop node v (i,j) along direction dir; -1 = ground
 __device__ __forceinline__ long long pred_node(const Graph &g, int i, int j, int dir) {
     switch (dir) {
@@ -767,7 +786,8 @@ __device__ long long walk_root(const Graph &g, Ctl *ctl, long long v, int gsrc, 
         const unsigned long long l = g.lab[v];
         const int dir = (int)(l & 7);
         if (dir == DIR_NONE) return v;
-        const int i = (int)(v / g.C), j = (int)(v % g.C);
+        int i, j;
+        node_rc(g, v, i, j);
         long long u = pred_node(g, i, j, dir);
         if (u < 0) {
             if (gsrc) {
@@ -845,7 +865,8 @@ __global__ void k_gsub_select(Graph g, Ctl *ctl, const unsigned int *gsub_list,
 }
 
 __device__ __forceinline__ void flip_into(Graph &g, long long v, int dir) {
-    const int i = (int)(v / g.C), j = (int)(v % g.C);
+    int i, j;
+    node_rc(g, v, i, j);
     switch (dir) {
         case DIR_UP: g.fx[(long long)i * g.C + j] += 1; break;
         case DIR_DOWN: g.fx[(long long)(i + 1) * g.C + j] -= 1; break;
@@ -885,7 +906,9 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
             for (long long w = t == N ? -1 : t, steps = 0; !needs && w >= 0 && steps <= N + 2; ++steps) {
                 const int dir = (int)(g.lab[w] & 7);
                 if (dir == DIR_NONE) break;
-                w = pred_node(g, (int)(w / g.C), (int)(w % g.C), dir);
+                int wi, wj;
+                node_rc(g, w, wi, wj);
+                w = pred_node(g, wi, wj, dir);
                 if (w < 0) needs = true;
             }
             if (needs) {
@@ -909,7 +932,8 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
             if (dir == DIR_NONE) break;  // reached the supply r
             flip_into(g, v, dir);
             ++flips;
-            const int i = (int)(v / g.C), j = (int)(v % g.C);
+            int i, j;
+            node_rc(g, v, i, j);
             long long u = pred_node(g, i, j, dir);
             if (u < 0) {
                 if (is_g) break;  // the ground is the supply
