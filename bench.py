@@ -38,7 +38,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
 TRAFFIC_SOURCE_SHA = "d2038e18998f90f5"
-TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024)
+TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 2)
 TRAFFIC_BYTES_PER_LAUNCH = 10.81e6
 
 
@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the components, Goldstein and bridging legs (for counter runs)")
-    ap.add_argument("--schedule", default=None, metavar="H0,DSTEP[,FULL,FIRSTDEF,REVERSE]",
+    ap.add_argument("--schedule", default=None, metavar="H0,DSTEP[,FULL,FIRSTDEF,REVERSE[,GROWTH]]",
                     help="solve schedule to time (skips tuning), e.g. 64,256,2,0,0")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the library's default solve schedule instead of tuning it on a "
@@ -115,10 +115,12 @@ def _pct(xs, q):
 
 
 def _sched_dict(sched):
-    """A solve schedule (2 to 5 fields, missing ones 0) as a dict."""
-    full = tuple(sched) + (0,) * (5 - len(sched))
+    """A solve schedule (2 to 6 fields, missing ones at their defaults) as a
+    dict."""
+    from paper_2609_36267_amd import autotune
+    full = autotune.pad(sched)
     return {"first_hop_window": full[0], "first_distance_step": full[1], "full_passes": full[2],
-            "first_deficit_after": full[3], "reverse_below": full[4]}
+            "first_deficit_after": full[3], "reverse_below": full[4], "hop_growth": full[5]}
 
 
 def stack_scenes(args, synth):

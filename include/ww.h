@@ -104,7 +104,8 @@ typedef struct {
  * relaxation rounds against windows) and when a pass stops searching.  Every
  * schedule reaches an optimum of the same cost.
  *   first_hop_window     hop limit of a pass's first, zero-distance window
- *                        (1 .. 2^29-2; later zero-distance windows double)
+ *                        (1 .. 2^29-2; later zero-distance windows grow by
+ *                        hop_growth)
  *   first_distance_step  first increment of the distance bound (1 .. 2^30;
  *                        later increments double)
  *   full_passes          number of first passes that search until every
@@ -121,6 +122,9 @@ typedef struct {
  *                        the demands instead (the same successive shortest
  *                        paths on the reversed problem: arcs turned round,
  *                        supplies and demands exchanged, potentials negated)
+ *   hop_growth           factor by which the hop limit of each later
+ *                        zero-distance window grows (2 .. 2^20; the limit is
+ *                        at least the hops of the smallest parked candidate)
  * Process-wide; applies to solves that start after the call. */
 typedef struct {
     int32_t first_hop_window;
@@ -128,10 +132,11 @@ typedef struct {
     int32_t full_passes;
     int32_t first_deficit_after;
     int32_t reverse_below;
+    int32_t hop_growth;
 } ww_mcf_params;
 
 /* Defaults: first_hop_window 64, first_distance_step 256, full_passes 0,
- * first_deficit_after 0, reverse_below 0. */
+ * first_deficit_after 0, reverse_below 0, hop_growth 2. */
 void ww_default_mcf_params(ww_mcf_params *p);
 /* Errors: WW_E_INVALID_ARG (NULL or out of range). */
 ww_status ww_set_mcf_params(const ww_mcf_params *p);

@@ -21,19 +21,26 @@ import time
 from . import binding as ww
 
 # (first_hop_window, first_distance_step[, full_passes, first_deficit_after
-# [, reverse_below]]), missing fields 0;
-# the last one is the paper's pass schedule (Section II-C: eight full
+# [, reverse_below[, hop_growth]]]), missing fields 0 (hop_growth 2);
+# PAPER_SCHEDULE is the paper's pass schedule (Section II-C: eight full
 # multi-source passes, then searches that stop at the first deficit)
 PAPER_SCHEDULE = (64, 256, 8, 1)
 CANDIDATES = [(64, 256), (16, 256), (512, 256), (64, 64), (16, 64), (512, 64), (64, 1024),
               (16, 1024), (512, 1024), (64, 256, 2, 0), (64, 256, 4, 0), PAPER_SCHEDULE,
               (64, 256, 0, 0, 1024), (64, 256, 2, 0, 1024), (64, 256, 4, 0, 1024),
-              (64, 256, 8, 0, 1024), (512, 64, 0, 0, 1024)]
+              (64, 256, 8, 0, 1024), (512, 64, 0, 0, 1024),
+              (64, 256, 0, 0, 1024, 8), (64, 256, 4, 0, 1024, 4), (64, 256, 4, 0, 1024, 6),
+              (64, 256, 4, 0, 1024, 8), (64, 256, 4, 0, 1024, 16), (64, 256, 0, 0, 0, 8)]
+
+FIELDS = 6
+DEFAULT_TAIL = (0, 0, 0, 2)  # full_passes, first_deficit_after, reverse_below, hop_growth
 
 
 def pad(c):
-    """A candidate with its missing trailing fields set to 0."""
-    return tuple(c) + (0,) * (5 - len(c))
+    """A candidate with its missing trailing fields set to their defaults
+    (0, and 2 for hop_growth)."""
+    c = tuple(c)
+    return c + DEFAULT_TAIL[len(c) - 2:]
 
 
 def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):

@@ -1204,6 +1204,7 @@ std::atomic<int> g_first_dstep{256};
 std::atomic<int> g_full_passes{0};
 std::atomic<int> g_first_deficit{0};
 std::atomic<int> g_reverse_below{0};
+std::atomic<int> g_hop_growth{2};
 
 static unsigned long long mk_label(unsigned int d, unsigned int h) {
     return ((unsigned long long)d << 32) | ((unsigned long long)h << 3) | 7ull;
@@ -1331,6 +1332,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const unsigned int full_passes = (unsigned int)g_full_passes.load();
     const bool first_deficit = g_first_deficit.load() != 0;
     const long long reverse_below = g_reverse_below.load();
+    const unsigned long long hop_growth = (unsigned long long)g_hop_growth.load();
     bool reversed = false;
     const int rev_grid = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx + ny, N), 256 * 16)));
     auto flip_frame = [&]() -> ww_status {
@@ -1444,7 +1446,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             const unsigned int d = (unsigned int)(lb >> 32), hcur = (unsigned int)((lb >> 3) & 0x1fffffffu);
             if ((unsigned int)(mr >> 32) == d && d == 0) {
                 // the zero-distance plateau: widen the hop limit
-                unsigned long long hn = std::max<unsigned long long>((mr >> 3) & 0x1fffffffu, 2ull * hcur);
+                unsigned long long hn = std::max<unsigned long long>((mr >> 3) & 0x1fffffffu, hop_growth * hcur);
                 lb = mk_label(0, (unsigned int)std::min<unsigned long long>(hn, HMAX));
             } else {
                 unsigned long long dn = std::max<unsigned long long>(mr >> 32, (unsigned long long)d + dstep);
@@ -1555,6 +1557,7 @@ void ww_default_mcf_params(ww_mcf_params *p) {
     p->full_passes = 0;
     p->first_deficit_after = 0;
     p->reverse_below = 0;
+    p->hop_growth = 2;
 }
 
 ww_status ww_set_mcf_params(const ww_mcf_params *p) {
@@ -1563,13 +1566,15 @@ ww_status ww_set_mcf_params(const ww_mcf_params *p) {
         p->first_distance_step < 1 || p->first_distance_step > (1 << 30))
         return ww::fail(WW_E_INVALID_ARG, "window schedule out of range");
     if (p->full_passes < 0 || p->full_passes > (1 << 20) ||
-        (p->first_deficit_after != 0 && p->first_deficit_after != 1) || p->reverse_below < 0)
+        (p->first_deficit_after != 0 && p->first_deficit_after != 1) || p->reverse_below < 0 ||
+        p->hop_growth < 2 || p->hop_growth > (1 << 20))
         return ww::fail(WW_E_INVALID_ARG, "pass schedule out of range");
     ww::g_first_hops.store(p->first_hop_window);
     ww::g_first_dstep.store(p->first_distance_step);
     ww::g_full_passes.store(p->full_passes);
     ww::g_first_deficit.store(p->first_deficit_after);
     ww::g_reverse_below.store(p->reverse_below);
+    ww::g_hop_growth.store(p->hop_growth);
     return WW_OK;
 }
 
@@ -1580,6 +1585,7 @@ void ww_get_mcf_params(ww_mcf_params *p) {
     p->full_passes = ww::g_full_passes.load();
     p->first_deficit_after = ww::g_first_deficit.load();
     p->reverse_below = ww::g_reverse_below.load();
+    p->hop_growth = ww::g_hop_growth.load();
 }
 
 }  // extern "C"

@@ -195,7 +195,9 @@ def test_mcf_parity_random(torch_cuda, shape, seed):
 SCHEDULES = [(64, 256, 0, 0, 1 << 30),   # every pass from the demands (reversed problem)
              (64, 256, 4, 0, 16),        # full passes, then reversal for the last units
              (1, 1, 2, 1, 1),            # tiny windows, first-deficit passes, last unit reversed
-             (64, 256, 8, 1, 0)]         # the paper's pass schedule
+             (64, 256, 8, 1, 0),         # the paper's pass schedule
+             (64, 256, 4, 0, 16, 8),     # hop windows growing eightfold
+             (4, 64, 0, 1, 0, 1 << 20)]  # one small hop window, then the whole plateau
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
