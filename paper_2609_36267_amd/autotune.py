@@ -30,7 +30,8 @@ CANDIDATES = [(64, 256), (16, 256), (512, 256), (64, 64), (16, 64), (512, 64), (
               (64, 256, 0, 0, 1024), (64, 256, 2, 0, 1024), (64, 256, 4, 0, 1024),
               (64, 256, 8, 0, 1024), (512, 64, 0, 0, 1024),
               (64, 256, 0, 0, 1024, 8), (64, 256, 4, 0, 1024, 4), (64, 256, 4, 0, 1024, 6),
-              (64, 256, 4, 0, 1024, 8), (64, 256, 4, 0, 1024, 16), (64, 256, 0, 0, 0, 8)]
+              (64, 256, 4, 0, 1024, 8), (64, 256, 4, 0, 1024, 16), (64, 256, 0, 0, 0, 8),
+              (64, 1024, 4, 0, 1024, 8), (64, 1024, 0, 0, 1024, 8), (64, 256, 4, 0, 4096, 8)]
 
 FIELDS = 6
 DEFAULT_TAIL = (0, 0, 0, 2)  # full_passes, first_deficit_after, reverse_below, hop_growth
