@@ -1158,19 +1158,44 @@ __global__ void k_reverse_frame(Graph g, Ctl *ctl, long long nx, long long ny, l
     }
 }
 
+// sum of the costs of the corrected edges of one plane: the flows are read
+// 16 bytes at a time (scalar head and tail where f is not 16-byte aligned)
+// and a cost is read only where the flow is not zero
+__device__ __forceinline__ long long cost_span(const int8_t *f, const int16_t *cp, const int16_t *cn,
+                                               long long n, long long tid, long long stride) {
+    long long s = 0;
+    auto one = [&](long long e, int v) { s += v > 0 ? cp[e] : (v < 0 ? cn[e] : 0); };
+    const long long head = min(n, (long long)((16u - ((unsigned int)(uintptr_t)f & 15u)) & 15u));
+    for (long long k = tid; k < head; k += stride) one(k, f[k]);
+    const long long nvec = (n - head) / 16;
+    const uint4 *v = reinterpret_cast<const uint4 *>(f + head);
+    for (long long k = tid; k < nvec; k += stride) {
+        const uint4 x = v[k];
+        if ((x.x | x.y | x.z | x.w) == 0u) continue;
+        const unsigned int w[4] = {x.x, x.y, x.z, x.w};
+        const long long e0 = head + 16 * k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!w[q]) continue;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int fv = (int)(signed char)(w[q] >> (8 * b));
+                if (fv) one(e0 + 4 * q + b, fv);
+            }
+        }
+    }
+    for (long long k = head + nvec * 16 + tid; k < n; k += stride) one(k, f[k]);
+    return s;
+}
+
 __global__ __launch_bounds__(256) void k_total_cost(const int8_t *fx, const int8_t *fy,
                                                    const int16_t *cxp, const int16_t *cxn,
                                                    const int16_t *cyp, const int16_t *cyn,
                                                    long long nx, long long ny,
                                                    long long *__restrict__ part) {
-    long long s = 0;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nx + ny;
-         e += (long long)gridDim.x * blockDim.x) {
-        int f, cp, cn;
-        if (e < nx) { f = fx[e]; cp = cxp[e]; cn = cxn[e]; }
-        else { f = fy[e - nx]; cp = cyp[e - nx]; cn = cyn[e - nx]; }
-        s += f > 0 ? cp : (f < 0 ? cn : 0);
-    }
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long s = cost_span(fx, cxp, cxn, nx, tid, stride) + cost_span(fy, cyp, cyn, ny, tid, stride);
     __shared__ long long red[4];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
