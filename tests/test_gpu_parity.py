@@ -155,6 +155,24 @@ def test_costs_parity_steep_cap_binds(torch_cuda, lut9):
             assert np.array_equal(np_(g), w)
 
 
+@pytest.mark.parametrize("levels,pct", [(7, 1), (7, 3), (5, 2), (11, 5)])
+def test_costs_parity_steep_ties(torch_cuda, lut9, levels, pct):
+    """Phases on a few levels give steep candidates with many equal |d|: the
+    cap then falls inside a run of ties, resolved by the edge id (the last
+    digits of the select), or takes a whole run at once (the select's early
+    end); either way the zeroed edges equal the oracle's."""
+    rng = np.random.default_rng(levels * 10 + pct)
+    m, n = 96, 120
+    psi = (rng.integers(0, levels, (m, n)) * (2 * np.pi / levels) - np.pi).astype(np.float32)
+    coh = np.full((m, n), 0.8, np.float32)
+    valid = (rng.random((m, n)) > 0.05).astype(np.uint8)
+    want, st = oracle.edge_costs(psi, coh, valid, lut9, steep_cap_pct=pct, want_stats=True)
+    assert st["steep_candidates"] > st["steep_zeroed"] > 0
+    got = ww.edge_costs(psi, coh, valid, lut9, ww.default_cost_params(steep_cap_pct=pct))
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+
+
 def test_costs_parity_c0_with_gpu_table(torch_cuda, c0):
     T = ww.build_cost_lut(9)
     got = ww.edge_costs(c0.psi, c0.coh, c0.valid, T)
