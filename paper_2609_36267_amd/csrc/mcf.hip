@@ -899,25 +899,18 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
         const long long t = (long long)(b & 0xffffffffull);
         long long v;
         unsigned long long flips = 0;
+        // A path through the ground needs the ground's predecessor arc, which
+        // exists whenever the ground is settled, and only then can a path
+        // cross it (labels grow along paths).  Its absence is checked where
+        // the arc is used: the walk stops with ERR_WALK, which fails the
+        // solve, before any index is formed from it.
         const unsigned int na = 2u * g.C + 2u * g.R;
-        if (ctl->gpred >= na && !is_g) {
-            // a path that needs the ground's predecessor cannot be traced
-            bool needs = (t == N);
-            for (long long w = t == N ? -1 : t, steps = 0; !needs && w >= 0 && steps <= N + 2; ++steps) {
-                const int dir = (int)(g.lab[w] & 7);
-                if (dir == DIR_NONE) break;
-                int wi, wj;
-                node_rc(g, w, wi, wj);
-                w = pred_node(g, wi, wj, dir);
-                if (w < 0) needs = true;
-            }
-            if (needs) {
+        if (t == N) {  // into the ground through its predecessor arc
+            const unsigned int a = ctl->gpred;
+            if (a >= na) {
                 atomicOr(&ctl->error, ERR_WALK);
                 continue;
             }
-        }
-        if (t == N) {  // into the ground through its predecessor arc
-            const unsigned int a = ctl->gpred;
             flip_ground_arc(g, a);
             int pi, pj, kind, delta;
             long long e;
@@ -938,6 +931,10 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
             if (u < 0) {
                 if (is_g) break;  // the ground is the supply
                 const unsigned int a = ctl->gpred;
+                if (a >= na) {
+                    atomicOr(&ctl->error, ERR_WALK);
+                    break;
+                }
                 flip_ground_arc(g, a);
                 ++flips;
                 int pi, pj, kind, delta;
