@@ -1,5 +1,6 @@
 // C ABI entry points: argument checks, workspace, error reporting.  Every
 // numeric step runs in the HIP kernels of the sibling sources.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -40,6 +41,7 @@ struct Workspace {
     void *host = nullptr;
     size_t host_bytes = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t wait_ev = nullptr;  // marks the point a host wait returns at
     ww_mcf_stats stats{};
 };
 
@@ -60,6 +62,7 @@ void workspace_destroy(Workspace *ws) {
     if (ws->host) (void)hipHostFree(ws->host);
     for (auto &e : ws->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ws->wait_ev) (void)hipEventDestroy(ws->wait_ev);
     delete ws;
 }
 
@@ -136,6 +139,24 @@ ww_status workspace_events(hipEvent_t *ev0, hipEvent_t *ev1) {
     }
     *ev0 = ws->ev[0];
     *ev1 = ws->ev[1];
+    return WW_OK;
+}
+
+ww_status wait_stream(hipStream_t st) {
+    Workspace *ws = current_workspace();
+    if (!ws->wait_ev) WW_HIP(hipEventCreateWithFlags(&ws->wait_ev, hipEventDisableTiming));
+    WW_HIP(hipEventRecord(ws->wait_ev, st));
+    // Poll first: a blocking wait sleeps until an interrupt, which costs
+    // tens of microseconds per return and the solver loop returns to the
+    // host after every batch of rounds.  Long waits block after 2 ms.
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(ws->wait_ev);
+        if (e == hipSuccess) return WW_OK;
+        if (e != hipErrorNotReady) WW_HIP(e);
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+    }
+    WW_HIP(hipEventSynchronize(ws->wait_ev));
     return WW_OK;
 }
 

@@ -920,15 +920,19 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
         } else {
             v = t;
         }
+        // The next label is loaded before the flow byte of the current arc
+        // is updated, so that the two loads of a step are in flight together
+        // (the flow update is not on the walk's dependence chain).
+        unsigned long long l = g.lab[v];
         for (long long steps = 0; steps <= N + 2; ++steps) {
-            const int dir = (int)(g.lab[v] & 7);
+            const int dir = (int)(l & 7);
             if (dir == DIR_NONE) break;  // reached the supply r
-            flip_into(g, v, dir);
-            ++flips;
             int i, j;
             node_rc(g, v, i, j);
             long long u = pred_node(g, i, j, dir);
             if (u < 0) {
+                flip_into(g, v, dir);
+                ++flips;
                 if (is_g) break;  // the ground is the supply
                 const unsigned int a = ctl->gpred;
                 if (a >= na) {
@@ -941,6 +945,11 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
                 long long e;
                 ground_arc(g, a, pi, pj, kind, e, delta);
                 u = (long long)pi * g.C + pj;
+                l = g.lab[u];
+            } else {
+                l = g.lab[u];
+                flip_into(g, v, dir);
+                ++flips;
             }
             v = u;
         }
@@ -1326,7 +1335,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     WW_LAUNCH_CHECK();
     auto sync_ctl = [&]() -> ww_status {
         WW_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-        WW_HIP(hipStreamSynchronize(st));
+        WW_TRY(wait_stream(st));
         if (h->error) return decode_error(h->error);
         return WW_OK;
     };

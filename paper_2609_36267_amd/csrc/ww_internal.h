@@ -66,6 +66,8 @@ ww_status scratch(int slot, size_t bytes, void **out);
 ww_status host_scratch(size_t bytes, void **out);
 // Two timing events of the current workspace.
 ww_status workspace_events(hipEvent_t *ev0, hipEvent_t *ev1);
+// Waits for all work queued on `st` so far (polls briefly, then blocks).
+ww_status wait_stream(hipStream_t st);
 // Serialises construction of the shared cost-table cache.
 std::mutex &lut_lock();
 
