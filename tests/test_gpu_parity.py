@@ -240,6 +240,56 @@ def test_mcf_parity_schedules(torch_cuda, sched, shape, seed):
         ww.set_mcf_params(*old.as_tuple())
 
 
+def _long_path_case(kind):
+    """Residue layouts whose augmenting paths run for hundreds of steps:
+    far-apart dipoles whose supplies sit next to each other in the supply
+    list (so that one wave holds many long walks), and lone residues in the
+    middle of the grid, whose paths run to the ground."""
+    rng = np.random.default_rng({"dipoles": 11, "ground_supply": 12, "ground_demand": 13}[kind])
+    if kind == "dipoles":
+        m, n = 200, 430
+        res = np.zeros((m - 1, n - 1), np.int8)
+        for k in range(14):
+            res[10 + 13 * k, 12] = 1
+            res[10 + 13 * k, n - 14] = -1
+    else:
+        m, n = 257, 301
+        res = np.zeros((m - 1, n - 1), np.int8)
+        res[128, 150] = 1 if kind == "ground_supply" else -1
+        res[100, 120] = res[128, 150]
+    costs = tuple(rng.integers(1, 60, sz).astype(np.int16)
+                  for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+    if kind == "dipoles":  # a costly rim keeps the dipoles' paths off the ground
+        for c in costs:
+            c[:6] = c[-6:] = 2000
+            c[:, :6] = c[:, -6:] = 2000
+    return res, costs, m, n
+
+
+@pytest.mark.parametrize("sched", [None, (64, 256, 0, 0, 1 << 30)])
+@pytest.mark.parametrize("kind", ["dipoles", "ground_supply", "ground_demand"])
+def test_mcf_long_paths(torch_cuda, kind, sched):
+    """Paths far longer than a walker's solo steps, crossing many 32 x 32
+    windows and the ground, are augmented as the oracle's optimum has it."""
+    res, costs, m, n = _long_path_case(kind)
+    dkx_o, dky_o, pot_o, tot_o = oracle.mcf(res, costs, m=m, n=n)
+    old = ww.get_mcf_params()
+    try:
+        if sched is not None:
+            ww.set_mcf_params(*sched)
+        r = ww.mcf_solve(res, costs, m, n, want_potentials=True)
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
+    dkx_g, dky_g, pot_g = np_(r.dk_x), np_(r.dk_y), np_(r.potentials)
+    assert r.total_cost == tot_o, (r.total_cost, tot_o, r.stats)
+    assert flow_cost(dkx_g, dky_g, costs) == tot_o
+    cert = oracle.check_optimal(res, costs, dkx_g, dky_g, pot_g)
+    assert cert["ok"], cert
+    assert_same_on_fixed_edges(costs, dkx_o, dky_o, pot_o, dkx_g, dky_g)
+    assert r.stats["path_arcs"] >= {"dipoles": 14 * 400, "ground_supply": 150,
+                                    "ground_demand": 150}[kind], r.stats
+
+
 def test_mcf_degenerate_shapes(torch_cuda):
     for m, n in ((1, 1), (1, 12), (12, 1)):
         costs = (np.ones((m, max(n - 1, 0)), np.int16), np.ones((m, max(n - 1, 0)), np.int16),
