@@ -78,6 +78,8 @@ struct Ctl {
     unsigned long long vt_max;  // longest visit
     unsigned long long vt_stage;  // staging part of the visits
     unsigned long long vt_sweep;  // staging and sweeps of the visits
+    unsigned int prev_naug;       // naug and arcs of the previous pass, kept by
+    unsigned long long prev_arcs;  // the pass set-up when it clears them
 };
 
 struct Graph {
@@ -258,10 +260,14 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const 
 }
 
 // Pass start: sources get label 0 and their tiles are activated for round rr.
+// The ground is a source while it holds surplus; that is read here rather
+// than passed in, so that a pass can be queued before the host has seen how
+// the previous one ended.
 __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned int *act,
                             unsigned int *lists, unsigned int NT, unsigned int rr,
-                            int ground_source, const unsigned int *perim_tiles, int nperim) {
+                            const unsigned int *perim_tiles, int nperim) {
     const unsigned int ns = ctl->nsrc;
+    const int ground_source = ctl->gex > 0;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
         const unsigned int v = src[k];
         g.lab[v] = 0ull;
@@ -283,6 +289,8 @@ __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->glab = ground_source ? 0ull : LINF;
         // per-pass counters back to zero (none of them is read by this kernel)
+        ctl->prev_naug = ctl->naug;
+        ctl->prev_arcs = ctl->arcs;
         ctl->naug = 0;
         ctl->gsub_count = 0;
         ctl->gpred = 0xffffffffu;
@@ -1403,15 +1411,23 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         for (int k = 0; k < 64; ++k) s += hv[k * 16];
         return s;
     };
+    // Once no frame reversal can follow, a pass is queued right behind the
+    // previous one's augmentation: the host reads how the previous pass ended
+    // (its counters kept by the pass set-up) together with the new pass's
+    // first batch of rounds, one round trip instead of two.  When no units
+    // were left, that queued pass had no sources: its rounds found empty
+    // lists and it changed no flow or potential.
+    bool prev_unread = false;  // the previous pass ended without a host check
     for (;;) {
-        if (h->nsrc == 0 && h->gex <= 0) break;
-        // few units left: search from the demands instead (in the reversed
-        // frame), where the plateaus that earlier passes made tight around
-        // the supplies do not lie
-        if (!reversed && reverse_below > 0 &&
-            (long long)h->nsrc + std::max<long long>(h->gex, 0) <= reverse_below)
-            WW_TRY(flip_frame());
-        const int gsrc = h->gex > 0;
+        if (!prev_unread) {
+            if (h->nsrc == 0 && h->gex <= 0) break;
+            // few units left: search from the demands instead (in the
+            // reversed frame), where the plateaus that earlier passes made
+            // tight around the supplies do not lie
+            if (!reversed && reverse_below > 0 &&
+                (long long)h->nsrc + std::max<long long>(h->gex, 0) <= reverse_below)
+                WW_TRY(flip_frame());
+        }
         const auto tp0 = std::chrono::steady_clock::now();
         const long long r0 = S.rounds, w0 = S.windows;
         const unsigned long long v0 = trace ? host_visits() : 0, it0 = h->iters, vs0 = h->vt_sum,
@@ -1420,7 +1436,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         const long long gex0 = h->gex;
         ++pass;
         hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.act,
-                           ra.lists, NT, rr, gsrc, ra.perim_tiles, ra.nperim);
+                           ra.lists, NT, rr, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
         // Windows in lexicographic (distance, hops) order: every label <= lb
         // is exact at the end of a window.  The first window admits only
@@ -1429,6 +1445,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         unsigned long long lb = mk_label(0, h0);
         unsigned int settled = 0;  // deficits settled by the last window
         unsigned int dstep = dstep0;
+        bool finished = false;  // the previous pass left no units: this one is void
         for (;;) {  // windows
             ++S.windows;
             const long long rw0 = S.rounds;
@@ -1455,8 +1472,21 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 float ms = 0.f;
                 WW_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
                 S.relax_ms += ms;
+                if (prev_unread) {  // the previous pass's end
+                    prev_unread = false;
+                    ++S.passes;
+                    S.augmentations += h->prev_naug;
+                    S.path_arcs += (long long)h->prev_arcs;
+                    if (h->prev_naug == 0)
+                        return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
+                    if (h->nsrc == 0 && h->gex <= 0) {
+                        finished = true;
+                        break;
+                    }
+                }
                 if (h->count[rr % 3][0] == 0) break;
             }
+            if (finished) break;
             // settled deficits and the smallest parked candidate (the latter
             // is only read when the window does not end the pass)
             const int tg = (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB);
@@ -1489,6 +1519,11 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             hipLaunchKernelGGL(k_requeue_pending, dim3(tg), dim3(SB), 0, st, ctl, ra.pstamp, pass,
                                ra.tile_rej, lb, ra.act, ra.lists, NT, rr);
             WW_LAUNCH_CHECK();
+        }
+        if (finished) {  // not a pass: leave the counts as if it never ran
+            --S.windows;
+            S.rounds -= rounds_per_sync;
+            break;
         }
         if (settled == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: %u supplies reach no demand", h->nsrc);
@@ -1534,6 +1569,10 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         WW_LAUNCH_CHECK();
         std::swap(src, src2);
         std::swap(def, def2);
+        if ((reversed || reverse_below <= 0) && !trace && !check) {
+            prev_unread = true;
+            continue;
+        }
         WW_TRY(sync_ctl());
         ++S.passes;
         S.augmentations += h->naug;
