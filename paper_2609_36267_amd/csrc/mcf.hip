@@ -143,6 +143,7 @@ __device__ __forceinline__ void ground_arc(const Graph &g, unsigned int a, int &
 constexpr int INIT_THREADS = 256;
 constexpr int INIT_PER = 16;
 constexpr int INIT_CHUNK = INIT_THREADS * INIT_PER;
+static_assert(INIT_CHUNK < (1 << 16), "packed per-block counts of the list writer");
 
 __device__ __forceinline__ int block_sum_int(int v, int *red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -174,23 +175,75 @@ __device__ __forceinline__ int block_scan_int(int v, int *red, int *total) {
     return before + inc - v;
 }
 
+// The residues of loop nodes v0 .. v0 + INIT_PER - 1 (zero beyond N): one
+// 16-byte load where the plane is 16-byte aligned and the group is whole.
+static_assert(INIT_PER == 16, "residue groups are 16-byte loads");
+__device__ __forceinline__ bool load_res16(const int8_t *res, long long v0, long long N, int8_t r[16]) {
+    const bool whole = v0 + 16 <= N;
+    if (whole && ((uintptr_t)res & 15u) == 0) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(res + v0);
+        const unsigned int w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) r[q] = (int8_t)(w[q >> 2] >> (8 * (q & 3)));
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) r[q] = v0 + q < N ? res[v0 + q] : (int8_t)0;
+    }
+    return whole;
+}
+
+// Node state of a block's chunk of INIT_CHUNK nodes, each thread taking
+// INIT_PER consecutive nodes: the excess is a copy of the residues, the
+// potentials zero, the labels infinite, all in 16-byte stores.
 __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const int8_t *__restrict__ res,
                                                                 int *__restrict__ bc) {
     __shared__ int red[INIT_THREADS / 64];
     const long long N = (long long)g.R * g.C;
-    const long long base = (long long)blockIdx.x * INIT_CHUNK;
+    const long long c0 = (long long)blockIdx.x * INIT_CHUNK;
+    const long long v0 = c0 + (long long)threadIdx.x * INIT_PER;
+    int8_t r[INIT_PER];
+    const bool whole = load_res16(res, v0, N, r);
     int np = 0, nn = 0, sum = 0;
-    for (int k = 0; k < INIT_PER; ++k) {
-        const long long v = base + k * INIT_THREADS + threadIdx.x;
-        if (v >= N) break;
-        const int r = res[v];
-        g.ex[v] = (int8_t)r;
-        g.pot[v] = 0;
-        g.lab[v] = LINF;
-        g.best[v] = LINF;
-        np += r > 0;
-        nn += r < 0;
-        sum += r;
+    unsigned int w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < INIT_PER; ++q) {
+        np += r[q] > 0;
+        nn += r[q] < 0;
+        sum += r[q];
+        w[q >> 2] |= (unsigned int)(uint8_t)r[q] << (8 * (q & 3));
+        // best (a root's chosen deficit) is only kept at roots: supplies,
+        // which are residues in one frame or the other, and perimeter nodes
+        // (ground-rooted subtrees); other nodes' entries are never read
+        if (r[q] != 0) g.best[v0 + q] = LINF;
+    }
+    if (whole) {
+        *reinterpret_cast<uint4 *>(g.ex + v0) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else {
+        for (int q = 0; q < INIT_PER; ++q)
+            if (v0 + q < N) g.ex[v0 + q] = r[q];
+    }
+    if (c0 + INIT_CHUNK <= N) {
+        uint4 *pot = reinterpret_cast<uint4 *>(g.pot + c0);
+        uint4 *lab = reinterpret_cast<uint4 *>(g.lab + c0);
+        const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+        const uint4 inf = make_uint4((unsigned int)LINF, (unsigned int)(LINF >> 32), (unsigned int)LINF,
+                                     (unsigned int)(LINF >> 32));
+#pragma unroll
+        for (int k = 0; k < INIT_CHUNK / 4 / INIT_THREADS; ++k) pot[k * INIT_THREADS + threadIdx.x] = zero;
+#pragma unroll
+        for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) lab[k * INIT_THREADS + threadIdx.x] = inf;
+    } else {
+        for (long long v = c0 + threadIdx.x; v < N; v += INIT_THREADS) {
+            g.pot[v] = 0;
+            g.lab[v] = LINF;
+        }
+    }
+    for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < 2u * g.C + 2u * g.R;
+         a += gridDim.x * blockDim.x) {
+        int i, j, kind, delta;
+        long long e;
+        ground_arc(g, a, i, j, kind, e, delta);
+        g.best[(long long)i * g.C + j] = LINF;
     }
     np = block_sum_int(np, red);
     nn = block_sum_int(nn, red);
@@ -202,36 +255,34 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
     }
 }
 
-// one block: exclusive scans of the per-block counts, totals into ctl
+// one block: exclusive scans of the per-block counts, totals into ctl; each
+// thread sums a run of consecutive blocks, one block scan joins the runs
 __global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict__ bc, Ctl *ctl) {
     __shared__ int red[16];
-    int carry_p = 0, carry_n = 0;
-    long long sum = 0;
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int b = b0 + threadIdx.x;
-        int p = 0, q = 0, s = 0;
-        if (b < nb) {
-            p = bc[3 * b];
-            q = bc[3 * b + 1];
-            s = bc[3 * b + 2];
-        }
-        int tp, tq;
-        const int ep = block_scan_int(p, red, &tp);
-        const int eq = block_scan_int(q, red, &tq);
-        const int ts = block_sum_int(s, red);
-        if (b < nb) {
-            bc[3 * b] = carry_p + ep;
-            bc[3 * b + 1] = carry_n + eq;
-        }
-        carry_p += tp;
-        carry_n += tq;
-        sum += ts;
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+    int p = 0, q = 0, s = 0;
+    for (int b = b0; b < b1; ++b) {
+        p += bc[3 * b];
+        q += bc[3 * b + 1];
+        s += bc[3 * b + 2];
+    }
+    int tp, tq;
+    int ep = block_scan_int(p, red, &tp);
+    int eq = block_scan_int(q, red, &tq);
+    const int ts = block_sum_int(s, red);
+    for (int b = b0; b < b1; ++b) {
+        const int bp = bc[3 * b], bq = bc[3 * b + 1];
+        bc[3 * b] = ep;
+        bc[3 * b + 1] = eq;
+        ep += bp;
+        eq += bq;
     }
     if (threadIdx.x == 0) {
-        ctl->nsrc = carry_p;
-        ctl->ndef = carry_n;
-        ctl->sum_res = sum;
-        ctl->gex = -sum;
+        ctl->nsrc = tp;
+        ctl->ndef = tq;
+        ctl->sum_res = ts;
+        ctl->gex = -(long long)ts;
         ctl->gpot = 0;
         ctl->glab = LINF;
         ctl->wminrej[0] = ctl->wminrej[1] = LINF;
@@ -242,20 +293,25 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const 
                                                                 const int *__restrict__ bc,
                                                                 unsigned int *__restrict__ src,
                                                                 unsigned int *__restrict__ def) {
+    // each thread takes INIT_PER consecutive nodes of the block's chunk, so
+    // one scan of the packed (supplies, demands) counts places them all in
+    // node order (a thread's counts are at most INIT_PER and a block's at
+    // most INIT_CHUNK < 2^16, so the two halves never carry into each other)
     __shared__ int red[INIT_THREADS / 64];
     const long long N = (long long)g.R * g.C;
-    const long long base = (long long)blockIdx.x * INIT_CHUNK;
-    int op = bc[3 * blockIdx.x], on = bc[3 * blockIdx.x + 1];
-    for (int k = 0; k < INIT_PER; ++k) {
-        const long long v = base + k * INIT_THREADS + threadIdx.x;
-        const int r = v < N ? res[v] : 0;
-        int tp, tn;
-        const int ep = block_scan_int(r > 0, red, &tp);
-        const int en = block_scan_int(r < 0, red, &tn);
-        if (r > 0) src[op + ep] = (unsigned int)v;
-        if (r < 0) def[on + en] = (unsigned int)v;
-        op += tp;
-        on += tn;
+    const long long v0 = (long long)blockIdx.x * INIT_CHUNK + (long long)threadIdx.x * INIT_PER;
+    int8_t r[INIT_PER];
+    load_res16(res, v0, N, r);
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < INIT_PER; ++q) cnt += (r[q] > 0) + ((r[q] < 0) << 16);
+    int tot;
+    const int ex = block_scan_int(cnt, red, &tot);
+    int op = bc[3 * blockIdx.x] + (ex & 0xffff), on = bc[3 * blockIdx.x + 1] + (ex >> 16);
+#pragma unroll
+    for (int q = 0; q < INIT_PER; ++q) {
+        if (r[q] > 0) src[op++] = (unsigned int)(v0 + q);
+        if (r[q] < 0) def[on++] = (unsigned int)(v0 + q);
     }
 }
 

@@ -374,6 +374,43 @@ def test_errors_raise(torch_cuda, c0):
                       ww.default_cost_params(box_half=40))
 
 
+def test_mcf_unaligned_residues(torch_cuda):
+    """A residue plane at odd byte offsets, over several 4096-node set-up
+    chunks and a ragged last one: the set-up reads it byte by byte instead of
+    16 bytes at a time, and the solve equals the aligned one and the
+    oracle's optimum."""
+    import ctypes as C
+    torch = torch_cuda
+    m, n = 90, 160
+    rng = np.random.default_rng(12)
+    res = np.zeros((m - 1, n - 1), np.int8)
+    idx = rng.choice((m - 1) * (n - 1), 400, replace=False)
+    res.flat[idx[:190]] = 1
+    res.flat[idx[190:]] = -1
+    costs = [rng.integers(1, 600, s).astype(np.int16)
+             for s in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n))]
+    ref = ww.mcf_solve(res, costs, m, n)
+    assert ref.total_cost == oracle.mcf(res, tuple(costs), m=m, n=n)[3]
+    cs = [torch.from_numpy(c).cuda() for c in costs]
+    nx, ny = m * (n - 1), (m - 1) * n
+    for off in (1, 5, 8):
+        buf = torch.zeros(res.size + 32, dtype=torch.int8, device="cuda")
+        buf[off:off + res.size] = torch.from_numpy(res.ravel()).cuda()
+        fx = torch.empty(nx, dtype=torch.int8, device="cuda")
+        fy = torch.empty(ny, dtype=torch.int8, device="cuda")
+        tot = C.c_int64(0)
+        st = ww.McfStats()
+        ww._check(ww.load().ww_mcf_solve(
+            C.c_void_p(buf.data_ptr() + off), m, n, *[C.c_void_p(c.data_ptr()) for c in cs],
+            C.c_void_p(fx.data_ptr()), C.c_void_p(fy.data_ptr()), None,
+            C.byref(tot), C.byref(st), ww._stream()))
+        torch.cuda.synchronize()
+        assert tot.value == ref.total_cost
+        assert st.as_dict()["supplies"] == ref.stats["supplies"]
+        assert np.array_equal(fx.cpu().numpy().reshape(m, n - 1), np_(ref.dk_x))
+        assert np.array_equal(fy.cpu().numpy().reshape(m - 1, n), np_(ref.dk_y))
+
+
 def test_mcf_unaligned_outputs_reversed_frame(torch_cuda):
     """Flow planes at odd byte offsets (the C ABI allows any pointer) through
     a schedule that searches from the demands from the first pass on, so that
