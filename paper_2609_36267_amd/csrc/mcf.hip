@@ -1458,8 +1458,13 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const unsigned int bound_cap = 0xffff0000u;
     unsigned int rr = 1, pass = 0;  // next round, current pass
     const int SB = 256;
-    const int list_grid = (int)std::min<long long>(4096, std::max<long long>(1, ceil_div(N, 256)));
-    const int we_grid = std::max(list_grid, (int)std::min<unsigned int>(1024u, (NT + SB - 1) / SB));
+    // Kernels over the node lists are grid-stride loops sized from the list
+    // lengths the host last read: the lists only shrink between two reads
+    // (a frame reversal swaps them and is read at once), and a grid that
+    // matches the list spares late passes thousands of idle workgroups.
+    auto lgrid = [&](long long items) {
+        return (int)std::min<long long>(4096, std::max<long long>(1, ceil_div(items, SB)));
+    };
     std::vector<unsigned long long> hv(64 * 16);
     auto host_visits = [&]() -> unsigned long long {
         if (hipMemcpy(hv.data(), ra.vpart, 8192, hipMemcpyDeviceToHost) != hipSuccess) return 0;
@@ -1491,7 +1496,9 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         const unsigned int nsrc0 = h->nsrc;
         const long long gex0 = h->gex;
         ++pass;
-        hipLaunchKernelGGL(k_pass_init, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, ra.act,
+        const long long ns_h = h->nsrc, nd_h = h->ndef;  // list lengths, upper bounds
+        hipLaunchKernelGGL(k_pass_init, dim3(lgrid(std::max<long long>(ns_h, ra.nperim))), dim3(SB), 0, st,
+                           g, ctl, src, ra.act,
                            ra.lists, NT, rr, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
         // Windows in lexicographic (distance, hops) order: every label <= lb
@@ -1518,7 +1525,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 // that ends the window needs no further round trip (each run
                 // writes the slot of its batch parity and clears the other)
                 wslot = (int)(nbatch++ & 1);
-                hipLaunchKernelGGL(k_window_end, dim3(we_grid), dim3(SB), 0, st, g, ctl, def, lb,
+                hipLaunchKernelGGL(k_window_end, dim3(lgrid(std::max<long long>(nd_h, NT))), dim3(SB), 0,
+                                   st, g, ctl, def, lb,
                                    ra.pstamp, pass, ra.tile_rej, NT, wslot, rr);
                 WW_LAUNCH_CHECK();
                 S.rounds += rounds_per_sync;
@@ -1586,11 +1594,12 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         const int pg = (int)std::min<long long>(1024, ceil_div(nperim_arcs, SB));
         hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, lb);
         WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_roots, dim3(list_grid), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
+        hipLaunchKernelGGL(k_roots, dim3(lgrid(nd_h + 1)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_gsub_select, dim3(pg), dim3(SB), 0, st, g, ctl, gsub_list, drop);
         WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_augment, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, gsub_list, drop);
+        hipLaunchKernelGGL(k_augment, dim3(lgrid(ns_h + nperim_arcs)), dim3(SB), 0, st, g, ctl, src,
+                           gsub_list, drop);
         WW_LAUNCH_CHECK();
         if (check)
             WW_HIP(hipMemcpyAsync(lab_copy, g.lab, sizeof(unsigned long long) * N,
@@ -1619,7 +1628,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 return fail(WW_E_DEVICE, "min-cost flow check failed (details on stderr)");
             }
         }
-        hipLaunchKernelGGL(k_compact, dim3(list_grid), dim3(SB), 0, st, g, ctl, src, def, src2, def2);
+        hipLaunchKernelGGL(k_compact, dim3(lgrid(ns_h + nd_h)), dim3(SB), 0, st, g, ctl, src, def, src2,
+                           def2);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_swap_lists, dim3(1), dim3(1), 0, st, ctl);
         WW_LAUNCH_CHECK();
