@@ -262,6 +262,8 @@ __global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict_
     const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
     const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
     int p = 0, q = 0, s = 0;
+    // unrolled so that the loads of several blocks' counts are in flight at once
+#pragma unroll 8
     for (int b = b0; b < b1; ++b) {
         p += bc[3 * b];
         q += bc[3 * b + 1];
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict_
     int ep = block_scan_int(p, red, &tp);
     int eq = block_scan_int(q, red, &tq);
     const int ts = block_sum_int(s, red);
+#pragma unroll 8
     for (int b = b0; b < b1; ++b) {
         const int bp = bc[3 * b], bq = bc[3 * b + 1];
         bc[3 * b] = ep;
