@@ -1594,13 +1594,21 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         }
         if (settled == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: %u supplies reach no demand", h->nsrc);
+        // The host's last read followed the pass's last round, so it holds
+        // the pass's final ground label and excess: the ground's predecessor
+        // is only needed when the ground is a settled deficit, and subtrees
+        // hang off the ground only while it is a source.
         const int pg = (int)std::min<long long>(1024, ceil_div(nperim_arcs, SB));
-        hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, lb);
-        WW_LAUNCH_CHECK();
+        if (h->glab <= lb && h->gex <= 0) {
+            hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, lb);
+            WW_LAUNCH_CHECK();
+        }
         hipLaunchKernelGGL(k_roots, dim3(lgrid(nd_h + 1)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
         WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_gsub_select, dim3(pg), dim3(SB), 0, st, g, ctl, gsub_list, drop);
-        WW_LAUNCH_CHECK();
+        if (h->gex > 0) {
+            hipLaunchKernelGGL(k_gsub_select, dim3(pg), dim3(SB), 0, st, g, ctl, gsub_list, drop);
+            WW_LAUNCH_CHECK();
+        }
         hipLaunchKernelGGL(k_augment, dim3(lgrid(ns_h + nperim_arcs)), dim3(SB), 0, st, g, ctl, src,
                            gsub_list, drop);
         WW_LAUNCH_CHECK();
