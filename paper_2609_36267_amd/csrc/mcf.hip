@@ -1441,7 +1441,12 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         std::swap(src, def);
         std::swap(src2, def2);
         reversed = !reversed;
-        return sync_ctl();
+        // the host's copy of the counters follows the kernel's own exchange
+        // (no round trip: the next read of the block checks the error flags)
+        std::swap(h->nsrc, h->ndef);
+        h->gex = -h->gex;
+        h->gpot = -h->gpot;
+        return WW_OK;
     };
     const bool trace_windows = trace_env && trace_env[0] == '2';
     // one wave of resident workgroups: more would only add workgroups that
