@@ -196,7 +196,8 @@ __device__ __forceinline__ bool load_res16(const int8_t *res, long long v0, long
 // INIT_PER consecutive nodes: the excess is a copy of the residues, the
 // potentials zero, the labels infinite, all in 16-byte stores.
 __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const int8_t *__restrict__ res,
-                                                                int *__restrict__ bc) {
+                                                                int *__restrict__ bc,
+                                                                unsigned int *__restrict__ flip) {
     __shared__ int red[INIT_THREADS / 64];
     const long long N = (long long)g.R * g.C;
     const long long c0 = (long long)blockIdx.x * INIT_CHUNK;
@@ -224,17 +225,22 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
     }
     if (c0 + INIT_CHUNK <= N) {
         uint4 *pot = reinterpret_cast<uint4 *>(g.pot + c0);
+        uint4 *fl = reinterpret_cast<uint4 *>(flip + c0);
         uint4 *lab = reinterpret_cast<uint4 *>(g.lab + c0);
         const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
         const uint4 inf = make_uint4((unsigned int)LINF, (unsigned int)(LINF >> 32), (unsigned int)LINF,
                                      (unsigned int)(LINF >> 32));
 #pragma unroll
-        for (int k = 0; k < INIT_CHUNK / 4 / INIT_THREADS; ++k) pot[k * INIT_THREADS + threadIdx.x] = zero;
+        for (int k = 0; k < INIT_CHUNK / 4 / INIT_THREADS; ++k) {
+            pot[k * INIT_THREADS + threadIdx.x] = zero;
+            fl[k * INIT_THREADS + threadIdx.x] = zero;
+        }
 #pragma unroll
         for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) lab[k * INIT_THREADS + threadIdx.x] = inf;
     } else {
         for (long long v = c0 + threadIdx.x; v < N; v += INIT_THREADS) {
             g.pot[v] = 0;
+            flip[v] = 0;
             g.lab[v] = LINF;
         }
     }
@@ -951,8 +957,15 @@ __device__ __forceinline__ void flip_ground_arc(Graph &g, unsigned int a) {
 }
 
 // Apply one unit along root r's chosen path: from the deficit back to r.
+// The in-grid arcs of a path are not flipped here: the walk stores
+// (pass, direction) at the node each arc enters, and k_potentials, which
+// visits every node of the tiles relaxed in the pass (path nodes are
+// settled, so their tiles were relaxed), applies the flip.  A step of the
+// walk is then one dependent label load and one store.  Paths from
+// different roots are vertex-disjoint, so a node holds one arc per pass;
+// no kernel reads the flows between the two.
 __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *gsub_list,
-                          const unsigned char *drop) {
+                          const unsigned char *drop, unsigned int *flip, unsigned int pass) {
     const unsigned int ns = ctl->nsrc, ng = ctl->gsub_count;
     const long long N = (long long)g.R * g.C;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns + ng;
@@ -987,9 +1000,6 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
         } else {
             v = t;
         }
-        // The next label is loaded before the flow byte of the current arc
-        // is updated, so that the two loads of a step are in flight together
-        // (the flow update is not on the walk's dependence chain).
         unsigned long long l = g.lab[v];
         for (long long steps = 0; steps <= N + 2; ++steps) {
             const int dir = (int)(l & 7);
@@ -997,9 +1007,9 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
             int i, j;
             node_rc(g, v, i, j);
             long long u = pred_node(g, i, j, dir);
+            flip[v] = (pass << 3) | (unsigned int)dir;
+            ++flips;
             if (u < 0) {
-                flip_into(g, v, dir);
-                ++flips;
                 if (is_g) break;  // the ground is the supply
                 const unsigned int a = ctl->gpred;
                 if (a >= na) {
@@ -1012,12 +1022,8 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
                 long long e;
                 ground_arc(g, a, pi, pj, kind, e, delta);
                 u = (long long)pi * g.C + pj;
-                l = g.lab[u];
-            } else {
-                l = g.lab[u];
-                flip_into(g, v, dir);
-                ++flips;
             }
+            l = g.lab[u];
             v = u;
         }
         if (is_g) atomicAdd((unsigned long long *)&ctl->gex, (unsigned long long)-1ll);
@@ -1039,7 +1045,7 @@ constexpr int POT_CHUNK = 8;
 
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
                                                     unsigned int pass, unsigned int NT,
-                                                    unsigned long long lb) {
+                                                    unsigned long long lb, const unsigned int *flip) {
     __shared__ unsigned int todo[POT_CHUNK];
     __shared__ int ntodo;
     const unsigned int bound = ldist(lb);
@@ -1058,16 +1064,20 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
             const int i0 = (int)(tile / g.TC) * TJ, j0 = (int)(tile % g.TC) * TJ;
             long long v[TJ * TJ / 256];
             unsigned long long l[TJ * TJ / 256];
+            unsigned int fr[TJ * TJ / 256];
 #pragma unroll
             for (int s = 0; s < TJ * TJ / 256; ++s) {
                 const int t = threadIdx.x + 256 * s;
                 const int i = i0 + t / TJ, j = j0 + t % TJ;
                 v[s] = (i < g.R && j < g.C) ? (long long)i * g.C + j : -1;
                 l[s] = v[s] >= 0 ? g.lab[v[s]] : LINF;
+                fr[s] = v[s] >= 0 ? flip[v[s]] : 0u;
             }
 #pragma unroll
             for (int s = 0; s < TJ * TJ / 256; ++s) {
                 if (l[s] == LINF) continue;
+                // the arc into this node on a path augmented in this pass
+                if ((fr[s] >> 3) == pass) flip_into(g, v[s], (int)(fr[s] & 7u));
                 g.lab[v[s]] = LINF;
                 if (l[s] > lb) continue;
                 const unsigned int d = ldist(l[s]);
@@ -1394,7 +1404,9 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const int nib = ceil_div(N, INIT_CHUNK);
     int *bc = nullptr;
     WW_TRY(scratch(SLOT_MCF_PART, sizeof(long long) * (size_t)std::max(3 * nib, 8192) + 256, (void **)&bc));
-    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res, bc);
+    unsigned int *flip = nullptr;  // deferred path flips: (pass, direction) per node
+    WW_TRY(scratch(SLOT_MCF_FLIP, sizeof(unsigned int) * (size_t)N, (void **)&flip));
+    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res, bc, flip);
     WW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mcf_init_scan, dim3(1), dim3(1024), 0, st, nib, bc, ctl);
     WW_LAUNCH_CHECK();
@@ -1615,13 +1627,13 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             WW_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(k_augment, dim3(lgrid(ns_h + nperim_arcs)), dim3(SB), 0, st, g, ctl, src,
-                           gsub_list, drop);
+                           gsub_list, drop, flip, pass);
         WW_LAUNCH_CHECK();
         if (check)
             WW_HIP(hipMemcpyAsync(lab_copy, g.lab, sizeof(unsigned long long) * N,
                                   hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_potentials, dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass,
-                           NT, lb);
+                           NT, lb, flip);
         WW_LAUNCH_CHECK();
         if (check) {
             WW_HIP(hipMemsetAsync(crec, 0, sizeof(CheckRec), st));

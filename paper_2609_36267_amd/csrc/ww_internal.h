@@ -79,6 +79,7 @@ enum Slot {
     SLOT_LUT_WORK, SLOT_CC_LABEL, SLOT_CC_SIZE, SLOT_CC_SMALL,
     SLOT_GS_PLANES, SLOT_GS_SHIFT, SLOT_GS_PSI,
     SLOT_BR_LABEL, SLOT_BR_RANK, SLOT_BR_SMALL, SLOT_BR_SIZES, SLOT_BR_Q,
+    SLOT_MCF_FLIP,
     SLOT_COUNT
 };
 
