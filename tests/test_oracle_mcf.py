@@ -298,3 +298,163 @@ def test_c0_self_certificate(scene_c0, lut9):
     cert = oracle.check_optimal(out["res"], out["costs"], out["dkx"], out["dky"], out["pot"])
     assert cert["ok"] and cert["min_reduced_cost"] >= 0
     assert out["total"] == flow_cost(out["dkx"], out["dky"], out["costs"])
+
+
+# ----------------------------------------------------------------------------
+# The optimality checker must reject what is not an optimum (Section II-C:
+# successive shortest paths end at a flow whose residual arcs all have
+# non-negative reduced cost and whose divergence equals the residues).  Each
+# case starts from an optimum that brute-force enumeration confirms and breaks
+# exactly one of the two conditions.
+# ----------------------------------------------------------------------------
+
+def _pinned_optimum(seed, m, n, hi=50):
+    """A random grid whose optimum is unique (brute force), solved by the
+    oracle; returns (res, costs, dkx, dky, pot)."""
+    rng = np.random.default_rng(seed)
+    for _ in range(200):
+        psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+        wx, wy = wraps_from_psi(psi)
+        costs = random_costs(rng, m, n, hi)
+        costs = tuple(np.maximum(c, 1).astype(np.int16) for c in costs)  # no zero-cost arc
+        best, count = oracle.bruteforce(wx, wy, costs)
+        res, _, _ = oracle.residues(psi)
+        if count != 1 or not np.abs(res).sum():
+            continue
+        dkx, dky, pot, total = oracle.mcf(res, costs, m=m, n=n)
+        assert total == best
+        cert = oracle.check_optimal(res, costs, dkx, dky, pot)
+        assert cert["ok"] and cert["divergence_violations"] == 0
+        assert cert["negative_reduced_costs"] == 0
+        return res, costs, dkx, dky, pot
+    raise AssertionError("no unique-optimum grid found")
+
+
+CHECK_CASES = [(11, 3, 4), (12, 4, 4), (13, 4, 3), (14, 3, 5)]
+
+
+@pytest.mark.parametrize("seed,m,n", CHECK_CASES)
+def test_check_rejects_flipped_edge(seed, m, n):
+    """Changing one edge's cycle difference by one moves one unit of
+    divergence at each of its two dual endpoints: two violations (an edge on
+    the image border has the ground as one endpoint)."""
+    res, costs, dkx, dky, pot = _pinned_optimum(seed, m, n)
+    for plane, i, j in [("x", 0, 0), ("x", 1, n - 2), ("y", 0, 1), ("y", m - 2, n - 1)]:
+        bx, by = dkx.copy(), dky.copy()
+        b = bx if plane == "x" else by
+        b[i, j] = 1 if b[i, j] <= 0 else 0
+        cert = oracle.check_optimal(res, costs, bx, by, pot)
+        assert not cert["ok"]
+        assert cert["divergence_violations"] == 2, (plane, i, j, cert)
+
+
+@pytest.mark.parametrize("seed,m,n", CHECK_CASES)
+def test_check_rejects_out_of_range_cycle_difference(seed, m, n):
+    """|dk| = 2 is not a flow of the unit-capacity problem."""
+    res, costs, dkx, dky, pot = _pinned_optimum(seed, m, n)
+    bx, by = dkx.copy(), dky.copy()
+    # +1 then another +1 around the same loop keeps divergence intact only if
+    # both are counted; the range check alone must already fail it
+    bx[1, 0] = 2 if bx[1, 0] >= 0 else -2
+    cert = oracle.check_optimal(res, costs, bx, by, pot)
+    assert not cert["ok"] and cert["divergence_violations"] >= 1
+
+
+@pytest.mark.parametrize("seed,m,n", CHECK_CASES)
+def test_check_rejects_feasible_but_costlier_flow(seed, m, n):
+    """One unit pushed around a residual cycle (the four loops around an
+    interior pixel, which is K += 1 at that pixel) keeps the divergence but
+    raises the cost; since the optimum is unique the cycle costs more than
+    zero, so under the old potentials the reversed arcs of that cycle have
+    negative reduced cost and the checker must say so."""
+    res, costs, dkx, dky, pot = _pinned_optimum(seed, m, n)
+    base = flow_cost(dkx, dky, costs)
+    tried = 0
+    for i in range(1, m - 1):
+        for j in range(1, n - 1):
+            for s in (1, -1):
+                bx, by = dkx.astype(int), dky.astype(int)
+                bx[i, j - 1] += s   # edge (i,j-1)->(i,j): K_v rises
+                bx[i, j] -= s       # edge (i,j)->(i,j+1): K_u rises
+                by[i - 1, j] += s
+                by[i, j] -= s
+                if np.abs(bx).max() > 1 or np.abs(by).max() > 1:
+                    continue
+                bx, by = bx.astype(np.int8), by.astype(np.int8)
+                assert flow_cost(bx, by, costs) > base
+                cert = oracle.check_optimal(res, costs, bx, by, pot)
+                assert not cert["ok"]
+                assert cert["divergence_violations"] == 0
+                assert cert["negative_reduced_costs"] >= 1 and cert["min_reduced_cost"] < 0
+                tried += 1
+    assert tried >= 1
+
+
+@pytest.mark.parametrize("seed,m,n", CHECK_CASES)
+def test_check_rejects_perturbed_potential(seed, m, n):
+    """Raising one node's potential by one, where an arc leaves it with
+    reduced cost zero (a tight arc, which every shortest-path tree arc is),
+    makes that arc's reduced cost -1."""
+    res, costs, dkx, dky, pot = _pinned_optimum(seed, m, n)
+    R, C = m - 1, n - 1
+    cxp, cxn, cyp, cyn = costs
+    found = 0
+    for u in range(R * C):
+        i, j = divmod(u, C)
+        # the four arcs out of u with their heads and cycle-difference moves
+        outs = [(0, i, j, -1, (i - 1) * C + j if i > 0 else R * C),
+                (0, i + 1, j, +1, (i + 1) * C + j if i + 1 < R else R * C),
+                (1, i, j, +1, u - 1 if j > 0 else R * C),
+                (1, i, j + 1, -1, u + 1 if j + 1 < C else R * C)]
+        tight = False
+        for kind, ei, ej, d, v in outs:
+            f = int((dkx if kind == 0 else dky)[ei, ej])
+            cp = int((cxp if kind == 0 else cyp)[ei, ej])
+            cn = int((cxn if kind == 0 else cyn)[ei, ej])
+            if f == 0:
+                c = cp if d > 0 else cn
+            elif f == -d:
+                c = -(cp if f > 0 else cn)
+            else:
+                continue
+            if c - int(pot[u]) + int(pot[v]) == 0:
+                tight = True
+        if not tight:
+            continue
+        bp = pot.copy()
+        bp[u] += 1
+        cert = oracle.check_optimal(res, costs, dkx, dky, bp)
+        assert not cert["ok"]
+        assert cert["divergence_violations"] == 0
+        assert cert["min_reduced_cost"] == -1 and cert["negative_reduced_costs"] >= 1
+        found += 1
+    assert found >= 1
+
+
+@pytest.mark.parametrize("seed,m,n", CHECK_CASES)
+def test_check_accepts_shifted_potentials(seed, m, n):
+    """Positive control: adding one constant to every potential (ground
+    included) changes no reduced cost."""
+    res, costs, dkx, dky, pot = _pinned_optimum(seed, m, n)
+    cert = oracle.check_optimal(res, costs, dkx, dky, pot + 12345)
+    assert cert["ok"]
+
+
+def test_mcf_reports_infeasible_when_supply_exceeds_cut():
+    """A 5 x 5 block of +1 loops inside a 12 x 12 image: 25 units must leave
+    the block, but only 20 unit-capacity arcs cross its boundary (5 per
+    side), so no feasible flow exists (Section II-A, unit capacities)."""
+    m = n = 12
+    res = np.zeros((m - 1, n - 1), np.int8)
+    res[3:8, 3:8] = 1
+    rng = np.random.default_rng(5)
+    costs = random_costs(rng, m, n, 100)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.mcf(res, costs, m=m, n=n)
+    assert e.value.code == oracle.E_INFEASIBLE
+    # with the centre 3 x 3 cleared, 16 supplies meet the same cut of 20:
+    # feasible (every set holding the supplies has at least 20 arcs out)
+    res2 = res.copy()
+    res2[4:7, 4:7] = 0
+    _, _, pot, total = oracle.mcf(res2, costs, m=m, n=n)
+    assert total > 0
