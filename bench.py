@@ -498,7 +498,8 @@ def main():
     golden = None
     if args.workload == "c2" and os.path.exists(GOLDEN):
         golden = json.load(open(GOLDEN))["total_cost"]
-    exact = bool(len(set(totals)) == 1 and (golden is None or totals[0] == golden))
+    same_every_step = bool(len(set(totals)) == 1)
+    equals_oracle = None if golden is None else bool(same_every_step and totals[0] == golden)
 
     achieved = visits * BYTES_PER_TILE_VISIT / (relax_ms / 1e3) / 1e9 if relax_ms > 0 else 0.0
     sha = round_kernel_sha()
@@ -523,7 +524,8 @@ def main():
                                 "c0": "ramp+bump scene 256x256, L=9"}[args.workload],
                    "pixels": m * n, "looks": sc.looks, "seed": {"c0": 0, "c1": 1, "c2": 2}[args.workload]},
         "total_cost": totals[-1],
-        "exact_cost": exact,
+        "same_cost_every_step": same_every_step,
+        "equals_oracle": equals_oracle,
         "oracle_cost": golden,
         "roofline": {"bound": "hbm", "kernel": "k_sssp_round",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

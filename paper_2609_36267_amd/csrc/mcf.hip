@@ -1156,6 +1156,26 @@ __global__ void k_check_rc(Graph g, const Ctl *ctl, const unsigned long long *la
     }
 }
 
+// Debug check (WW_MCF_CHECK=1) of the tile-list protocol after a batch of
+// rounds: the list of the next round rr holds count <= NT entries, every
+// entry is a tile index below NT whose round stamp is rr, and exactly count
+// tiles carry that stamp (so no tile is listed twice).  bad[0]: an entry out
+// of range; bad[1]: an entry without the stamp; bad[2]: tiles with the stamp.
+__global__ void k_check_lists(const Ctl *ctl, const unsigned int *act, const unsigned int *lists,
+                              unsigned int NT, unsigned int rr, unsigned int *bad) {
+    const unsigned int cnt = ctl->count[rr % 3][0];
+    const unsigned int *list = lists + (size_t)(rr % 3) * NT;
+    const unsigned int lim = cnt < NT ? cnt : NT;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < NT; k += gridDim.x * blockDim.x) {
+        if (k < lim) {
+            const unsigned int t = list[k];
+            if (t >= NT) atomicOr(&bad[0], 1u);
+            else if (act[t] != rr) atomicOr(&bad[1], 1u);
+        }
+        if (act[k] == rr) atomicAdd(&bad[2], 1u);
+    }
+}
+
 // keep supplies / demands that still carry excess; one counter atomic per
 // wave and list (the lanes' slots follow from a ballot)
 __global__ void k_compact(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *def,
@@ -1425,12 +1445,27 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const bool trace = trace_env && (trace_env[0] == '1' || trace_env[0] == '2');
     const char *check_env = getenv("WW_MCF_CHECK");
     const bool check = check_env && check_env[0] == '1';
-    unsigned long long *lab_copy = nullptr;
-    CheckRec *crec = nullptr, *hcrec = nullptr;
+    // debug-check buffers, released on every way out of the solve (the
+    // release waits for the device, so queued kernels never outlive them)
+    struct CheckBufs {
+        unsigned long long *lab = nullptr;
+        CheckRec *rec = nullptr, *hrec = nullptr;
+        unsigned int *bad = nullptr;
+        ~CheckBufs() {
+            if (lab || rec || bad) (void)hipDeviceSynchronize();
+            if (lab) (void)hipFree(lab);
+            if (rec) (void)hipFree(rec);
+            if (bad) (void)hipFree(bad);
+            if (hrec) (void)hipHostFree(hrec);
+        }
+    } cb;
+    unsigned long long *&lab_copy = cb.lab;
+    CheckRec *&crec = cb.rec, *&hcrec = cb.hrec;
     if (check) {
         WW_HIP(hipMalloc(&lab_copy, sizeof(unsigned long long) * N));
         WW_HIP(hipMalloc(&crec, sizeof(CheckRec)));
         WW_HIP(hipHostMalloc(&hcrec, sizeof(CheckRec)));
+        WW_HIP(hipMalloc(&cb.bad, 4 * sizeof(unsigned int)));
     }
 #ifndef WW_ROUNDS_PER_SYNC
 #define WW_ROUNDS_PER_SYNC 12
@@ -1553,6 +1588,24 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 if (S.rounds > 50000000)
                     return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
                 WW_TRY(sync_ctl());
+                if (check) {
+                    for (int q = 0; q < 3; ++q)
+                        if (h->count[q][0] > NT)
+                            return fail(WW_E_DEVICE, "min-cost flow check: list %d holds %u > %u tiles", q,
+                                        h->count[q][0], NT);
+                    unsigned int hb[4] = {0u, 0u, 0u, 0u};
+                    WW_HIP(hipMemsetAsync(cb.bad, 0, sizeof(hb), st));
+                    hipLaunchKernelGGL(k_check_lists, dim3(std::min<unsigned int>(1024u, (NT + 255) / 256)),
+                                       dim3(256), 0, st, ctl, ra.act, ra.lists, NT, rr, cb.bad);
+                    WW_LAUNCH_CHECK();
+                    WW_HIP(hipMemcpyAsync(hb, cb.bad, sizeof(hb), hipMemcpyDeviceToHost, st));
+                    WW_HIP(hipStreamSynchronize(st));
+                    if (hb[0] || hb[1] || hb[2] != h->count[rr % 3][0])
+                        return fail(WW_E_DEVICE,
+                                    "min-cost flow check: round %u list: out of range %u, unstamped %u, "
+                                    "stamped %u, count %u",
+                                    rr, hb[0], hb[1], hb[2], h->count[rr % 3][0]);
+                }
                 float ms = 0.f;
                 WW_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
                 S.relax_ms += ms;

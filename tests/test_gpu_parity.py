@@ -98,8 +98,10 @@ def test_residues_parity_c0(torch_cuda, c0):
 
 # ------------------------------------------------------------------ LUT ---
 
-@pytest.mark.parametrize("L", [9, 15, 5, 2, 64])
+@pytest.mark.parametrize("L", list(range(2, 65)))
 def test_lut_parity(torch_cuda, L):
+    """Every allowed number of looks: the device's FP64 table (its own exp,
+    log, log1p, lgamma and cos) floors to the same integers as the oracle's."""
     T_g = ww.build_cost_lut(L)
     T_o = oracle.build_lut(L)
     diff = np.argwhere(T_g != T_o)
@@ -185,6 +187,10 @@ def test_costs_parity_c0_with_gpu_table(torch_cuda, c0):
 
 def _mcf_case(psi, costs, m, n):
     res_o, _, _ = oracle.residues(psi)
+    return _mcf_case_res(res_o, costs, m, n)
+
+
+def _mcf_case_res(res_o, costs, m, n):
     dkx_o, dky_o, pot_o, tot_o = oracle.mcf(res_o, costs, m=m, n=n)
     r = ww.mcf_solve(res_o, costs, m, n, want_potentials=True)
     dkx_g, dky_g, pot_g = np_(r.dk_x), np_(r.dk_y), np_(r.potentials)
@@ -297,6 +303,38 @@ def test_mcf_degenerate_shapes(torch_cuda):
         r = ww.mcf_solve(np.zeros((max(m - 1, 0), max(n - 1, 0)), np.int8), costs, m, n)
         assert r.total_cost == 0
         assert not np_(r.dk_x).any() and not np_(r.dk_y).any()
+
+
+INFEASIBLE_SCHEDULES = [None, (64, 256, 0, 0, 1 << 30), (64, 256, 8, 1, 0), (64, 256, 4, 0, 16, 8)]
+
+
+@pytest.mark.parametrize("sched", INFEASIBLE_SCHEDULES)
+def test_mcf_infeasible_supply_exceeds_cut(torch_cuda, sched):
+    """25 supplies in a 5 x 5 block of a 12 x 12 image have 20 unit arcs
+    out of the block: the solve returns WW_E_INFEASIBLE (the oracle does
+    too), under every schedule, and the library stays usable."""
+    m = n = 12
+    res = np.zeros((m - 1, n - 1), np.int8)
+    res[3:8, 3:8] = 1
+    rng = np.random.default_rng(5)
+    costs = tuple(rng.integers(0, 101, sz).astype(np.int16)
+                  for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.mcf(res, costs, m=m, n=n)
+    assert eo.value.code == oracle.E_INFEASIBLE
+    old = ww.get_mcf_params()
+    try:
+        if sched is not None:
+            ww.set_mcf_params(*sched)
+        with pytest.raises(ww.WWError) as e:
+            ww.mcf_solve(res, costs, m, n)
+        assert e.value.code == ww.E_INFEASIBLE, str(e.value)
+        # a feasible neighbour (centre cleared: 16 supplies, cut 20) right after
+        res2 = res.copy()
+        res2[4:7, 4:7] = 0
+        _mcf_case_res(res2, costs, m, n)
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
 
 
 def test_mcf_parity_c0(torch_cuda, c0, lut9):
@@ -450,5 +488,32 @@ def test_mcf_unaligned_outputs_reversed_frame(torch_cuda):
             # nothing written outside the planes
             assert (bx[:off] == 99).all() and (bx[off + nx:] == 99).all()
             assert (by[:off] == 99).all() and (by[off + ny:] == 99).all()
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
+
+
+@pytest.mark.parametrize("sched", [None, (64, 256, 0, 0, 1 << 30), (1, 1, 2, 1, 1), (64, 256, 4, 0, 16, 8)])
+def test_mcf_debug_checks_pass(torch_cuda, sched, monkeypatch):
+    """With WW_MCF_CHECK=1 the solver checks, after every pass, that every
+    residual arc has a non-negative reduced cost, and after every batch of
+    rounds that the next round's tile list is within bounds and lists each
+    tile once.  The 96 x 130 scene with disks and a mask (15 tiles) and a
+    multi-tile random grid pass both checks and reach the oracle's cost."""
+    monkeypatch.setenv("WW_MCF_CHECK", "1")
+    sc = synth.make(96, 130, looks=9, seed=7, mask_frac=0.05, disks=2, disk_radius=(18, 30),
+                    keep_truth=False, workers=1)
+    T = oracle.build_lut(9)
+    cases = [(sc.psi, oracle.edge_costs(sc.psi, sc.coh, sc.valid, T), 96, 130)]
+    rng = np.random.default_rng(99)
+    m, n = 130, 257
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    cases.append((psi, tuple(rng.integers(0, 3000, s).astype(np.int16)
+                             for s in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n))), m, n))
+    old = ww.get_mcf_params()
+    try:
+        if sched is not None:
+            ww.set_mcf_params(*sched)
+        for psi, costs, m, n in cases:
+            _mcf_case(psi, costs, m, n)
     finally:
         ww.set_mcf_params(*old.as_tuple())
