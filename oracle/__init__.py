@@ -94,6 +94,7 @@ def _declare(L):
     L.wwo_build_lut.argtypes = [I32, P, P, P, P, P]
     L.wwo_edge_costs.argtypes = [P, P, P, I32, I32, P, I32, I32, I32, I32, D, I32, I32, P, P, P, P, P]
     L.wwo_lut_pair.argtypes = [P, I32, I32, I64, I64, D, I32, P, P]
+    L.wwo_lut_blend_looks.argtypes = [P, P, I64, I32, P]
     L.wwo_mcf.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P, P]
     L.wwo_check_optimal.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P]
     L.wwo_fixed_edges.argtypes = [I32, I32, P, P, P, P, P, P, P, P, P]
@@ -203,6 +204,28 @@ def build_lut(L, params=None, want_probs=False):
     if want_probs:
         return T, P0, Pp, sg
     return T
+
+
+def build_lut_q16(looks_q16, params=None):
+    """Table at the effective number of looks looks_q16 / 2^16 (2 <= L <=
+    64): the tables of the two neighbouring integers blended entry by entry
+    in 2^-16 fixed point, rounded down (wwo_lut_blend_looks)."""
+    l0, f = int(looks_q16) >> 16, int(looks_q16) & 0xffff
+    if l0 < 2 or l0 > 64 or (l0 == 64 and f):
+        raise OracleError(E_INVALID_ARG, "build_lut_q16")
+    T0 = build_lut(l0, params)
+    if f == 0:
+        return T0
+    T1 = build_lut(l0 + 1, params)
+    return lut_blend_looks(T0, T1, f)
+
+
+def lut_blend_looks(T0, T1, f):
+    T0 = _c(T0, np.int16)
+    T1 = _c(T1, np.int16)
+    out = np.zeros_like(T0)
+    lib().wwo_lut_blend_looks(_p(T0), _p(T1), int(T0.size), int(f), _p(out))
+    return out
 
 
 # ------------------------------------------------------------------- costs ---

@@ -432,6 +432,20 @@ int wwo_build_lut(int L, const wwo_lut_params *pin, int16_t *T, double *P0o, dou
     return WWO_OK;
 }
 
+/* The table at a non-integer number of looks (Section II-B: the table is
+ * precomputed on a grid that includes L and read by interpolation at run
+ * time).  The L grid is the integers; an effective L given in 2^-16 fixed
+ * point, L = l0 + f / 2^16 with 0 <= f < 2^16, blends the tables of the
+ * two neighbouring integers entry by entry:
+ *   T[c][b] = floor((T_l0[c][b] (2^16 - f) + T_l0+1[c][b] f) / 2^16),
+ * so f = 0 gives T_l0 itself.  n entries.  Pinned by the integer nodes,
+ * the halfway floor-of-mean, and agreement with numpy's linear
+ * interpolation over L and with the model evaluated at non-integer L. */
+void wwo_lut_blend_looks(const int16_t *T0, const int16_t *T1, int64_t n, int32_t f, int16_t *out) {
+    for (int64_t k = 0; k < n; k++)
+        out[k] = (int16_t)(((int64_t)T0[k] * (65536 - f) + (int64_t)T1[k] * f) >> 16);
+}
+
 /* ------------------------------------------------------------------------ */
 /* O4  per-edge integer costs (Section II-B: slope box filter, edge          */
 /*     coherence = min of endpoints, LUT lookup, mirror, mask, steep rule)   */
