@@ -73,7 +73,13 @@ typedef struct {
  *                 each split into a cell and a 16-bit fraction and clamped to
  *                 the outermost centres; the int64 blend of the four entries
  *                 is shifted right by 32; the reverse arc uses
- *                 (n_alpha-1) 2^16 - t16.                                 */
+ *                 (n_alpha-1) 2^16 - t16.
+ *   looks_frac16  0 (default): the table of the integer number of looks;
+ *                 f in [1, 65535]: the effective number of looks is
+ *                 looks + f / 2^16 (looks <= 63), and the table is the
+ *                 blend of the integer tables of looks and looks + 1
+ *                 (Section II-B reads its table grid, which includes L, by
+ *                 interpolation), see ww_build_cost_lut_q16.             */
 typedef struct {
     int32_t box_half;
     int32_t steep_rule;
@@ -82,6 +88,7 @@ typedef struct {
     int32_t ref_i, ref_j;
     float nodata;
     int32_t lut_interp;
+    int32_t looks_frac16;
 } ww_cost_params;
 
 /* Solver counters (all optional outputs). */
@@ -96,6 +103,11 @@ typedef struct {
     int64_t max_potential;   /* largest node potential at exit              */
     double relax_ms;         /* device time of the relaxation rounds        */
     double solve_ms;         /* wall time of the whole solve                */
+    int64_t settled_nodes;   /* nodes settled, summed over passes, and their */
+    int64_t arcs_scanned;    /* residual out-arcs: the work of a textbook    */
+                             /* search settling the same nodes; counted when */
+                             /* the environment sets WW_MCF_COUNT=1 (which  */
+                             /* slows the solve), else -1                   */
 } ww_mcf_stats;
 
 /* Schedule of the min-cost-flow solve: the shortest-path windows of every
@@ -175,6 +187,18 @@ ww_status ww_residues(const float *psi, const uint8_t *valid, int32_t m, int32_t
  *   lut_host  int16 [n_gamma * n_alpha] out, row = coherence bin.
  * Synchronous.  Errors: WW_E_INVALID_ARG, WW_E_OOM, WW_E_DEVICE. */
 ww_status ww_build_cost_lut(int32_t looks, const ww_lut_params *p, int16_t *lut_host);
+
+/* The table at a non-integer number of looks (Section II-B: the table is
+ * precomputed on a grid over slope, coherence and L and read by
+ * interpolation at run time; the L grid here is the integers).
+ *   looks_q16  effective looks in 2^-16 fixed point, 2 <= looks_q16 / 2^16
+ *              <= 64; with l0 = looks_q16 >> 16 and f = looks_q16 & 0xffff,
+ *              entry [c][b] = floor((T_l0[c][b] (2^16 - f) +
+ *              T_l0+1[c][b] f) / 2^16), the integer tables of
+ *              ww_build_cost_lut (f = 0: T_l0 itself).
+ * Synchronous; the table is cached per device.  Errors as
+ * ww_build_cost_lut. */
+ww_status ww_build_cost_lut_q16(int32_t looks_q16, const ww_lut_params *p, int16_t *lut_host);
 
 /* Per-edge integer costs of Section II-B.  For every edge e = (u -> v):
  *   cx_pos/cy_pos  cost of the arc that raises the edge's cycle difference by
@@ -388,6 +412,10 @@ typedef struct {
     double t_submit, t_start, t_end;  /* seconds on ww_clock()          */
     int64_t footprint_bytes;          /* device bytes reserved for it   */
     char error[160];                  /* message when status != WW_OK  */
+    /* input: the job's own solve schedule (used by the server when
+     * use_sched = 1; 0 = the process-wide schedule) */
+    int32_t use_sched;
+    ww_mcf_params sched;
 } ww_job;
 
 typedef struct ww_server ww_server;
@@ -396,8 +424,13 @@ typedef struct ww_server ww_server;
 double ww_clock(void);
 
 /* Starts `slots` workers (1..64) on the current device with an HBM budget
- * in bytes for the jobs in flight (<= 0: 3/4 of the device memory that is
- * free at creation).  Errors: WW_E_INVALID_ARG, WW_E_DEVICE. */
+ * in bytes (<= 0: 3/4 of the device memory that is free at creation).  A
+ * job is admitted when the device bytes held by all workers, counting for
+ * each the larger of its (grow-only) workspace and its running job's
+ * footprint, stay within the budget; a job's footprint is every device
+ * byte that ww_unwrap's workspace requests for its shape, plus device
+ * copies of host-side inputs and outputs.
+ * Errors: WW_E_INVALID_ARG, WW_E_DEVICE. */
 ww_status ww_server_create(int32_t slots, int64_t hbm_budget_bytes, ww_server **out);
 
 /* Queues a job (stamps t_submit).  Errors: WW_E_INVALID_ARG (NULL job or
@@ -416,11 +449,28 @@ int64_t ww_server_in_flight(ww_server *s);
  * server (finished jobs not yet polled keep their outputs). */
 ww_status ww_server_destroy(ww_server *s);
 
-/* Unwraps njobs jobs on a temporary server with `slots` workers, largest
- * first, and returns when all have finished; per-job results are in the
- * structs.  Returns WW_OK if every job succeeded, else the first failure's
- * status. */
-ww_status ww_unwrap_batch(ww_job *jobs, int32_t njobs, int32_t slots);
+/* Unwraps njobs jobs (a time-series stack of interferograms of any sizes)
+ * as a batch on the current device and returns when all have finished.
+ * Residues, costs and integration run per job; the min-cost-flow solve
+ * runs once for a whole group of jobs: the jobs' loop graphs, each with
+ * its own ground node, form one disjoint graph whose flow problem is the
+ * sum of the jobs' problems (Section II-A eq. 2), and one run of successive
+ * shortest paths (Section II-C) solves it, every relaxation round covering
+ * the frontier tiles of all jobs of the group.  Each job's cost equals
+ * what ww_unwrap computes on it (default cost rules); its K is an optimum's
+ * cycle field, equal to ww_unwrap's wherever the optimum is unique (where
+ * several optima exist the shared passes may pick another one; group = 1
+ * reproduces ww_unwrap byte for byte).  Repeated calls on the same jobs in
+ * the same order give identical bytes.
+ *   group  jobs per solve at most (1..256; 0 = 256); consecutive jobs in
+ *          the given order form a group, which also stays below 2^31 loops
+ *          and 400 Mpixel;
+ *   sched  the solve schedule, NULL = the process-wide one.
+ * A job that cannot be unwrapped gets its status and message; when a group
+ * solve fails, its jobs are solved one by one so that only the failing job
+ * fails.  Returns WW_OK if every job succeeded, else the first failure's
+ * status.  Uses the library workspace of the current device. */
+ww_status ww_unwrap_batch(ww_job *jobs, int32_t njobs, int32_t group, const ww_mcf_params *sched);
 
 #ifdef __cplusplus
 }

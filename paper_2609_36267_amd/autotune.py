@@ -44,13 +44,13 @@ def pad(c):
     return c + DEFAULT_TAIL[len(c) - 2:]
 
 
-def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
+def tune_schedule(jobs, candidates=None, reps: int = 1, batch: bool = False):
     """jobs: list of (psi, coh, valid, looks) device tensors.  Times each
-    candidate on all jobs (sequential plain calls, or ww_unwrap_batch with
-    `slots` workers when slots > 0), keeps the fastest and returns
-    (best candidate, {candidate: seconds}).  A two-field candidate keeps
-    the default stop rule.  Costs must agree across candidates (they are
-    exact); a disagreement raises."""
+    candidate on all jobs (sequential plain calls, or one ww_unwrap_batch
+    solve of all of them when batch is true), keeps the fastest, installs
+    it process-wide and returns (best candidate, {candidate: seconds}).  A
+    two-field candidate keeps the default stop rule.  Costs must agree
+    across candidates (they are exact); a disagreement raises."""
     import torch
     cands = list(candidates or CANDIDATES)
     old = ww.get_mcf_params()
@@ -62,8 +62,8 @@ def tune_schedule(jobs, candidates=None, reps: int = 1, slots: int = 0):
             for _ in range(max(1, reps)):
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                if slots > 0:
-                    res, _ = ww.unwrap_batch(jobs, slots=slots)
+                if batch:
+                    res, _ = ww.unwrap_batch(jobs, sched=pad(c))
                     got = [r[2] for r in res]
                 else:
                     got = [ww.unwrap(*j[:3], j[3])[2] for j in jobs]

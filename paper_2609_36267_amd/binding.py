@@ -49,14 +49,16 @@ class CostParams(C.Structure):
     _fields_ = [("box_half", C.c_int32), ("steep_rule", C.c_int32),
                 ("steep_thresh_rad", C.c_double), ("steep_cap_pct", C.c_int32),
                 ("ref_i", C.c_int32), ("ref_j", C.c_int32), ("nodata", C.c_float),
-                ("lut_interp", C.c_int32)]
+                ("lut_interp", C.c_int32), ("looks_frac16", C.c_int32)]
 
 
 class McfStats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("passes", "windows", "rounds", "tile_visits",
                                          "augmentations", "path_arcs", "supplies",
                                          "max_potential")] + [("relax_ms", C.c_double),
-                                                              ("solve_ms", C.c_double)]
+                                                              ("solve_ms", C.c_double),
+                                                              ("settled_nodes", C.c_int64),
+                                                              ("arcs_scanned", C.c_int64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
@@ -259,11 +261,12 @@ def _declare(L):
     L.ww_default_cost_params.argtypes = [P]
     L.ww_residues.argtypes = [P, P, I32, I32, P, P, P, P]
     L.ww_build_cost_lut.argtypes = [I32, P, P]
+    L.ww_build_cost_lut_q16.argtypes = [I32, P, P]
     L.ww_edge_costs.argtypes = [P, P, P, I32, I32, P, P, P, P, P, P, P, P]
     L.ww_mcf_solve.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P, P, P]
     L.ww_integrate.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
     L.ww_unwrap.argtypes = [P, P, P, I32, I32, I32, P, P, P, P, P]
-    for f in ("ww_residues", "ww_build_cost_lut", "ww_edge_costs", "ww_mcf_solve",
+    for f in ("ww_residues", "ww_build_cost_lut", "ww_build_cost_lut_q16", "ww_edge_costs", "ww_mcf_solve",
               "ww_integrate", "ww_unwrap"):
         getattr(L, f).restype = C.c_int32
     L.ww_clock.restype = C.c_double
@@ -278,7 +281,7 @@ def _declare(L):
     L.ww_server_in_flight.restype = C.c_int64
     L.ww_server_destroy.argtypes = [P]
     L.ww_server_destroy.restype = C.c_int32
-    L.ww_unwrap_batch.argtypes = [P, I32, I32]
+    L.ww_unwrap_batch.argtypes = [P, I32, I32, P]
     L.ww_unwrap_batch.restype = C.c_int32
     L.ww_default_mcf_params.argtypes = [P]
     L.ww_get_mcf_params.argtypes = [P]
@@ -367,6 +370,14 @@ def build_cost_lut(looks, params: LutParams | None = None) -> np.ndarray:
     p = params or default_lut_params()
     out = np.zeros((p.n_gamma, p.n_alpha), np.int16)
     _check(load().ww_build_cost_lut(int(looks), C.byref(p), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def build_cost_lut_q16(looks_q16, params: LutParams | None = None) -> np.ndarray:
+    """The table at looks_q16 / 2^16 looks (ww_build_cost_lut_q16)."""
+    p = params or default_lut_params()
+    out = np.zeros((p.n_gamma, p.n_alpha), np.int16)
+    _check(load().ww_build_cost_lut_q16(int(looks_q16), C.byref(p), out.ctypes.data_as(C.c_void_p)))
     return out
 
 
@@ -462,7 +473,7 @@ class Job(C.Structure):
                 ("K", C.c_void_p), ("phi", C.c_void_p), ("tag", C.c_int64),
                 ("status", C.c_int32), ("total_cost", C.c_int64), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_end", C.c_double), ("footprint_bytes", C.c_int64),
-                ("error", C.c_char * 160)]
+                ("error", C.c_char * 160), ("use_sched", C.c_int32), ("sched", McfParams)]
 
 
 def clock() -> float:
@@ -483,7 +494,7 @@ def _host_ptr(a, dtype):
     return C.c_void_p(a.data_ptr()), a
 
 
-def make_job(psi, coh, valid, looks, K=None, phi=None, tag=0):
+def make_job(psi, coh, valid, looks, K=None, phi=None, tag=0, sched=None):
     """A Job over device tensors (host_io = 0) or host arrays / pinned CPU
     tensors (host_io = 1; the worker copies in and out).  Outputs are
     allocated beside the inputs when not given.  Returns (job, keep) where
@@ -492,6 +503,10 @@ def make_job(psi, coh, valid, looks, K=None, phi=None, tag=0):
     m, n = psi.shape
     j = Job()
     j.m, j.n, j.looks, j.tag = m, n, int(looks), int(tag)
+    if sched is not None:
+        from .autotune import pad
+        j.use_sched = 1
+        j.sched = McfParams(*pad(sched))
     if on_device:
         torch = _torch()
         if K is None:
@@ -526,8 +541,9 @@ class Server:
         _check(load().ww_server_create(int(slots), int(hbm_budget_bytes), C.byref(self._h)))
         self._live = {}
 
-    def submit(self, psi, coh, valid, looks, K=None, phi=None, tag=0) -> Job:
-        j, keep = make_job(psi, coh, valid, looks, K, phi, tag)
+    def submit(self, psi, coh, valid, looks, K=None, phi=None, tag=0, sched=None) -> Job:
+        """sched: this job's own solve schedule (None: the process-wide one)."""
+        j, keep = make_job(psi, coh, valid, looks, K, phi, tag, sched)
         self._live[C.addressof(j)] = (j, keep)
         rc = load().ww_server_submit(self._h, C.byref(j))
         if rc != OK:
@@ -565,17 +581,23 @@ class Server:
         self.close()
 
 
-def unwrap_batch(jobs, slots: int = 4):
-    """jobs: list of (psi, coh, valid, looks) device tensors.  Runs them on a
-    temporary server (ww_unwrap_batch) and returns [(K, phi, total_cost)]
-    in the input order."""
+def unwrap_batch(jobs, group: int = 0, sched=None):
+    """jobs: list of (psi, coh, valid, looks) device tensors.  ww_unwrap_batch:
+    the jobs' min-cost-flow problems solved together, `group` jobs per solve
+    at most (0: up to 256), with the schedule `sched` (a tuple as for
+    set_mcf_params; None: the process-wide one).  Returns
+    ([(K, phi, total_cost)] in the input order, the Job array)."""
     arr = (Job * len(jobs))()
     keep = []
     for k, (psi, coh, valid, looks) in enumerate(jobs):
         j, kp = make_job(psi, coh, valid, looks, tag=k)
         arr[k] = j
         keep.append(kp)
-    rc = load().ww_unwrap_batch(arr, len(jobs), int(slots))
+    sp = None
+    if sched is not None:
+        from .autotune import pad
+        sp = McfParams(*pad(sched))
+    rc = load().ww_unwrap_batch(arr, len(jobs), int(group), C.byref(sp) if sp is not None else None)
     if rc != OK:
         bad = [a for a in arr if a.status != OK]
         raise WWError(rc, bad[0].error.decode() if bad else load().ww_last_error().decode())

@@ -1,5 +1,6 @@
 // C ABI entry points: argument checks, workspace, error reporting.  Every
 // numeric step runs in the HIP kernels of the sibling sources.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -176,6 +177,8 @@ ww_status check_cost_params(const ww_cost_params &p) {
         return fail(WW_E_INVALID_ARG, "steep-rule parameters out of range");
     if (p.lut_interp != 0 && p.lut_interp != 1)
         return fail(WW_E_INVALID_ARG, "lut_interp must be 0 or 1");
+    if (p.looks_frac16 < 0 || p.looks_frac16 > 65535)
+        return fail(WW_E_INVALID_ARG, "looks_frac16 must lie in [0, 65535]");
     return WW_OK;
 }
 
@@ -185,37 +188,46 @@ static ww_status check_shape(int32_t m, int32_t n) {
     return WW_OK;
 }
 
-// Device-resident cost tables, one per (device, looks, parameters).
+// Device-resident cost tables, one per (device, looks in 2^-16 fixed point,
+// parameters).
 struct LutKey {
-    int dev, looks;
+    int dev, looks_q16;
     ww_lut_params p;
     bool operator<(const LutKey &o) const {
         if (dev != o.dev) return dev < o.dev;
-        if (looks != o.looks) return looks < o.looks;
+        if (looks_q16 != o.looks_q16) return looks_q16 < o.looks_q16;
         return memcmp(&p, &o.p, sizeof(p)) < 0;
     }
 };
 
-ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, const int16_t **out) {
-    std::lock_guard<std::mutex> g(lut_lock());
+// lut_lock() held.  A non-integer number of looks blends the cached tables
+// of its two integer neighbours (each built on first use).
+static ww_status lut_device_locked(int looks_q16, const ww_lut_params &p, hipStream_t stream,
+                                   const int16_t **out) {
     static std::map<LutKey, int16_t *> cache;
     LutKey key;
     memset(&key, 0, sizeof(key));
     key.dev = current_device();
-    key.looks = looks;
+    key.looks_q16 = looks_q16;
     key.p = p;
     auto it = cache.find(key);
     if (it != cache.end()) {
         *out = it->second;
         return WW_OK;
     }
+    const int l0 = looks_q16 >> 16, f = looks_q16 & 0xffff;
+    const int16_t *t0 = nullptr, *t1 = nullptr;
+    if (f) {
+        WW_TRY(lut_device_locked(l0 << 16, p, stream, &t0));
+        WW_TRY(lut_device_locked((l0 + 1) << 16, p, stream, &t1));
+    }
     int16_t *d = nullptr;
-    size_t bytes = sizeof(int16_t) * (size_t)p.n_alpha * p.n_gamma;
-    if (hipMalloc(&d, bytes) != hipSuccess) {
+    const size_t n = (size_t)p.n_alpha * p.n_gamma;
+    if (hipMalloc(&d, sizeof(int16_t) * n) != hipSuccess) {
         (void)hipGetLastError();
         return fail(WW_E_OOM, "cost-table allocation failed");
     }
-    ww_status s = build_lut_impl(looks, p, d, stream);
+    ww_status s = f ? blend_lut_looks(t0, t1, (int64_t)n, f, d, stream) : build_lut_impl(l0, p, d, stream);
     // other streams may use the table as soon as it is in the cache
     if (s == WW_OK && hipStreamSynchronize(stream) != hipSuccess)
         s = fail(WW_E_DEVICE, "cost-table build failed: %s", hipGetErrorString(hipGetLastError()));
@@ -228,24 +240,42 @@ ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, cons
     return WW_OK;
 }
 
+ww_status lut_device(int looks_q16, const ww_lut_params &p, hipStream_t stream, const int16_t **out) {
+    std::lock_guard<std::mutex> g(lut_lock());
+    return lut_device_locked(looks_q16, p, stream, out);
+}
+
 ww_status check_unwrap_args(const float *psi, const float *coh, int m, int n, int looks,
                             const int32_t *K, const float *phi, const ww_cost_params &cp) {
     WW_TRY(check_shape(m, n));
     if (looks < 2 || looks > 64) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
     if (!psi || !coh || !K || !phi) return fail(WW_E_INVALID_ARG, "input or output array is NULL");
     WW_TRY(check_cost_params(cp));
+    if (looks == 64 && cp.looks_frac16) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
     if (cp.ref_i >= 0 && (cp.ref_i >= m || cp.ref_j < 0 || cp.ref_j >= n))
         return fail(WW_E_INVALID_ARG, "reference pixel outside the image");
     return WW_OK;
 }
 
+int64_t unwrap_workspace_bytes(int m, int n) {
+    const int64_t N = (int64_t)(m - 1) * (n - 1), nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
+    const int64_t NT = (int64_t)ceil_div(m - 1, 32) * ceil_div(n - 1, 32);
+    int64_t b = 0;
+    b += N + 2 * (2 * nx + 2 * ny) + nx + ny + 64;          // residues, costs, flows, counters
+    b += 12 * (nx + ny) + 512 + 4096;                       // steep-rule keys and state
+    b += (8 + 8 + 4 + 1 + 16 + 4) * N + 2 * (2 * n + 2 * m) + 4096;  // solver node state and lists
+    b += 40 * NT + 8192 + 8 * std::max<int64_t>(3 * ceil_div(N, 4096), 8192) + 4096;  // tiles, parts
+    b += 256 + 4 * (int64_t)m;                              // integration
+    return b + b / 8;                                       // the workspace's growth margin
+}
+
 ww_status unwrap_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
                       int looks, const ww_cost_params &cp, int32_t *K, float *phi,
-                      int64_t *total_out, hipStream_t st) {
+                      int64_t *total_out, hipStream_t st, const ww_mcf_params *sched) {
     ww_lut_params lp;
     ww_default_lut_params(&lp);
     const int16_t *lut = nullptr;
-    WW_TRY(lut_device(looks, lp, st, &lut));
+    WW_TRY(lut_device((looks << 16) | cp.looks_frac16, lp, st, &lut));
     int64_t nl = (int64_t)(m - 1) * (n - 1), nx = (int64_t)m * (n - 1), ny = (int64_t)(m - 1) * n;
     int8_t *res, *dkx, *dky;
     int16_t *cxp, *cxn, *cyp, *cyn;
@@ -262,7 +292,7 @@ ww_status unwrap_impl(const float *psi, const float *coh, const uint8_t *valid, 
     WW_TRY(edge_costs_impl(psi, coh, valid, m, n, lut, lp.n_alpha, lp.n_gamma, cp, cxp, cxn, cyp,
                            cyn, st));
     int64_t total = 0;
-    WW_TRY(mcf_impl(res, m, n, cxp, cxn, cyp, cyn, dkx, dky, nullptr, &total, nullptr, st));
+    WW_TRY(mcf_impl(res, m, n, cxp, cxn, cyp, cyn, dkx, dky, nullptr, &total, nullptr, st, sched));
     WW_TRY(integrate_impl(psi, valid, dkx, dky, m, n, cp, K, phi, st));
     WW_HIP(hipStreamSynchronize(st));
     *total_out = total;
@@ -306,6 +336,7 @@ void ww_default_cost_params(ww_cost_params *p) {
     p->ref_j = -1;
     p->nodata = std::nanf("");
     p->lut_interp = 0;
+    p->looks_frac16 = 0;
 }
 
 ww_status ww_residues(const float *psi, const uint8_t *valid, int32_t m, int32_t n, int8_t *res,
@@ -336,7 +367,24 @@ ww_status ww_build_cost_lut(int32_t looks, const ww_lut_params *pin, int16_t *lu
     if (looks < 2 || looks > 64) return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
     if (!lut_host) return fail(WW_E_INVALID_ARG, "lut_host must be non-NULL");
     const int16_t *d = nullptr;
-    WW_TRY(lut_device(looks, p, nullptr, &d));
+    WW_TRY(lut_device(looks << 16, p, nullptr, &d));
+    WW_HIP(hipMemcpy(lut_host, d, sizeof(int16_t) * (size_t)p.n_alpha * p.n_gamma,
+                     hipMemcpyDeviceToHost));
+    return WW_OK;
+}
+
+ww_status ww_build_cost_lut_q16(int32_t looks_q16, const ww_lut_params *pin, int16_t *lut_host) {
+    std::lock_guard<std::mutex> g(lock());
+    clear_error();
+    ww_lut_params p;
+    if (pin) p = *pin;
+    else ww_default_lut_params(&p);
+    WW_TRY(check_lut_params(p));
+    if (looks_q16 < (2 << 16) || looks_q16 > (64 << 16))
+        return fail(WW_E_INVALID_ARG, "looks must lie in [2, 64]");
+    if (!lut_host) return fail(WW_E_INVALID_ARG, "lut_host must be non-NULL");
+    const int16_t *d = nullptr;
+    WW_TRY(lut_device(looks_q16, p, nullptr, &d));
     WW_HIP(hipMemcpy(lut_host, d, sizeof(int16_t) * (size_t)p.n_alpha * p.n_gamma,
                      hipMemcpyDeviceToHost));
     return WW_OK;

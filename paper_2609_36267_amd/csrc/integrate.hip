@@ -242,20 +242,24 @@ __global__ __launch_bounds__(IT_THREADS) void k_rows(const float *__restrict__ p
     }
 }
 
-ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *dkx,
-                         const int8_t *dky, int m, int n, const ww_cost_params &cp, int32_t *K,
-                         float *phi, hipStream_t stream) {
-    char *buf = nullptr;
-    const size_t k0_off = 256;
-    WW_TRY(scratch(SLOT_INTEG, k0_off + sizeof(int) * (size_t)m, (void **)&buf));
-    IntegState *st = (IntegState *)buf;
-    int *K0 = (int *)(buf + k0_off);
+// Sets the integration state before a call: first_valid = N (none found
+// yet) when a mask is given, else 0; K(ref) = 0.  A kernel rather than a
+// copy from host memory, so that nothing on the host must outlive the call.
+__global__ void k_integ_init(IntegState *st, long long first_valid) {
+    st->first_valid = first_valid;
+    st->kref = 0;
+    st->pad = 0;
+}
+
+// The integration proper, on caller-provided state: st (an IntegState) and
+// K0 (m ints of column-0 prefix sums).
+static ww_status integrate_run(const float *psi, const uint8_t *valid, const int8_t *dkx,
+                               const int8_t *dky, int m, int n, const ww_cost_params &cp,
+                               int32_t *K, float *phi, IntegState *st, int *K0,
+                               hipStream_t stream) {
     const int64_t N = (int64_t)m * n;
-    IntegState init;
-    init.first_valid = valid ? (long long)N : 0;
-    init.kref = 0;
-    init.pad = 0;
-    WW_HIP(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_integ_init, dim3(1), dim3(1), 0, stream, st, valid ? (long long)N : 0ll);
+    WW_LAUNCH_CHECK();
     if (valid && cp.ref_i < 0) {
         hipLaunchKernelGGL(k_first_valid, dim3(1), dim3(1024), 0, stream, valid, N, st);
         WW_LAUNCH_CHECK();
@@ -273,9 +277,18 @@ ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *d
         hipLaunchKernelGGL(k_rows<1>, dim3(m), dim3(IT_THREADS), 0, stream, psi, valid, dkx, m, n,
                            st, K0, cp.nodata, K, phi);
     WW_LAUNCH_CHECK();
-    // the host-side init struct must outlive the async copy
-    WW_HIP(hipStreamSynchronize(stream));
     return WW_OK;
+}
+
+constexpr size_t K0_OFF = 256;  // K0 follows the state, 256-byte aligned
+
+ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *dkx,
+                         const int8_t *dky, int m, int n, const ww_cost_params &cp, int32_t *K,
+                         float *phi, hipStream_t stream) {
+    char *buf = nullptr;
+    WW_TRY(scratch(SLOT_INTEG, K0_OFF + sizeof(int) * (size_t)m, (void **)&buf));
+    return integrate_run(psi, valid, dkx, dky, m, n, cp, K, phi, (IntegState *)buf,
+                         (int *)(buf + K0_OFF), stream);
 }
 
 const long long *integrate_ref_index() {

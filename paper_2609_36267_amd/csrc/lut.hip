@@ -356,4 +356,21 @@ ww_status build_lut_impl(int looks, const ww_lut_params &p, int16_t *lut_dev, hi
     return WW_OK;
 }
 
+// The table at a non-integer number of looks l0 + f / 2^16: the tables of
+// the two neighbouring integers blended entry by entry in 2^-16 fixed point,
+// rounded down (the interpolation over L of Section II-B's table grid).
+__global__ void k_lut_blend_looks(const int16_t *__restrict__ T0, const int16_t *__restrict__ T1,
+                                  int64_t n, int f, int16_t *__restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = (int16_t)(((int64_t)T0[k] * (65536 - f) + (int64_t)T1[k] * f) >> 16);
+}
+
+ww_status blend_lut_looks(const int16_t *T0, const int16_t *T1, int64_t n, int f, int16_t *out,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_lut_blend_looks, dim3(ceil_div(n, 256)), dim3(256), 0, stream, T0, T1, n, f, out);
+    WW_LAUNCH_CHECK();
+    return WW_OK;
+}
+
 }  // namespace ww

@@ -8,6 +8,15 @@
 // moving past +-1 is not allowed.  Potentials pot (int32, guarded) keep every
 // residual arc's reduced cost c - pot(u) + pot(v) >= 0.
 //
+// One solve may hold several images ("jobs") at once: their loop graphs,
+// each with its own ground node, form one disjoint graph, and the flow
+// problem on it is the sum of the jobs' problems.  Successive shortest paths
+// on that union are exact for every job, so the jobs share every pass, every
+// window and every relaxation round (one launch relaxes the listed tiles of
+// all jobs).  Node and tile indices are global: job k owns nodes
+// [noff_k, noff_k + R_k C_k) and tiles [toff_k, toff_k + TR_k TC_k); a tile
+// list entry is (job << 24) | tile-within-job.
+//
 // One pass:
 //  1. Multi-source shortest paths from every node with positive excess over
 //     reduced costs.  Labels are 64-bit (dist:32 | hops:29 | dir:3) and every
@@ -29,7 +38,7 @@
 //     each root keeps its nearest deficit (64-bit atomicMin on dist|node).
 //  3. One unit is augmented along each root's chosen path.  Different trees
 //     are vertex-disjoint, so all paths are applied in parallel.  Trees that
-//     hang off the ground as a supply are split at the ground's arcs and at
+//     hang off a ground as a supply are split at the ground's arcs and at
 //     most its excess of them augment.
 //  4. pot(v) += B - d(v) for every reached node.  Every tree arc is then
 //     tight and reversing it keeps all reduced costs >= 0, so the final flow
@@ -51,26 +60,20 @@ namespace {
 
 constexpr unsigned long long LINF = ~0ull;
 constexpr int RC_INF = 0x7fffffff;
-constexpr int DIR_NONE = 0, DIR_UP = 1, DIR_DOWN = 2, DIR_LEFT = 3, DIR_RIGHT = 4;
+constexpr int DIR_NONE = 0, DIR_UP = 1, DIR_DOWN = 2, DIR_LEFT = 3;
 constexpr int POT_LIMIT = 1 << 30;
 
 enum : int { ERR_NEG_RC = 1, ERR_POT = 2, ERR_WALK = 4, ERR_ITERS = 8 };
 
 struct Ctl {
-    unsigned long long glab;   // ground label
-    long long gex;             // ground excess
-    long long gpot;            // ground potential
     unsigned int count[3][32]; // list lengths (one 128-byte line each)
     unsigned int nsrc, ndef;   // node lists
     unsigned int nsrc2, ndef2; // compaction targets
-    unsigned int gsub_count;   // ground-rooted subtrees with a deficit
-    unsigned int gpred;        // ground predecessor (perimeter arc index)
     unsigned int wsettled[2];  // deficits reached in the window (by window parity)
     unsigned int naug;         // augmentations in this pass
     unsigned long long arcs;   // arcs flipped in this pass
     int error;
     int max_pot;
-    long long total_cost;
     long long sum_res;
     unsigned long long wminrej[2];  // smallest candidate beyond the window (by parity)
     unsigned long long iters;   // in-tile relaxation iterations, all visits
@@ -80,18 +83,48 @@ struct Ctl {
     unsigned long long vt_sweep;  // staging and sweeps of the visits
     unsigned int prev_naug;       // naug and arcs of the previous pass, kept by
     unsigned long long prev_arcs;  // the pass set-up when it clears them
+    unsigned long long settled;   // work counters (counting solves only): nodes
+    unsigned long long scanned;   // settled and their residual out-arcs
 };
+constexpr size_t CTL_BYTES = (sizeof(Ctl) + 63) / 64 * 64;
 
-struct Graph {
+// State of one job's ground node.
+struct GState {
+    unsigned long long glab;   // label
+    long long gex;             // excess
+    long long gpot;            // potential
+    unsigned int gpred;        // predecessor (perimeter arc index)
+    unsigned int gsub_count;   // ground-rooted subtrees with a deficit
+    long long total_cost;      // the job's flow cost at the end of the solve
+    long long pad[3];
+};
+static_assert(sizeof(GState) == 64, "one 64-byte record per ground");
+
+// One job's loop grid inside the solve.
+struct Job {
     int R, C, n;               // loop rows, loop cols, image cols (= C + 1)
-    int th, tw;                // tile shape (rows, cols)
     int TR, TC;                // tile grid
+    unsigned int toff;         // first global tile
+    unsigned int poff;         // first entry of its perimeter tiles
+    unsigned int nptiles;      // perimeter tiles
+    unsigned int aoff;         // first slot of its ground-subtree list (perimeter arcs before it)
+    long long noff;            // first global node
     const int16_t *cxp, *cxn, *cyp, *cyn;
     int8_t *fx, *fy;
+};
+
+// Node state of all jobs, and the jobs.  A single-job solve reads its job
+// from the kernel argument j0; a multi-job solve reads jobs[k].
+struct Graph {
     unsigned long long *lab;
     int *pot;
     int8_t *ex;
     unsigned long long *best;
+    GState *gs;
+    const Job *jobs;
+    int njobs;
+    long long N;               // nodes of all jobs
+    Job j0;
 };
 
 __device__ __forceinline__ unsigned int ldist(unsigned long long l) { return (unsigned int)(l >> 32); }
@@ -106,29 +139,70 @@ __device__ __forceinline__ int move_cost(int f, int delta, int cp, int cn) {
     return RC_INF;
 }
 
-// Append tile t to the list of round r unless it is already there
-// (act[t] == r).  Lists: lists[(r % 3) * NT ...], lengths ctl->count[r % 3].
+template <bool MULTI>
+__device__ __forceinline__ Job job_at(const Graph &g, int k) {
+    return MULTI ? g.jobs[k] : g.j0;
+}
+
+// The job holding global node v, tile t, or ground-subtree slot q: the last
+// job whose offset is at most the index (binary search; one job: 0).
+__device__ __forceinline__ int job_of_node(const Graph &g, long long v) {
+    int lo = 0, hi = g.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.jobs[mid].noff <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int job_of_tile(const Graph &g, unsigned int t) {
+    int lo = 0, hi = g.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.jobs[mid].toff <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int job_of_slot(const Graph &g, unsigned int q) {
+    int lo = 0, hi = g.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.jobs[mid].aoff <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Append a tile to the list of round r unless it is already there
+// (act[gt] == r).  gt: global tile; entry: its list entry.
+// Lists: lists[(r % 3) * NT ...], lengths ctl->count[r % 3].
 __device__ __forceinline__ void activate(unsigned int *act, unsigned int *lists, unsigned int NT,
-                                         Ctl *ctl, unsigned int t, unsigned int r) {
-    if (atomicExch(&act[t], r) != r) {
+                                         Ctl *ctl, unsigned int gt, unsigned int entry,
+                                         unsigned int r) {
+    if (atomicExch(&act[gt], r) != r) {
         const unsigned int pos = atomicAdd(&ctl->count[r % 3][0], 1u);
-        lists[(size_t)(r % 3) * NT + pos] = t;
+        lists[(size_t)(r % 3) * NT + pos] = entry;
     }
 }
 
-// perimeter arc a -> (node row, node col, edge kind, edge index, delta of
-// the move node -> ground)
-__device__ __forceinline__ void ground_arc(const Graph &g, unsigned int a, int &i, int &j,
-                                           int &kind, long long &e, int &delta) {
-    const int C = g.C, R = g.R;
+__device__ __forceinline__ unsigned int entry_of(int job, unsigned int lt) {
+    return ((unsigned int)job << 24) | lt;
+}
+
+// perimeter arc a of job J -> (node row, node col, edge kind, edge index,
+// delta of the move node -> ground)
+__device__ __forceinline__ void ground_arc(const Job &J, unsigned int a, int &i, int &j, int &kind,
+                                           long long &e, int &delta) {
+    const int C = J.C, R = J.R;
     if (a < (unsigned)C) {  // top: up across hx(0, j)
         i = 0; j = a; kind = 0; e = j; delta = -1;
     } else if (a < 2u * C) {  // bottom: down across hx(R, j)
         i = R - 1; j = a - C; kind = 0; e = (long long)R * C + j; delta = +1;
     } else if (a < 2u * C + R) {  // left: left across vy(i, 0)
-        i = a - 2 * C; j = 0; kind = 1; e = (long long)i * g.n; delta = +1;
+        i = a - 2 * C; j = 0; kind = 1; e = (long long)i * J.n; delta = +1;
     } else {  // right: right across vy(i, C)
-        i = a - 2 * C - R; j = C - 1; kind = 1; e = (long long)i * g.n + C; delta = -1;
+        i = a - 2 * C - R; j = C - 1; kind = 1; e = (long long)i * J.n + C; delta = -1;
     }
 }
 
@@ -139,7 +213,8 @@ __device__ __forceinline__ void ground_arc(const Graph &g, unsigned int a, int &
 // Set-up in three launches with no contended atomics: every block of
 // INIT_CHUNK nodes initialises its state and counts its supplies / demands;
 // one block scans the counts; every block then writes its supplies and
-// demands in node order.
+// demands in node order.  The residues of all jobs are one array in global
+// node order.
 constexpr int INIT_THREADS = 256;
 constexpr int INIT_PER = 16;
 constexpr int INIT_CHUNK = INIT_THREADS * INIT_PER;
@@ -175,7 +250,7 @@ __device__ __forceinline__ int block_scan_int(int v, int *red, int *total) {
     return before + inc - v;
 }
 
-// The residues of loop nodes v0 .. v0 + INIT_PER - 1 (zero beyond N): one
+// The residues of nodes v0 .. v0 + INIT_PER - 1 (zero beyond N): one
 // 16-byte load where the plane is 16-byte aligned and the group is whole.
 static_assert(INIT_PER == 16, "residue groups are 16-byte loads");
 __device__ __forceinline__ bool load_res16(const int8_t *res, long long v0, long long N, int8_t r[16]) {
@@ -199,7 +274,7 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
                                                                 int *__restrict__ bc,
                                                                 unsigned int *__restrict__ flip) {
     __shared__ int red[INIT_THREADS / 64];
-    const long long N = (long long)g.R * g.C;
+    const long long N = g.N;
     const long long c0 = (long long)blockIdx.x * INIT_CHUNK;
     const long long v0 = c0 + (long long)threadIdx.x * INIT_PER;
     int8_t r[INIT_PER];
@@ -214,7 +289,8 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
         w[q >> 2] |= (unsigned int)(uint8_t)r[q] << (8 * (q & 3));
         // best (a root's chosen deficit) is only kept at roots: supplies,
         // which are residues in one frame or the other, and perimeter nodes
-        // (ground-rooted subtrees); other nodes' entries are never read
+        // (ground-rooted subtrees, set by k_init_ground); other nodes'
+        // entries are never read
         if (r[q] != 0) g.best[v0 + q] = LINF;
     }
     if (whole) {
@@ -244,13 +320,6 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
             g.lab[v] = LINF;
         }
     }
-    for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < 2u * g.C + 2u * g.R;
-         a += gridDim.x * blockDim.x) {
-        int i, j, kind, delta;
-        long long e;
-        ground_arc(g, a, i, j, kind, e, delta);
-        g.best[(long long)i * g.C + j] = LINF;
-    }
     np = block_sum_int(np, red);
     nn = block_sum_int(nn, red);
     sum = block_sum_int(sum, red);
@@ -261,9 +330,40 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
     }
 }
 
+// Ground state of every job (blockIdx.y = job): best entries of its
+// perimeter nodes; with several jobs also its charge, minus the sum of its
+// residues (a single job's comes from the set-up scan).
+__global__ __launch_bounds__(256) void k_init_ground(Graph g, const int8_t *__restrict__ res) {
+    __shared__ int red[4];
+    const int k = blockIdx.y;
+    const Job J = g.njobs > 1 ? g.jobs[k] : g.j0;
+    for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < 2u * J.C + 2u * J.R;
+         a += gridDim.x * blockDim.x) {
+        int i, j, kind, delta;
+        long long e;
+        ground_arc(J, a, i, j, kind, e, delta);
+        g.best[J.noff + (long long)i * J.C + j] = LINF;
+    }
+    if (g.njobs > 1) {
+        const long long Nk = (long long)J.R * J.C;
+        int s = 0;
+        for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < Nk;
+             v += (long long)gridDim.x * blockDim.x)
+            s += res[J.noff + v];
+        s = block_sum_int(s, red);
+        if (threadIdx.x == 0 && s != 0)
+            atomicAdd((unsigned long long *)&g.gs[k].gex, (unsigned long long)(-(long long)s));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.gs[k].glab = LINF;
+        g.gs[k].gpred = 0xffffffffu;
+    }
+}
+
 // one block: exclusive scans of the per-block counts, totals into ctl; each
 // thread sums a run of consecutive blocks, one block scan joins the runs
-__global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict__ bc, Ctl *ctl) {
+__global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict__ bc, Ctl *ctl,
+                                                       GState *gs, int njobs) {
     __shared__ int red[16];
     const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
     const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
@@ -291,9 +391,7 @@ __global__ __launch_bounds__(1024) void k_mcf_init_scan(int nb, int *__restrict_
         ctl->nsrc = tp;
         ctl->ndef = tq;
         ctl->sum_res = ts;
-        ctl->gex = -(long long)ts;
-        ctl->gpot = 0;
-        ctl->glab = LINF;
+        if (njobs == 1) gs[0].gex = -(long long)ts;
         ctl->wminrej[0] = ctl->wminrej[1] = LINF;
     }
 }
@@ -307,7 +405,7 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const 
     // node order (a thread's counts are at most INIT_PER and a block's at
     // most INIT_CHUNK < 2^16, so the two halves never carry into each other)
     __shared__ int red[INIT_THREADS / 64];
-    const long long N = (long long)g.R * g.C;
+    const long long N = g.N;
     const long long v0 = (long long)blockIdx.x * INIT_CHUNK + (long long)threadIdx.x * INIT_PER;
     int8_t r[INIT_PER];
     load_res16(res, v0, N, r);
@@ -325,40 +423,52 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const 
 }
 
 // Pass start: sources get label 0 and their tiles are activated for round rr.
-// The ground is a source while it holds surplus; that is read here rather
+// A ground is a source while it holds surplus; that is read here rather
 // than passed in, so that a pass can be queued before the host has seen how
 // the previous one ended.
+template <bool MULTI>
 __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned int *act,
                             unsigned int *lists, unsigned int NT, unsigned int rr,
                             const unsigned int *perim_tiles, int nperim) {
     const unsigned int ns = ctl->nsrc;
-    const int ground_source = ctl->gex > 0;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += gridDim.x * blockDim.x) {
         const unsigned int v = src[k];
         g.lab[v] = 0ull;
-        const int i = v / g.C, j = v % g.C;
-        const int ti = i / g.th, tj = j / g.tw, li = i % g.th, lj = j % g.tw;
-        const unsigned int t = ti * g.TC + tj;
-        activate(act, lists, NT, ctl, t, rr);
+        const int job = MULTI ? job_of_node(g, v) : 0;
+        const Job J = job_at<MULTI>(g, job);
+        const unsigned int lv = (unsigned int)(v - J.noff);
+        const int i = lv / J.C, j = lv % J.C;
+        const int ti = i / 32, tj = j / 32, li = i % 32, lj = j % 32;
+        const unsigned int lt = ti * J.TC + tj;
+        activate(act, lists, NT, ctl, J.toff + lt, entry_of(job, lt), rr);
         // a supply on a tile border also feeds the tile across that border,
         // whose relaxation must run although this label never "changes"
-        if (li == 0 && ti > 0) activate(act, lists, NT, ctl, t - g.TC, rr);
-        if (li == g.th - 1 && ti < g.TR - 1) activate(act, lists, NT, ctl, t + g.TC, rr);
-        if (lj == 0 && tj > 0) activate(act, lists, NT, ctl, t - 1, rr);
-        if (lj == g.tw - 1 && tj < g.TC - 1) activate(act, lists, NT, ctl, t + 1, rr);
+        if (li == 0 && ti > 0) activate(act, lists, NT, ctl, J.toff + lt - J.TC, entry_of(job, lt - J.TC), rr);
+        if (li == 31 && ti < J.TR - 1)
+            activate(act, lists, NT, ctl, J.toff + lt + J.TC, entry_of(job, lt + J.TC), rr);
+        if (lj == 0 && tj > 0) activate(act, lists, NT, ctl, J.toff + lt - 1, entry_of(job, lt - 1), rr);
+        if (lj == 31 && tj < J.TC - 1)
+            activate(act, lists, NT, ctl, J.toff + lt + 1, entry_of(job, lt + 1), rr);
     }
-    if (ground_source) {
-        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x)
-            activate(act, lists, NT, ctl, perim_tiles[k], rr);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x) {
+        const unsigned int e = perim_tiles[k];
+        const int job = (int)(e >> 24);
+        if (g.gs[job].gex > 0) {
+            const unsigned int toff = MULTI ? g.jobs[job].toff : g.j0.toff;
+            activate(act, lists, NT, ctl, toff + (e & 0xffffffu), e, rr);
+        }
+    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.njobs; k += gridDim.x * blockDim.x) {
+        GState &G = g.gs[k];
+        G.glab = G.gex > 0 ? 0ull : LINF;
+        G.gpred = 0xffffffffu;
+        G.gsub_count = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->glab = ground_source ? 0ull : LINF;
         // per-pass counters back to zero (none of them is read by this kernel)
         ctl->prev_naug = ctl->naug;
         ctl->prev_arcs = ctl->arcs;
         ctl->naug = 0;
-        ctl->gsub_count = 0;
-        ctl->gpred = 0xffffffffu;
         ctl->arcs = 0;
         ctl->nsrc2 = 0;
         ctl->ndef2 = 0;
@@ -374,7 +484,7 @@ struct RoundArgs {
     unsigned int *tstamp;       // pass stamp: the tile was relaxed
     unsigned long long *tile_rej;  // smallest parked candidate of each tile
     unsigned long long *vpart;  // striped visit counters (64 x 16)
-    const unsigned int *perim_tiles;
+    const unsigned int *perim_tiles;  // list entries of every job's perimeter tiles
     int nperim;
     unsigned int NT;
 };
@@ -424,6 +534,7 @@ __device__ __forceinline__ void rej_one(unsigned long long &rej, unsigned long l
 #endif
 constexpr int VISIT_ITERS = WW_VISIT_ITERS;  // sweeps per tile visit at most
 
+template <bool MULTI>
 __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
                                                    unsigned int round, unsigned int pass_stamp,
                                                    unsigned long long lb, int stats) {
@@ -440,16 +551,24 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
     const unsigned int *list = ra.lists + (size_t)(round % 3) * NT;
     // list (round + 2) % 3 was consumed by the previous round
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->count[(round + 2) % 3][0] = 0;
-    const unsigned long long glab = ctl->glab;
-    const int gpot = (int)ctl->gpot;
-    const int R = g.R, C = g.C;
+    // one job: its ground's label and potential once per launch
+    const unsigned long long glab0 = MULTI ? 0ull : g.gs[0].glab;
+    const int gpot0 = MULTI ? 0 : (int)g.gs[0].gpot;
     unsigned int my_visits = 0;
 
     for (unsigned int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
-        const unsigned int tile = list[idx];
+        const unsigned int entry = list[idx];
+        const int job = MULTI ? (int)(entry >> 24) : 0;
+        const unsigned int lt = entry & 0xffffffu;
+        const Job J = job_at<MULTI>(g, job);
+        const unsigned int tile = J.toff + lt;  // global tile
+        const unsigned long long glab = MULTI ? g.gs[job].glab : glab0;
+        const int gpot = MULTI ? (int)g.gs[job].gpot : gpot0;
+        const int R = J.R, C = J.C;
+        const long long noff = J.noff;
         ++my_visits;
         const unsigned long long t_start = stats ? wall_clock64() : 0ull;
-        const int ti = tile / g.TC, tj = tile % g.TC;
+        const int ti = lt / J.TC, tj = lt % J.TC;
         const int i0 = ti * TJ, j0 = tj * TJ;
         const int rows = min(TJ, R - i0), cols = min(TJ, C - j0);
         if (threadIdx.x < 4) flags[threadIdx.x] = 0;
@@ -475,7 +594,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 pv[s] = 0;
                 if (t < (TJ + 2) * (TJ + 2) && r <= rows + 1 && c <= cols + 1) {
                     if (i >= 0 && i < R && j >= 0 && j < C) {
-                        const long long v = (long long)i * C + j;
+                        const long long v = noff + (long long)i * C + j;
                         lv[s] = g.lab[v];
                         pv[s] = g.pot[v];
                     } else {
@@ -495,13 +614,13 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                     const int i = i0 + li, j = j0 + lj;
                     long long e;
                     e = (long long)i * C + j;  // hx(i,j): from above, +1
-                    cst[s][0] = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
+                    cst[s][0] = move_cost(J.fx[e], +1, J.cxp[e], J.cxn[e]);
                     e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
-                    cst[s][1] = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
-                    e = (long long)i * g.n + j;  // vy(i,j): from the left, -1
-                    cst[s][2] = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
-                    e = (long long)i * g.n + j + 1;  // vy(i,j+1): from the right, +1
-                    cst[s][3] = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
+                    cst[s][1] = move_cost(J.fx[e], -1, J.cxp[e], J.cxn[e]);
+                    e = (long long)i * J.n + j;  // vy(i,j): from the left, -1
+                    cst[s][2] = move_cost(J.fy[e], -1, J.cyp[e], J.cyn[e]);
+                    e = (long long)i * J.n + j + 1;  // vy(i,j+1): from the right, +1
+                    cst[s][3] = move_cost(J.fy[e], +1, J.cyp[e], J.cyn[e]);
                 }
             }
 #pragma unroll
@@ -629,7 +748,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             if (li >= rows || lj >= cols) continue;
             const unsigned long long l = L[li + 1][lj + 1];
             if (l != init[k]) {
-                g.lab[(long long)(i0 + li) * C + (j0 + lj)] = l;
+                g.lab[noff + (long long)(i0 + li) * C + (j0 + lj)] = l;
                 if (li == 0) flags[0] = 1;
                 if (li == rows - 1) flags[1] = 1;
                 if (lj == 0) flags[2] = 1;
@@ -652,19 +771,19 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 if (side == 0) {
                     if (i != 0) continue;
                     e = j;
-                    c = move_cost(g.fx[e], -1, g.cxp[e], g.cxn[e]);
+                    c = move_cost(J.fx[e], -1, J.cxp[e], J.cxn[e]);
                 } else if (side == 1) {
                     if (i != R - 1) continue;
                     e = (long long)R * C + j;
-                    c = move_cost(g.fx[e], +1, g.cxp[e], g.cxn[e]);
+                    c = move_cost(J.fx[e], +1, J.cxp[e], J.cxn[e]);
                 } else if (side == 2) {
                     if (j != 0) continue;
-                    e = (long long)i * g.n;
-                    c = move_cost(g.fy[e], +1, g.cyp[e], g.cyn[e]);
+                    e = (long long)i * J.n;
+                    c = move_cost(J.fy[e], +1, J.cyp[e], J.cyn[e]);
                 } else {
                     if (j != C - 1) continue;
-                    e = (long long)i * g.n + C;
-                    c = move_cost(g.fy[e], -1, g.cyp[e], g.cyn[e]);
+                    e = (long long)i * J.n + C;
+                    c = move_cost(J.fy[e], -1, J.cyp[e], J.cyn[e]);
                 }
                 if (c == RC_INF) continue;
                 int rc = c - pv + gpot;
@@ -693,12 +812,12 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             const unsigned int nr = round + 1;
             unsigned int nb = 0;
             bool want = false;
-            if (lane == 0) { want = flags[0] && ti > 0; nb = tile - g.TC; }
-            if (lane == 1) { want = flags[1] && ti < g.TR - 1; nb = tile + g.TC; }
-            if (lane == 2) { want = flags[2] && tj > 0; nb = tile - 1; }
-            if (lane == 3) { want = flags[3] && tj < g.TC - 1; nb = tile + 1; }
-            if (lane == 7) { want = unconverged; nb = tile; }
-            const bool fresh = want && atomicExch(&ra.act[nb], nr) != nr;
+            if (lane == 0) { want = flags[0] && ti > 0; nb = lt - J.TC; }
+            if (lane == 1) { want = flags[1] && ti < J.TR - 1; nb = lt + J.TC; }
+            if (lane == 2) { want = flags[2] && tj > 0; nb = lt - 1; }
+            if (lane == 3) { want = flags[3] && tj < J.TC - 1; nb = lt + 1; }
+            if (lane == 7) { want = unconverged; nb = lt; }
+            const bool fresh = want && atomicExch(&ra.act[J.toff + nb], nr) != nr;
             const unsigned long long fm = __ballot(fresh);
             if (fm) {
                 const int leader = __ffsll((long long)fm) - 1;
@@ -707,7 +826,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 pos = __shfl(pos, leader, 64);
                 if (fresh) {
                     const unsigned int rank = (unsigned int)__popcll(fm & ((1ull << lane) - 1ull));
-                    ra.lists[(size_t)(nr % 3) * NT + pos + rank] = nb;
+                    ra.lists[(size_t)(nr % 3) * NT + pos + rank] = entry_of(job, nb);
                 }
             }
             if (lane == 4) {
@@ -718,8 +837,9 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             }
             if (lane == 5) {
                 int any = 0;
-                if (sh_gcand != LINF && sh_gcand < ctl->glab) {
-                    unsigned long long old = atomicMin(&ctl->glab, sh_gcand);
+                unsigned long long *gl = &g.gs[job].glab;
+                if (sh_gcand != LINF && sh_gcand < *gl) {
+                    unsigned long long old = atomicMin(gl, sh_gcand);
                     if (sh_gcand < old) any = 1;
                 }
                 sh_any = any;
@@ -734,8 +854,10 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         }
         __syncthreads();
         if (sh_any) {
-            for (int k = threadIdx.x; k < ra.nperim; k += 256)
-                activate(ra.act, ra.lists, NT, ctl, ra.perim_tiles[k], round + 1);
+            for (unsigned int k = threadIdx.x; k < J.nptiles; k += 256) {
+                const unsigned int e = ra.perim_tiles[J.poff + k];
+                activate(ra.act, ra.lists, NT, ctl, J.toff + (e & 0xffffffu), e, round + 1);
+            }
         }
         __syncthreads();
     }
@@ -743,12 +865,17 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         atomicAdd(&ra.vpart[(blockIdx.x % 64) * 16], (unsigned long long)my_visits);
 }
 
-__global__ void k_requeue_pending(Ctl *ctl, const unsigned int *pstamp, unsigned int pass,
+template <bool MULTI>
+__global__ void k_requeue_pending(Graph g, Ctl *ctl, const unsigned int *pstamp, unsigned int pass,
                                   const unsigned long long *tile_rej, unsigned long long lb,
                                   unsigned int *act, unsigned int *lists, unsigned int NT,
                                   unsigned int rr) {
     for (unsigned int t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x)
-        if (pstamp[t] == pass && tile_rej[t] <= lb) activate(act, lists, NT, ctl, t, rr);
+        if (pstamp[t] == pass && tile_rej[t] <= lb) {
+            const int job = MULTI ? job_of_tile(g, t) : 0;
+            const unsigned int toff = MULTI ? g.jobs[job].toff : 0u;
+            activate(act, lists, NT, ctl, t, entry_of(job, t - toff), rr);
+        }
 }
 
 // End of a window, in one launch: the deficits settled in it (a settled
@@ -771,6 +898,11 @@ __global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigne
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += gridDim.x * blockDim.x) {
         const unsigned long long l = g.lab[def[k]];
         if (l <= lb) ++c;
+    }
+    // settled grounds with a deficit absorb all of it
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.njobs; k += gridDim.x * blockDim.x) {
+        const long long gx = g.gs[k].gex;
+        if (gx < 0 && g.gs[k].glab <= lb) c += (unsigned int)(-gx);
     }
     unsigned long long mn = LINF;
     for (unsigned int t = blockIdx.x * blockDim.x + threadIdx.x; t < NT; t += gridDim.x * blockDim.x)
@@ -798,81 +930,81 @@ __global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigne
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wc[k];
         if (t) atomicAdd(&ctl->wsettled[w], t);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const unsigned long long gl = ctl->glab;
-        if (ctl->gex < 0 && gl <= lb) atomicAdd(&ctl->wsettled[w], (unsigned int)(-ctl->gex));
-    }
 }
 
 // ---------------------------------------------------------- augmentation ---
 
-// The ground's predecessor: the smallest perimeter arc index whose label
-// candidate equals the ground label.
-__global__ void k_ground_pred(Graph g, Ctl *ctl, unsigned long long lb) {
-    const unsigned long long gl = ctl->glab;
-    if (gl > lb || ctl->gex > 0) return;
-    const unsigned int na = 2u * g.C + 2u * g.R;
-    const int gpot = (int)ctl->gpot;
+// A ground's predecessor (blockIdx.y = job): the smallest perimeter arc
+// index whose label candidate equals the ground label.
+__global__ void k_ground_pred(Graph g, unsigned long long lb) {
+    const int k = blockIdx.y;
+    GState &G = g.gs[k];
+    const unsigned long long gl = G.glab;
+    if (gl > lb || G.gex > 0) return;
+    const Job J = g.njobs > 1 ? g.jobs[k] : g.j0;
+    const unsigned int na = 2u * J.C + 2u * J.R;
+    const int gpot = (int)G.gpot;
     for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < na; a += gridDim.x * blockDim.x) {
         int i, j, kind, delta;
         long long e;
-        ground_arc(g, a, i, j, kind, e, delta);
-        const long long v = (long long)i * g.C + j;
+        ground_arc(J, a, i, j, kind, e, delta);
+        const long long v = J.noff + (long long)i * J.C + j;
         const unsigned long long l = g.lab[v];
         if (l == LINF) continue;
-        const int c = kind == 0 ? move_cost(g.fx[e], delta, g.cxp[e], g.cxn[e])
-                                : move_cost(g.fy[e], delta, g.cyp[e], g.cyn[e]);
+        const int c = kind == 0 ? move_cost(J.fx[e], delta, J.cxp[e], J.cxn[e])
+                                : move_cost(J.fy[e], delta, J.cyp[e], J.cyn[e]);
         if (c == RC_INF) continue;
         const long long rc = (long long)c - g.pot[v] + gpot;
         const unsigned long long nd = (unsigned long long)ldist(l) + (unsigned long long)max(rc, 0ll);
         const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
-        if (cand == gl) atomicMin(&ctl->gpred, a);
+        if (cand == gl) atomicMin(&G.gpred, a);
     }
 }
 
-// row and column of loop node v (v < 2^29, so 32-bit arithmetic suffices:
-// the walks below take one step per memory round trip, and a 64-bit
-// division would add to every step)
-__device__ __forceinline__ void node_rc(const Graph &g, long long v, int &i, int &j) {
-    const unsigned int u = (unsigned int)v, C = (unsigned int)g.C;
+// row and column of global node v of job J (v - noff < 2^29, so 32-bit
+// arithmetic suffices: the walks below take one step per memory round trip,
+// and a 64-bit division would add to every step)
+__device__ __forceinline__ void node_rc(const Job &J, long long v, int &i, int &j) {
+    const unsigned int u = (unsigned int)(v - J.noff), C = (unsigned int)J.C;
     const unsigned int q = u / C;
     i = (int)q;
     j = (int)(u - q * C);
 }
 
-// predecessor of loop node v (i,j) along direction dir; -1 = ground
-__device__ __forceinline__ long long pred_node(const Graph &g, int i, int j, int dir) {
+// predecessor of node (i,j) of job J along direction dir; -1 = its ground
+__device__ __forceinline__ long long pred_node(const Job &J, int i, int j, int dir) {
     switch (dir) {
-        case DIR_UP: return i > 0 ? (long long)(i - 1) * g.C + j : -1;
-        case DIR_DOWN: return i < g.R - 1 ? (long long)(i + 1) * g.C + j : -1;
-        case DIR_LEFT: return j > 0 ? (long long)i * g.C + j - 1 : -1;
-        default: return j < g.C - 1 ? (long long)i * g.C + j + 1 : -1;
+        case DIR_UP: return i > 0 ? J.noff + (long long)(i - 1) * J.C + j : -1;
+        case DIR_DOWN: return i < J.R - 1 ? J.noff + (long long)(i + 1) * J.C + j : -1;
+        case DIR_LEFT: return j > 0 ? J.noff + (long long)i * J.C + j - 1 : -1;
+        default: return j < J.C - 1 ? J.noff + (long long)i * J.C + j + 1 : -1;
     }
 }
 
-// Walk from v to its root.  Returns the root node; *gsub = 1 when the root
-// is a child of the ground acting as a supply.
-__device__ long long walk_root(const Graph &g, Ctl *ctl, long long v, int gsrc, int *gsub) {
+// Walk from v to its root within job J.  Returns the root node; *gsub = 1
+// when the root is a child of the job's ground acting as a supply.
+__device__ long long walk_root(const Graph &g, const Job &J, const GState &G, Ctl *ctl, long long v,
+                               int gsrc, int *gsub) {
     *gsub = 0;
-    const long long N = (long long)g.R * g.C;
-    for (long long steps = 0; steps <= N + 2; ++steps) {
+    const long long Nk = (long long)J.R * J.C;
+    for (long long steps = 0; steps <= Nk + 2; ++steps) {
         const unsigned long long l = g.lab[v];
         const int dir = (int)(l & 7);
         if (dir == DIR_NONE) return v;
         int i, j;
-        node_rc(g, v, i, j);
-        long long u = pred_node(g, i, j, dir);
+        node_rc(J, v, i, j);
+        long long u = pred_node(J, i, j, dir);
         if (u < 0) {
             if (gsrc) {
                 *gsub = 1;
                 return v;
             }
-            const unsigned int a = ctl->gpred;
-            if (a >= 2u * g.C + 2u * g.R) break;  // no ground predecessor: report below
+            const unsigned int a = G.gpred;
+            if (a >= 2u * J.C + 2u * J.R) break;  // no ground predecessor: report below
             int pi, pj, kind, delta;
             long long e;
-            ground_arc(g, a, pi, pj, kind, e, delta);
-            u = (long long)pi * g.C + pj;
+            ground_arc(J, a, pi, pj, kind, e, delta);
+            u = J.noff + (long long)pi * J.C + pj;
         }
         v = u;
     }
@@ -880,80 +1012,89 @@ __device__ long long walk_root(const Graph &g, Ctl *ctl, long long v, int gsrc, 
     return -1;
 }
 
+template <bool MULTI>
 __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb,
                         unsigned int *gsub_list) {
     const unsigned int nd = ctl->ndef;
-    const int gsrc = ctl->gex > 0;
-    const long long N = (long long)g.R * g.C;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k <= nd; k += gridDim.x * blockDim.x) {
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd + (unsigned)g.njobs;
+         k += gridDim.x * blockDim.x) {
         long long start;
         unsigned long long key;
+        int job;
         if (k < nd) {
             const unsigned int t = def[k];
             const unsigned long long l = g.lab[t];
             if (l > lb) continue;
             start = t;
             key = ((unsigned long long)ldist(l) << 32) | t;
+            job = MULTI ? job_of_node(g, t) : 0;
         } else {
-            // the ground as a demand: its path enters through gpred
-            const unsigned long long gl = ctl->glab;
-            if (!(ctl->gex < 0 && gl <= lb)) continue;
-            if (ctl->gpred >= 2u * g.C + 2u * g.R) {
+            // a ground as a demand: its path enters through gpred
+            job = (int)(k - nd);
+            const GState &G = g.gs[job];
+            const unsigned long long gl = G.glab;
+            if (!(G.gex < 0 && gl <= lb)) continue;
+            const Job J = job_at<MULTI>(g, job);
+            if (G.gpred >= 2u * J.C + 2u * J.R) {
                 atomicOr(&ctl->error, ERR_WALK);
                 continue;
             }
             int pi, pj, kind, delta;
             long long e;
-            ground_arc(g, ctl->gpred, pi, pj, kind, e, delta);
-            start = (long long)pi * g.C + pj;
-            key = ((unsigned long long)ldist(gl) << 32) | (unsigned long long)N;
+            ground_arc(J, G.gpred, pi, pj, kind, e, delta);
+            start = J.noff + (long long)pi * J.C + pj;
+            key = ((unsigned long long)ldist(gl) << 32) | (unsigned long long)(g.N + job);
         }
+        const Job J = job_at<MULTI>(g, job);
+        GState &G = g.gs[job];
         int gsub = 0;
-        const long long root = walk_root(g, ctl, start, gsrc, &gsub);
+        const long long root = walk_root(g, J, G, ctl, start, G.gex > 0, &gsub);
         if (root < 0) continue;
         const unsigned long long old = atomicMin(&g.best[root], key);
-        if (gsub && old == LINF) gsub_list[atomicAdd(&ctl->gsub_count, 1u)] = (unsigned int)root;
+        if (gsub && old == LINF) gsub_list[J.aoff + atomicAdd(&G.gsub_count, 1u)] = (unsigned int)root;
     }
 }
 
-// Keep at most gex ground-rooted subtrees: those with the smallest
-// (best key, root id).  O(k^2), k <= perimeter length.
-__global__ void k_gsub_select(Graph g, Ctl *ctl, const unsigned int *gsub_list,
-                              unsigned char *drop) {
-    const unsigned int k = ctl->gsub_count;
-    const long long allow = ctl->gex;
+// Keep at most gex of a ground's subtrees (blockIdx.y = job): those with
+// the smallest (best key, root id).  O(k^2), k <= the job's perimeter.
+__global__ void k_gsub_select(Graph g, const unsigned int *gsub_list, unsigned char *drop) {
+    const int job = blockIdx.y;
+    const Job J = g.njobs > 1 ? g.jobs[job] : g.j0;
+    const unsigned int k = g.gs[job].gsub_count;
+    const long long allow = g.gs[job].gex;
+    const unsigned int *list = gsub_list + J.aoff;
     for (unsigned int a = blockIdx.x * blockDim.x + threadIdx.x; a < k; a += gridDim.x * blockDim.x) {
-        drop[a] = 0;
+        drop[J.aoff + a] = 0;
         if ((long long)k <= allow) continue;
-        const unsigned int ra = gsub_list[a];
+        const unsigned int ra = list[a];
         const unsigned long long ka = g.best[ra];
         long long rank = 0;
         for (unsigned int b = 0; b < k; ++b) {
-            const unsigned int rb = gsub_list[b];
+            const unsigned int rb = list[b];
             const unsigned long long kb = g.best[rb];
             if (kb < ka || (kb == ka && rb < ra)) ++rank;
         }
-        if (rank >= allow) drop[a] = 1;
+        if (rank >= allow) drop[J.aoff + a] = 1;
     }
 }
 
-__device__ __forceinline__ void flip_into(Graph &g, long long v, int dir) {
+__device__ __forceinline__ void flip_into(const Job &J, long long v, int dir) {
     int i, j;
-    node_rc(g, v, i, j);
+    node_rc(J, v, i, j);
     switch (dir) {
-        case DIR_UP: g.fx[(long long)i * g.C + j] += 1; break;
-        case DIR_DOWN: g.fx[(long long)(i + 1) * g.C + j] -= 1; break;
-        case DIR_LEFT: g.fy[(long long)i * g.n + j] -= 1; break;
-        default: g.fy[(long long)i * g.n + j + 1] += 1; break;
+        case DIR_UP: J.fx[(long long)i * J.C + j] += 1; break;
+        case DIR_DOWN: J.fx[(long long)(i + 1) * J.C + j] -= 1; break;
+        case DIR_LEFT: J.fy[(long long)i * J.n + j] -= 1; break;
+        default: J.fy[(long long)i * J.n + j + 1] += 1; break;
     }
 }
 
-__device__ __forceinline__ void flip_ground_arc(Graph &g, unsigned int a) {
+__device__ __forceinline__ void flip_ground_arc(const Job &J, unsigned int a) {
     int i, j, kind, delta;
     long long e;
-    ground_arc(g, a, i, j, kind, e, delta);
-    if (kind == 0) g.fx[e] += (int8_t)delta;
-    else g.fy[e] += (int8_t)delta;
+    ground_arc(J, a, i, j, kind, e, delta);
+    if (kind == 0) J.fx[e] += (int8_t)delta;
+    else J.fy[e] += (int8_t)delta;
 }
 
 // Apply one unit along root r's chosen path: from the deficit back to r.
@@ -963,20 +1104,36 @@ __device__ __forceinline__ void flip_ground_arc(Graph &g, unsigned int a) {
 // settled, so their tiles were relaxed), applies the flip.  A step of the
 // walk is then one dependent label load and one store.  Paths from
 // different roots are vertex-disjoint, so a node holds one arc per pass;
-// no kernel reads the flows between the two.
+// no kernel reads the flows between the two.  Work items: the supplies,
+// then every job's ground-subtree slots (nslots in all).
+template <bool MULTI>
 __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *gsub_list,
-                          const unsigned char *drop, unsigned int *flip, unsigned int pass) {
-    const unsigned int ns = ctl->nsrc, ng = ctl->gsub_count;
-    const long long N = (long long)g.R * g.C;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns + ng;
+                          const unsigned char *drop, unsigned int *flip, unsigned int pass,
+                          unsigned int nslots) {
+    const unsigned int ns = ctl->nsrc;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < ns + nslots;
          k += gridDim.x * blockDim.x) {
         const bool is_g = k >= ns;
-        const unsigned int r = is_g ? gsub_list[k - ns] : src[k];
+        int job;
+        unsigned int r;
+        if (is_g) {
+            const unsigned int qs = k - ns;
+            job = MULTI ? job_of_slot(g, qs) : 0;
+            const unsigned int aoff = MULTI ? g.jobs[job].aoff : 0u;
+            if (qs - aoff >= g.gs[job].gsub_count) continue;
+            r = gsub_list[qs];
+        } else {
+            r = src[k];
+            job = MULTI ? job_of_node(g, r) : 0;
+        }
         const unsigned long long b = g.best[r];
         if (b == LINF) continue;
         g.best[r] = LINF;
         if (is_g && drop[k - ns]) continue;
+        const Job J = job_at<MULTI>(g, job);
+        GState &G = g.gs[job];
         const long long t = (long long)(b & 0xffffffffull);
+        const bool into_ground = t >= g.N;
         long long v;
         unsigned long long flips = 0;
         // A path through the ground needs the ground's predecessor arc, which
@@ -984,51 +1141,52 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
         // cross it (labels grow along paths).  Its absence is checked where
         // the arc is used: the walk stops with ERR_WALK, which fails the
         // solve, before any index is formed from it.
-        const unsigned int na = 2u * g.C + 2u * g.R;
-        if (t == N) {  // into the ground through its predecessor arc
-            const unsigned int a = ctl->gpred;
+        const unsigned int na = 2u * J.C + 2u * J.R;
+        if (into_ground) {  // into the ground through its predecessor arc
+            const unsigned int a = G.gpred;
             if (a >= na) {
                 atomicOr(&ctl->error, ERR_WALK);
                 continue;
             }
-            flip_ground_arc(g, a);
+            flip_ground_arc(J, a);
             int pi, pj, kind, delta;
             long long e;
-            ground_arc(g, a, pi, pj, kind, e, delta);
-            v = (long long)pi * g.C + pj;
+            ground_arc(J, a, pi, pj, kind, e, delta);
+            v = J.noff + (long long)pi * J.C + pj;
             ++flips;
         } else {
             v = t;
         }
+        const long long Nk = (long long)J.R * J.C;
         unsigned long long l = g.lab[v];
-        for (long long steps = 0; steps <= N + 2; ++steps) {
+        for (long long steps = 0; steps <= Nk + 2; ++steps) {
             const int dir = (int)(l & 7);
             if (dir == DIR_NONE) break;  // reached the supply r
             int i, j;
-            node_rc(g, v, i, j);
-            long long u = pred_node(g, i, j, dir);
+            node_rc(J, v, i, j);
+            long long u = pred_node(J, i, j, dir);
             flip[v] = (pass << 3) | (unsigned int)dir;
             ++flips;
             if (u < 0) {
                 if (is_g) break;  // the ground is the supply
-                const unsigned int a = ctl->gpred;
+                const unsigned int a = G.gpred;
                 if (a >= na) {
                     atomicOr(&ctl->error, ERR_WALK);
                     break;
                 }
-                flip_ground_arc(g, a);
+                flip_ground_arc(J, a);
                 ++flips;
                 int pi, pj, kind, delta;
                 long long e;
-                ground_arc(g, a, pi, pj, kind, e, delta);
-                u = (long long)pi * g.C + pj;
+                ground_arc(J, a, pi, pj, kind, e, delta);
+                u = J.noff + (long long)pi * J.C + pj;
             }
             l = g.lab[u];
             v = u;
         }
-        if (is_g) atomicAdd((unsigned long long *)&ctl->gex, (unsigned long long)-1ll);
+        if (is_g) atomicAdd((unsigned long long *)&G.gex, (unsigned long long)-1ll);
         else g.ex[r] -= 1;
-        if (t == N) atomicAdd((unsigned long long *)&ctl->gex, 1ull);
+        if (into_ground) atomicAdd((unsigned long long *)&G.gex, 1ull);
         else g.ex[t] += 1;
         atomicAdd(&ctl->naug, 1u);
         atomicAdd(&ctl->arcs, flips);
@@ -1040,16 +1198,21 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 // only the tiles relaxed in this pass, so that a pass that reached a few
 // tiles costs little more than one read of the stamps.  The relaxed tiles
 // of a pass lie close together, so chunks are kept small: a workgroup
-// updates at most POT_CHUNK tiles one after another.
+// updates at most POT_CHUNK tiles one after another.  A counting solve also
+// adds up the settled nodes and their residual out-arcs (the work of a
+// textbook search that settles the same nodes).
 constexpr int POT_CHUNK = 8;
 
+template <bool MULTI>
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
                                                     unsigned int pass, unsigned int NT,
-                                                    unsigned long long lb, const unsigned int *flip) {
+                                                    unsigned long long lb, const unsigned int *flip,
+                                                    int count) {
     __shared__ unsigned int todo[POT_CHUNK];
     __shared__ int ntodo;
     const unsigned int bound = ldist(lb);
     int mx = 0;
+    unsigned long long n_set = 0, n_arc = 0;
     for (unsigned int base = blockIdx.x * POT_CHUNK; base < NT; base += gridDim.x * POT_CHUNK) {
         if (threadIdx.x == 0) ntodo = 0;
         __syncthreads();
@@ -1061,7 +1224,10 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
         const int nt = ntodo;
         for (int k = 0; k < nt; ++k) {
             const unsigned int tile = todo[k];
-            const int i0 = (int)(tile / g.TC) * TJ, j0 = (int)(tile % g.TC) * TJ;
+            const int job = MULTI ? job_of_tile(g, tile) : 0;
+            const Job J = job_at<MULTI>(g, job);
+            const unsigned int lt = tile - J.toff;
+            const int i0 = (int)(lt / J.TC) * TJ, j0 = (int)(lt % J.TC) * TJ;
             long long v[TJ * TJ / 256];
             unsigned long long l[TJ * TJ / 256];
             unsigned int fr[TJ * TJ / 256];
@@ -1069,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
             for (int s = 0; s < TJ * TJ / 256; ++s) {
                 const int t = threadIdx.x + 256 * s;
                 const int i = i0 + t / TJ, j = j0 + t % TJ;
-                v[s] = (i < g.R && j < g.C) ? (long long)i * g.C + j : -1;
+                v[s] = (i < J.R && j < J.C) ? J.noff + (long long)i * J.C + j : -1;
                 l[s] = v[s] >= 0 ? g.lab[v[s]] : LINF;
                 fr[s] = v[s] >= 0 ? flip[v[s]] : 0u;
             }
@@ -1077,9 +1243,23 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
             for (int s = 0; s < TJ * TJ / 256; ++s) {
                 if (l[s] == LINF) continue;
                 // the arc into this node on a path augmented in this pass
-                if ((fr[s] >> 3) == pass) flip_into(g, v[s], (int)(fr[s] & 7u));
+                if ((fr[s] >> 3) == pass) flip_into(J, v[s], (int)(fr[s] & 7u));
                 g.lab[v[s]] = LINF;
                 if (l[s] > lb) continue;
+                if (count) {
+                    int i, j;
+                    node_rc(J, v[s], i, j);
+                    long long e;
+                    ++n_set;
+                    e = (long long)i * J.C + j;  // up across hx(i,j): -1
+                    n_arc += move_cost(J.fx[e], -1, J.cxp[e], J.cxn[e]) != RC_INF;
+                    e = (long long)(i + 1) * J.C + j;  // down across hx(i+1,j): +1
+                    n_arc += move_cost(J.fx[e], +1, J.cxp[e], J.cxn[e]) != RC_INF;
+                    e = (long long)i * J.n + j;  // left across vy(i,j): +1
+                    n_arc += move_cost(J.fy[e], +1, J.cyp[e], J.cyn[e]) != RC_INF;
+                    e = (long long)i * J.n + j + 1;  // right across vy(i,j+1): -1
+                    n_arc += move_cost(J.fy[e], -1, J.cyp[e], J.cyn[e]) != RC_INF;
+                }
                 const unsigned int d = ldist(l[s]);
                 const long long np = (long long)g.pot[v[s]] + (bound - d);
                 if (np > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
@@ -1094,18 +1274,31 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
     // atomics on one address from every wave cost more than the updates
     if ((threadIdx.x & 63) == 0 && mx > 0 && mx > *(volatile int *)&ctl->max_pot)
         atomicMax(&ctl->max_pot, mx);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const unsigned long long gl = ctl->glab;
-        if (gl <= lb) {
-            ctl->gpot += bound - ldist(gl);
-            if (ctl->gpot > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
+    if (count) {
+        for (int off = 32; off > 0; off >>= 1) {
+            n_set += __shfl_down(n_set, off, 64);
+            n_arc += __shfl_down(n_arc, off, 64);
         }
-        ctl->glab = LINF;
+        if ((threadIdx.x & 63) == 0 && n_set) {
+            atomicAdd(&ctl->settled, n_set);
+            atomicAdd(&ctl->scanned, n_arc);
+        }
+    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.njobs; k += gridDim.x * blockDim.x) {
+        GState &G = g.gs[k];
+        const unsigned long long gl = G.glab;
+        if (gl <= lb) {
+            G.gpot += bound - ldist(gl);
+            if (G.gpot > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
+            if (count) atomicAdd(&ctl->settled, 1ull);
+        }
+        G.glab = LINF;
     }
 }
 
 // Debug check (WW_MCF_CHECK=1): every residual arc must have a non-negative
-// reduced cost after a pass.  Records the first offending arc.
+// reduced cost after a pass (blockIdx.y = job).  Records the first
+// offending arc.
 struct CheckRec {
     int found;
     int kind;          // in-arc direction at v (1..4) or 8+side for an arc into the ground
@@ -1116,26 +1309,28 @@ struct CheckRec {
     int f, cp, cn;
 };
 
-__global__ void k_check_rc(Graph g, const Ctl *ctl, const unsigned long long *lab_before,
-                           CheckRec *rec) {
-    const long long N = (long long)g.R * g.C;
-    const long long gpot = ctl->gpot;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N;
-         v += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(v / g.C), j = (int)(v % g.C);
+__global__ void k_check_rc(Graph g, const unsigned long long *lab_before, CheckRec *rec) {
+    const int job = blockIdx.y;
+    const Job J = g.njobs > 1 ? g.jobs[job] : g.j0;
+    const long long Nk = (long long)J.R * J.C;
+    const long long gpot = g.gs[job].gpot;
+    for (long long lv = (long long)blockIdx.x * blockDim.x + threadIdx.x; lv < Nk;
+         lv += (long long)gridDim.x * blockDim.x) {
+        const long long v = J.noff + lv;
+        const int i = (int)(lv / J.C), j = (int)(lv % J.C);
         for (int dir = 1; dir <= 4; ++dir) {
             long long e;
             int kind, delta;
-            if (dir == DIR_UP) { e = (long long)i * g.C + j; kind = 0; delta = +1; }
-            else if (dir == DIR_DOWN) { e = (long long)(i + 1) * g.C + j; kind = 0; delta = -1; }
-            else if (dir == DIR_LEFT) { e = (long long)i * g.n + j; kind = 1; delta = -1; }
-            else { e = (long long)i * g.n + j + 1; kind = 1; delta = +1; }
-            const int f = kind == 0 ? g.fx[e] : g.fy[e];
-            const int cp = kind == 0 ? g.cxp[e] : g.cyp[e];
-            const int cn = kind == 0 ? g.cxn[e] : g.cyn[e];
+            if (dir == DIR_UP) { e = (long long)i * J.C + j; kind = 0; delta = +1; }
+            else if (dir == DIR_DOWN) { e = (long long)(i + 1) * J.C + j; kind = 0; delta = -1; }
+            else if (dir == DIR_LEFT) { e = (long long)i * J.n + j; kind = 1; delta = -1; }
+            else { e = (long long)i * J.n + j + 1; kind = 1; delta = +1; }
+            const int f = kind == 0 ? J.fx[e] : J.fy[e];
+            const int cp = kind == 0 ? J.cxp[e] : J.cyp[e];
+            const int cn = kind == 0 ? J.cxn[e] : J.cyn[e];
             const int c = move_cost(f, delta, cp, cn);
             if (c == RC_INF) continue;
-            const long long u = pred_node(g, i, j, dir);
+            const long long u = pred_node(J, i, j, dir);
             const long long pu = u < 0 ? gpot : g.pot[u];
             const long long rc = (long long)c - pu + g.pot[v];
             if (rc < 0 && atomicCAS(&rec->found, 0, 1) == 0) {
@@ -1158,19 +1353,27 @@ __global__ void k_check_rc(Graph g, const Ctl *ctl, const unsigned long long *la
 
 // Debug check (WW_MCF_CHECK=1) of the tile-list protocol after a batch of
 // rounds: the list of the next round rr holds count <= NT entries, every
-// entry is a tile index below NT whose round stamp is rr, and exactly count
+// entry names a tile below NT whose round stamp is rr, and exactly count
 // tiles carry that stamp (so no tile is listed twice).  bad[0]: an entry out
 // of range; bad[1]: an entry without the stamp; bad[2]: tiles with the stamp.
-__global__ void k_check_lists(const Ctl *ctl, const unsigned int *act, const unsigned int *lists,
-                              unsigned int NT, unsigned int rr, unsigned int *bad) {
+template <bool MULTI>
+__global__ void k_check_lists(Graph g, const Ctl *ctl, const unsigned int *act,
+                              const unsigned int *lists, unsigned int NT, unsigned int rr,
+                              unsigned int *bad) {
     const unsigned int cnt = ctl->count[rr % 3][0];
     const unsigned int *list = lists + (size_t)(rr % 3) * NT;
     const unsigned int lim = cnt < NT ? cnt : NT;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < NT; k += gridDim.x * blockDim.x) {
         if (k < lim) {
-            const unsigned int t = list[k];
-            if (t >= NT) atomicOr(&bad[0], 1u);
-            else if (act[t] != rr) atomicOr(&bad[1], 1u);
+            const unsigned int e = list[k];
+            const unsigned int job = e >> 24, lt = e & 0xffffffu;
+            if ((int)job >= g.njobs) {
+                atomicOr(&bad[0], 1u);
+            } else {
+                const Job J = job_at<MULTI>(g, (int)job);
+                if (lt >= (unsigned)(J.TR * J.TC) || J.toff + lt >= NT) atomicOr(&bad[0], 1u);
+                else if (act[J.toff + lt] != rr) atomicOr(&bad[1], 1u);
+            }
         }
         if (act[k] == rr) atomicAdd(&bad[2], 1u);
     }
@@ -1245,19 +1448,24 @@ __device__ __forceinline__ void negate_span(T *a, long long n, long long tid, lo
 // with potentials negated its reduced costs equal the original ones, so a
 // forward search in the reversed frame is a search towards the demands in
 // the original one.  Applying the map twice restores the original state.
-__global__ void k_reverse_frame(Graph g, Ctl *ctl, long long nx, long long ny, long long N) {
+// The flow planes of all jobs are two contiguous arrays (fx: nx entries,
+// fy: ny).
+__global__ void k_reverse_frame(Graph g, Ctl *ctl, int8_t *fx, long long nx, int8_t *fy,
+                                long long ny) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    negate_span(g.fx, nx, tid, stride);
-    negate_span(g.fy, ny, tid, stride);
-    negate_span(g.ex, N, tid, stride);
-    negate_span(g.pot, N, tid, stride);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    negate_span(fx, nx, tid, stride);
+    negate_span(fy, ny, tid, stride);
+    negate_span(g.ex, g.N, tid, stride);
+    negate_span(g.pot, g.N, tid, stride);
+    for (long long k = tid; k < g.njobs; k += stride) {
+        g.gs[k].gex = -g.gs[k].gex;
+        g.gs[k].gpot = -g.gs[k].gpot;
+    }
+    if (tid == 0) {
         const unsigned int ns = ctl->nsrc;
         ctl->nsrc = ctl->ndef;
         ctl->ndef = ns;
-        ctl->gex = -ctl->gex;
-        ctl->gpot = -ctl->gpot;
     }
 }
 
@@ -1291,48 +1499,66 @@ __device__ __forceinline__ long long cost_span(const int8_t *f, const int16_t *c
     return s;
 }
 
-__global__ __launch_bounds__(256) void k_total_cost(const int8_t *fx, const int8_t *fy,
-                                                   const int16_t *cxp, const int16_t *cxn,
-                                                   const int16_t *cyp, const int16_t *cyn,
-                                                   long long nx, long long ny,
-                                                   long long *__restrict__ part) {
+// Each job's flow cost (blockIdx.y = job), one atomic per workgroup into
+// its ground record (zeroed at set-up).
+__global__ __launch_bounds__(256) void k_total_cost(Graph g) {
+    const int job = blockIdx.y;
+    const Job J = g.njobs > 1 ? g.jobs[job] : g.j0;
+    const long long nx = (long long)(J.R + 1) * J.C, ny = (long long)J.R * J.n;
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    long long s = cost_span(fx, cxp, cxn, nx, tid, stride) + cost_span(fy, cyp, cyn, ny, tid, stride);
+    long long s = cost_span(J.fx, J.cxp, J.cxn, nx, tid, stride) +
+                  cost_span(J.fy, J.cyp, J.cyn, ny, tid, stride);
     __shared__ long long red[4];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        const long long t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd((unsigned long long *)&g.gs[job].total_cost, (unsigned long long)t);
+    }
 }
 
-__global__ void k_total_finish(int nb, const long long *part, Ctl *ctl) {
-    __shared__ long long red[4];
-    long long s = 0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) ctl->total_cost = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ void k_export_pot(const int *pot, const Ctl *ctl, long long N, int64_t *out) {
+__global__ void k_export_pot(const int *pot, const GState *gs, long long N, int64_t *out) {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v <= N;
          v += (long long)gridDim.x * blockDim.x)
-        out[v] = v < N ? (int64_t)pot[v] : (int64_t)ctl->gpot;
+        out[v] = v < N ? (int64_t)pot[v] : (int64_t)gs[0].gpot;
 }
 
 // ------------------------------------------------------------------ host ---
 
 constexpr unsigned int HMAX = 0x1fffffffu;
 
-// window schedule (ww_set_mcf_params), read once per solve
+// process-wide window schedule (ww_set_mcf_params), read once per solve by
+// the calls that take no schedule of their own
 std::atomic<int> g_first_hops{64};
 std::atomic<int> g_first_dstep{256};
 std::atomic<int> g_full_passes{0};
 std::atomic<int> g_first_deficit{0};
 std::atomic<int> g_reverse_below{0};
 std::atomic<int> g_hop_growth{2};
+
+ww_mcf_params process_mcf_params() {
+    ww_mcf_params p;
+    p.first_hop_window = g_first_hops.load();
+    p.first_distance_step = g_first_dstep.load();
+    p.full_passes = g_full_passes.load();
+    p.first_deficit_after = g_first_deficit.load();
+    p.reverse_below = g_reverse_below.load();
+    p.hop_growth = g_hop_growth.load();
+    return p;
+}
+
+ww_status check_mcf_params(const ww_mcf_params &p) {
+    if (p.first_hop_window < 1 || p.first_hop_window > (int32_t)HMAX - 1 || p.first_distance_step < 1 ||
+        p.first_distance_step > (1 << 30))
+        return fail(WW_E_INVALID_ARG, "window schedule out of range");
+    if (p.full_passes < 0 || p.full_passes > (1 << 20) ||
+        (p.first_deficit_after != 0 && p.first_deficit_after != 1) || p.reverse_below < 0 ||
+        p.hop_growth < 2 || p.hop_growth > (1 << 20))
+        return fail(WW_E_INVALID_ARG, "pass schedule out of range");
+    return WW_OK;
+}
 
 static unsigned long long mk_label(unsigned int d, unsigned int h) {
     return ((unsigned long long)d << 32) | ((unsigned long long)h << 3) | 7ull;
@@ -1346,37 +1572,61 @@ static ww_status decode_error(int e) {
     return fail(WW_E_DEVICE, "min-cost flow: error flags 0x%x", e);
 }
 
-ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const int16_t *cxn,
-                   const int16_t *cyp, const int16_t *cyn, int8_t *dkx, int8_t *dky,
-                   int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t st) {
-    const long long nx = (long long)m * (n - 1), ny = (long long)(m - 1) * n;
-    if (nx > 0) WW_HIP(hipMemsetAsync(dkx, 0, nx, st));
-    if (ny > 0) WW_HIP(hipMemsetAsync(dky, 0, ny, st));
+// The solve of one job (mj.size() == 1, MULTI = false) or of several at
+// once.  The jobs' residues, x-flow planes and y-flow planes each lie in one
+// contiguous array, job after job (res_all, fx_all, fy_all, flows zeroed by
+// the caller); each job's total goes to *mj[k].total.
+template <bool MULTI>
+static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int8_t *fx_all,
+                       int8_t *fy_all, int64_t *pot_out, ww_mcf_stats *stats,
+                       const ww_mcf_params &sp, hipStream_t st) {
     ww_mcf_stats S;
     memset(&S, 0, sizeof(S));
     last_mcf_stats() = S;
     const auto t_start = std::chrono::steady_clock::now();
-    const int R = m - 1, C = n - 1;
-    if (R < 1 || C < 1) {
-        if (pot_out) WW_HIP(hipMemsetAsync(pot_out, 0, sizeof(int64_t), st));
-        WW_HIP(hipStreamSynchronize(st));
-        *total = 0;
-        if (stats) *stats = S;
-        return WW_OK;
-    }
+    const int nj = (int)mj.size();
     hipEvent_t ev[2];
     WW_TRY(workspace_events(&ev[0], &ev[1]));
-    const long long N = (long long)R * C;
-    if (N >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
+    // job layout: nodes, tiles, perimeter tiles and ground-subtree slots
+    std::vector<Job> jobs(nj);
+    std::vector<unsigned int> ptiles;
+    long long N = 0, nx_all = 0, ny_all = 0;
+    unsigned int NT = 0, nslots = 0;
+    int max_arcs = 0;
+    for (int k = 0; k < nj; ++k) {
+        const McfJob &q = mj[k];
+        Job &J = jobs[k];
+        J.R = q.m - 1;
+        J.C = q.n - 1;
+        J.n = q.n;
+        J.TR = ceil_div(J.R, TJ);
+        J.TC = ceil_div(J.C, TJ);
+        J.noff = N;
+        J.toff = NT;
+        J.aoff = nslots;
+        J.cxp = q.cxp; J.cxn = q.cxn; J.cyp = q.cyp; J.cyn = q.cyn;
+        J.fx = fx_all + nx_all;
+        J.fy = fy_all + ny_all;
+        if (q.dkx != J.fx || q.dky != J.fy || q.res != res_all + N)
+            return fail(WW_E_INVALID_ARG, "min-cost flow: job %d planes are not contiguous", k);
+        J.poff = (unsigned int)ptiles.size();
+        for (int ti = 0; ti < J.TR; ++ti)
+            for (int tj = 0; tj < J.TC; ++tj)
+                if (ti == 0 || tj == 0 || ti == J.TR - 1 || tj == J.TC - 1)
+                    ptiles.push_back(((unsigned int)k << 24) | (unsigned)(ti * J.TC + tj));
+        J.nptiles = (unsigned int)ptiles.size() - J.poff;
+        N += (long long)J.R * J.C;
+        NT += (unsigned int)(J.TR * J.TC);
+        nslots += 2u * J.C + 2u * J.R;
+        max_arcs = std::max(max_arcs, 2 * J.C + 2 * J.R);
+        nx_all += (long long)q.m * (q.n - 1);
+        ny_all += (long long)(q.m - 1) * q.n;
+    }
+    if (N >= (1ll << 31) - 512) return fail(WW_E_INVALID_ARG, "more than 2^31 loops in one solve");
     Graph g;
-    g.R = R; g.C = C; g.n = n;
-    g.th = TJ;
-    g.tw = TJ;
-    g.TR = ceil_div(R, g.th); g.TC = ceil_div(C, g.tw);
-    g.cxp = cxp; g.cxn = cxn; g.cyp = cyp; g.cyn = cyn;
-    g.fx = dkx; g.fy = dky;
-    const unsigned int NT = (unsigned)g.TR * g.TC;
-    const int nperim_arcs = 2 * C + 2 * R;
+    g.N = N;
+    g.njobs = nj;
+    g.j0 = jobs[0];
     WW_TRY(scratch(SLOT_MCF_LAB, sizeof(unsigned long long) * N, (void **)&g.lab));
     WW_TRY(scratch(SLOT_MCF_BEST, sizeof(unsigned long long) * N, (void **)&g.best));
     WW_TRY(scratch(SLOT_MCF_POT, sizeof(int) * N, (void **)&g.pot));
@@ -1398,53 +1648,84 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     ra.vpart = (unsigned long long *)(tiles + tiles_words + 2 * (size_t)NT);
     char *nodes = nullptr;
     const size_t nl_bytes = sizeof(unsigned int) * (size_t)N;
-    const size_t gs_bytes = sizeof(unsigned int) * (size_t)nperim_arcs + 256;
-    WW_TRY(scratch(SLOT_MCF_NODES, 4 * nl_bytes + gs_bytes + nperim_arcs + 1024, (void **)&nodes));
+    const size_t gs_bytes = sizeof(unsigned int) * (size_t)nslots + 256;
+    WW_TRY(scratch(SLOT_MCF_NODES, 4 * nl_bytes + gs_bytes + nslots + 1024, (void **)&nodes));
     unsigned int *src = (unsigned int *)nodes, *def = src + N, *src2 = def + N, *def2 = src2 + N;
     unsigned int *gsub_list = def2 + N;
     unsigned char *drop = (unsigned char *)(nodes + 4 * nl_bytes + gs_bytes);
-    Ctl *ctl = nullptr;
-    WW_TRY(scratch(SLOT_MCF_LISTS, sizeof(Ctl), (void **)&ctl));
-    Ctl *h = nullptr;
-    WW_TRY(host_scratch(sizeof(Ctl), (void **)&h));
-
-    std::vector<unsigned int> ptiles;
-    for (int ti = 0; ti < g.TR; ++ti)
-        for (int tj = 0; tj < g.TC; ++tj)
-            if (ti == 0 || tj == 0 || ti == g.TR - 1 || tj == g.TC - 1)
-                ptiles.push_back((unsigned)(ti * g.TC + tj));
-    ra.nperim = (int)ptiles.size();
+    // counters, ground records and (several jobs) the two frames' job tables
+    const size_t jobs_bytes = MULTI ? (sizeof(Job) * (size_t)nj + 255) / 256 * 256 : 0;
+    const size_t cg_bytes = CTL_BYTES + sizeof(GState) * (size_t)nj;
+    const size_t cg_round = (cg_bytes + 255) / 256 * 256;
+    char *cg = nullptr;
+    WW_TRY(scratch(SLOT_MCF_LISTS, cg_round + 2 * jobs_bytes, (void **)&cg));
+    Ctl *ctl = (Ctl *)cg;
+    g.gs = (GState *)(cg + CTL_BYTES);
+    Job *jobs_dev[2] = {nullptr, nullptr};
+    char *hc = nullptr;
+    WW_TRY(host_scratch(cg_round + 2 * jobs_bytes, (void **)&hc));
+    Ctl *h = (Ctl *)hc;
+    GState *hg = (GState *)(hc + CTL_BYTES);
+    g.jobs = nullptr;
+    if (MULTI) {
+        // the job tables of both frames, uploaded once (a frame reversal
+        // exchanges each job's two cost planes)
+        jobs_dev[0] = (Job *)(cg + cg_round);
+        jobs_dev[1] = (Job *)(cg + cg_round + jobs_bytes);
+        Job *hj0 = (Job *)(hc + cg_round), *hj1 = (Job *)(hc + cg_round + jobs_bytes);
+        for (int k = 0; k < nj; ++k) {
+            hj0[k] = jobs[k];
+            hj1[k] = jobs[k];
+            std::swap(hj1[k].cxp, hj1[k].cxn);
+            std::swap(hj1[k].cyp, hj1[k].cyn);
+        }
+        WW_HIP(hipMemcpyAsync(jobs_dev[0], hc + cg_round, 2 * jobs_bytes, hipMemcpyHostToDevice, st));
+        g.jobs = jobs_dev[0];
+    }
     WW_HIP(hipMemcpyAsync((void *)ra.perim_tiles, ptiles.data(), sizeof(unsigned int) * ptiles.size(),
                           hipMemcpyHostToDevice, st));
+    ra.nperim = (int)ptiles.size();
     // stamps start at zero on every call: rounds and passes count from 1
     WW_HIP(hipMemsetAsync(ra.act, 0, sizeof(unsigned int) * 3 * (size_t)NT, st));
     WW_HIP(hipMemsetAsync(ra.vpart, 0, 8192, st));
-    WW_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+    WW_HIP(hipMemsetAsync(ctl, 0, cg_bytes, st));
     const int IB = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(N, 256)));
     const int nib = ceil_div(N, INIT_CHUNK);
     int *bc = nullptr;
     WW_TRY(scratch(SLOT_MCF_PART, sizeof(long long) * (size_t)std::max(3 * nib, 8192) + 256, (void **)&bc));
     unsigned int *flip = nullptr;  // deferred path flips: (pass, direction) per node
     WW_TRY(scratch(SLOT_MCF_FLIP, sizeof(unsigned int) * (size_t)N, (void **)&flip));
-    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res, bc, flip);
+    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc, flip);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mcf_init_scan, dim3(1), dim3(1024), 0, st, nib, bc, ctl);
+    const int gx = MULTI ? (int)std::min<long long>(64, std::max<long long>(1, ceil_div(N / nj, 4096)))
+                         : std::max(1, ceil_div(max_arcs, 256));
+    hipLaunchKernelGGL(k_init_ground, dim3(gx, nj), dim3(256), 0, st, g, res_all);
     WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mcf_init_write, dim3(nib), dim3(INIT_THREADS), 0, st, g, res, bc, src, def);
+    hipLaunchKernelGGL(k_mcf_init_scan, dim3(1), dim3(1024), 0, st, nib, bc, ctl, g.gs, nj);
+    WW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mcf_init_write, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc, src, def);
     WW_LAUNCH_CHECK();
     auto sync_ctl = [&]() -> ww_status {
-        WW_HIP(hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        WW_HIP(hipMemcpyAsync(h, ctl, cg_bytes, hipMemcpyDeviceToHost, st));
         WW_TRY(wait_stream(st));
         if (h->error) return decode_error(h->error);
         return WW_OK;
     };
+    // units still to route: supplies plus the grounds' surplus
+    auto ground_surplus = [&]() {
+        long long s = 0;
+        for (int k = 0; k < nj; ++k) s += std::max<long long>(hg[k].gex, 0);
+        return s;
+    };
     WW_TRY(sync_ctl());
-    S.supplies = (long long)h->nsrc + std::max<long long>(h->gex, 0);
+    S.supplies = (long long)h->nsrc + ground_surplus();
 
     const char *trace_env = getenv("WW_MCF_TRACE");
     const bool trace = trace_env && (trace_env[0] == '1' || trace_env[0] == '2');
     const char *check_env = getenv("WW_MCF_CHECK");
     const bool check = check_env && check_env[0] == '1';
+    const char *count_env = getenv("WW_MCF_COUNT");
+    const int count = (count_env && count_env[0] == '1') ? 1 : 0;
     // debug-check buffers, released on every way out of the solve (the
     // release waits for the device, so queued kernels never outlive them)
     struct CheckBufs {
@@ -1459,12 +1740,10 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             if (hrec) (void)hipHostFree(hrec);
         }
     } cb;
-    unsigned long long *&lab_copy = cb.lab;
-    CheckRec *&crec = cb.rec, *&hcrec = cb.hrec;
     if (check) {
-        WW_HIP(hipMalloc(&lab_copy, sizeof(unsigned long long) * N));
-        WW_HIP(hipMalloc(&crec, sizeof(CheckRec)));
-        WW_HIP(hipHostMalloc(&hcrec, sizeof(CheckRec)));
+        WW_HIP(hipMalloc(&cb.lab, sizeof(unsigned long long) * N));
+        WW_HIP(hipMalloc(&cb.rec, sizeof(CheckRec)));
+        WW_HIP(hipHostMalloc(&cb.hrec, sizeof(CheckRec)));
         WW_HIP(hipMalloc(&cb.bad, 4 * sizeof(unsigned int)));
     }
 #ifndef WW_ROUNDS_PER_SYNC
@@ -1473,26 +1752,31 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     // relaxation rounds launched between two host checks of the list
     // lengths (a round whose list is empty returns at once)
     const int rounds_per_sync = WW_ROUNDS_PER_SYNC;
-    const unsigned int h0 = (unsigned int)g_first_hops.load(), dstep0 = (unsigned int)g_first_dstep.load();
-    const unsigned int full_passes = (unsigned int)g_full_passes.load();
-    const bool first_deficit = g_first_deficit.load() != 0;
-    const long long reverse_below = g_reverse_below.load();
-    const unsigned long long hop_growth = (unsigned long long)g_hop_growth.load();
+    const unsigned int h0 = (unsigned int)sp.first_hop_window, dstep0 = (unsigned int)sp.first_distance_step;
+    const unsigned int full_passes = (unsigned int)sp.full_passes;
+    const bool first_deficit = sp.first_deficit_after != 0;
+    const long long reverse_below = sp.reverse_below;
+    const unsigned long long hop_growth = (unsigned long long)sp.hop_growth;
     bool reversed = false;
-    const int rev_grid = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx + ny, N), 256 * 16)));
+    const int rev_grid =
+        (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx_all + ny_all, N), 256 * 16)));
     auto flip_frame = [&]() -> ww_status {
-        hipLaunchKernelGGL(k_reverse_frame, dim3(rev_grid), dim3(256), 0, st, g, ctl, nx, ny, N);
+        hipLaunchKernelGGL(k_reverse_frame, dim3(rev_grid), dim3(256), 0, st, g, ctl, fx_all, nx_all,
+                           fy_all, ny_all);
         WW_LAUNCH_CHECK();
-        std::swap(g.cxp, g.cxn);
-        std::swap(g.cyp, g.cyn);
+        reversed = !reversed;
+        if (MULTI) g.jobs = jobs_dev[reversed ? 1 : 0];
+        std::swap(g.j0.cxp, g.j0.cxn);
+        std::swap(g.j0.cyp, g.j0.cyn);
         std::swap(src, def);
         std::swap(src2, def2);
-        reversed = !reversed;
         // the host's copy of the counters follows the kernel's own exchange
         // (no round trip: the next read of the block checks the error flags)
         std::swap(h->nsrc, h->ndef);
-        h->gex = -h->gex;
-        h->gpot = -h->gpot;
+        for (int k = 0; k < nj; ++k) {
+            hg[k].gex = -hg[k].gex;
+            hg[k].gpot = -hg[k].gpot;
+        }
         return WW_OK;
     };
     const bool trace_windows = trace_env && trace_env[0] == '2';
@@ -1502,7 +1786,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
         ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sssp_round, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sssp_round<MULTI>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 4;
     (void)hipGetLastError();
@@ -1536,12 +1820,11 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     bool prev_unread = false;  // the previous pass ended without a host check
     for (;;) {
         if (!prev_unread) {
-            if (h->nsrc == 0 && h->gex <= 0) break;
+            if (h->nsrc == 0 && ground_surplus() == 0) break;
             // few units left: search from the demands instead (in the
             // reversed frame), where the plateaus that earlier passes made
             // tight around the supplies do not lie
-            if (!reversed && reverse_below > 0 &&
-                (long long)h->nsrc + std::max<long long>(h->gex, 0) <= reverse_below)
+            if (!reversed && reverse_below > 0 && (long long)h->nsrc + ground_surplus() <= reverse_below)
                 WW_TRY(flip_frame());
         }
         const auto tp0 = std::chrono::steady_clock::now();
@@ -1549,12 +1832,11 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         const unsigned long long v0 = trace ? host_visits() : 0, it0 = h->iters, vs0 = h->vt_sum,
                                  vst0 = h->vt_stage, vsw0 = h->vt_sweep;
         const unsigned int nsrc0 = h->nsrc;
-        const long long gex0 = h->gex;
+        const long long gex0 = ground_surplus();
         ++pass;
         const long long ns_h = h->nsrc, nd_h = h->ndef;  // list lengths, upper bounds
-        hipLaunchKernelGGL(k_pass_init, dim3(lgrid(std::max<long long>(ns_h, ra.nperim))), dim3(SB), 0, st,
-                           g, ctl, src, ra.act,
-                           ra.lists, NT, rr, ra.perim_tiles, ra.nperim);
+        hipLaunchKernelGGL(k_pass_init<MULTI>, dim3(lgrid(std::max<long long>(ns_h, ra.nperim))), dim3(SB), 0,
+                           st, g, ctl, src, ra.act, ra.lists, NT, rr, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
         // Windows in lexicographic (distance, hops) order: every label <= lb
         // is exact at the end of a window.  The first window admits only
@@ -1570,7 +1852,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             for (;;) {  // rounds
                 WW_HIP(hipEventRecord(ev[0], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
-                    hipLaunchKernelGGL(k_sssp_round, dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
+                    hipLaunchKernelGGL(k_sssp_round<MULTI>, dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
                                        rr, pass, lb, trace ? 1 : 0);
                     WW_LAUNCH_CHECK();
                     ++rr;
@@ -1581,8 +1863,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 // writes the slot of its batch parity and clears the other)
                 wslot = (int)(nbatch++ & 1);
                 hipLaunchKernelGGL(k_window_end, dim3(lgrid(std::max<long long>(nd_h, NT))), dim3(SB), 0,
-                                   st, g, ctl, def, lb,
-                                   ra.pstamp, pass, ra.tile_rej, NT, wslot, rr);
+                                   st, g, ctl, def, lb, ra.pstamp, pass, ra.tile_rej, NT, wslot, rr);
                 WW_LAUNCH_CHECK();
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
@@ -1595,8 +1876,8 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                                         h->count[q][0], NT);
                     unsigned int hb[4] = {0u, 0u, 0u, 0u};
                     WW_HIP(hipMemsetAsync(cb.bad, 0, sizeof(hb), st));
-                    hipLaunchKernelGGL(k_check_lists, dim3(std::min<unsigned int>(1024u, (NT + 255) / 256)),
-                                       dim3(256), 0, st, ctl, ra.act, ra.lists, NT, rr, cb.bad);
+                    hipLaunchKernelGGL(k_check_lists<MULTI>, dim3(std::min<unsigned int>(1024u, (NT + 255) / 256)),
+                                       dim3(256), 0, st, g, ctl, ra.act, ra.lists, NT, rr, cb.bad);
                     WW_LAUNCH_CHECK();
                     WW_HIP(hipMemcpyAsync(hb, cb.bad, sizeof(hb), hipMemcpyDeviceToHost, st));
                     WW_HIP(hipStreamSynchronize(st));
@@ -1616,7 +1897,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                     S.path_arcs += (long long)h->prev_arcs;
                     if (h->prev_naug == 0)
                         return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
-                    if (h->nsrc == 0 && h->gex <= 0) {
+                    if (h->nsrc == 0 && ground_surplus() == 0) {
                         finished = true;
                         break;
                     }
@@ -1634,7 +1915,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                         settled);
             // stop rule: all units in a full pass, else the first deficit or
             // half of the units
-            const long long units = (long long)h->nsrc + std::max<long long>(h->gex, 0);
+            const long long units = (long long)h->nsrc + ground_surplus();
             const long long need = pass <= full_passes ? std::max<long long>(1, units)
                                    : first_deficit    ? 1
                                                       : std::max<long long>(1, (units + 1) / 2);
@@ -1653,7 +1934,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
                 dstep = dstep > (1u << 30) ? dstep : dstep * 2;
                 lb = mk_label((unsigned int)dn, HMAX);
             }
-            hipLaunchKernelGGL(k_requeue_pending, dim3(tg), dim3(SB), 0, st, ctl, ra.pstamp, pass,
+            hipLaunchKernelGGL(k_requeue_pending<MULTI>, dim3(tg), dim3(SB), 0, st, g, ctl, ra.pstamp, pass,
                                ra.tile_rej, lb, ra.act, ra.lists, NT, rr);
             WW_LAUNCH_CHECK();
         }
@@ -1665,52 +1946,54 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
         if (settled == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: %u supplies reach no demand", h->nsrc);
         // The host's last read followed the pass's last round, so it holds
-        // the pass's final ground label and excess: the ground's predecessor
-        // is only needed when the ground is a settled deficit, and subtrees
-        // hang off the ground only while it is a source.
-        const int pg = (int)std::min<long long>(1024, ceil_div(nperim_arcs, SB));
-        if (h->glab <= lb && h->gex <= 0) {
-            hipLaunchKernelGGL(k_ground_pred, dim3(pg), dim3(SB), 0, st, g, ctl, lb);
+        // the pass's final ground labels and excesses: a ground's predecessor
+        // is only needed when it is a settled deficit, and subtrees hang off
+        // a ground only while it is a source.
+        bool ground_deficit = false, ground_source = false;
+        for (int k = 0; k < nj; ++k) {
+            ground_deficit |= hg[k].glab <= lb && hg[k].gex <= 0;
+            ground_source |= hg[k].gex > 0;
+        }
+        const int pg = (int)std::min<long long>(1024, ceil_div(max_arcs, SB));
+        if (ground_deficit) {
+            hipLaunchKernelGGL(k_ground_pred, dim3(pg, nj), dim3(SB), 0, st, g, lb);
             WW_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_roots, dim3(lgrid(nd_h + 1)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
+        hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
         WW_LAUNCH_CHECK();
-        if (h->gex > 0) {
-            hipLaunchKernelGGL(k_gsub_select, dim3(pg), dim3(SB), 0, st, g, ctl, gsub_list, drop);
+        if (ground_source) {
+            hipLaunchKernelGGL(k_gsub_select, dim3(pg, nj), dim3(SB), 0, st, g, gsub_list, drop);
             WW_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_augment, dim3(lgrid(ns_h + nperim_arcs)), dim3(SB), 0, st, g, ctl, src,
-                           gsub_list, drop, flip, pass);
+        hipLaunchKernelGGL(k_augment<MULTI>, dim3(lgrid(ns_h + nslots)), dim3(SB), 0, st, g, ctl, src,
+                           gsub_list, drop, flip, pass, nslots);
         WW_LAUNCH_CHECK();
         if (check)
-            WW_HIP(hipMemcpyAsync(lab_copy, g.lab, sizeof(unsigned long long) * N,
-                                  hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_potentials, dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass,
-                           NT, lb, flip);
+            WW_HIP(hipMemcpyAsync(cb.lab, g.lab, sizeof(unsigned long long) * N, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_potentials<MULTI>, dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass, NT,
+                           lb, flip, count);
         WW_LAUNCH_CHECK();
         if (check) {
-            WW_HIP(hipMemsetAsync(crec, 0, sizeof(CheckRec), st));
-            hipLaunchKernelGGL(k_check_rc, dim3(IB), dim3(256), 0, st, g, ctl, lab_copy, crec);
+            WW_HIP(hipMemsetAsync(cb.rec, 0, sizeof(CheckRec), st));
+            hipLaunchKernelGGL(k_check_rc, dim3(std::min(IB, 2048), nj), dim3(256), 0, st, g, cb.lab, cb.rec);
             WW_LAUNCH_CHECK();
-            WW_HIP(hipMemcpyAsync(hcrec, crec, sizeof(CheckRec), hipMemcpyDeviceToHost, st));
+            WW_HIP(hipMemcpyAsync(cb.hrec, cb.rec, sizeof(CheckRec), hipMemcpyDeviceToHost, st));
             WW_HIP(hipStreamSynchronize(st));
-            if (hcrec->found) {
+            if (cb.hrec->found) {
                 auto pl = [](unsigned long long l) {
                     return l == LINF ? std::string("inf") :
                         std::to_string(l >> 32) + "/" + std::to_string((l >> 3) & 0x1fffffff) + "/" + std::to_string(l & 7);
                 };
+                const CheckRec &c = *cb.hrec;
                 fprintf(stderr,
                         "[ww-mcf-check] pass %lld lb %u/%u: arc kind %d u %lld v %lld rc %lld pot %lld %lld "
-                        "labels %s %s flow %d c+ %d c- %d gex %lld\n",
+                        "labels %s %s flow %d c+ %d c- %d\n",
                         (long long)S.passes + 1, (unsigned)(lb >> 32), (unsigned)((lb >> 3) & 0x1fffffff),
-                        hcrec->kind, hcrec->u, hcrec->v, hcrec->rc, hcrec->pu, hcrec->pv,
-                        pl(hcrec->lu).c_str(), pl(hcrec->lv).c_str(), hcrec->f, hcrec->cp, hcrec->cn,
-                        (long long)h->gex);
+                        c.kind, c.u, c.v, c.rc, c.pu, c.pv, pl(c.lu).c_str(), pl(c.lv).c_str(), c.f, c.cp, c.cn);
                 return fail(WW_E_DEVICE, "min-cost flow check failed (details on stderr)");
             }
         }
-        hipLaunchKernelGGL(k_compact, dim3(lgrid(ns_h + nd_h)), dim3(SB), 0, st, g, ctl, src, def, src2,
-                           def2);
+        hipLaunchKernelGGL(k_compact, dim3(lgrid(ns_h + nd_h)), dim3(SB), 0, st, g, ctl, src, def, src2, def2);
         WW_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_swap_lists, dim3(1), dim3(1), 0, st, ctl);
         WW_LAUNCH_CHECK();
@@ -1742,25 +2025,75 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
             return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
     }
     if (reversed) WW_TRY(flip_frame());
-    const int cg = (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(nx + ny, 256 * 8)));
-    long long *part = (long long *)bc;
-    hipLaunchKernelGGL(k_total_cost, dim3(cg), dim3(256), 0, st, dkx, dky, cxp, cxn, cyp, cyn, nx,
-                       ny, part);
-    WW_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_total_finish, dim3(1), dim3(256), 0, st, cg, part, ctl);
-    WW_LAUNCH_CHECK();
-    if (pot_out) {
-        hipLaunchKernelGGL(k_export_pot, dim3(IB), dim3(256), 0, st, g.pot, ctl, N, pot_out);
+    {
+        // each job's cost from its flows (original frame)
+        long long mx_e = 0;
+        for (int k = 0; k < nj; ++k)
+            mx_e = std::max<long long>(mx_e, (long long)jobs[k].R * jobs[k].n + (long long)(jobs[k].R + 1) * jobs[k].C);
+        const int tcg = (int)std::min<long long>(MULTI ? 256 : 8192, std::max<long long>(1, ceil_div(mx_e, 256 * 8)));
+        hipLaunchKernelGGL(k_total_cost, dim3(tcg, nj), dim3(256), 0, st, g);
+        WW_LAUNCH_CHECK();
+    }
+    if (pot_out && !MULTI) {
+        hipLaunchKernelGGL(k_export_pot, dim3(IB), dim3(256), 0, st, g.pot, g.gs, N, pot_out);
         WW_LAUNCH_CHECK();
     }
     WW_TRY(sync_ctl());
-    *total = h->total_cost;
+    for (int k = 0; k < nj; ++k) *mj[k].total = hg[k].total_cost;
     S.tile_visits = (long long)host_visits();
-    S.max_potential = std::max<long long>(h->max_pot, h->gpot);
+    long long mxp = h->max_pot;
+    for (int k = 0; k < nj; ++k) mxp = std::max<long long>(mxp, hg[k].gpot);
+    S.max_potential = mxp;
+    S.settled_nodes = count ? (long long)h->settled : -1;
+    S.arcs_scanned = count ? (long long)h->scanned : -1;
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     last_mcf_stats() = S;
     if (stats) *stats = S;
     return WW_OK;
+}
+
+ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const int16_t *cxn,
+                   const int16_t *cyp, const int16_t *cyn, int8_t *dkx, int8_t *dky,
+                   int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t st,
+                   const ww_mcf_params *sched) {
+    const long long nx = (long long)m * (n - 1), ny = (long long)(m - 1) * n;
+    if (nx > 0) WW_HIP(hipMemsetAsync(dkx, 0, nx, st));
+    if (ny > 0) WW_HIP(hipMemsetAsync(dky, 0, ny, st));
+    const int R = m - 1, C = n - 1;
+    if (R < 1 || C < 1) {
+        ww_mcf_stats S;
+        memset(&S, 0, sizeof(S));
+        last_mcf_stats() = S;
+        if (pot_out) WW_HIP(hipMemsetAsync(pot_out, 0, sizeof(int64_t), st));
+        WW_HIP(hipStreamSynchronize(st));
+        *total = 0;
+        if (stats) *stats = S;
+        return WW_OK;
+    }
+    if ((long long)R * C >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
+    const ww_mcf_params sp = sched ? *sched : process_mcf_params();
+    std::vector<McfJob> one(1);
+    one[0] = McfJob{m, n, res, cxp, cxn, cyp, cyn, dkx, dky, total};
+    return solve<false>(one, res, dkx, dky, pot_out, stats, sp, st);
+}
+
+ww_status mcf_multi_impl(const std::vector<McfJob> &jobs, const int8_t *res_all, int8_t *fx_all,
+                         int8_t *fy_all, ww_mcf_stats *stats, const ww_mcf_params &sp, hipStream_t st) {
+    if (jobs.empty()) return WW_OK;
+    if (jobs.size() > 256) return fail(WW_E_INVALID_ARG, "more than 256 jobs in one solve");
+    long long nx = 0, ny = 0;
+    for (const McfJob &q : jobs) {
+        if (q.m < 2 || q.n < 2) return fail(WW_E_INVALID_ARG, "multi-job solve: every job needs loops");
+        if ((long long)(q.m - 1) * (q.n - 1) >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
+        if ((long long)ceil_div(q.m - 1, TJ) * ceil_div(q.n - 1, TJ) >= (1ll << 24))
+            return fail(WW_E_INVALID_ARG, "more than 2^24 tiles in one job");
+        nx += (long long)q.m * (q.n - 1);
+        ny += (long long)(q.m - 1) * q.n;
+    }
+    WW_HIP(hipMemsetAsync(fx_all, 0, nx, st));
+    WW_HIP(hipMemsetAsync(fy_all, 0, ny, st));
+    if (jobs.size() == 1) return solve<false>(jobs, res_all, fx_all, fy_all, nullptr, stats, sp, st);
+    return solve<true>(jobs, res_all, fx_all, fy_all, nullptr, stats, sp, st);
 }
 
 }  // namespace ww
@@ -1779,13 +2112,8 @@ void ww_default_mcf_params(ww_mcf_params *p) {
 
 ww_status ww_set_mcf_params(const ww_mcf_params *p) {
     ww::clear_error();
-    if (!p || p->first_hop_window < 1 || p->first_hop_window > (int32_t)ww::HMAX - 1 ||
-        p->first_distance_step < 1 || p->first_distance_step > (1 << 30))
-        return ww::fail(WW_E_INVALID_ARG, "window schedule out of range");
-    if (p->full_passes < 0 || p->full_passes > (1 << 20) ||
-        (p->first_deficit_after != 0 && p->first_deficit_after != 1) || p->reverse_below < 0 ||
-        p->hop_growth < 2 || p->hop_growth > (1 << 20))
-        return ww::fail(WW_E_INVALID_ARG, "pass schedule out of range");
+    if (!p) return ww::fail(WW_E_INVALID_ARG, "window schedule out of range");
+    WW_TRY(ww::check_mcf_params(*p));
     ww::g_first_hops.store(p->first_hop_window);
     ww::g_first_dstep.store(p->first_distance_step);
     ww::g_full_passes.store(p->full_passes);
@@ -1797,12 +2125,7 @@ ww_status ww_set_mcf_params(const ww_mcf_params *p) {
 
 void ww_get_mcf_params(ww_mcf_params *p) {
     if (!p) return;
-    p->first_hop_window = ww::g_first_hops.load();
-    p->first_distance_step = ww::g_first_dstep.load();
-    p->full_passes = ww::g_full_passes.load();
-    p->first_deficit_after = ww::g_first_deficit.load();
-    p->reverse_below = ww::g_reverse_below.load();
-    p->hop_growth = ww::g_hop_growth.load();
+    *p = ww::process_mcf_params();
 }
 
 }  // extern "C"

@@ -1,8 +1,14 @@
-// Job server for many interferograms on one device: a fixed set of worker
-// threads, each with its own HIP stream and private workspace, fed from a
-// queue with admission by device-memory footprint.  Jobs on different
-// workers overlap on the GPU (their round kernels interleave on the device's
-// hardware queues); every job runs exactly the computation of ww_unwrap.
+// Many interferograms on one device.
+//
+// The job server: a fixed set of worker threads, each with its own HIP
+// stream and private workspace, fed from a queue with admission by
+// device-memory footprint.  Jobs on different workers overlap on the GPU
+// (their round kernels interleave on the device's hardware queues); every
+// job runs exactly the computation of ww_unwrap.
+//
+// The batch call: a stack of jobs whose min-cost-flow problems are solved
+// together, one solve per group of jobs over the union of their graphs
+// (mcf_multi_impl), with residues, costs and integration per job.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -22,19 +28,15 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Device bytes one job holds while it runs: the workspace of the whole path
-// per pixel (residues 1, four cost planes 8, two flow planes 2, solver
-// labels 8 + root picks 8 + potentials 4 + excess 1 + node lists 16) and,
-// for host-side jobs, the device copies of the inputs (9) and outputs (8).
-constexpr int64_t WS_BYTES_PER_PX = 1 + 8 + 2 + 8 + 8 + 4 + 1 + 16;
+// Device copies of a host-side job's inputs (psi, coh, mask) and outputs
+// (K, phi), per pixel.
 constexpr int64_t IO_BYTES_PER_PX = 4 + 4 + 1 + 4 + 4;
-constexpr int64_t WS_FIXED_BYTES = 8 << 20;
 // a queued job older than this blocks the jobs behind it until it fits
 constexpr double STARVE_S = 1.0;
 
 int64_t footprint(const ww_job *j) {
-    const int64_t px = (int64_t)j->m * j->n;
-    return WS_FIXED_BYTES + px * (WS_BYTES_PER_PX + (j->host_io ? IO_BYTES_PER_PX : 0));
+    if (j->m < 1 || j->n < 1) return 0;
+    return unwrap_workspace_bytes(j->m, j->n) + (j->host_io ? IO_BYTES_PER_PX * j->m * (int64_t)j->n : 0);
 }
 
 struct Worker {
@@ -42,6 +44,8 @@ struct Worker {
     Workspace *ws = nullptr;
     // device copies for host-side jobs (grow-only)
     Buffer io[5];
+    int64_t held = 0;     // device bytes its workspace and copies hold (grow-only)
+    int64_t running = 0;  // footprint of the job it runs, 0 when idle
 };
 
 ww_status grow(Buffer &b, size_t bytes) {
@@ -66,6 +70,7 @@ ww_status run_job(Worker &w, ww_job *j) {
     ww_cost_params cp;
     ww_default_cost_params(&cp);
     WW_TRY(check_unwrap_args(j->psi, j->coh, j->m, j->n, j->looks, j->K, j->phi, cp));
+    if (j->use_sched) WW_TRY(check_mcf_params(j->sched));
     const size_t px = (size_t)j->m * j->n;
     hipStream_t st = w.stream;
     const float *psi = j->psi, *coh = j->coh;
@@ -88,7 +93,8 @@ ww_status run_job(Worker &w, ww_job *j) {
         phi = (float *)w.io[4].ptr;
     }
     int64_t total = 0;
-    WW_TRY(unwrap_impl(psi, coh, valid, j->m, j->n, j->looks, cp, K, phi, &total, st));
+    WW_TRY(unwrap_impl(psi, coh, valid, j->m, j->n, j->looks, cp, K, phi, &total, st,
+                       j->use_sched ? &j->sched : nullptr));
     if (j->host_io) {
         WW_HIP(hipMemcpyAsync(j->K, K, 4 * px, hipMemcpyDeviceToHost, st));
         WW_HIP(hipMemcpyAsync(j->phi, phi, 4 * px, hipMemcpyDeviceToHost, st));
@@ -97,6 +103,104 @@ ww_status run_job(Worker &w, ww_job *j) {
     j->total_cost = total;
     return WW_OK;
 }
+
+// ------------------------------------------------------------- batches ---
+
+inline size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+// One group of valid jobs (each m, n >= 2), solved together on stream st
+// with the current workspace.  Totals go into the jobs; nothing else of
+// the jobs is touched.
+ww_status batch_group(ww_job *const *jobs, int nj, const ww_mcf_params &sp, hipStream_t st) {
+    ww_cost_params cp;
+    ww_default_cost_params(&cp);
+    ww_lut_params lp;
+    ww_default_lut_params(&lp);
+    size_t res_bytes = 0, nx_all = 0, ny_all = 0, cost_bytes = 0, io_bytes = 0;
+    std::vector<size_t> coff(nj), ioff(nj);
+    for (int k = 0; k < nj; ++k) {
+        const ww_job *j = jobs[k];
+        const size_t px = (size_t)j->m * j->n, nx = (size_t)j->m * (j->n - 1), ny = (size_t)(j->m - 1) * j->n;
+        res_bytes += (size_t)(j->m - 1) * (j->n - 1);
+        nx_all += nx;
+        ny_all += ny;
+        coff[k] = cost_bytes;
+        cost_bytes += 2 * up256(2 * nx) + 2 * up256(2 * ny);
+        ioff[k] = io_bytes;
+        if (j->host_io) io_bytes += 4 * up256(4 * px) + up256(px);
+    }
+    int8_t *res_all = nullptr, *fx_all = nullptr, *fy_all = nullptr;
+    char *costs = nullptr, *io = nullptr;
+    int64_t *gdev = nullptr;
+    WW_TRY(scratch(SLOT_B_RES, res_bytes + 64, (void **)&res_all));
+    WW_TRY(scratch(SLOT_B_FX, nx_all + 64, (void **)&fx_all));
+    WW_TRY(scratch(SLOT_B_FY, ny_all + 64, (void **)&fy_all));
+    WW_TRY(scratch(SLOT_B_COST, cost_bytes + 256, (void **)&costs));
+    if (io_bytes) WW_TRY(scratch(SLOT_B_IO, io_bytes, (void **)&io));
+    WW_TRY(scratch(SLOT_COUNTERS, 64, (void **)&gdev));
+    std::vector<McfJob> mj(nj);
+    std::vector<int64_t> totals(nj, 0);
+    std::vector<const float *> P(nj);
+    std::vector<const uint8_t *> V(nj);
+    std::vector<int32_t *> KK(nj);
+    std::vector<float *> PH(nj);
+    size_t noff = 0, xoff = 0, yoff = 0;
+    for (int k = 0; k < nj; ++k) {
+        ww_job *j = jobs[k];
+        const size_t px = (size_t)j->m * j->n, nx = (size_t)j->m * (j->n - 1), ny = (size_t)(j->m - 1) * j->n;
+        const float *psi = j->psi, *coh = j->coh;
+        const uint8_t *valid = j->valid;
+        int32_t *K = j->K;
+        float *phi = j->phi;
+        if (j->host_io) {
+            char *b = io + ioff[k];
+            float *dpsi = (float *)b, *dcoh = (float *)(b + up256(4 * px));
+            K = (int32_t *)(b + 2 * up256(4 * px));
+            phi = (float *)(b + 3 * up256(4 * px));
+            uint8_t *dval = (uint8_t *)(b + 4 * up256(4 * px));
+            WW_HIP(hipMemcpyAsync(dpsi, j->psi, 4 * px, hipMemcpyHostToDevice, st));
+            WW_HIP(hipMemcpyAsync(dcoh, j->coh, 4 * px, hipMemcpyHostToDevice, st));
+            if (j->valid) WW_HIP(hipMemcpyAsync(dval, j->valid, px, hipMemcpyHostToDevice, st));
+            psi = dpsi;
+            coh = dcoh;
+            valid = j->valid ? dval : nullptr;
+        }
+        P[k] = psi;
+        V[k] = valid;
+        KK[k] = K;
+        PH[k] = phi;
+        int16_t *cxp = (int16_t *)(costs + coff[k]);
+        int16_t *cxn = (int16_t *)(costs + coff[k] + up256(2 * nx));
+        int16_t *cyp = (int16_t *)(costs + coff[k] + 2 * up256(2 * nx));
+        int16_t *cyn = (int16_t *)(costs + coff[k] + 2 * up256(2 * nx) + up256(2 * ny));
+        const int16_t *lut = nullptr;
+        WW_TRY(lut_device(j->looks << 16, lp, st, &lut));
+        WW_TRY(residues_impl(psi, valid, j->m, j->n, res_all + noff, nullptr, gdev, st));
+        WW_TRY(edge_costs_impl(psi, coh, valid, j->m, j->n, lut, lp.n_alpha, lp.n_gamma, cp, cxp, cxn, cyp,
+                               cyn, st));
+        mj[k] = McfJob{j->m, j->n, res_all + noff, cxp, cxn, cyp, cyn, fx_all + xoff, fy_all + yoff, &totals[k]};
+        noff += (size_t)(j->m - 1) * (j->n - 1);
+        xoff += nx;
+        yoff += ny;
+    }
+    WW_TRY(mcf_multi_impl(mj, res_all, fx_all, fy_all, nullptr, sp, st));
+    for (int k = 0; k < nj; ++k) {
+        ww_job *j = jobs[k];
+        const size_t px = (size_t)j->m * j->n;
+        WW_TRY(integrate_impl(P[k], V[k], mj[k].dkx, mj[k].dky, j->m, j->n, cp, KK[k], PH[k], st));
+        if (j->host_io) {
+            WW_HIP(hipMemcpyAsync(j->K, KK[k], 4 * px, hipMemcpyDeviceToHost, st));
+            WW_HIP(hipMemcpyAsync(j->phi, PH[k], 4 * px, hipMemcpyDeviceToHost, st));
+        }
+    }
+    WW_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < nj; ++k) jobs[k]->total_cost = totals[k];
+    return WW_OK;
+}
+
+// Jobs per group and pixels per group at most.
+constexpr int GROUP_MAX_JOBS = 256;
+constexpr int64_t GROUP_MAX_PX = 400ll << 20;
 
 }  // namespace
 
@@ -112,22 +216,31 @@ struct ww_server {
     std::condition_variable cv_done;  // pollers: a job finished
     std::deque<ww_job *> pending;
     std::deque<ww_job *> done;
-    int64_t reserved = 0;  // footprint of the running jobs
     int running = 0;
     int64_t in_flight = 0;  // submitted, not yet polled
     bool stopping = false;
     std::vector<Worker> workers;
     std::vector<std::thread> threads;
 
-    // Picks the job to start (lock held): the first queued job that fits
-    // beside the running ones, unless the head has waited past the
-    // starvation bound; a job larger than the budget runs alone.
-    ww_job *pick(double t) {
+    // Device bytes held or reserved by every worker but w (lock held).
+    int64_t others(int w) const {
+        int64_t s = 0;
+        for (int k = 0; k < (int)workers.size(); ++k)
+            if (k != w) s += std::max(workers[k].held, workers[k].running);
+        return s;
+    }
+
+    // Picks the job for worker w to start (lock held): the first queued job
+    // that fits beside what the other workers hold, unless the head has
+    // waited past the starvation bound; a job runs alone when nothing else
+    // runs, whatever its size.
+    ww_job *pick(int w, double t) {
         if (pending.empty()) return nullptr;
         const bool head_only = t - pending.front()->t_submit > STARVE_S;
+        const int64_t rest = others(w);
         for (auto it = pending.begin(); it != pending.end(); ++it) {
-            const int64_t f = footprint(*it);
-            if (reserved + f <= budget || running == 0) {
+            const int64_t f = std::max(footprint(*it), workers[w].held);
+            if (rest + f <= budget || running == 0) {
                 ww_job *j = *it;
                 pending.erase(it);
                 return j;
@@ -146,14 +259,14 @@ struct ww_server {
             {
                 std::unique_lock<std::mutex> g(mu);
                 for (;;) {
-                    j = pick(now_s());
+                    j = pick(k, now_s());
                     if (j || (stopping && pending.empty())) break;
                     // a starving head re-checks periodically
                     cv_work.wait_for(g, std::chrono::milliseconds(50));
                 }
                 if (!j) break;
                 j->footprint_bytes = footprint(j);
-                reserved += j->footprint_bytes;
+                w.running = j->footprint_bytes;
                 ++running;
             }
             j->t_start = now_s();
@@ -166,9 +279,12 @@ struct ww_server {
                 j->error[sizeof(j->error) - 1] = 0;
             }
             j->t_end = now_s();
+            int64_t held = (int64_t)workspace_bytes(w.ws);
+            for (auto &b : w.io) held += (int64_t)b.bytes;
             {
                 std::lock_guard<std::mutex> g(mu);
-                reserved -= j->footprint_bytes;
+                w.held = held;
+                w.running = 0;
                 --running;
                 done.push_back(j);
             }
@@ -277,28 +393,84 @@ ww_status ww_server_destroy(ww_server *s) {
     return WW_OK;
 }
 
-ww_status ww_unwrap_batch(ww_job *jobs, int32_t njobs, int32_t slots) {
+ww_status ww_unwrap_batch(ww_job *jobs, int32_t njobs, int32_t group, const ww_mcf_params *sched) {
+    std::lock_guard<std::mutex> lk(lock());
     clear_error();
     if (njobs < 0 || (njobs > 0 && !jobs)) return fail(WW_E_INVALID_ARG, "bad job array");
+    if (group < 0) return fail(WW_E_INVALID_ARG, "group must be >= 0");
+    if (sched) WW_TRY(check_mcf_params(*sched));
     if (njobs == 0) return WW_OK;
-    ww_server *s = nullptr;
-    WW_TRY(ww_server_create(slots, 0, &s));
-    std::vector<int> order(njobs);
-    for (int k = 0; k < njobs; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (int64_t)jobs[a].m * jobs[a].n > (int64_t)jobs[b].m * jobs[b].n;
-    });
-    for (int k : order) {
-        ww_status st = ww_server_submit(s, &jobs[k]);
-        if (st != WW_OK) {
-            (void)ww_server_destroy(s);
-            return st;
+    const int gmax = (group == 0 || group > GROUP_MAX_JOBS) ? GROUP_MAX_JOBS : group;
+    const ww_mcf_params sp = sched ? *sched : process_mcf_params();
+    ww_cost_params cp;
+    ww_default_cost_params(&cp);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+        return fail(WW_E_DEVICE, "stream creation failed");
+    auto finish = [&](ww_job *j, ww_status s, double t0) {
+        j->status = s;
+        j->error[0] = 0;
+        if (s != WW_OK) {
+            strncpy(j->error, ww_last_error(), sizeof(j->error) - 1);
+            j->error[sizeof(j->error) - 1] = 0;
         }
+        j->t_start = t0;
+        j->t_end = now_s();
+    };
+    const double t_sub = now_s();
+    std::vector<ww_job *> valid_jobs;
+    for (int k = 0; k < njobs; ++k) {
+        ww_job *j = &jobs[k];
+        j->t_submit = t_sub;
+        j->total_cost = 0;
+        j->footprint_bytes = footprint(j);
+        clear_error();
+        ww_status s = check_unwrap_args(j->psi, j->coh, j->m, j->n, j->looks, j->K, j->phi, cp);
+        if (s != WW_OK) {
+            finish(j, s, t_sub);
+            continue;
+        }
+        if (j->m < 2 || j->n < 2) {  // no loops: nothing to solve
+            const double t0 = now_s();
+            if (j->host_io) s = fail(WW_E_INVALID_ARG, "batch: host-side jobs need m, n >= 2");
+            else s = unwrap_impl(j->psi, j->coh, j->valid, j->m, j->n, j->looks, cp, j->K, j->phi,
+                                 &j->total_cost, st, &sp);
+            finish(j, s, t0);
+            continue;
+        }
+        valid_jobs.push_back(j);
     }
-    std::vector<ww_job *> buf(njobs);
-    int64_t got = 0;
-    while (got < njobs) got += ww_server_poll(s, buf.data(), njobs, -1);
-    (void)ww_server_destroy(s);
+    size_t a = 0;
+    while (a < valid_jobs.size()) {
+        size_t b = a;
+        int64_t px = 0, loops = 0;
+        while (b < valid_jobs.size() && (int)(b - a) < gmax) {
+            const ww_job *j = valid_jobs[b];
+            const int64_t p = (int64_t)j->m * j->n, l = (int64_t)(j->m - 1) * (j->n - 1);
+            if (b > a && (px + p > GROUP_MAX_PX || loops + l >= (1ll << 31) - 512)) break;
+            px += p;
+            loops += l;
+            ++b;
+        }
+        const double t0 = now_s();
+        clear_error();
+        ww_status s = batch_group(valid_jobs.data() + a, (int)(b - a), sp, st);
+        if (s == WW_OK) {
+            for (size_t k = a; k < b; ++k) finish(valid_jobs[k], WW_OK, t0);
+        } else {
+            // isolate the failure: every job of the group alone
+            (void)hipStreamSynchronize(st);
+            for (size_t k = a; k < b; ++k) {
+                const double t1 = now_s();
+                clear_error();
+                ww_status s1 = batch_group(valid_jobs.data() + k, 1, sp, st);
+                finish(valid_jobs[k], s1, t1);
+            }
+        }
+        a = b;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
     for (int k = 0; k < njobs; ++k)
         if (jobs[k].status != WW_OK) return fail(jobs[k].status, "job %d: %s", k, jobs[k].error);
     return WW_OK;

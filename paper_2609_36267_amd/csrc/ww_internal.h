@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/ww.h"
 
@@ -80,6 +81,7 @@ enum Slot {
     SLOT_GS_PLANES, SLOT_GS_SHIFT, SLOT_GS_PSI,
     SLOT_BR_LABEL, SLOT_BR_RANK, SLOT_BR_SMALL, SLOT_BR_SIZES, SLOT_BR_Q,
     SLOT_MCF_FLIP,
+    SLOT_B_RES, SLOT_B_FX, SLOT_B_FY, SLOT_B_COST, SLOT_B_IO,
     SLOT_COUNT
 };
 
@@ -106,16 +108,39 @@ __device__ __forceinline__ double phase_at(const float *psi, const uint8_t *vali
 
 // -------------------------------------------------------- entry helpers ---
 
-ww_status lut_device(int looks, const ww_lut_params &p, hipStream_t stream, const int16_t **out);
+// Cached device table at looks_q16 / 2^16 looks (built or blended on first use).
+ww_status lut_device(int looks_q16, const ww_lut_params &p, hipStream_t stream, const int16_t **out);
+// out[k] = floor((T0[k] (2^16 - f) + T1[k] f) / 2^16), k < n.
+ww_status blend_lut_looks(const int16_t *T0, const int16_t *T1, int64_t n, int f, int16_t *out,
+                          hipStream_t stream);
 ww_status residues_impl(const float *psi, const uint8_t *valid, int m, int n, int8_t *res,
                         int8_t *perim, int64_t *ground_dev, hipStream_t stream);
 ww_status edge_costs_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
                           const int16_t *lut, int n_alpha, int n_gamma, const ww_cost_params &cp,
                           int16_t *cxp, int16_t *cxn, int16_t *cyp, int16_t *cyn,
                           hipStream_t stream);
+// One image of a min-cost-flow solve: shape, residues, cost planes, flow
+// planes (outputs) and where its total cost goes.
+struct McfJob {
+    int m, n;
+    const int8_t *res;
+    const int16_t *cxp, *cxn, *cyp, *cyn;
+    int8_t *dkx, *dky;
+    int64_t *total;
+};
+// One image; sched NULL = the process-wide schedule.
 ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const int16_t *cxn,
                    const int16_t *cyp, const int16_t *cyn, int8_t *dkx, int8_t *dky,
-                   int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t stream);
+                   int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t stream,
+                   const ww_mcf_params *sched = nullptr);
+// Several images in one solve (their union graph).  Every job has m, n >= 2;
+// the jobs' residues, x-flow planes and y-flow planes each lie in one
+// contiguous array in job order (res_all, fx_all, fy_all).
+ww_status mcf_multi_impl(const std::vector<McfJob> &jobs, const int8_t *res_all, int8_t *fx_all,
+                         int8_t *fy_all, ww_mcf_stats *stats, const ww_mcf_params &sched,
+                         hipStream_t stream);
+ww_mcf_params process_mcf_params();
+ww_status check_mcf_params(const ww_mcf_params &p);
 ww_status integrate_impl(const float *psi, const uint8_t *valid, const int8_t *dkx,
                          const int8_t *dky, int m, int n, const ww_cost_params &cp, int32_t *K,
                          float *phi, hipStream_t stream);
@@ -136,7 +161,10 @@ ww_mcf_stats &last_mcf_stats();  // of the current workspace
 // current workspace; the cost table comes from the shared cache.
 ww_status unwrap_impl(const float *psi, const float *coh, const uint8_t *valid, int m, int n,
                       int looks, const ww_cost_params &cp, int32_t *K, float *phi,
-                      int64_t *total, hipStream_t stream);
+                      int64_t *total, hipStream_t stream, const ww_mcf_params *sched = nullptr);
+// Device bytes that unwrap_impl's workspace requests for an m x n image
+// (every slot it and its steps ask for, with the allocator's growth margin).
+int64_t unwrap_workspace_bytes(int m, int n);
 ww_status check_unwrap_args(const float *psi, const float *coh, int m, int n, int looks,
                             const int32_t *K, const float *phi, const ww_cost_params &cp);
 

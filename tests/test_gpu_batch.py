@@ -1,7 +1,8 @@
-"""Many interferograms through the job server (ww_server_*, ww_unwrap_batch):
-every job's K, phi and cost must be byte-identical to the plain one-job
-ww_unwrap on the same inputs, alone or in a mix, with host or device arrays,
-and its cost must equal the CPU oracle's optimum."""
+"""Many interferograms through the job server (ww_server_*) and the batch
+call (ww_unwrap_batch, one min-cost-flow solve over the union of the jobs'
+graphs): every job's K, phi and cost must be byte-identical to the plain
+one-job ww_unwrap on the same inputs, alone or in a mix, with host or device
+arrays, and its cost must equal the CPU oracle's optimum."""
 import time
 
 import numpy as np
@@ -56,18 +57,131 @@ def test_plain_costs_equal_oracle(plain, scenes):
         assert tot == total, (sc.psi.shape, sc.looks)
 
 
-@pytest.mark.parametrize("slots", [1, 3, 8])
-def test_batch_matches_plain(torch_cuda, scenes, plain, slots):
+@pytest.fixture(scope="module")
+def certs(scenes):
+    """The oracle's optimum of every job: (K, fixed-edge masks, reference)."""
+    out = []
+    for sc in scenes:
+        m, n = sc.psi.shape
+        o = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, want=True)
+        fx, fy = oracle.fixed_edges(o["costs"], o["dkx"], o["dky"], o["pot"])
+        out.append((o["K"], fx, fy, oracle.ref_index(sc.valid, m, n), o["total"]))
+    return out
+
+
+def check_batch_job(sc, cert, K, phi, tot):
+    """A batch result: the oracle's optimal cost, the oracle's K on every
+    pixel the optimum fixes, phi within tolerance of psi + 2 pi K."""
+    from tests.helpers import assert_same_on_certified_pixels, phase_tolerance_ok
+    Ko, fx, fy, ref, total = cert
+    assert tot == total
+    K = K if isinstance(K, np.ndarray) else K.cpu().numpy()
+    phi = phi if isinstance(phi, np.ndarray) else phi.cpu().numpy()
+    assert_same_on_certified_pixels(K, Ko, fx, fy, ref)
+    ok, err = phase_tolerance_ok(phi, sc.psi, K, sc.valid)
+    assert ok, err
+
+
+@pytest.mark.parametrize("group", [1, 3, 8, 0])
+def test_batch_matches_plain(torch_cuda, scenes, plain, certs, group):
+    """Groups of 1, 3 and all jobs per solve (the two jobs without loops
+    take the plain path inside the call): the plain path's cost, the
+    oracle's K wherever the optimum is unique, byte-identical to the plain
+    path for one job per solve, and identical bytes on a repeated call."""
     torch = torch_cuda
     jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
              torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes]
-    results, arr = ww.unwrap_batch(jobs, slots=slots)
-    for (K, phi, tot), (Kp, phip, totp), j in zip(results, plain, arr):
+    results, arr = ww.unwrap_batch(jobs, group=group)
+    again, _ = ww.unwrap_batch(jobs, group=group)
+    for sc, cert, (K, phi, tot), (Kp, phip, totp), j, (K2, phi2, tot2) in zip(
+            scenes, certs, results, plain, arr, again):
         assert j.status == 0
-        assert tot == totp
-        assert np.array_equal(K.cpu().numpy(), Kp)
-        assert same_phi(phi.cpu().numpy(), phip)
+        assert tot == totp == tot2
+        check_batch_job(sc, cert, K, phi, tot)
+        assert np.array_equal(K.cpu().numpy(), K2.cpu().numpy())
+        assert same_phi(phi.cpu().numpy(), phi2.cpu().numpy())
+        if group == 1:
+            assert np.array_equal(K.cpu().numpy(), Kp)
+            assert same_phi(phi.cpu().numpy(), phip)
         assert j.t_submit <= j.t_start <= j.t_end
+
+
+@pytest.mark.parametrize("sched", [(64, 256, 0, 0, 1 << 30), (1, 1, 2, 1, 1), (64, 256, 8, 1, 0),
+                                   (64, 256, 4, 0, 1024, 8)])
+def test_batch_schedules_and_checks(torch_cuda, scenes, certs, sched, monkeypatch):
+    """One solve over all jobs under extreme schedules, the reversed frame
+    included, with the solver's debug checks on (non-negative reduced costs
+    in every job after every pass, tile lists in bounds and without
+    repeats): every job reaches the oracle's optimum."""
+    torch = torch_cuda
+    monkeypatch.setenv("WW_MCF_CHECK", "1")
+    jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+             torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes]
+    results, arr = ww.unwrap_batch(jobs, sched=sched)
+    for sc, cert, (K, phi, tot), j in zip(scenes, certs, results, arr):
+        assert j.status == 0, j.error
+        check_batch_job(sc, cert, K, phi, tot)
+
+
+def test_batch_stack_of_many_jobs(torch_cuda):
+    """24 jobs of the stack recipe at reduced size (rows 64-300, cols
+    64-420, L in {5, 9, 15}) in one solve, host-side arrays for every third:
+    each reaches the CPU oracle's optimum."""
+    torch = torch_cuda
+    rng = np.random.default_rng(77)
+    scs, jobs = [], []
+    for k in range(24):
+        m, n = int(rng.integers(64, 301)), int(rng.integers(64, 421))
+        sc = synth.make(m, n, looks=int(rng.choice([5, 9, 15])), seed=300 + k, mask_frac=0.03,
+                        disks=1, disk_radius=(6, 16), keep_truth=False, workers=1)
+        scs.append(sc)
+        if k % 3 == 0:
+            jobs.append((sc.psi, sc.coh, sc.valid, sc.looks))
+        else:
+            jobs.append((torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+                         torch.from_numpy(sc.valid).cuda(), sc.looks))
+    results, arr = ww.unwrap_batch(jobs)
+    for sc, (K, phi, tot), j in zip(scs, results, arr):
+        assert j.status == 0, j.error
+        m, n = sc.psi.shape
+        o = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, want=True)
+        fx, fy = oracle.fixed_edges(o["costs"], o["dkx"], o["dky"], o["pot"])
+        check_batch_job(sc, (o["K"], fx, fy, oracle.ref_index(sc.valid, m, n), o["total"]), K, phi, tot)
+
+
+def test_batch_bad_job_fails_alone(torch_cuda, scenes, plain):
+    torch = torch_cuda
+    jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+             torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes[:4]]
+    jobs[2] = jobs[2][:3] + (1,)  # L = 1 is outside [2, 64]
+    arr = (ww.Job * 4)()
+    keep = []
+    for k, (psi, coh, valid, looks) in enumerate(jobs):
+        j, kp = ww.make_job(psi, coh, valid, looks, tag=k)
+        arr[k] = j
+        keep.append(kp)
+    rc = ww.load().ww_unwrap_batch(arr, 4, 0, None)
+    assert rc == ww.E_INVALID_ARG
+    assert arr[2].status == ww.E_INVALID_ARG and b"looks" in arr[2].error
+    for k in (0, 1, 3):
+        assert arr[k].status == 0 and arr[k].total_cost == plain[k][2]
+
+
+def test_server_per_job_schedule(torch_cuda, scenes, plain):
+    """Jobs carrying their own schedule (use_sched) keep the optimum, and
+    the process-wide schedule is untouched."""
+    torch = torch_cuda
+    before = ww.get_mcf_params().as_tuple()
+    with ww.Server(slots=3) as srv:
+        for k, sc in enumerate(scenes[:6]):
+            j = srv.submit(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+                           torch.from_numpy(sc.valid).cuda(), sc.looks, tag=k,
+                           sched=[(1, 1, 2, 1, 1), (64, 256, 0, 0, 1 << 30), None][k % 3])
+        done = srv.drain()
+    assert ww.get_mcf_params().as_tuple() == before
+    for j, K, phi in done:
+        assert j.status == 0, j.error
+        assert j.total_cost == plain[j.tag][2]
 
 
 def test_server_host_arrays_in_a_mix(torch_cuda, scenes, plain):

@@ -129,3 +129,32 @@ def test_interp_rejects_bad_flag(torch_cuda, lut9):
     psi, coh, valid = scene(1, 8, 8)
     with pytest.raises(RuntimeError):
         ww.edge_costs(psi, coh, valid, lut9, ww.default_cost_params(lut_interp=2))
+
+
+# ------------------------------------------------- non-integer looks (L) ---
+
+@pytest.mark.parametrize("q", [(9 << 16) | 0x8000, (2 << 16) | 1, (15 << 16) | 40000,
+                               (63 << 16) | 65535, 64 << 16, 7 << 16])
+def test_lut_at_non_integer_looks_parity(torch_cuda, q):
+    """The device's blend of two integer tables equals the oracle's, entry
+    for entry (integer nodes included)."""
+    assert np.array_equal(ww.build_cost_lut_q16(q), oracle.build_lut_q16(q))
+
+
+def test_unwrap_at_non_integer_looks(torch_cuda):
+    """ww_unwrap with looks = 9 + 0.3 (looks_frac16 = 19661): the same cost
+    planes and optimal cost as the oracle's path on the blended table."""
+    from tests.helpers import np_
+    sc = synth.make(120, 170, looks=9, seed=21, mask_frac=0.05, disks=1, disk_radius=(10, 20),
+                    keep_truth=False, workers=1)
+    q = (9 << 16) | 19661
+    T = oracle.build_lut_q16(q)
+    out = oracle.unwrap(sc.psi, sc.coh, sc.valid, 9, lut=T, want=True)
+    costs_g = ww.edge_costs(sc.psi, sc.coh, sc.valid, ww.build_cost_lut_q16(q))
+    for a, b in zip(costs_g, out["costs"]):
+        assert np.array_equal(np_(a), b)
+    cp = ww.default_cost_params(looks_frac16=19661)
+    K, phi, tot = ww.unwrap(sc.psi, sc.coh, sc.valid, 9, params=cp)
+    assert tot == out["total"]
+    with pytest.raises(ww.WWError):
+        ww.unwrap(sc.psi, sc.coh, sc.valid, 64, params=cp)
