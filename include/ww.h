@@ -252,6 +252,19 @@ ww_status ww_integrate(const float *psi, const uint8_t *valid, const int8_t *dk_
                        const int8_t *dk_y, int32_t m, int32_t n, const ww_cost_params *cp,
                        int32_t *K, float *phi, void *stream);
 
+/* ww_integrate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and errors as ww_integrate, and WW_E_INVALID_ARG
+ * for m > 65536.  Its scratch (the integration state and one int32 per row:
+ * 256 B + 256 KiB) is a static device array, one copy per device, held until
+ * the process ends; the call allocates nothing.  The first call on a device
+ * looks up that copy's address.  Every call on one device shares the array:
+ * calls that overlap on one device (other streams or threads) race, so the
+ * caller serialises them.  The state is re-initialised by every call. */
+ww_status ww_integrate_noalloc(const float *psi, const uint8_t *valid, const int8_t *dk_x,
+                               const int8_t *dk_y, int32_t m, int32_t n,
+                               const ww_cost_params *cp, int32_t *K, float *phi, void *stream);
+
 /* The whole path: residues -> cost table (cached per L) -> edge costs ->
  * min-cost flow -> integration, on one device with library workspace.
  *   coh    float32 [m*n] sample coherence; looks as ww_build_cost_lut.

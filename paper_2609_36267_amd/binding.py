@@ -265,9 +265,10 @@ def _declare(L):
     L.ww_edge_costs.argtypes = [P, P, P, I32, I32, P, P, P, P, P, P, P, P]
     L.ww_mcf_solve.argtypes = [P, I32, I32, P, P, P, P, P, P, P, P, P, P]
     L.ww_integrate.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
+    L.ww_integrate_noalloc.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
     L.ww_unwrap.argtypes = [P, P, P, I32, I32, I32, P, P, P, P, P]
     for f in ("ww_residues", "ww_build_cost_lut", "ww_build_cost_lut_q16", "ww_edge_costs", "ww_mcf_solve",
-              "ww_integrate", "ww_unwrap"):
+              "ww_integrate", "ww_integrate_noalloc", "ww_unwrap"):
         getattr(L, f).restype = C.c_int32
     L.ww_clock.restype = C.c_double
     L.ww_clock.argtypes = []
@@ -442,6 +443,21 @@ def integrate(psi, valid, dkx, dky, ref=None, nodata=math.nan):
     nz = lambda t: _ptr(t) if t.numel() else None  # noqa: E731
     _check(load().ww_integrate(_ptr(psi), _ptr(valid), nz(dkx), nz(dky), m, n, C.byref(cp),
                                _ptr(K), _ptr(phi), _stream()))
+    return K, phi
+
+
+def integrate_noalloc(psi, valid, dkx, dky, K, phi, ref=None, nodata=math.nan):
+    """ww_integrate_noalloc: the integration into caller-provided device
+    tensors K (int32) and phi (float32); the library allocates nothing."""
+    torch = _torch()
+    m, n = psi.shape
+    cp = default_cost_params(nodata=nodata)
+    if ref is not None:
+        cp.ref_i, cp.ref_j = ref
+    nz = lambda t: _ptr(t) if t.numel() else None  # noqa: E731
+    _check(load().ww_integrate_noalloc(_ptr(psi), _ptr(valid), nz(dkx), nz(dky), m, n,
+                                       C.byref(cp), _ptr(K), _ptr(phi), _stream()))
+    del torch
     return K, phi
 
 

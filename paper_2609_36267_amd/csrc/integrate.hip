@@ -298,3 +298,60 @@ const long long *integrate_ref_index() {
 }
 
 }  // namespace ww
+
+// ------------------------------------------------------ allocation-free ---
+
+// Scratch of ww_integrate_noalloc: the integration state and the column-0
+// prefix sums of up to NOALLOC_MAX_ROWS rows.  Every device the library runs
+// on holds its own copy until the process ends.  In host code the name is
+// not a device address: host code only ever uses the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int NOALLOC_MAX_ROWS = 1 << 16;
+static __device__ __align__(256) char scratch[ww::K0_OFF + sizeof(int) * NOALLOC_MAX_ROWS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+extern "C" ww_status ww_integrate_noalloc(const float *psi, const uint8_t *valid,
+                                          const int8_t *dk_x, const int8_t *dk_y, int32_t m,
+                                          int32_t n, const ww_cost_params *cpin, int32_t *K,
+                                          float *phi, void *stream) {
+    ww::clear_error();
+    if (m < 1 || n < 1 || (int64_t)m * n >= ((int64_t)1 << 31))
+        return ww::fail(WW_E_INVALID_ARG, "image shape %d x %d outside 1 <= m,n, m*n < 2^31", m, n);
+    if (m > NOALLOC_MAX_ROWS)
+        return ww::fail(WW_E_INVALID_ARG, "ww_integrate_noalloc: %d rows above its limit of %d", m,
+                    NOALLOC_MAX_ROWS);
+    ww_cost_params cp;
+    if (cpin) cp = *cpin;
+    else ww_default_cost_params(&cp);
+    if (cp.ref_i >= 0 && (cp.ref_i >= m || cp.ref_j < 0 || cp.ref_j >= n))
+        return ww::fail(WW_E_INVALID_ARG, "reference pixel outside the image");
+    if (!psi || !K || !phi || (n > 1 && !dk_x) || (m > 1 && !dk_y))
+        return ww::fail(WW_E_INVALID_ARG, "input or output array is NULL");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ww::fail(WW_E_DEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return ww::fail(WW_E_INVALID_ARG, "device %d above the supported %d", dev, NOALLOC_MAX_DEVICES);
+    void *base = nullptr;
+    {
+        // the device address of this device's copy, looked up once per device
+        // (with that device current: each device has its own address)
+        std::lock_guard<std::mutex> g(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess)
+                return ww::fail(WW_E_DEVICE, "hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+            if (!p) return ww::fail(WW_E_DEVICE, "hipGetSymbolAddress returned NULL");
+            g_noalloc_ptr[dev] = p;
+        }
+        base = g_noalloc_ptr[dev];
+    }
+    char *buf = (char *)base;
+    return ww::integrate_run(psi, valid, dk_x, dk_y, m, n, cp, K, phi, (ww::IntegState *)buf,
+                             (int *)(buf + ww::K0_OFF), (hipStream_t)stream);
+}
