@@ -5,8 +5,9 @@
 // in integers, so any integration order gives the same K when the corrected
 // gradients are curl-free.  K is fixed by K(ref) = 0.
 //
-//   k_first_valid : reference pixel = first valid pixel, row-major (atomicMin)
-//   k_col0        : one workgroup; column-0 prefix sums K0[i] and K(ref)
+//   k_col0        : one workgroup of 1024: the reference pixel (first valid
+//                   pixel, row-major, unless given), column-0 prefix sums
+//                   K0[i] and K(ref)
 //   k_rows        : one workgroup per row; chunked workgroup scan of the
 //                   row's x-edge increments (8 pixels per thread, 16-byte
 //                   accesses where rows are 4-aligned, next chunk prefetched),
@@ -27,34 +28,12 @@ struct IntegState {
     int pad;
 };
 
-// First valid pixel (row-major).  One workgroup scans chunks from the start
-// and stops at the first chunk holding a valid pixel: typical masks end the
-// search in the first chunk, an all-invalid image reads the mask once.
-__global__ __launch_bounds__(1024) void k_first_valid(const uint8_t *__restrict__ valid, int64_t N,
-                                                     IntegState *st) {
-    __shared__ unsigned long long best;
-    if (threadIdx.x == 0) best = (unsigned long long)N;
-    __syncthreads();
-    for (int64_t base = 0; base < N; base += 1024 * 16) {
-        const int64_t k0 = base + (int64_t)threadIdx.x * 16;
-        for (int q = 0; q < 16; ++q) {
-            const int64_t k = k0 + q;
-            if (k < N && valid[k]) {
-                atomicMin(&best, (unsigned long long)k);
-                break;
-            }
-        }
-        __syncthreads();
-        if (best < (unsigned long long)N) break;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) st->first_valid = (long long)best;
-}
-
-// Block-wide exclusive scan of one int per thread; returns the exclusive
-// prefix and writes the block total to *total.
+// Block-wide exclusive scan of one int per thread (THREADS a multiple of
+// 64, at most 1024); returns the exclusive prefix and writes the block
+// total to *total.
+template <int THREADS>
 __device__ int block_exclusive_scan(int v, int *total) {
-    __shared__ int wsum[IT_THREADS / 64];
+    __shared__ int wsum[THREADS / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int inc = v;
     for (int off = 1; off < 64; off <<= 1) {
@@ -64,7 +43,7 @@ __device__ int block_exclusive_scan(int v, int *total) {
     if (lane == 63) wsum[wid] = inc;
     __syncthreads();
     int before = 0, tot = 0;
-    for (int w = 0; w < IT_THREADS / 64; ++w) {
+    for (int w = 0; w < THREADS / 64; ++w) {
         if (w < wid) before += wsum[w];
         tot += wsum[w];
     }
@@ -80,56 +59,88 @@ __device__ __forceinline__ int gx_at(const float *psi, const uint8_t *valid, con
            wrap_cycles(phase_at(psi, valid, a + 1) - phase_at(psi, valid, a));
 }
 
-// Column 0 and K(ref), one workgroup.  Column-0 increments
-// g(i) = dk_y(i-1, 0) - w_y(i-1, 0) are scanned in chunks of 8 rows per
-// thread, each thread's 8 loads issued together.
-__global__ __launch_bounds__(IT_THREADS) void k_col0(const float *__restrict__ psi,
-                                                    const uint8_t *__restrict__ valid,
-                                                    const int8_t *__restrict__ dkx,
-                                                    const int8_t *__restrict__ dky, int m, int n,
-                                                    int ref_i, int ref_j, IntegState *st,
-                                                    int *__restrict__ K0) {
+// Everything before the rows, in one workgroup of COL_THREADS:
+//  1. the reference pixel: ref_i/ref_j, or the first valid pixel in
+//     row-major order (chunks scanned from the start, stopping at the first
+//     chunk holding one: typical masks end the search in the first chunk);
+//  2. column 0: K0[i] = sum over 1 <= i' <= i of g(i') = dk_y(i'-1, 0) -
+//     w_y(i'-1, 0), in chunks of COL_THREADS x COL_PER rows (each thread's
+//     COL_PER loads issued together; 8192 rows per chunk);
+//  3. K(ref) = K0[ref_i] + the x-edge increments along the reference row
+//     before ref_j.
+constexpr int COL_THREADS = 1024;
+constexpr int COL_PER = 8;
+
+__global__ __launch_bounds__(COL_THREADS) void k_col0(const float *__restrict__ psi,
+                                                     const uint8_t *__restrict__ valid,
+                                                     const int8_t *__restrict__ dkx,
+                                                     const int8_t *__restrict__ dky, int m, int n,
+                                                     int ref_i, int ref_j, IntegState *st,
+                                                     int *__restrict__ K0) {
+    __shared__ unsigned long long best;
+    __shared__ int kref_row;
+    const int64_t N = (int64_t)m * n;
+    if (threadIdx.x == 0) best = (unsigned long long)N;
+    __syncthreads();
+    if (valid && ref_i < 0) {
+        for (int64_t base = 0; base < N; base += COL_THREADS * 16) {
+            const int64_t k0 = base + (int64_t)threadIdx.x * 16;
+            for (int q = 0; q < 16; ++q) {
+                const int64_t k = k0 + q;
+                if (k < N && valid[k]) {
+                    atomicMin(&best, (unsigned long long)k);
+                    break;
+                }
+            }
+            __syncthreads();
+            if (best < (unsigned long long)N) break;
+            __syncthreads();
+        }
+    }
+    __syncthreads();
     int ri = ref_i, rj = ref_j;
     if (ri < 0) {
-        long long fv = st->first_valid;
-        if (fv >= (long long)m * n) fv = 0;
+        long long fv = valid ? (long long)best : 0ll;
+        if (threadIdx.x == 0) st->first_valid = valid ? fv : 0ll;
+        if (fv >= N) fv = 0;
         ri = (int)(fv / n);
         rj = (int)(fv % n);
+    } else if (threadIdx.x == 0) {
+        st->first_valid = valid ? (long long)N : 0ll;
     }
     auto g_col = [&](int i) -> int {  // increment from row i-1 to row i, i >= 1
         const int64_t a = (int64_t)(i - 1) * n;
         return (int)dky[a] - wrap_cycles(phase_at(psi, valid, a + n) - phase_at(psi, valid, a));
     };
-    // K0[i] = sum_{1 <= i' <= i} g(i'), in chunks of IT_THREADS x 8 rows:
-    // thread t owns 8 consecutive rows of a chunk, all 8 loads in flight
-    constexpr int PER = 8;
     int carry = 0;
-    for (int base = 0; base < m; base += IT_THREADS * PER) {
-        const int lo = base + threadIdx.x * PER;
-        int g[PER];
+    for (int base = 0; base < m; base += COL_THREADS * COL_PER) {
+        const int lo = base + threadIdx.x * COL_PER;
+        int g[COL_PER];
         int local = 0;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
+        for (int q = 0; q < COL_PER; ++q) {
             const int i = lo + q;
             g[q] = (i >= 1 && i < m) ? g_col(i) : 0;
             local += g[q];
         }
         int tot;
-        int run = carry + block_exclusive_scan(local, &tot);
+        int run = carry + block_exclusive_scan<COL_THREADS>(local, &tot);
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
+        for (int q = 0; q < COL_PER; ++q) {
             run += g[q];
             if (lo + q < m) K0[lo + q] = run;
+            if (lo + q == ri) kref_row = run;
         }
         carry += tot;
     }
     __syncthreads();
-    // K(ref) = K0[ri] + sum_{j < rj} g_x(ri, j)
     int part = 0, tot;
-    for (int j = threadIdx.x; j < rj; j += IT_THREADS) part += gx_at(psi, valid, dkx, n, ri, j);
-    (void)block_exclusive_scan(part, &tot);
-    __syncthreads();
-    if (threadIdx.x == 0) st->kref = K0[ri] + tot;
+    for (int j = threadIdx.x; j < rj; j += COL_THREADS) part += gx_at(psi, valid, dkx, n, ri, j);
+    (void)block_exclusive_scan<COL_THREADS>(part, &tot);
+    if (threadIdx.x == 0) {
+        st->kref = kref_row + tot;
+        st->pad = 0;
+    }
 }
 
 // Loads of one chunk of a row: elements j0 .. j0+RP-1 of psi/valid/dk_x and
@@ -214,7 +225,7 @@ __global__ __launch_bounds__(IT_THREADS) void k_rows(const float *__restrict__ p
             local += v;
         }
         int tot;
-        const int ex = block_exclusive_scan(local, &tot);
+        const int ex = block_exclusive_scan<IT_THREADS>(local, &tot);
         int k = carry + ex;
         int kk[RP];
         float ph[RP];
@@ -242,29 +253,13 @@ __global__ __launch_bounds__(IT_THREADS) void k_rows(const float *__restrict__ p
     }
 }
 
-// Sets the integration state before a call: first_valid = N (none found
-// yet) when a mask is given, else 0; K(ref) = 0.  A kernel rather than a
-// copy from host memory, so that nothing on the host must outlive the call.
-__global__ void k_integ_init(IntegState *st, long long first_valid) {
-    st->first_valid = first_valid;
-    st->kref = 0;
-    st->pad = 0;
-}
-
 // The integration proper, on caller-provided state: st (an IntegState) and
 // K0 (m ints of column-0 prefix sums).
 static ww_status integrate_run(const float *psi, const uint8_t *valid, const int8_t *dkx,
                                const int8_t *dky, int m, int n, const ww_cost_params &cp,
                                int32_t *K, float *phi, IntegState *st, int *K0,
                                hipStream_t stream) {
-    const int64_t N = (int64_t)m * n;
-    hipLaunchKernelGGL(k_integ_init, dim3(1), dim3(1), 0, stream, st, valid ? (long long)N : 0ll);
-    WW_LAUNCH_CHECK();
-    if (valid && cp.ref_i < 0) {
-        hipLaunchKernelGGL(k_first_valid, dim3(1), dim3(1024), 0, stream, valid, N, st);
-        WW_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_col0, dim3(1), dim3(IT_THREADS), 0, stream, psi, valid, dkx, dky, m, n,
+    hipLaunchKernelGGL(k_col0, dim3(1), dim3(COL_THREADS), 0, stream, psi, valid, dkx, dky, m, n,
                        cp.ref_i, cp.ref_j, st, K0);
     WW_LAUNCH_CHECK();
     // 16-byte accesses need 4-aligned rows and base pointers
