@@ -81,7 +81,7 @@ enum Slot {
     SLOT_GS_PLANES, SLOT_GS_SHIFT, SLOT_GS_PSI,
     SLOT_BR_LABEL, SLOT_BR_RANK, SLOT_BR_SMALL, SLOT_BR_SIZES, SLOT_BR_Q,
     SLOT_MCF_FLIP,
-    SLOT_B_RES, SLOT_B_FX, SLOT_B_FY, SLOT_B_COST, SLOT_B_IO,
+    SLOT_B_RES, SLOT_B_FX, SLOT_B_FY, SLOT_B_COST, SLOT_B_IO, SLOT_STEEP_PARTS,
     SLOT_COUNT
 };
 

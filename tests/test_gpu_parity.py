@@ -175,6 +175,30 @@ def test_costs_parity_steep_ties(torch_cuda, lut9, levels, pct):
         assert np.array_equal(np_(g), w)
 
 
+@pytest.mark.parametrize("n", [416, 413])
+def test_costs_parity_steep_large_boundary(torch_cuda, lut9, n):
+    """Five phase levels on a 400-row scene: the candidates' |d| take two
+    values (up to float rounding), so the coarse bin at the cap holds over
+    a hundred thousand tied candidates, more than the one-workgroup select
+    takes; the multi-workgroup passes then choose among the ties by edge id.
+    Rows of 416 columns take the pre-pass's 16-byte loads, 413 the scalar
+    ones."""
+    rng = np.random.default_rng(n)
+    m = 400
+    psi = (rng.integers(0, 5, (m, n)) * (2 * np.pi / 5) - np.pi).astype(np.float32)
+    coh = np.full((m, n), 0.8, np.float32)
+    valid = (rng.random((m, n)) > 0.02).astype(np.uint8)
+    want, st = oracle.edge_costs(psi, coh, valid, lut9, steep_cap_pct=3, want_stats=True)
+    assert st["steep_candidates"] > st["steep_zeroed"] > 0
+    w = [np.abs(d - 2 * np.pi * np.round(d / (2 * np.pi)))
+         for d in (np.diff(psi.astype(np.float64), axis=1), np.diff(psi.astype(np.float64), axis=0))]
+    top = max(x.max() for x in w)
+    assert sum(int(np.isclose(x, top, atol=1e-5).sum()) for x in w) > 2 * 65536
+    got = ww.edge_costs(psi, coh, valid, lut9, ww.default_cost_params(steep_cap_pct=3))
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+
+
 def test_costs_parity_c0_with_gpu_table(torch_cuda, c0):
     T = ww.build_cost_lut(9)
     got = ww.edge_costs(c0.psi, c0.coh, c0.valid, T)
