@@ -485,6 +485,23 @@ ww_status ww_server_destroy(ww_server *s);
  * status.  Uses the library workspace of the current device. */
 ww_status ww_unwrap_batch(ww_job *jobs, int32_t njobs, int32_t group, const ww_mcf_params *sched);
 
+/* ---------------------------------------------------------------------
+ * Measurement
+ * ------------------------------------------------------------------- */
+
+/* Streaming ceiling of the device (not part of the unwrapping path): times
+ * `reps` launches of a hand-written grid sweep over `bytes` bytes with
+ * 16-byte accesses, after one untimed launch, and returns the average
+ * launch time in *ms_host (HIP events on `stream`; synchronises it).
+ *   mode 0  copy src -> dst (bytes read + bytes written);
+ *   mode 1  read src only; dst receives one 16-byte word per workgroup
+ *           (it must hold 32 KiB);
+ *   mode 2  copy with non-temporal loads and stores.
+ * src and dst are device pointers, 16-byte aligned; bytes a positive
+ * multiple of 16; they must not overlap. */
+ww_status ww_stream_probe(const void *src, void *dst, int64_t bytes, int32_t mode, int32_t reps,
+                          float *ms_host, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -297,6 +297,8 @@ def _declare(L):
     L.ww_unwrap_filtered.argtypes = [P, P, P, I32, I32, I32, P, P, P, P, P, P]
     for f in ("ww_goldstein_filter", "ww_transfer_ambiguity", "ww_unwrap_filtered"):
         getattr(L, f).restype = C.c_int32
+    L.ww_stream_probe.argtypes = [P, P, I64, I32, I32, P, P]
+    L.ww_stream_probe.restype = C.c_int32
     L.ww_default_bridge_params.argtypes = [P]
     L.ww_bridge.argtypes = [P, P, P, I32, I32, P, C.c_float, P, P, P, P, P]
     L.ww_bridge.restype = C.c_int32
@@ -490,6 +492,16 @@ class Job(C.Structure):
                 ("status", C.c_int32), ("total_cost", C.c_int64), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_end", C.c_double), ("footprint_bytes", C.c_int64),
                 ("error", C.c_char * 160), ("use_sched", C.c_int32), ("sched", McfParams)]
+
+
+def stream_probe(src, dst, mode: int = 0, reps: int = 5) -> float:
+    """ww_stream_probe: average milliseconds of one hand-written streaming
+    sweep over src's bytes (mode 0 copy, 1 read only, 2 non-temporal
+    copy)."""
+    ms = C.c_float(0.0)
+    _check(load().ww_stream_probe(_ptr(src), _ptr(dst), src.numel() * src.element_size(), int(mode),
+                                  int(reps), C.byref(ms), _stream()))
+    return float(ms.value)
 
 
 def clock() -> float:

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libww.so")
 SOURCES = ["api.hip", "residues.hip", "lut.hip", "costs.hip", "mcf.hip", "integrate.hip",
            "server.hip", "components.hip", "goldstein.hip",
-           "bridge.hip"]
+           "bridge.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

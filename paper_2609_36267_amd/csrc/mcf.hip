@@ -176,13 +176,17 @@ __device__ __forceinline__ int job_of_slot(const Graph &g, unsigned int q) {
 
 // Append a tile to the list of round r unless it is already there
 // (act[gt] == r).  gt: global tile; entry: its list entry.
-// Lists: lists[(r % 3) * NT ...], lengths ctl->count[r % 3].
+// Lists: lists[(r % 3) * list_stride(NT) ...], lengths ctl->count[r % 3].
+// A tile enters a list only when its round stamp changes, so a list holds
+// at most NT entries.
+__host__ __device__ __forceinline__ size_t list_stride(unsigned int NT) { return (size_t)NT; }
+
 __device__ __forceinline__ void activate(unsigned int *act, unsigned int *lists, unsigned int NT,
                                          Ctl *ctl, unsigned int gt, unsigned int entry,
                                          unsigned int r) {
     if (atomicExch(&act[gt], r) != r) {
         const unsigned int pos = atomicAdd(&ctl->count[r % 3][0], 1u);
-        lists[(size_t)(r % 3) * NT + pos] = entry;
+        lists[(size_t)(r % 3) * list_stride(NT) + pos] = entry;
     }
 }
 
@@ -541,14 +545,18 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
     __shared__ unsigned long long L[TJ + 2][TJ + 3];
     __shared__ int P[TJ + 2][TJ + 2];
     __shared__ int4 RC4[TJ][TJ];  // reduced costs of the in-arcs: from above, below, left, right
+    __shared__ int GA[TJ][TJ];    // cheapest move to the ground of a perimeter node (RC_INF: none)
     __shared__ int wchg[3][4];    // per-iteration "a label changed" flag of each wave's band
     __shared__ int flags[4];  // changed border: top, bottom, left, right
     __shared__ int sh_any;
     __shared__ unsigned long long sh_gcand, sh_rej;
 
     const unsigned int NT = ra.NT;
+    const unsigned int *list = ra.lists + (size_t)(round % 3) * list_stride(NT);
+    // the first entry is read together with the length (the slot lies inside
+    // the list's storage, whatever the length): one memory round trip less
+    const unsigned int first = blockIdx.x < list_stride(NT) ? list[blockIdx.x] : 0u;
     const unsigned int cnt = ctl->count[round % 3][0];
-    const unsigned int *list = ra.lists + (size_t)(round % 3) * NT;
     // list (round + 2) % 3 was consumed by the previous round
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->count[(round + 2) % 3][0] = 0;
     // one job: its ground's label and potential once per launch
@@ -557,7 +565,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
     unsigned int my_visits = 0;
 
     for (unsigned int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
-        const unsigned int entry = list[idx];
+        const unsigned int entry = idx == blockIdx.x ? first : list[idx];
         const int job = MULTI ? (int)(entry >> 24) : 0;
         const unsigned int lt = entry & 0xffffffu;
         const Job J = job_at<MULTI>(g, job);
@@ -577,58 +585,90 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             sh_gcand = LINF;
         }
         // stage labels and potentials with a one-node halo; outside = ground.
-        // All loads of a thread (labels, potentials, arc costs and flows) are
-        // issued before any LDS store, so that their latencies overlap.
+        // Every load of a thread (labels, potentials, arc costs and flows)
+        // is issued unconditionally, from an address clamped into the tile,
+        // before any of them is used: one memory latency for all of them.
+        // Values of positions outside the tile are replaced afterwards.
         constexpr int NSTAGE = ((TJ + 2) * (TJ + 2) + 255) / 256;
         constexpr int NRC = TJ * TJ / 256;
         int cst[NRC][4];
         {
             unsigned long long lv[NSTAGE];
             int pv[NSTAGE];
+            bool inside[NSTAGE], halo[NSTAGE];
 #pragma unroll
             for (int s = 0; s < NSTAGE; ++s) {
                 const int t = threadIdx.x + 256 * s;
                 const int r = t / (TJ + 2), c = t % (TJ + 2);
                 const int i = i0 - 1 + r, j = j0 - 1 + c;
-                lv[s] = LINF;
-                pv[s] = 0;
-                if (t < (TJ + 2) * (TJ + 2) && r <= rows + 1 && c <= cols + 1) {
-                    if (i >= 0 && i < R && j >= 0 && j < C) {
-                        const long long v = noff + (long long)i * C + j;
-                        lv[s] = g.lab[v];
-                        pv[s] = g.pot[v];
-                    } else {
-                        lv[s] = glab;
-                        pv[s] = gpot;
-                    }
-                }
+                halo[s] = t < (TJ + 2) * (TJ + 2) && r <= rows + 1 && c <= cols + 1;
+                inside[s] = halo[s] && i >= 0 && i < R && j >= 0 && j < C;
+                const long long v = noff + (long long)(inside[s] ? i : i0) * C + (inside[s] ? j : j0);
+                lv[s] = g.lab[v];
+                pv[s] = g.pot[v];
             }
-            // arc costs and flows of the four in-arcs of every node, issued
-            // with the label and potential loads (one memory latency for all)
+            // arc flows and both costs of the four in-arcs of every node
+            int8_t af[NRC][4];
+            int16_t ap[NRC][4], an[NRC][4];
+            bool own[NRC];
 #pragma unroll
             for (int s = 0; s < NRC; ++s) {
                 const int t = threadIdx.x + 256 * s;
                 const int li = t / TJ, lj = t % TJ;
-                cst[s][0] = cst[s][1] = cst[s][2] = cst[s][3] = RC_INF;
-                if (li < rows && lj < cols) {
-                    const int i = i0 + li, j = j0 + lj;
-                    long long e;
-                    e = (long long)i * C + j;  // hx(i,j): from above, +1
-                    cst[s][0] = move_cost(J.fx[e], +1, J.cxp[e], J.cxn[e]);
-                    e = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
-                    cst[s][1] = move_cost(J.fx[e], -1, J.cxp[e], J.cxn[e]);
-                    e = (long long)i * J.n + j;  // vy(i,j): from the left, -1
-                    cst[s][2] = move_cost(J.fy[e], -1, J.cyp[e], J.cyn[e]);
-                    e = (long long)i * J.n + j + 1;  // vy(i,j+1): from the right, +1
-                    cst[s][3] = move_cost(J.fy[e], +1, J.cyp[e], J.cyn[e]);
+                own[s] = li < rows && lj < cols;
+                const int i = i0 + (own[s] ? li : 0), j = j0 + (own[s] ? lj : 0);
+                const long long ex0 = (long long)i * C + j;        // hx(i,j): from above, +1
+                const long long ex1 = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
+                const long long ey0 = (long long)i * J.n + j;      // vy(i,j): from the left, -1
+                const long long ey1 = ey0 + 1;                     // vy(i,j+1): from the right, +1
+                af[s][0] = J.fx[ex0]; ap[s][0] = J.cxp[ex0]; an[s][0] = J.cxn[ex0];
+                af[s][1] = J.fx[ex1]; ap[s][1] = J.cxp[ex1]; an[s][1] = J.cxn[ex1];
+                af[s][2] = J.fy[ey0]; ap[s][2] = J.cyp[ey0]; an[s][2] = J.cyn[ey0];
+                af[s][3] = J.fy[ey1]; ap[s][3] = J.cyp[ey1]; an[s][3] = J.cyn[ey1];
+            }
+            // (the empty asm statements use every loaded value here, so that
+            // no load is moved into the conditional code below and waited
+            // for on its own)
+#pragma unroll
+            for (int s = 0; s < NRC; ++s)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    int a = af[s][k], b = ap[s][k], c = an[s][k];
+                    asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+                    af[s][k] = (int8_t)a;
+                    ap[s][k] = (int16_t)b;
+                    an[s][k] = (int16_t)c;
                 }
+            // a node on the image's perimeter reaches the ground across the
+            // same edge its in-arc from outside crosses, in the other
+            // direction: the cheapest such move, from the values just loaded
+#pragma unroll
+            for (int s = 0; s < NRC; ++s) {
+                const int t = threadIdx.x + 256 * s;
+                const int li = t / TJ, lj = t % TJ;
+                const int i = i0 + li, j = j0 + lj;
+                int ga = RC_INF;
+                if (own[s]) {
+                    if (i == 0) ga = min(ga, move_cost(af[s][0], -1, ap[s][0], an[s][0]));
+                    if (i == R - 1) ga = min(ga, move_cost(af[s][1], +1, ap[s][1], an[s][1]));
+                    if (j == 0) ga = min(ga, move_cost(af[s][2], +1, ap[s][2], an[s][2]));
+                    if (j == C - 1) ga = min(ga, move_cost(af[s][3], -1, ap[s][3], an[s][3]));
+                }
+                GA[li][lj] = ga;
+            }
+#pragma unroll
+            for (int s = 0; s < NRC; ++s) {
+                cst[s][0] = own[s] ? move_cost(af[s][0], +1, ap[s][0], an[s][0]) : RC_INF;
+                cst[s][1] = own[s] ? move_cost(af[s][1], -1, ap[s][1], an[s][1]) : RC_INF;
+                cst[s][2] = own[s] ? move_cost(af[s][2], -1, ap[s][2], an[s][2]) : RC_INF;
+                cst[s][3] = own[s] ? move_cost(af[s][3], +1, ap[s][3], an[s][3]) : RC_INF;
             }
 #pragma unroll
             for (int s = 0; s < NSTAGE; ++s) {
                 const int t = threadIdx.x + 256 * s;
                 if (t < (TJ + 2) * (TJ + 2)) {
-                    L[t / (TJ + 2)][t % (TJ + 2)] = lv[s];
-                    P[t / (TJ + 2)][t % (TJ + 2)] = pv[s];
+                    L[t / (TJ + 2)][t % (TJ + 2)] = inside[s] ? lv[s] : (halo[s] ? glab : LINF);
+                    P[t / (TJ + 2)][t % (TJ + 2)] = inside[s] ? pv[s] : (halo[s] ? gpot : 0);
                 }
             }
         }
@@ -756,50 +796,29 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             }
         }
         // candidate labels for the ground from perimeter nodes of this tile
+        // (the cheapest of a corner's two moves gives its smallest candidate)
         unsigned long long gc = LINF;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int li = q * 4 + k;
             if (li >= rows || lj >= cols) continue;
-            const int i = i0 + li, j = j0 + lj;
+            const int c = GA[li][lj];
+            if (c == RC_INF) continue;
             const unsigned long long l = L[li + 1][lj + 1];
             if (l == LINF) continue;
-            const int pv = P[li + 1][lj + 1];
-            for (int side = 0; side < 4; ++side) {
-                long long e;
-                int c;
-                if (side == 0) {
-                    if (i != 0) continue;
-                    e = j;
-                    c = move_cost(J.fx[e], -1, J.cxp[e], J.cxn[e]);
-                } else if (side == 1) {
-                    if (i != R - 1) continue;
-                    e = (long long)R * C + j;
-                    c = move_cost(J.fx[e], +1, J.cxp[e], J.cxn[e]);
-                } else if (side == 2) {
-                    if (j != 0) continue;
-                    e = (long long)i * J.n;
-                    c = move_cost(J.fy[e], +1, J.cyp[e], J.cyn[e]);
-                } else {
-                    if (j != C - 1) continue;
-                    e = (long long)i * J.n + C;
-                    c = move_cost(J.fy[e], -1, J.cyp[e], J.cyn[e]);
-                }
-                if (c == RC_INF) continue;
-                int rc = c - pv + gpot;
-                if (rc < 0) {
-                    atomicOr(&ctl->error, ERR_NEG_RC);
-                    rc = 0;
-                }
-                const unsigned long long nd = (unsigned long long)ldist(l) + (unsigned)rc;
-                if (nd > 0xffffffffull) continue;
-                const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
-                if (cand > lb) {
-                    if (glab == LINF && cand < rej) rej = cand;
-                    continue;
-                }
-                if (cand < gc) gc = cand;
+            int rc = c - P[li + 1][lj + 1] + gpot;
+            if (rc < 0) {
+                atomicOr(&ctl->error, ERR_NEG_RC);
+                rc = 0;
             }
+            const unsigned long long nd = (unsigned long long)ldist(l) + (unsigned)rc;
+            if (nd > 0xffffffffull) continue;
+            const unsigned long long cand = (nd << 32) | ((unsigned long long)(lhops(l) + 1) << 3);
+            if (cand > lb) {
+                if (glab == LINF && cand < rej) rej = cand;
+                continue;
+            }
+            if (cand < gc) gc = cand;
         }
         if (gc != LINF) atomicMin(&sh_gcand, gc);
         if (rej != LINF) atomicMin(&sh_rej, rej & ~7ull);
@@ -826,7 +845,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 pos = __shfl(pos, leader, 64);
                 if (fresh) {
                     const unsigned int rank = (unsigned int)__popcll(fm & ((1ull << lane) - 1ull));
-                    ra.lists[(size_t)(nr % 3) * NT + pos + rank] = entry_of(job, nb);
+                    ra.lists[(size_t)(nr % 3) * list_stride(NT) + pos + rank] = entry_of(job, nb);
                 }
             }
             if (lane == 4) {
@@ -838,7 +857,9 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             if (lane == 5) {
                 int any = 0;
                 unsigned long long *gl = &g.gs[job].glab;
-                if (sh_gcand != LINF && sh_gcand < *gl) {
+                // the label read at the visit's start is an upper bound of
+                // the current one: no second read before the atomic
+                if (sh_gcand != LINF && sh_gcand < glab) {
                     unsigned long long old = atomicMin(gl, sh_gcand);
                     if (sh_gcand < old) any = 1;
                 }
@@ -1355,16 +1376,20 @@ __global__ void k_check_rc(Graph g, const unsigned long long *lab_before, CheckR
 // rounds: the list of the next round rr holds count <= NT entries, every
 // entry names a tile below NT whose round stamp is rr, and exactly count
 // tiles carry that stamp (so no tile is listed twice).  bad[0]: an entry out
-// of range; bad[1]: an entry without the stamp; bad[2]: tiles with the stamp.
+// of range; bad[1]: an entry without the stamp; bad[2]: tiles with the
+// stamp; bad[3]: entries read.
 template <bool MULTI>
 __global__ void k_check_lists(Graph g, const Ctl *ctl, const unsigned int *act,
                               const unsigned int *lists, unsigned int NT, unsigned int rr,
                               unsigned int *bad) {
     const unsigned int cnt = ctl->count[rr % 3][0];
-    const unsigned int *list = lists + (size_t)(rr % 3) * NT;
-    const unsigned int lim = cnt < NT ? cnt : NT;
-    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < NT; k += gridDim.x * blockDim.x) {
+    const size_t ls = list_stride(NT);
+    const unsigned int *list = lists + (size_t)(rr % 3) * ls;
+    const unsigned int lim = cnt < ls ? cnt : (unsigned int)ls;
+    for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < (unsigned int)ls;
+         k += gridDim.x * blockDim.x) {
         if (k < lim) {
+            atomicAdd(&bad[3], 1u);
             const unsigned int e = list[k];
             const unsigned int job = e >> 24, lt = e & 0xffffffu;
             if ((int)job >= g.njobs) {
@@ -1375,7 +1400,7 @@ __global__ void k_check_lists(Graph g, const Ctl *ctl, const unsigned int *act,
                 else if (act[J.toff + lt] != rr) atomicOr(&bad[1], 1u);
             }
         }
-        if (act[k] == rr) atomicAdd(&bad[2], 1u);
+        if (k < NT && act[k] == rr) atomicAdd(&bad[2], 1u);
     }
 }
 
@@ -1632,20 +1657,22 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     WW_TRY(scratch(SLOT_MCF_POT, sizeof(int) * N, (void **)&g.pot));
     WW_TRY(scratch(SLOT_MCF_EX, N, (void **)&g.ex));
     // per-tile state: act, pstamp, tstamp (NT each, cleared per call),
-    // lists (3 NT), perim_tiles (NT), tile_rej (NT x 8 B), vpart (64 x 16 x 8 B)
+    // lists (3 x list_stride(NT)), perim_tiles (NT), tile_rej (NT x 8 B,
+    // 8-byte aligned), vpart (64 x 16 x 8 B)
     unsigned int *tiles = nullptr;
-    const size_t tiles_words = 8 * (size_t)NT + 2;
-    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * (tiles_words + 2 * (size_t)NT) + 8192 + 256,
-                   (void **)&tiles));
+    const size_t lists_end = 3 * (size_t)NT + 3 * list_stride(NT);  // perim_tiles start
+    const size_t rej_at = lists_end + (size_t)NT + ((lists_end + (size_t)NT) & 1);  // 8-byte aligned
+    const size_t tiles_words = rej_at + 2 * (size_t)NT;
+    WW_TRY(scratch(SLOT_MCF_TILES, sizeof(unsigned int) * tiles_words + 8192 + 256, (void **)&tiles));
     RoundArgs ra;
     ra.NT = NT;
     ra.act = tiles;
     ra.pstamp = tiles + (size_t)NT;
     ra.tstamp = tiles + 2 * (size_t)NT;
     ra.lists = tiles + 3 * (size_t)NT;
-    ra.perim_tiles = tiles + 6 * (size_t)NT;
-    ra.tile_rej = (unsigned long long *)(tiles + 7 * (size_t)NT + ((7 * (size_t)NT) & 1));
-    ra.vpart = (unsigned long long *)(tiles + tiles_words + 2 * (size_t)NT);
+    ra.perim_tiles = tiles + lists_end;
+    ra.tile_rej = (unsigned long long *)(tiles + rej_at);
+    ra.vpart = (unsigned long long *)(tiles + tiles_words + ((tiles_words) & 1));
     char *nodes = nullptr;
     const size_t nl_bytes = sizeof(unsigned int) * (size_t)N;
     const size_t gs_bytes = sizeof(unsigned int) * (size_t)nslots + 256;
@@ -1871,21 +1898,22 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
                 WW_TRY(sync_ctl());
                 if (check) {
                     for (int q = 0; q < 3; ++q)
-                        if (h->count[q][0] > NT)
-                            return fail(WW_E_DEVICE, "min-cost flow check: list %d holds %u > %u tiles", q,
-                                        h->count[q][0], NT);
+                        if (h->count[q][0] > list_stride(NT))
+                            return fail(WW_E_DEVICE, "min-cost flow check: list %d holds %u > %zu slots", q,
+                                        h->count[q][0], list_stride(NT));
                     unsigned int hb[4] = {0u, 0u, 0u, 0u};
                     WW_HIP(hipMemsetAsync(cb.bad, 0, sizeof(hb), st));
-                    hipLaunchKernelGGL(k_check_lists<MULTI>, dim3(std::min<unsigned int>(1024u, (NT + 255) / 256)),
+                    hipLaunchKernelGGL(k_check_lists<MULTI>,
+                                       dim3((unsigned)std::min<size_t>(1024u, (list_stride(NT) + 255) / 256)),
                                        dim3(256), 0, st, g, ctl, ra.act, ra.lists, NT, rr, cb.bad);
                     WW_LAUNCH_CHECK();
                     WW_HIP(hipMemcpyAsync(hb, cb.bad, sizeof(hb), hipMemcpyDeviceToHost, st));
                     WW_HIP(hipStreamSynchronize(st));
-                    if (hb[0] || hb[1] || hb[2] != h->count[rr % 3][0])
+                    if (hb[0] || hb[1] || hb[2] != h->count[rr % 3][0] || hb[3] != h->count[rr % 3][0])
                         return fail(WW_E_DEVICE,
                                     "min-cost flow check: round %u list: out of range %u, unstamped %u, "
-                                    "stamped %u, count %u",
-                                    rr, hb[0], hb[1], hb[2], h->count[rr % 3][0]);
+                                    "stamped %u, read %u, count %u",
+                                    rr, hb[0], hb[1], hb[2], hb[3], h->count[rr % 3][0]);
                 }
                 float ms = 0.f;
                 WW_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));

@@ -29,7 +29,11 @@ Workloads (sizes, phase fields, coherence fields, masks and seeds):
     [512, 4096], c0 recipe with bump peak U[5, 80] rad, L in {5, 9, 15},
     seed 1000 + k.
   * ``serve``  request pool, rows/cols log-uniform in [256, 8192], c1 recipe,
-    seed 2000 + k.
+    seed 2000 + k.  :func:`serve_request_device` draws the same recipe with
+    torch's generator on a GPU (a pool of hundreds of requests up to 67
+    Mpixel each is far too slow to simulate on the host); its numbers differ
+    from :func:`serve_request`'s, and a check against the oracle copies them
+    back to the host.
 
   * ``river`` masks (bridging inputs, :func:`river_mask`): a meandering
     river of width w (centre column n/2 + (n/8) sin(2 pi i / (m/2))) cuts the
@@ -49,7 +53,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Scene", "make", "config", "stack_job", "serve_request", "CONFIGS"]
+__all__ = ["Scene", "make", "config", "stack_job", "serve_request", "serve_request_device",
+           "make_device", "CONFIGS"]
 
 ROW_BLOCK = 64
 
@@ -310,3 +315,91 @@ def serve_request(k: int, workers=None) -> Scene:
     n = _logu(rng, 256, 8192)
     return make(m, n, looks=9, seed=2000 + k, disks=6, mask_frac=0.05,
                 name=f"req{k}", keep_truth=False, workers=workers)
+
+
+# ----------------------------------------------------------------------------
+# the same recipes drawn on a GPU (torch), for large request pools
+# ----------------------------------------------------------------------------
+
+def _blur_axis(u, sigma, axis):
+    """Gaussian filter (truncated at 4 sigma, half-sample symmetric borders
+    like scipy's "reflect") along one axis of a 2-D float tensor."""
+    import torch
+    r = int(4.0 * sigma + 0.5)
+    size = u.shape[axis]
+    r = max(1, min(r, size))
+    x = torch.arange(-r, r + 1, dtype=torch.float64)
+    w = torch.exp(-x * x / (2.0 * sigma * sigma))
+    w = (w / w.sum()).tolist()
+    lo = u.narrow(axis, 0, r).flip(axis)
+    hi = u.narrow(axis, size - r, r).flip(axis)
+    pad = torch.cat([lo, u, hi], dim=axis)
+    out = torch.zeros_like(u)
+    for t in range(2 * r + 1):
+        out += w[t] * pad.narrow(axis, t, size)
+    return out
+
+
+def make_device(m, n, *, looks=9, seed=0, ramp=0.3, peak=40.0, bump_sigma=30.0,
+                coh_lo=0.2, coh_hi=0.95, coh_sigma=16.0, disks=0, disk_coh=(0.05, 0.15),
+                disk_radius=(40, 150), mask_frac=0.0, device="cuda", rows_per_draw=256):
+    """The c0/c1 recipe of :func:`make` drawn on ``device`` with a seeded
+    torch generator (float64 arithmetic, float32 outputs): returns device
+    tensors (psi, coh, valid).  The disks and the nodata rectangles come
+    from numpy generators seeded as in :func:`make`; the smooth coherence
+    field and the looks from torch's."""
+    import torch
+    ss = np.random.SeedSequence(seed)
+    s_field, s_disk, s_mask, s_looks = ss.spawn(4)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(s_field.generate_state(1)[0]))
+    ii = torch.arange(m, dtype=torch.float64, device=device)[:, None]
+    jj = torch.arange(n, dtype=torch.float64, device=device)[None, :]
+    ci, cj = m / 2.0, n / 2.0
+    phi = ramp * jj + peak * torch.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2 * bump_sigma ** 2))
+    sig = min(coh_sigma, max(1.0, min(m, n) / 4))
+    u = torch.rand((m, n), generator=gen, dtype=torch.float32, device=device)
+    f = _blur_axis(_blur_axis(u, sig, 1), sig, 0)
+    del u
+    f = (f - f.min()) / torch.clamp(f.max() - f.min(), min=1e-30)
+    gam = (coh_lo + (coh_hi - coh_lo) * f).to(torch.float64)
+    del f
+    if disks:
+        rng = np.random.default_rng(s_disk)
+        for _ in range(disks):
+            r = rng.uniform(*disk_radius)
+            di = rng.uniform(0, m)
+            dj = rng.uniform(0, n)
+            g = rng.uniform(*disk_coh)
+            gam[(ii - di) ** 2 + (jj - dj) ** 2 <= r * r] = g
+    valid = torch.from_numpy(rect_mask(m, n, mask_frac, np.random.default_rng(s_mask))).to(device)
+    gen.manual_seed(int(s_looks.generate_state(1)[0]))
+    psi = torch.empty((m, n), dtype=torch.float32, device=device)
+    coh = torch.empty((m, n), dtype=torch.float32, device=device)
+    s2 = math.sqrt(0.5)
+    for r0 in range(0, m, rows_per_draw):
+        r1 = min(m, r0 + rows_per_draw)
+        # a_k, b_k ~ CN(0, 1); z1 = a, z2 = (g a + sqrt(1 - g^2) b) e^{-i phi}
+        ar, ai, br, bi = torch.randn((4, looks, r1 - r0, n), generator=gen, dtype=torch.float64,
+                                     device=device).mul_(s2).unbind(0)
+        g = gam[r0:r1][None]
+        h = torch.sqrt(1.0 - g * g)
+        xr, xi = g * ar + h * br, g * ai + h * bi
+        c, s_ = torch.cos(phi[r0:r1])[None], torch.sin(phi[r0:r1])[None]
+        zr, zi = xr * c + xi * s_, xi * c - xr * s_
+        Sr = (ar * zr + ai * zi).sum(0)
+        Si = (ai * zr - ar * zi).sum(0)
+        p1 = (ar * ar + ai * ai).sum(0)
+        p2 = (zr * zr + zi * zi).sum(0)
+        psi[r0:r1] = torch.atan2(Si, Sr).to(torch.float32)
+        coh[r0:r1] = (torch.sqrt(Sr * Sr + Si * Si) / torch.sqrt(p1 * p2)).to(torch.float32)
+    return psi, coh, valid
+
+
+def serve_request_device(k: int, device="cuda"):
+    """Request k of the serving pool, drawn on ``device`` (c1 recipe at the
+    size :func:`serve_request` gives it): (psi, coh, valid) device tensors."""
+    rng = np.random.default_rng(2000 + k)
+    m = _logu(rng, 256, 8192)
+    n = _logu(rng, 256, 8192)
+    return make_device(m, n, looks=9, seed=2000 + k, disks=6, mask_frac=0.05, device=device)
