@@ -35,9 +35,12 @@
 //     atomic add.  Tiles relaxed in a pass, and tiles holding candidates
 //     beyond the current window, are marked with plain-store pass stamps.
 //  2. Every reached deficit walks its predecessor chain to its tree root;
-//     each root keeps its nearest deficit (64-bit atomicMin on dist|node).
+//     each root keeps its nearest deficit (64-bit atomicMin on dist|node),
+//     and every node on the way keeps the smallest such key through it.
 //  3. One unit is augmented along each root's chosen path.  Different trees
-//     are vertex-disjoint, so all paths are applied in parallel.  Trees that
+//     are vertex-disjoint, so all paths are applied in parallel: a path
+//     node's arc flips when its kept key names a chosen deficit (the key
+//     through a node of the chosen path is the root's own).  Trees that
 //     hang off a ground as a supply are split at the ground's arcs and at
 //     most its excess of them augment.
 //  4. pot(v) += B - d(v) for every reached node.  Every tree arc is then
@@ -96,7 +99,9 @@ struct GState {
     unsigned int gpred;        // predecessor (perimeter arc index)
     unsigned int gsub_count;   // ground-rooted subtrees with a deficit
     long long total_cost;      // the job's flow cost at the end of the solve
-    long long pad[3];
+    unsigned int gchosen;      // pass in which a path into the ground was chosen
+    unsigned int gpad;
+    long long pad[2];
 };
 static_assert(sizeof(GState) == 64, "one 64-byte record per ground");
 
@@ -273,7 +278,8 @@ __device__ __forceinline__ bool load_res16(const int8_t *res, long long v0, long
 
 // Node state of a block's chunk of INIT_CHUNK nodes, each thread taking
 // INIT_PER consecutive nodes: the excess is a copy of the residues, the
-// potentials zero, the labels infinite, all in 16-byte stores.
+// potentials zero, the labels and path tags infinite, all in 16-byte
+// stores.
 __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const int8_t *__restrict__ res,
                                                                 int *__restrict__ bc,
                                                                 unsigned int *__restrict__ flip) {
@@ -291,11 +297,6 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
         nn += r[q] < 0;
         sum += r[q];
         w[q >> 2] |= (unsigned int)(uint8_t)r[q] << (8 * (q & 3));
-        // best (a root's chosen deficit) is only kept at roots: supplies,
-        // which are residues in one frame or the other, and perimeter nodes
-        // (ground-rooted subtrees, set by k_init_ground); other nodes'
-        // entries are never read
-        if (r[q] != 0) g.best[v0 + q] = LINF;
     }
     if (whole) {
         *reinterpret_cast<uint4 *>(g.ex + v0) = make_uint4(w[0], w[1], w[2], w[3]);
@@ -307,6 +308,7 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
         uint4 *pot = reinterpret_cast<uint4 *>(g.pot + c0);
         uint4 *fl = reinterpret_cast<uint4 *>(flip + c0);
         uint4 *lab = reinterpret_cast<uint4 *>(g.lab + c0);
+        uint4 *best = reinterpret_cast<uint4 *>(g.best + c0);
         const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
         const uint4 inf = make_uint4((unsigned int)LINF, (unsigned int)(LINF >> 32), (unsigned int)LINF,
                                      (unsigned int)(LINF >> 32));
@@ -316,12 +318,16 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
             fl[k * INIT_THREADS + threadIdx.x] = zero;
         }
 #pragma unroll
-        for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) lab[k * INIT_THREADS + threadIdx.x] = inf;
+        for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) {
+            lab[k * INIT_THREADS + threadIdx.x] = inf;
+            best[k * INIT_THREADS + threadIdx.x] = inf;
+        }
     } else {
         for (long long v = c0 + threadIdx.x; v < N; v += INIT_THREADS) {
             g.pot[v] = 0;
             flip[v] = 0;
             g.lab[v] = LINF;
+            g.best[v] = LINF;
         }
     }
     np = block_sum_int(np, red);
@@ -1004,12 +1010,22 @@ __device__ __forceinline__ long long pred_node(const Job &J, int i, int j, int d
 
 // Walk from v to its root within job J.  Returns the root node; *gsub = 1
 // when the root is a child of the job's ground acting as a supply.
+// Walks from v along the predecessor arcs to the tree's root and returns it
+// (-1 on a broken walk).  Every node before the root gets the walk's key as
+// a candidate path tag (best[u] = the smallest key of the walks through u)
+// and the pass's stamp in its tag byte; *crossed is set when the walk
+// passes through the ground.
 __device__ long long walk_root(const Graph &g, const Job &J, const GState &G, Ctl *ctl, long long v,
-                               int gsrc, int *gsub) {
+                               int gsrc, int *gsub, unsigned long long key, int *crossed,
+                               uint8_t *tag, uint8_t stamp) {
     *gsub = 0;
+    *crossed = 0;
     const long long Nk = (long long)J.R * J.C;
+    unsigned long long l = g.lab[v];
+    // the first label is waited for here, so that the loop's head waits for
+    // nothing (the latch waits for the next label alone)
+    asm volatile("" ::"v"(l));
     for (long long steps = 0; steps <= Nk + 2; ++steps) {
-        const unsigned long long l = g.lab[v];
         const int dir = (int)(l & 7);
         if (dir == DIR_NONE) return v;
         int i, j;
@@ -1026,16 +1042,28 @@ __device__ long long walk_root(const Graph &g, const Job &J, const GState &G, Ct
             long long e;
             ground_arc(J, a, pi, pj, kind, e, delta);
             u = J.noff + (long long)pi * J.C + pj;
+            *crossed = 1;
         }
+        // the next label is requested before the tag is offered, so that
+        // the walk waits for the load alone, not for the atomic behind it
+        const unsigned long long ln = g.lab[u];
+        atomicMin(&g.best[v], key);
+        tag[v] = stamp;
         v = u;
+        l = ln;
     }
     atomicOr(&ctl->error, ERR_WALK);
     return -1;
 }
 
+// Every settled deficit (and every job's ground as a settled demand) walks
+// to its tree's root and offers its key (distance, deficit) there; the
+// walks also tag their nodes (walk_root).  A deficit's own flip word
+// records the pass, and whether its walk crossed the ground (bit 2).
 template <bool MULTI>
 __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb,
-                        unsigned int *gsub_list) {
+                        unsigned int *gsub_list, unsigned int *flip, uint8_t *tag,
+                        unsigned int pass) {
     const unsigned int nd = ctl->ndef;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd + (unsigned)g.njobs;
          k += gridDim.x * blockDim.x) {
@@ -1068,9 +1096,12 @@ __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned lon
         }
         const Job J = job_at<MULTI>(g, job);
         GState &G = g.gs[job];
-        int gsub = 0;
-        const long long root = walk_root(g, J, G, ctl, start, G.gex > 0, &gsub);
+        int gsub = 0, crossed = 0;
+        const long long root =
+            walk_root(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass);
+        if (k < nd) flip[start] = (pass << 3) | (crossed ? 4u : 0u);
         if (root < 0) continue;
+        tag[root] = (uint8_t)pass;
         const unsigned long long old = atomicMin(&g.best[root], key);
         if (gsub && old == LINF) gsub_list[J.aoff + atomicAdd(&G.gsub_count, 1u)] = (unsigned int)root;
     }
@@ -1118,15 +1149,16 @@ __device__ __forceinline__ void flip_ground_arc(const Job &J, unsigned int a) {
     else J.fy[e] += (int8_t)delta;
 }
 
-// Apply one unit along root r's chosen path: from the deficit back to r.
-// The in-grid arcs of a path are not flipped here: the walk stores
-// (pass, direction) at the node each arc enters, and k_potentials, which
-// visits every node of the tiles relaxed in the pass (path nodes are
-// settled, so their tiles were relaxed), applies the flip.  A step of the
-// walk is then one dependent label load and one store.  Paths from
-// different roots are vertex-disjoint, so a node holds one arc per pass;
-// no kernel reads the flows between the two.  Work items: the supplies,
-// then every job's ground-subtree slots (nslots in all).
+// Choose the paths that augment: every root takes the deficit with its
+// smallest key (distance, deficit id), the flip word of that deficit gets
+// bit 0 (a ground demand: its gchosen field the pass), and the excesses
+// move by one unit.  The arcs of a chosen path are not walked here: the
+// walks of k_roots tagged each path node with the smallest key through it,
+// which on the chosen path is the root's own key (every walk through a
+// node ends at the same root), so k_potentials, which visits every settled
+// node, flips the arc into each node whose tag names a chosen deficit.
+// Only the arcs into and through the ground are flipped here.  Work items:
+// the supplies, then every job's ground-subtree slots (nslots in all).
 template <bool MULTI>
 __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsigned int *gsub_list,
                           const unsigned char *drop, unsigned int *flip, unsigned int pass,
@@ -1147,74 +1179,46 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
             r = src[k];
             job = MULTI ? job_of_node(g, r) : 0;
         }
-        const unsigned long long b = g.best[r];
+        const unsigned long long b = g.best[r];  // reset by k_potentials
         if (b == LINF) continue;
-        g.best[r] = LINF;
         if (is_g && drop[k - ns]) continue;
         const Job J = job_at<MULTI>(g, job);
         GState &G = g.gs[job];
         const long long t = (long long)(b & 0xffffffffull);
         const bool into_ground = t >= g.N;
-        long long v;
         unsigned long long flips = 0;
-        // A path through the ground needs the ground's predecessor arc, which
-        // exists whenever the ground is settled, and only then can a path
-        // cross it (labels grow along paths).  Its absence is checked where
-        // the arc is used: the walk stops with ERR_WALK, which fails the
-        // solve, before any index is formed from it.
         const unsigned int na = 2u * J.C + 2u * J.R;
-        if (into_ground) {  // into the ground through its predecessor arc
+        bool through_ground = into_ground;
+        if (into_ground) {
+            G.gchosen = pass;
+        } else {
+            const unsigned int f = flip[t];
+            flip[t] = f | 1u;
+            through_ground = (f & 4u) != 0;
+        }
+        // a path into or through the ground uses the ground's predecessor
+        // arc, which exists whenever the ground is settled; its absence
+        // fails the solve
+        if (through_ground) {
             const unsigned int a = G.gpred;
             if (a >= na) {
                 atomicOr(&ctl->error, ERR_WALK);
                 continue;
             }
             flip_ground_arc(J, a);
-            int pi, pj, kind, delta;
-            long long e;
-            ground_arc(J, a, pi, pj, kind, e, delta);
-            v = J.noff + (long long)pi * J.C + pj;
             ++flips;
-        } else {
-            v = t;
-        }
-        const long long Nk = (long long)J.R * J.C;
-        unsigned long long l = g.lab[v];
-        for (long long steps = 0; steps <= Nk + 2; ++steps) {
-            const int dir = (int)(l & 7);
-            if (dir == DIR_NONE) break;  // reached the supply r
-            int i, j;
-            node_rc(J, v, i, j);
-            long long u = pred_node(J, i, j, dir);
-            flip[v] = (pass << 3) | (unsigned int)dir;
-            ++flips;
-            if (u < 0) {
-                if (is_g) break;  // the ground is the supply
-                const unsigned int a = G.gpred;
-                if (a >= na) {
-                    atomicOr(&ctl->error, ERR_WALK);
-                    break;
-                }
-                flip_ground_arc(J, a);
-                ++flips;
-                int pi, pj, kind, delta;
-                long long e;
-                ground_arc(J, a, pi, pj, kind, e, delta);
-                u = J.noff + (long long)pi * J.C + pj;
-            }
-            l = g.lab[u];
-            v = u;
         }
         if (is_g) atomicAdd((unsigned long long *)&G.gex, (unsigned long long)-1ll);
         else g.ex[r] -= 1;
         if (into_ground) atomicAdd((unsigned long long *)&G.gex, 1ull);
         else g.ex[t] += 1;
         atomicAdd(&ctl->naug, 1u);
-        atomicAdd(&ctl->arcs, flips);
+        if (flips) atomicAdd(&ctl->arcs, flips);
     }
 }
 
-// pot(v) += B - d(v) on every reached node, labels back to infinity.  Each
+// pot(v) += B - d(v) on every reached node, labels and path tags back to
+// infinity, and the arc into every node of a chosen path flipped.  Each
 // workgroup checks the stamps of POT_CHUNK tiles at once and then updates
 // only the tiles relaxed in this pass, so that a pass that reached a few
 // tiles costs little more than one read of the stamps.  The relaxed tiles
@@ -1228,12 +1232,12 @@ template <bool MULTI>
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
                                                     unsigned int pass, unsigned int NT,
                                                     unsigned long long lb, const unsigned int *flip,
-                                                    int count) {
+                                                    const uint8_t *tag, int count) {
     __shared__ unsigned int todo[POT_CHUNK];
     __shared__ int ntodo;
     const unsigned int bound = ldist(lb);
     int mx = 0;
-    unsigned long long n_set = 0, n_arc = 0;
+    unsigned long long n_set = 0, n_arc = 0, n_flip = 0;
     for (unsigned int base = blockIdx.x * POT_CHUNK; base < NT; base += gridDim.x * POT_CHUNK) {
         if (threadIdx.x == 0) ntodo = 0;
         __syncthreads();
@@ -1251,20 +1255,34 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
             const int i0 = (int)(lt / J.TC) * TJ, j0 = (int)(lt % J.TC) * TJ;
             long long v[TJ * TJ / 256];
             unsigned long long l[TJ * TJ / 256];
-            unsigned int fr[TJ * TJ / 256];
+            uint8_t tb[TJ * TJ / 256];
 #pragma unroll
             for (int s = 0; s < TJ * TJ / 256; ++s) {
                 const int t = threadIdx.x + 256 * s;
                 const int i = i0 + t / TJ, j = j0 + t % TJ;
                 v[s] = (i < J.R && j < J.C) ? J.noff + (long long)i * J.C + j : -1;
                 l[s] = v[s] >= 0 ? g.lab[v[s]] : LINF;
-                fr[s] = v[s] >= 0 ? flip[v[s]] : 0u;
+                tb[s] = v[s] >= 0 ? tag[v[s]] : (uint8_t)0;
             }
 #pragma unroll
             for (int s = 0; s < TJ * TJ / 256; ++s) {
                 if (l[s] == LINF) continue;
-                // the arc into this node on a path augmented in this pass
-                if ((fr[s] >> 3) == pass) flip_into(J, v[s], (int)(fr[s] & 7u));
+                // a walk of this pass passed here (a stale byte of a pass 256
+                // earlier finds the key cleared: no effect)
+                const unsigned long long tgk = tb[s] == (uint8_t)pass ? g.best[v[s]] : LINF;
+                if (tgk != LINF) {
+                    // a path node (only settled nodes are tagged): the arc
+                    // into it flips when its key names a chosen deficit
+                    g.best[v[s]] = LINF;
+                    const int dir = (int)(l[s] & 7u);
+                    const long long t = (long long)(tgk & 0xffffffffull);
+                    const bool chosen = t < g.N ? flip[t] == ((pass << 3) | 1u) || flip[t] == ((pass << 3) | 5u)
+                                                : g.gs[t - g.N].gchosen == pass;
+                    if (dir != DIR_NONE && chosen) {
+                        flip_into(J, v[s], dir);
+                        ++n_flip;
+                    }
+                }
                 g.lab[v[s]] = LINF;
                 if (l[s] > lb) continue;
                 if (count) {
@@ -1295,6 +1313,8 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
     // atomics on one address from every wave cost more than the updates
     if ((threadIdx.x & 63) == 0 && mx > 0 && mx > *(volatile int *)&ctl->max_pot)
         atomicMax(&ctl->max_pot, mx);
+    for (int off = 32; off > 0; off >>= 1) n_flip += __shfl_down(n_flip, off, 64);
+    if ((threadIdx.x & 63) == 0 && n_flip) atomicAdd(&ctl->arcs, n_flip);
     if (count) {
         for (int off = 32; off > 0; off >>= 1) {
             n_set += __shfl_down(n_set, off, 64);
@@ -1720,8 +1740,11 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     const int nib = ceil_div(N, INIT_CHUNK);
     int *bc = nullptr;
     WW_TRY(scratch(SLOT_MCF_PART, sizeof(long long) * (size_t)std::max(3 * nib, 8192) + 256, (void **)&bc));
-    unsigned int *flip = nullptr;  // deferred path flips: (pass, direction) per node
-    WW_TRY(scratch(SLOT_MCF_FLIP, sizeof(unsigned int) * (size_t)N, (void **)&flip));
+    // per node: the flip word of a deficit ((pass << 3) | crossed the ground
+    // << 2 | chosen), and one byte with the pass of the last walk through it
+    unsigned int *flip = nullptr;
+    WW_TRY(scratch(SLOT_MCF_FLIP, (sizeof(unsigned int) + 1) * (size_t)N + 256, (void **)&flip));
+    uint8_t *tag = reinterpret_cast<uint8_t *>(flip + N);
     hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc, flip);
     WW_LAUNCH_CHECK();
     const int gx = MULTI ? (int)std::min<long long>(64, std::max<long long>(1, ceil_div(N / nj, 4096)))
@@ -1987,7 +2010,8 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             hipLaunchKernelGGL(k_ground_pred, dim3(pg, nj), dim3(SB), 0, st, g, lb);
             WW_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list);
+        hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list,
+                           flip, tag, pass);
         WW_LAUNCH_CHECK();
         if (ground_source) {
             hipLaunchKernelGGL(k_gsub_select, dim3(pg, nj), dim3(SB), 0, st, g, gsub_list, drop);
@@ -1999,7 +2023,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         if (check)
             WW_HIP(hipMemcpyAsync(cb.lab, g.lab, sizeof(unsigned long long) * N, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_potentials<MULTI>, dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass, NT,
-                           lb, flip, count);
+                           lb, flip, tag, count);
         WW_LAUNCH_CHECK();
         if (check) {
             WW_HIP(hipMemsetAsync(cb.rec, 0, sizeof(CheckRec), st));
