@@ -128,31 +128,29 @@ def cpu_baseline(sc, rows):
             "host": _cpu_model()}
 
 
-def cpu_baseline_configs(synth, stack_jobs=0):
+def cpu_baseline_configs(scenes, stack=None):
     """The oracle (single thread, cost table built beforehand) on the
-    smaller workloads in full: c0 and c1, and on request every stack job one
-    after another."""
+    smaller workloads in full: c0 and c1 (`scenes`, generated before the GPU
+    was initialised), and on request every stack job one after another."""
     import oracle
     out = {}
     luts = {}
-    for name in ("c0", "c1"):
-        sc = synth.config(name)
+    for name, sc in scenes.items():
         lut = luts.setdefault(sc.looks, oracle.build_lut(sc.looks))
         t0 = time.perf_counter()
         cost = oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, lut=lut)[2]
         dt = time.perf_counter() - t0
         out[name] = {"mpix_s": round(sc.psi.size / 1e6 / dt, 4), "seconds": round(dt, 2),
                      "pixels": int(sc.psi.size), "cost": int(cost)}
-    if stack_jobs:
+    if stack:
         px, dt, costs = 0, 0.0, []
-        for k in range(stack_jobs):
-            sc = synth.stack_job(k)
+        for sc in stack:
             lut = luts.setdefault(sc.looks, oracle.build_lut(sc.looks))
             t0 = time.perf_counter()
             costs.append(int(oracle.unwrap(sc.psi, sc.coh, sc.valid, sc.looks, lut=lut)[2]))
             dt += time.perf_counter() - t0
             px += sc.psi.size
-        out["stack"] = {"jobs": stack_jobs, "mpix_s": round(px / 1e6 / dt, 4), "seconds": round(dt, 1),
+        out["stack"] = {"jobs": len(stack), "mpix_s": round(px / 1e6 / dt, 4), "seconds": round(dt, 1),
                         "pixels": int(px), "total_cost_sum": int(sum(costs))}
     return out
 
@@ -611,6 +609,9 @@ def main():
     if not args.no_tune and args.schedule is None and args.workload == "c2":
         sib = synth.make_fault(m // 2, n // 2, looks=sc.looks, seed=3, mask_frac=0.03)
     stack = stack_scenes(args, synth) if args.stack_jobs > 0 else None
+    # the oracle's smaller workloads, also generated before the GPU is used
+    # (the generator forks worker processes)
+    cpu_scenes = {} if args.no_cpu_baseline else {name: synth.config(name) for name in ("c0", "c1")}
     print(f"# generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     assert torch.cuda.is_available(), "no GPU visible"
     psi = torch.from_numpy(sc.psi).cuda()
@@ -748,7 +749,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, min(args.cpu_rows, m))
         out["cpu_baseline"]["configs"] = cpu_baseline_configs(
-            synth, args.stack_jobs if args.cpu_baseline_stack else 0)
+            cpu_scenes, stack[0] if (args.cpu_baseline_stack and stack) else None)
         st_o = out["cpu_baseline"]["configs"].get("stack")
         if st_o and "stack" in out:
             st_o["equals_gpu_sum"] = st_o["total_cost_sum"] == out["stack"]["total_cost_sum"]
