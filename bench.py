@@ -45,7 +45,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
 TRAFFIC_SOURCE_SHA = "64ffedb398f12658"
-TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 8)
+TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 8, 32)
 TRAFFIC_BYTES_PER_LAUNCH = 15.00e6
 
 
@@ -77,7 +77,7 @@ def parse():
                     help="also time the oracle on all 64 stack jobs, one after another (minutes)")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the components, Goldstein and bridging legs (for counter runs)")
-    ap.add_argument("--schedule", default=None, metavar="H0,DSTEP[,FULL,FIRSTDEF,REVERSE[,GROWTH]]",
+    ap.add_argument("--schedule", default=None, metavar="H0,DSTEP[,FULL,FIRSTDEF,REVERSE[,GROWTH[,TILECOLS]]]",
                     help="solve schedule to time (skips tuning), e.g. 64,256,2,0,0")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the library's default solve schedule instead of tuning it on a "
@@ -166,7 +166,8 @@ def _sched_dict(sched):
     from paper_2609_36267_amd import autotune
     full = autotune.pad(sched)
     return {"first_hop_window": full[0], "first_distance_step": full[1], "full_passes": full[2],
-            "first_deficit_after": full[3], "reverse_below": full[4], "hop_growth": full[5]}
+            "first_deficit_after": full[3], "reverse_below": full[4], "hop_growth": full[5],
+            "tile_cols": full[6]}
 
 
 def stack_scenes(args, synth):

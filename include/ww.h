@@ -137,6 +137,10 @@ typedef struct {
  *   hop_growth           factor by which the hop limit of each later
  *                        zero-distance window grows (2 .. 2^20; the limit is
  *                        at least the hops of the smallest parked candidate)
+ *   tile_cols            columns of the loop tiles the relaxation rounds
+ *                        work on (16, 32 or 64; a tile holds 1024 loops, so
+ *                        64, 32 or 16 rows): the shape of the frontier's
+ *                        granule, a speed knob like the windows
  * Process-wide; applies to solves that start after the call. */
 typedef struct {
     int32_t first_hop_window;
@@ -145,10 +149,11 @@ typedef struct {
     int32_t first_deficit_after;
     int32_t reverse_below;
     int32_t hop_growth;
+    int32_t tile_cols;
 } ww_mcf_params;
 
 /* Defaults: first_hop_window 64, first_distance_step 256, full_passes 0,
- * first_deficit_after 0, reverse_below 0, hop_growth 2. */
+ * first_deficit_after 0, reverse_below 0, hop_growth 2, tile_cols 32. */
 void ww_default_mcf_params(ww_mcf_params *p);
 /* Errors: WW_E_INVALID_ARG (NULL or out of range). */
 ww_status ww_set_mcf_params(const ww_mcf_params *p);

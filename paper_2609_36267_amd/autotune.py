@@ -10,7 +10,9 @@ few passes that settle every deficit first pay off where most residues pair
 up over short distances (the fault scene) but not where low-coherence
 patches hold long paths, and searching from the demands once few units are
 left avoids the plateaus that the earlier passes made tight around the
-supplies. tune_schedule() times candidate schedules on sample jobs of a
+supplies. The tile shape (16, 32 or 64 columns of 1024 loops) changes how
+far labels travel inside one visit, vertically or horizontally, and how many
+tiles a frontier lists, never the labels. tune_schedule() times candidate schedules on sample jobs of a
 workload through the C ABI and installs the fastest process-wide (ties keep
 the earlier candidate, the default first).
 """
@@ -21,7 +23,8 @@ import time
 from . import binding as ww
 
 # (first_hop_window, first_distance_step[, full_passes, first_deficit_after
-# [, reverse_below[, hop_growth]]]), missing fields 0 (hop_growth 2);
+# [, reverse_below[, hop_growth[, tile_cols]]]]), missing fields 0
+# (hop_growth 2, tile_cols 32);
 # PAPER_SCHEDULE is the paper's pass schedule (Section II-C: eight full
 # multi-source passes, then searches that stop at the first deficit)
 PAPER_SCHEDULE = (64, 256, 8, 1)
@@ -31,10 +34,14 @@ CANDIDATES = [(64, 256), (16, 256), (512, 256), (64, 64), (16, 64), (512, 64), (
               (64, 256, 8, 0, 1024), (512, 64, 0, 0, 1024),
               (64, 256, 0, 0, 1024, 8), (64, 256, 4, 0, 1024, 4), (64, 256, 4, 0, 1024, 6),
               (64, 256, 4, 0, 1024, 8), (64, 256, 4, 0, 1024, 16), (64, 256, 0, 0, 0, 8),
-              (64, 1024, 4, 0, 1024, 8), (64, 1024, 0, 0, 1024, 8), (64, 256, 4, 0, 4096, 8)]
+              (64, 1024, 4, 0, 1024, 8), (64, 1024, 0, 0, 1024, 8), (64, 256, 4, 0, 4096, 8),
+              (64, 256, 4, 0, 1024, 8, 64), (64, 256, 4, 0, 1024, 8, 16),
+              (64, 256, 0, 0, 1024, 8, 64), (64, 256, 0, 0, 1024, 8, 16),
+              (64, 1024, 0, 0, 1024, 8, 64), (64, 1024, 0, 0, 1024, 8, 16)]
 
-FIELDS = 6
-DEFAULT_TAIL = (0, 0, 0, 2)  # full_passes, first_deficit_after, reverse_below, hop_growth
+FIELDS = 7
+# full_passes, first_deficit_after, reverse_below, hop_growth, tile_cols
+DEFAULT_TAIL = (0, 0, 0, 2, 32)
 
 
 def pad(c):

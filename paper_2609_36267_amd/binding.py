@@ -204,11 +204,11 @@ class McfParams(C.Structure):
     """Schedule of the min-cost-flow passes (ww_mcf_params)."""
     _fields_ = [("first_hop_window", C.c_int32), ("first_distance_step", C.c_int32),
                 ("full_passes", C.c_int32), ("first_deficit_after", C.c_int32),
-                ("reverse_below", C.c_int32), ("hop_growth", C.c_int32)]
+                ("reverse_below", C.c_int32), ("hop_growth", C.c_int32), ("tile_cols", C.c_int32)]
 
     def as_tuple(self):
         return (self.first_hop_window, self.first_distance_step, self.full_passes,
-                self.first_deficit_after, self.reverse_below, self.hop_growth)
+                self.first_deficit_after, self.reverse_below, self.hop_growth, self.tile_cols)
 
 
 def get_mcf_params() -> McfParams:
@@ -218,14 +218,16 @@ def get_mcf_params() -> McfParams:
 
 
 def set_mcf_params(first_hop_window=None, first_distance_step=None, full_passes=None,
-                   first_deficit_after=None, reverse_below=None, hop_growth=None) -> McfParams:
+                   first_deficit_after=None, reverse_below=None, hop_growth=None,
+                   tile_cols=None) -> McfParams:
     """Set the process-wide solve schedule (None keeps a field); returns the
     previous schedule."""
     old = get_mcf_params()
     p = McfParams(*old.as_tuple())
     for k, v in (("first_hop_window", first_hop_window), ("first_distance_step", first_distance_step),
                  ("full_passes", full_passes), ("first_deficit_after", first_deficit_after),
-                 ("reverse_below", reverse_below), ("hop_growth", hop_growth)):
+                 ("reverse_below", reverse_below), ("hop_growth", hop_growth),
+                 ("tile_cols", tile_cols)):
         if v is not None:
             setattr(p, k, int(v))
     _check(load().ww_set_mcf_params(C.byref(p)))

@@ -195,6 +195,8 @@ __device__ __forceinline__ void activate(unsigned int *act, unsigned int *lists,
     }
 }
 
+constexpr int TILE_NODES = 1024;  // loop nodes per tile (256 threads x 4)
+
 __device__ __forceinline__ unsigned int entry_of(int job, unsigned int lt) {
     return ((unsigned int)job << 24) | lt;
 }
@@ -436,7 +438,7 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_write(Graph g, const 
 // A ground is a source while it holds surplus; that is read here rather
 // than passed in, so that a pass can be queued before the host has seen how
 // the previous one ended.
-template <bool MULTI>
+template <bool MULTI, int TW>
 __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned int *act,
                             unsigned int *lists, unsigned int NT, unsigned int rr,
                             const unsigned int *perim_tiles, int nperim) {
@@ -448,16 +450,17 @@ __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned
         const Job J = job_at<MULTI>(g, job);
         const unsigned int lv = (unsigned int)(v - J.noff);
         const int i = lv / J.C, j = lv % J.C;
-        const int ti = i / 32, tj = j / 32, li = i % 32, lj = j % 32;
+        constexpr int TH = TILE_NODES / TW;
+        const int ti = i / TH, tj = j / TW, li = i % TH, lj = j % TW;
         const unsigned int lt = ti * J.TC + tj;
         activate(act, lists, NT, ctl, J.toff + lt, entry_of(job, lt), rr);
         // a supply on a tile border also feeds the tile across that border,
         // whose relaxation must run although this label never "changes"
         if (li == 0 && ti > 0) activate(act, lists, NT, ctl, J.toff + lt - J.TC, entry_of(job, lt - J.TC), rr);
-        if (li == 31 && ti < J.TR - 1)
+        if (li == TH - 1 && ti < J.TR - 1)
             activate(act, lists, NT, ctl, J.toff + lt + J.TC, entry_of(job, lt + J.TC), rr);
         if (lj == 0 && tj > 0) activate(act, lists, NT, ctl, J.toff + lt - 1, entry_of(job, lt - 1), rr);
-        if (lj == 31 && tj < J.TC - 1)
+        if (lj == TW - 1 && tj < J.TC - 1)
             activate(act, lists, NT, ctl, J.toff + lt + 1, entry_of(job, lt + 1), rr);
     }
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nperim; k += gridDim.x * blockDim.x) {
@@ -499,8 +502,8 @@ struct RoundArgs {
     unsigned int NT;
 };
 
-// 32 x 32 loop tiles, 256 threads, 4 nodes per thread.
-constexpr int TJ = 32;
+// Loop tiles of TILE_NODES nodes, TW columns by TILE_NODES / TW rows (TW =
+// 16, 32 or 64: a solve parameter), 256 threads, 4 nodes per thread.
 
 // Reduced costs of the in-arcs are staged as unsigned words, RC_NONE where
 // there is no arc (a valid reduced cost is below 2^31).
@@ -544,14 +547,15 @@ __device__ __forceinline__ void rej_one(unsigned long long &rej, unsigned long l
 #endif
 constexpr int VISIT_ITERS = WW_VISIT_ITERS;  // sweeps per tile visit at most
 
-template <bool MULTI>
+template <bool MULTI, int TW>
 __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
                                                    unsigned int round, unsigned int pass_stamp,
                                                    unsigned long long lb, int stats) {
-    __shared__ unsigned long long L[TJ + 2][TJ + 3];
-    __shared__ int P[TJ + 2][TJ + 2];
-    __shared__ int4 RC4[TJ][TJ];  // reduced costs of the in-arcs: from above, below, left, right
-    __shared__ int GA[TJ][TJ];    // cheapest move to the ground of a perimeter node (RC_INF: none)
+    constexpr int TH = TILE_NODES / TW;  // tile rows
+    __shared__ unsigned long long L[TH + 2][TW + 3];
+    __shared__ int P[TH + 2][TW + 2];
+    __shared__ int4 RC4[TH][TW];  // reduced costs of the in-arcs: from above, below, left, right
+    __shared__ int GA[TH][TW];    // cheapest move to the ground of a perimeter node (RC_INF: none)
     __shared__ int wchg[3][4];    // per-iteration "a label changed" flag of each wave's band
     __shared__ int flags[4];  // changed border: top, bottom, left, right
     __shared__ int sh_any;
@@ -583,8 +587,8 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         ++my_visits;
         const unsigned long long t_start = stats ? wall_clock64() : 0ull;
         const int ti = lt / J.TC, tj = lt % J.TC;
-        const int i0 = ti * TJ, j0 = tj * TJ;
-        const int rows = min(TJ, R - i0), cols = min(TJ, C - j0);
+        const int i0 = ti * TH, j0 = tj * TW;
+        const int rows = min(TH, R - i0), cols = min(TW, C - j0);
         if (threadIdx.x < 4) flags[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             sh_rej = LINF;
@@ -595,8 +599,8 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         // is issued unconditionally, from an address clamped into the tile,
         // before any of them is used: one memory latency for all of them.
         // Values of positions outside the tile are replaced afterwards.
-        constexpr int NSTAGE = ((TJ + 2) * (TJ + 2) + 255) / 256;
-        constexpr int NRC = TJ * TJ / 256;
+        constexpr int NSTAGE = ((TH + 2) * (TW + 2) + 255) / 256;
+        constexpr int NRC = TILE_NODES / 256;
         int cst[NRC][4];
         {
             unsigned long long lv[NSTAGE];
@@ -605,9 +609,9 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
 #pragma unroll
             for (int s = 0; s < NSTAGE; ++s) {
                 const int t = threadIdx.x + 256 * s;
-                const int r = t / (TJ + 2), c = t % (TJ + 2);
+                const int r = t / (TW + 2), c = t % (TW + 2);
                 const int i = i0 - 1 + r, j = j0 - 1 + c;
-                halo[s] = t < (TJ + 2) * (TJ + 2) && r <= rows + 1 && c <= cols + 1;
+                halo[s] = t < (TH + 2) * (TW + 2) && r <= rows + 1 && c <= cols + 1;
                 inside[s] = halo[s] && i >= 0 && i < R && j >= 0 && j < C;
                 const long long v = noff + (long long)(inside[s] ? i : i0) * C + (inside[s] ? j : j0);
                 lv[s] = g.lab[v];
@@ -620,7 +624,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
 #pragma unroll
             for (int s = 0; s < NRC; ++s) {
                 const int t = threadIdx.x + 256 * s;
-                const int li = t / TJ, lj = t % TJ;
+                const int li = t / TW, lj = t % TW;
                 own[s] = li < rows && lj < cols;
                 const int i = i0 + (own[s] ? li : 0), j = j0 + (own[s] ? lj : 0);
                 const long long ex0 = (long long)i * C + j;        // hx(i,j): from above, +1
@@ -651,7 +655,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
 #pragma unroll
             for (int s = 0; s < NRC; ++s) {
                 const int t = threadIdx.x + 256 * s;
-                const int li = t / TJ, lj = t % TJ;
+                const int li = t / TW, lj = t % TW;
                 const int i = i0 + li, j = j0 + lj;
                 int ga = RC_INF;
                 if (own[s]) {
@@ -672,9 +676,9 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
 #pragma unroll
             for (int s = 0; s < NSTAGE; ++s) {
                 const int t = threadIdx.x + 256 * s;
-                if (t < (TJ + 2) * (TJ + 2)) {
-                    L[t / (TJ + 2)][t % (TJ + 2)] = inside[s] ? lv[s] : (halo[s] ? glab : LINF);
-                    P[t / (TJ + 2)][t % (TJ + 2)] = inside[s] ? pv[s] : (halo[s] ? gpot : 0);
+                if (t < (TH + 2) * (TW + 2)) {
+                    L[t / (TW + 2)][t % (TW + 2)] = inside[s] ? lv[s] : (halo[s] ? glab : LINF);
+                    P[t / (TW + 2)][t % (TW + 2)] = inside[s] ? pv[s] : (halo[s] ? gpot : 0);
                 }
             }
         }
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
 #pragma unroll
         for (int s = 0; s < NRC; ++s) {
             const int t = threadIdx.x + 256 * s;
-            const int li = t / TJ, lj = t % TJ;
+            const int li = t / TW, lj = t % TW;
             int ru = RC_INF, rd = RC_INF, rl = RC_INF, rr = RC_INF;
             if (li < rows && lj < cols) {
                 const int pv = P[li + 1][lj + 1];
@@ -707,10 +711,11 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         // right and end neighbours are re-read from LDS at every step, so a
         // label written by the neighbouring lane of the same wave one step
         // earlier is already seen (labels only decrease, so any value read is
-        // a valid label).  Wave w owns rows 8w..8w+7; it skips an iteration
-        // when no label changed in its band or the two adjacent bands during
-        // the previous one.
-        const int lj = threadIdx.x % TJ, q = threadIdx.x / TJ, wv = threadIdx.x >> 6;
+        // a valid label).  Wave w owns the TH / 4 rows of band w (its
+        // segments are consecutive); it skips an iteration when no label
+        // changed in its band or the two adjacent bands during the previous
+        // one.
+        const int lj = threadIdx.x % TW, q = threadIdx.x / TW, wv = threadIdx.x >> 6;
         const int r0 = q * 4;
         unsigned long long init[4], y[4];
         int4 rc[4];
@@ -1228,7 +1233,7 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 // textbook search that settles the same nodes).
 constexpr int POT_CHUNK = 8;
 
-template <bool MULTI>
+template <bool MULTI, int TW>
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
                                                     unsigned int pass, unsigned int NT,
                                                     unsigned long long lb, const unsigned int *flip,
@@ -1252,20 +1257,21 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
             const int job = MULTI ? job_of_tile(g, tile) : 0;
             const Job J = job_at<MULTI>(g, job);
             const unsigned int lt = tile - J.toff;
-            const int i0 = (int)(lt / J.TC) * TJ, j0 = (int)(lt % J.TC) * TJ;
-            long long v[TJ * TJ / 256];
-            unsigned long long l[TJ * TJ / 256];
-            uint8_t tb[TJ * TJ / 256];
+            constexpr int TH = TILE_NODES / TW;
+            const int i0 = (int)(lt / J.TC) * TH, j0 = (int)(lt % J.TC) * TW;
+            long long v[TILE_NODES / 256];
+            unsigned long long l[TILE_NODES / 256];
+            uint8_t tb[TILE_NODES / 256];
 #pragma unroll
-            for (int s = 0; s < TJ * TJ / 256; ++s) {
+            for (int s = 0; s < TILE_NODES / 256; ++s) {
                 const int t = threadIdx.x + 256 * s;
-                const int i = i0 + t / TJ, j = j0 + t % TJ;
+                const int i = i0 + t / TW, j = j0 + t % TW;
                 v[s] = (i < J.R && j < J.C) ? J.noff + (long long)i * J.C + j : -1;
                 l[s] = v[s] >= 0 ? g.lab[v[s]] : LINF;
                 tb[s] = v[s] >= 0 ? tag[v[s]] : (uint8_t)0;
             }
 #pragma unroll
-            for (int s = 0; s < TJ * TJ / 256; ++s) {
+            for (int s = 0; s < TILE_NODES / 256; ++s) {
                 if (l[s] == LINF) continue;
                 // a walk of this pass passed here (a stale byte of a pass 256
                 // earlier finds the key cleared: no effect)
@@ -1582,6 +1588,7 @@ std::atomic<int> g_full_passes{0};
 std::atomic<int> g_first_deficit{0};
 std::atomic<int> g_reverse_below{0};
 std::atomic<int> g_hop_growth{2};
+std::atomic<int> g_tile_cols{32};
 
 ww_mcf_params process_mcf_params() {
     ww_mcf_params p;
@@ -1591,6 +1598,7 @@ ww_mcf_params process_mcf_params() {
     p.first_deficit_after = g_first_deficit.load();
     p.reverse_below = g_reverse_below.load();
     p.hop_growth = g_hop_growth.load();
+    p.tile_cols = g_tile_cols.load();
     return p;
 }
 
@@ -1602,6 +1610,8 @@ ww_status check_mcf_params(const ww_mcf_params &p) {
         (p.first_deficit_after != 0 && p.first_deficit_after != 1) || p.reverse_below < 0 ||
         p.hop_growth < 2 || p.hop_growth > (1 << 20))
         return fail(WW_E_INVALID_ARG, "pass schedule out of range");
+    if (p.tile_cols != 16 && p.tile_cols != 32 && p.tile_cols != 64)
+        return fail(WW_E_INVALID_ARG, "tile_cols must be 16, 32 or 64");
     return WW_OK;
 }
 
@@ -1621,7 +1631,7 @@ static ww_status decode_error(int e) {
 // once.  The jobs' residues, x-flow planes and y-flow planes each lie in one
 // contiguous array, job after job (res_all, fx_all, fy_all, flows zeroed by
 // the caller); each job's total goes to *mj[k].total.
-template <bool MULTI>
+template <bool MULTI, int TW>
 static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int8_t *fx_all,
                        int8_t *fy_all, int64_t *pot_out, ww_mcf_stats *stats,
                        const ww_mcf_params &sp, hipStream_t st) {
@@ -1644,8 +1654,8 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         J.R = q.m - 1;
         J.C = q.n - 1;
         J.n = q.n;
-        J.TR = ceil_div(J.R, TJ);
-        J.TC = ceil_div(J.C, TJ);
+        J.TR = ceil_div(J.R, TILE_NODES / TW);
+        J.TC = ceil_div(J.C, TW);
         J.noff = N;
         J.toff = NT;
         J.aoff = nslots;
@@ -1836,7 +1846,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
         ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sssp_round<MULTI>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sssp_round<MULTI, TW>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 4;
     (void)hipGetLastError();
@@ -1885,7 +1895,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         const long long gex0 = ground_surplus();
         ++pass;
         const long long ns_h = h->nsrc, nd_h = h->ndef;  // list lengths, upper bounds
-        hipLaunchKernelGGL(k_pass_init<MULTI>, dim3(lgrid(std::max<long long>(ns_h, ra.nperim))), dim3(SB), 0,
+        hipLaunchKernelGGL((k_pass_init<MULTI, TW>), dim3(lgrid(std::max<long long>(ns_h, ra.nperim))), dim3(SB), 0,
                            st, g, ctl, src, ra.act, ra.lists, NT, rr, ra.perim_tiles, ra.nperim);
         WW_LAUNCH_CHECK();
         // Windows in lexicographic (distance, hops) order: every label <= lb
@@ -1902,7 +1912,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             for (;;) {  // rounds
                 WW_HIP(hipEventRecord(ev[0], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
-                    hipLaunchKernelGGL(k_sssp_round<MULTI>, dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
+                    hipLaunchKernelGGL((k_sssp_round<MULTI, TW>), dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
                                        rr, pass, lb, trace ? 1 : 0);
                     WW_LAUNCH_CHECK();
                     ++rr;
@@ -2022,7 +2032,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         WW_LAUNCH_CHECK();
         if (check)
             WW_HIP(hipMemcpyAsync(cb.lab, g.lab, sizeof(unsigned long long) * N, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_potentials<MULTI>, dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass, NT,
+        hipLaunchKernelGGL((k_potentials<MULTI, TW>), dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass, NT,
                            lb, flip, tag, count);
         WW_LAUNCH_CHECK();
         if (check) {
@@ -2104,6 +2114,19 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     return WW_OK;
 }
 
+// The solve for the schedule's tile shape (checked by check_mcf_params).
+template <bool MULTI>
+static ww_status solve_shape(const std::vector<McfJob> &mj, const int8_t *res_all, int8_t *fx_all,
+                             int8_t *fy_all, int64_t *pot_out, ww_mcf_stats *stats,
+                             const ww_mcf_params &sp, hipStream_t st) {
+    switch (sp.tile_cols) {
+        case 16: return solve<MULTI, 16>(mj, res_all, fx_all, fy_all, pot_out, stats, sp, st);
+        case 32: return solve<MULTI, 32>(mj, res_all, fx_all, fy_all, pot_out, stats, sp, st);
+        case 64: return solve<MULTI, 64>(mj, res_all, fx_all, fy_all, pot_out, stats, sp, st);
+        default: return fail(WW_E_INVALID_ARG, "tile_cols must be 16, 32 or 64");
+    }
+}
+
 ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const int16_t *cxn,
                    const int16_t *cyp, const int16_t *cyn, int8_t *dkx, int8_t *dky,
                    int64_t *pot_out, int64_t *total, ww_mcf_stats *stats, hipStream_t st,
@@ -2126,7 +2149,7 @@ ww_status mcf_impl(const int8_t *res, int m, int n, const int16_t *cxp, const in
     const ww_mcf_params sp = sched ? *sched : process_mcf_params();
     std::vector<McfJob> one(1);
     one[0] = McfJob{m, n, res, cxp, cxn, cyp, cyn, dkx, dky, total};
-    return solve<false>(one, res, dkx, dky, pot_out, stats, sp, st);
+    return solve_shape<false>(one, res, dkx, dky, pot_out, stats, sp, st);
 }
 
 ww_status mcf_multi_impl(const std::vector<McfJob> &jobs, const int8_t *res_all, int8_t *fx_all,
@@ -2137,15 +2160,16 @@ ww_status mcf_multi_impl(const std::vector<McfJob> &jobs, const int8_t *res_all,
     for (const McfJob &q : jobs) {
         if (q.m < 2 || q.n < 2) return fail(WW_E_INVALID_ARG, "multi-job solve: every job needs loops");
         if ((long long)(q.m - 1) * (q.n - 1) >= (1ll << 29)) return fail(WW_E_INVALID_ARG, "more than 2^29 loops");
-        if ((long long)ceil_div(q.m - 1, TJ) * ceil_div(q.n - 1, TJ) >= (1ll << 24))
+        const int tw = sp.tile_cols, th = 1024 / std::max(1, tw);
+        if ((long long)ceil_div(q.m - 1, th) * ceil_div(q.n - 1, std::max(1, tw)) >= (1ll << 24))
             return fail(WW_E_INVALID_ARG, "more than 2^24 tiles in one job");
         nx += (long long)q.m * (q.n - 1);
         ny += (long long)(q.m - 1) * q.n;
     }
     WW_HIP(hipMemsetAsync(fx_all, 0, nx, st));
     WW_HIP(hipMemsetAsync(fy_all, 0, ny, st));
-    if (jobs.size() == 1) return solve<false>(jobs, res_all, fx_all, fy_all, nullptr, stats, sp, st);
-    return solve<true>(jobs, res_all, fx_all, fy_all, nullptr, stats, sp, st);
+    if (jobs.size() == 1) return solve_shape<false>(jobs, res_all, fx_all, fy_all, nullptr, stats, sp, st);
+    return solve_shape<true>(jobs, res_all, fx_all, fy_all, nullptr, stats, sp, st);
 }
 
 }  // namespace ww
@@ -2160,6 +2184,7 @@ void ww_default_mcf_params(ww_mcf_params *p) {
     p->first_deficit_after = 0;
     p->reverse_below = 0;
     p->hop_growth = 2;
+    p->tile_cols = 32;
 }
 
 ww_status ww_set_mcf_params(const ww_mcf_params *p) {
@@ -2172,6 +2197,7 @@ ww_status ww_set_mcf_params(const ww_mcf_params *p) {
     ww::g_first_deficit.store(p->first_deficit_after);
     ww::g_reverse_below.store(p->reverse_below);
     ww::g_hop_growth.store(p->hop_growth);
+    ww::g_tile_cols.store(p->tile_cols);
     return WW_OK;
 }
 

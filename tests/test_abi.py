@@ -81,17 +81,22 @@ def test_mcf_schedule_round_trip_and_range():
         p = ww.get_mcf_params()
         assert (p.first_hop_window, p.first_distance_step) == (16, 4096)
         ww.set_mcf_params(full_passes=8, first_deficit_after=1)
-        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 2)
+        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 2, 32)
         ww.set_mcf_params(hop_growth=8)
-        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 8)
+        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 8, 32)
         for bad in ((0, 256), (64, 0), (64, (1 << 30) + 1), (1 << 29, 256), (64, 256, -1, 0),
                     (64, 256, (1 << 20) + 1, 0), (64, 256, 0, 2), (64, 256, 0, 0, -1),
-                    (64, 256, 0, 0, 0, 1), (64, 256, 0, 0, 0, (1 << 20) + 1)):
+                    (64, 256, 0, 0, 0, 1), (64, 256, 0, 0, 0, (1 << 20) + 1),
+                    (64, 256, 0, 0, 0, 2, 48), (64, 256, 0, 0, 0, 2, 128), (64, 256, 0, 0, 0, 2, 0)):
             with pytest.raises(ww.WWError):
                 ww.set_mcf_params(*bad)
-        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 8)
+        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 8, 32)
+        ww.set_mcf_params(tile_cols=64)
+        assert ww.get_mcf_params().tile_cols == 64
+        ww.set_mcf_params(tile_cols=16)
+        assert ww.get_mcf_params().as_tuple() == (16, 4096, 8, 1, 0, 8, 16)
         d = ww.McfParams()
         ww.load().ww_default_mcf_params(ctypes.byref(d))
-        assert d.as_tuple() == (64, 256, 0, 0, 0, 2)
+        assert d.as_tuple() == (64, 256, 0, 0, 0, 2, 32)
     finally:
         ww.set_mcf_params(*old.as_tuple())

@@ -107,7 +107,8 @@ def test_batch_matches_plain(torch_cuda, scenes, plain, certs, group):
 
 
 @pytest.mark.parametrize("sched", [(64, 256, 0, 0, 1 << 30), (1, 1, 2, 1, 1), (64, 256, 8, 1, 0),
-                                   (64, 256, 4, 0, 1024, 8)])
+                                   (64, 256, 4, 0, 1024, 8), (64, 256, 4, 0, 1024, 8, 64),
+                                   (1, 1, 2, 1, 1, 2, 16)])
 def test_batch_schedules_and_checks(torch_cuda, scenes, certs, sched, monkeypatch):
     """One solve over all jobs under extreme schedules, the reversed frame
     included, with the solver's debug checks on (non-negative reduced costs
@@ -176,7 +177,7 @@ def test_server_per_job_schedule(torch_cuda, scenes, plain):
         for k, sc in enumerate(scenes[:6]):
             j = srv.submit(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
                            torch.from_numpy(sc.valid).cuda(), sc.looks, tag=k,
-                           sched=[(1, 1, 2, 1, 1), (64, 256, 0, 0, 1 << 30), None][k % 3])
+                           sched=[(1, 1, 2, 1, 1, 2, 64), (64, 256, 0, 0, 1 << 30, 2, 16), None][k % 3])
         done = srv.drain()
     assert ww.get_mcf_params().as_tuple() == before
     for j, K, phi in done:

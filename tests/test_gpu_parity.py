@@ -245,6 +245,8 @@ SCHEDULES = [(64, 256, 0, 0, 1 << 30),   # every pass from the demands (reversed
              (1, 1, 2, 1, 1),            # tiny windows, first-deficit passes, last unit reversed
              (64, 256, 8, 1, 0),         # the paper's pass schedule
              (64, 256, 4, 0, 16, 8),     # hop windows growing eightfold
+             (64, 256, 4, 0, 16, 8, 64),  # wide tiles (64 x 16)
+             (64, 256, 0, 0, 1 << 30, 2, 16),  # tall tiles (16 x 64), reversed problem
              (4, 64, 0, 1, 0, 1 << 20)]  # one small hop window, then the whole plateau
 
 
@@ -268,6 +270,36 @@ def test_mcf_parity_schedules(torch_cuda, sched, shape, seed):
         _mcf_case(psi, tuple(costs), m, n)
     finally:
         ww.set_mcf_params(*old.as_tuple())
+
+
+@pytest.mark.parametrize("shape,seed", [((130, 257), 0), ((257, 130), 1), ((33, 200), 0)])
+def test_mcf_tile_shapes_identical(torch_cuda, shape, seed):
+    """The labels are the unique lexicographic minima whatever tiles the
+    rounds relax, so every tile shape reaches the same flow, potentials and
+    pass structure byte for byte; only the rounds and visits differ."""
+    m, n = shape
+    rng = np.random.default_rng(seed * 101 + m + n)
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    res, _, _ = oracle.residues(psi)
+    costs = tuple(rng.integers(0, [50, 3000][seed], sz).astype(np.int16)
+                  for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+    old = ww.get_mcf_params()
+    out = {}
+    try:
+        for tc in (32, 16, 64):
+            ww.set_mcf_params(64, 256, 2, 0, 64, 4, tc)
+            r = ww.mcf_solve(res, costs, m, n, want_potentials=True)
+            out[tc] = (np_(r.dk_x), np_(r.dk_y), np_(r.potentials), r.total_cost, r.stats)
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
+    a = out[32]
+    for tc in (16, 64):
+        b = out[tc]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), tc
+        assert np.array_equal(a[2], b[2]) and a[3] == b[3], tc
+        for k in ("passes", "windows", "augmentations", "path_arcs"):
+            assert a[4][k] == b[4][k], (tc, k, a[4][k], b[4][k])
+    assert a[3] == oracle.mcf(res, costs, m=m, n=n)[3]
 
 
 def _long_path_case(kind):
@@ -296,7 +328,8 @@ def _long_path_case(kind):
     return res, costs, m, n
 
 
-@pytest.mark.parametrize("sched", [None, (64, 256, 0, 0, 1 << 30)])
+@pytest.mark.parametrize("sched", [None, (64, 256, 0, 0, 1 << 30), (64, 256, 0, 0, 0, 2, 64),
+                                   (64, 256, 0, 0, 1 << 30, 2, 16)])
 @pytest.mark.parametrize("kind", ["dipoles", "ground_supply", "ground_demand"])
 def test_mcf_long_paths(torch_cuda, kind, sched):
     """Paths far longer than a walker's solo steps, crossing many 32 x 32
@@ -516,7 +549,8 @@ def test_mcf_unaligned_outputs_reversed_frame(torch_cuda):
         ww.set_mcf_params(*old.as_tuple())
 
 
-@pytest.mark.parametrize("sched", [None, (64, 256, 0, 0, 1 << 30), (1, 1, 2, 1, 1), (64, 256, 4, 0, 16, 8)])
+@pytest.mark.parametrize("sched", [None, (64, 256, 0, 0, 1 << 30), (1, 1, 2, 1, 1), (64, 256, 4, 0, 16, 8),
+                                   (64, 256, 4, 0, 16, 8, 64), (1, 1, 2, 1, 1, 2, 16)])
 def test_mcf_debug_checks_pass(torch_cuda, sched, monkeypatch):
     """With WW_MCF_CHECK=1 the solver checks, after every pass, that every
     residual arc has a non-negative reduced cost, and after every batch of
