@@ -175,6 +175,27 @@ def test_costs_parity_steep_ties(torch_cuda, lut9, levels, pct):
         assert np.array_equal(np_(g), w)
 
 
+@pytest.mark.parametrize("thr,pct", [(0.0, 10), (0.5, 25), (3.0, 3), (3.2, 50), (1.0, 100)])
+@pytest.mark.parametrize("n", [112, 111])
+def test_costs_parity_steep_thresholds(torch_cuda, lut9, thr, pct, n):
+    """The coarse bins of the steep pre-pass start at the threshold's key
+    and cover the keys up to pi: a zero threshold (every nonzero gradient a
+    candidate), thresholds near and beyond pi (few or no candidates, inputs
+    outside one cycle in the last bin), and a cap that takes every
+    candidate; 16-byte (112 columns) and scalar (111) pre-pass loads."""
+    rng = np.random.default_rng(n * 100 + pct)
+    m = 90
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    psi[::7, ::5] *= 3.0  # phases outside one cycle: |d| beyond pi
+    coh = rng.uniform(0.1, 0.95, (m, n)).astype(np.float32)
+    valid = (rng.random((m, n)) > 0.05).astype(np.uint8)
+    want = oracle.edge_costs(psi, coh, valid, lut9, steep_thresh=thr, steep_cap_pct=pct)
+    cp = ww.default_cost_params(steep_thresh_rad=thr, steep_cap_pct=pct)
+    got = ww.edge_costs(psi, coh, valid, lut9, cp)
+    for g, w in zip(got, want):
+        assert np.array_equal(np_(g), w)
+
+
 @pytest.mark.parametrize("n", [416, 413])
 def test_costs_parity_steep_large_boundary(torch_cuda, lut9, n):
     """Five phase levels on a 400-row scene: the candidates' |d| take two
