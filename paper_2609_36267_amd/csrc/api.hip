@@ -3,9 +3,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <vector>
+
+#include <cstdlib>
 
 #include "ww_internal.h"
 
@@ -105,6 +108,11 @@ ww_status scratch(int slot, size_t bytes, void **out) {
         }
         size_t want = bytes + bytes / 8;
         void *p = nullptr;
+        // WW_SCRATCH_LIMIT (bytes): a test of the out-of-memory path makes
+        // any larger buffer fail as a failed allocation would
+        const char *lim = getenv("WW_SCRATCH_LIMIT");
+        if (lim && want > (size_t)std::max(0ll, atoll(lim)))
+            return fail(WW_E_OOM, "device allocation of %zu bytes refused (WW_SCRATCH_LIMIT)", want);
         if (hipMalloc(&p, want) != hipSuccess) {
             (void)hipGetLastError();
             return fail(WW_E_OOM, "device allocation of %zu bytes failed", want);
@@ -263,7 +271,8 @@ int64_t unwrap_workspace_bytes(int m, int n) {
     int64_t b = 0;
     b += N + 2 * (2 * nx + 2 * ny) + nx + ny + 64;          // residues, costs, flows, counters
     b += 12 * (nx + ny) + 512 + 4096;                       // steep-rule keys and state
-    b += (8 + 8 + 4 + 1 + 16 + 4) * N + 2 * (2 * n + 2 * m) + 4096;  // solver node state and lists
+    b += (8 + 8 + 4 + 1 + 16 + 5) * N + 2 * (2 * n + 2 * m) + 4096;  // solver node state and lists
+    b += 256 * (4096 * 4 + 8) + 4096;                       // steep pre-pass partial histograms
     b += 40 * NT + 8192 + 8 * std::max<int64_t>(3 * ceil_div(N, 4096), 8192) + 4096;  // tiles, parts
     b += 256 + 4 * (int64_t)m;                              // integration
     return b + b / 8;                                       // the workspace's growth margin

@@ -1237,7 +1237,7 @@ template <bool MULTI, int TW>
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
                                                     unsigned int pass, unsigned int NT,
                                                     unsigned long long lb, const unsigned int *flip,
-                                                    const uint8_t *tag, int count) {
+                                                    const uint8_t *tag, int count, int pot_limit) {
     __shared__ unsigned int todo[POT_CHUNK];
     __shared__ int ntodo;
     const unsigned int bound = ldist(lb);
@@ -1307,9 +1307,9 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
                 }
                 const unsigned int d = ldist(l[s]);
                 const long long np = (long long)g.pot[v[s]] + (bound - d);
-                if (np > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
-                g.pot[v[s]] = (int)min(np, (long long)POT_LIMIT);
-                mx = max(mx, (int)min(np, (long long)POT_LIMIT));
+                if (np > pot_limit) atomicOr(&ctl->error, ERR_POT);
+                g.pot[v[s]] = (int)min(np, (long long)pot_limit);
+                mx = max(mx, (int)min(np, (long long)pot_limit));
             }
         }
         __syncthreads();
@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const uns
         const unsigned long long gl = G.glab;
         if (gl <= lb) {
             G.gpot += bound - ldist(gl);
-            if (G.gpot > POT_LIMIT) atomicOr(&ctl->error, ERR_POT);
+            if (G.gpot > pot_limit) atomicOr(&ctl->error, ERR_POT);
             if (count) atomicAdd(&ctl->settled, 1ull);
         }
         G.glab = LINF;
@@ -1620,8 +1620,10 @@ static unsigned long long mk_label(unsigned int d, unsigned int h) {
 }
 
 static ww_status decode_error(int e) {
+    // a potential clamped at the limit breaks the reduced costs of later
+    // passes: the overflow is the cause to report
+    if (e & ERR_POT) return fail(WW_E_OVERFLOW, "min-cost flow: node potential above its limit (2^30)");
     if (e & ERR_NEG_RC) return fail(WW_E_DEVICE, "min-cost flow: negative reduced cost (invariant broken)");
-    if (e & ERR_POT) return fail(WW_E_OVERFLOW, "min-cost flow: node potential above 2^30");
     if (e & ERR_WALK) return fail(WW_E_DEVICE, "min-cost flow: predecessor walk did not end");
     if (e & ERR_ITERS) return fail(WW_E_DEVICE, "min-cost flow: tile relaxation did not converge");
     return fail(WW_E_DEVICE, "min-cost flow: error flags 0x%x", e);
@@ -1786,6 +1788,13 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     const bool check = check_env && check_env[0] == '1';
     const char *count_env = getenv("WW_MCF_COUNT");
     const int count = (count_env && count_env[0] == '1') ? 1 : 0;
+    // range guards (lowered only by tests of the error path): the largest
+    // potential, and the largest distance bound of a window
+    int pot_limit = POT_LIMIT;
+    unsigned int bound_cap = 0xffff0000u;
+    if (const char *e = getenv("WW_MCF_POT_LIMIT")) pot_limit = (int)std::min<long long>(POT_LIMIT, std::max(0ll, atoll(e)));
+    if (const char *e = getenv("WW_MCF_DIST_CAP"))
+        bound_cap = (unsigned int)std::min<long long>(0xffff0000ll, std::max(0ll, atoll(e)));
     // debug-check buffers, released on every way out of the solve (the
     // release waits for the device, so queued kernels never outlive them)
     struct CheckBufs {
@@ -1854,7 +1863,6 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     const int pot_grid = (int)std::min<unsigned int>((NT + POT_CHUNK - 1) / POT_CHUNK, 16384u);
     unsigned long long nbatch = 0;  // round batches so far (their parity picks the window-end slot)
     int wslot = 0;
-    const unsigned int bound_cap = 0xffff0000u;
     unsigned int rr = 1, pass = 0;  // next round, current pass
     const int SB = 256;
     // Kernels over the node lists are grid-stride loops sized from the list
@@ -2033,7 +2041,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         if (check)
             WW_HIP(hipMemcpyAsync(cb.lab, g.lab, sizeof(unsigned long long) * N, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL((k_potentials<MULTI, TW>), dim3(pot_grid), dim3(SB), 0, st, g, ctl, ra.tstamp, pass, NT,
-                           lb, flip, tag, count);
+                           lb, flip, tag, count, pot_limit);
         WW_LAUNCH_CHECK();
         if (check) {
             WW_HIP(hipMemsetAsync(cb.rec, 0, sizeof(CheckRec), st));

@@ -222,6 +222,41 @@ def test_server_device_arrays_and_poll(torch_cuda, scenes, plain):
         assert same_phi(phi.cpu().numpy(), phip)
 
 
+def test_job_out_of_memory_fails_alone(torch_cuda, scenes, plain, monkeypatch):
+    """A job whose workspace cannot be allocated (device allocations above
+    WW_SCRATCH_LIMIT refused as a failed allocation would be) ends with
+    WW_E_OOM and its message; the other jobs of the same server finish with
+    their costs alone, and the server takes the big job once the limit is
+    gone."""
+    torch = torch_cuda
+    big = synth.make(600, 600, looks=9, seed=21, mask_frac=0.05, disks=1, disk_radius=(20, 40),
+                     keep_truth=False, workers=1)
+    big_cost = ww.unwrap(big.psi, big.coh, big.valid, big.looks)[2]
+    small = list(range(4))  # at most 33 k pixels: every buffer well below 4 MB
+    assert max(scenes[k].psi.size for k in small) < 40000
+    dev = lambda sc: (torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),  # noqa: E731
+                      torch.from_numpy(sc.valid).cuda())
+    monkeypatch.setenv("WW_SCRATCH_LIMIT", str(4 << 20))  # the big job's keys alone take 8.6 MB
+    with ww.Server(slots=2) as srv:
+        for k in small:
+            srv.submit(*dev(scenes[k]), scenes[k].looks, tag=k)
+        srv.submit(*dev(big), big.looks, tag=99)
+        done = srv.drain()
+        monkeypatch.delenv("WW_SCRATCH_LIMIT")
+        assert len(done) == len(small) + 1
+        for j, K, phi in done:
+            if int(j.tag) == 99:
+                assert j.status == ww.E_OOM, (j.status, j.error)
+                assert b"WW_SCRATCH_LIMIT" in j.error
+            else:
+                assert j.status == 0, j.error
+                assert int(j.total_cost) == plain[int(j.tag)][2]
+        srv.submit(*dev(big), big.looks, tag=99)
+        (j, K, phi), = srv.drain()
+        assert j.status == 0, j.error
+        assert int(j.total_cost) == big_cost
+
+
 def test_tiny_budget_runs_jobs_one_at_a_time(torch_cuda, scenes, plain):
     """With a budget below any job's footprint each job runs alone."""
     with ww.Server(slots=4, hbm_budget_bytes=1) as srv:

@@ -323,6 +323,33 @@ def test_mcf_tile_shapes_identical(torch_cuda, shape, seed):
     assert a[3] == oracle.mcf(res, costs, m=m, n=n)[3]
 
 
+def _overflow_case():
+    rng = np.random.default_rng(77)
+    m, n = 80, 90
+    psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+    res, _, _ = oracle.residues(psi)
+    costs = tuple(rng.integers(20, 200, sz).astype(np.int16)
+                  for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+    return res, costs, m, n
+
+
+@pytest.mark.parametrize("var,value", [("WW_MCF_POT_LIMIT", "30"), ("WW_MCF_DIST_CAP", "50")])
+def test_mcf_range_guards_report_overflow(torch_cuda, monkeypatch, var, value):
+    """The solver's range guards (node potentials below 2^30, window bounds
+    below 2^32 - 2^16), lowered from the host so that an ordinary scene
+    trips them, fail the solve with WW_E_OVERFLOW and a message; the next
+    solve without them reaches the optimum."""
+    res, costs, m, n = _overflow_case()
+    monkeypatch.setenv(var, value)
+    with pytest.raises(ww.WWError) as ei:
+        ww.mcf_solve(res, costs, m, n)
+    assert ei.value.code == ww.E_OVERFLOW, str(ei.value)
+    assert ("potential" if var == "WW_MCF_POT_LIMIT" else "distance") in str(ei.value)
+    monkeypatch.delenv(var)
+    r = ww.mcf_solve(res, costs, m, n)
+    assert r.total_cost == oracle.mcf(res, costs, m=m, n=n)[3]
+
+
 def _long_path_case(kind):
     """Residue layouts whose augmenting paths run for hundreds of steps:
     far-apart dipoles whose supplies sit next to each other in the supply
