@@ -280,11 +280,11 @@ __device__ __forceinline__ bool load_res16(const int8_t *res, long long v0, long
 
 // Node state of a block's chunk of INIT_CHUNK nodes, each thread taking
 // INIT_PER consecutive nodes: the excess is a copy of the residues, the
-// potentials zero, the labels and path tags infinite, all in 16-byte
-// stores.
+// potentials zero, the labels and path keys infinite, all in 16-byte
+// stores.  A deficit's flip word needs no clearing: each pass writes it
+// (k_roots) before anything reads it.
 __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const int8_t *__restrict__ res,
-                                                                int *__restrict__ bc,
-                                                                unsigned int *__restrict__ flip) {
+                                                                int *__restrict__ bc) {
     __shared__ int red[INIT_THREADS / 64];
     const long long N = g.N;
     const long long c0 = (long long)blockIdx.x * INIT_CHUNK;
@@ -308,17 +308,13 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
     }
     if (c0 + INIT_CHUNK <= N) {
         uint4 *pot = reinterpret_cast<uint4 *>(g.pot + c0);
-        uint4 *fl = reinterpret_cast<uint4 *>(flip + c0);
         uint4 *lab = reinterpret_cast<uint4 *>(g.lab + c0);
         uint4 *best = reinterpret_cast<uint4 *>(g.best + c0);
         const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
         const uint4 inf = make_uint4((unsigned int)LINF, (unsigned int)(LINF >> 32), (unsigned int)LINF,
                                      (unsigned int)(LINF >> 32));
 #pragma unroll
-        for (int k = 0; k < INIT_CHUNK / 4 / INIT_THREADS; ++k) {
-            pot[k * INIT_THREADS + threadIdx.x] = zero;
-            fl[k * INIT_THREADS + threadIdx.x] = zero;
-        }
+        for (int k = 0; k < INIT_CHUNK / 4 / INIT_THREADS; ++k) pot[k * INIT_THREADS + threadIdx.x] = zero;
 #pragma unroll
         for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) {
             lab[k * INIT_THREADS + threadIdx.x] = inf;
@@ -327,7 +323,6 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
     } else {
         for (long long v = c0 + threadIdx.x; v < N; v += INIT_THREADS) {
             g.pot[v] = 0;
-            flip[v] = 0;
             g.lab[v] = LINF;
             g.best[v] = LINF;
         }
@@ -1757,7 +1752,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     unsigned int *flip = nullptr;
     WW_TRY(scratch(SLOT_MCF_FLIP, (sizeof(unsigned int) + 1) * (size_t)N + 256, (void **)&flip));
     uint8_t *tag = reinterpret_cast<uint8_t *>(flip + N);
-    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc, flip);
+    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc);
     WW_LAUNCH_CHECK();
     const int gx = MULTI ? (int)std::min<long long>(64, std::max<long long>(1, ceil_div(N / nj, 4096)))
                          : std::max(1, ceil_div(max_arcs, 256));
