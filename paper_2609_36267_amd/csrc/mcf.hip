@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
     __shared__ int P[TH + 2][TW + 2];
     __shared__ int4 RC4[TH][TW];  // reduced costs of the in-arcs: from above, below, left, right
     __shared__ int GA[TH][TW];    // cheapest move to the ground of a perimeter node (RC_INF: none)
-    __shared__ int wchg[3][4];    // per-iteration "a label changed" flag of each wave's band
+    __shared__ __align__(16) int wchg[3][4];  // per-iteration "a label changed" flag of each wave's band
     __shared__ int flags[4];  // changed border: top, bottom, left, right
     __shared__ int sh_any;
     __shared__ unsigned long long sh_gcand, sh_rej;
@@ -702,16 +702,25 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         const unsigned long long t_staged = stats ? wall_clock64() : 0ull;
         // Each thread owns a column segment of 4 nodes (column lj, rows
         // 4q..4q+3): their labels and in-arc reduced costs stay in registers,
-        // and every iteration sweeps down the segment and back up.  The left,
-        // right and end neighbours are re-read from LDS at every step, so a
-        // label written by the neighbouring lane of the same wave one step
-        // earlier is already seen (labels only decrease, so any value read is
-        // a valid label).  Wave w owns the TH / 4 rows of band w (its
-        // segments are consecutive); it skips an iteration when no label
-        // changed in its band or the two adjacent bands during the previous
-        // one.
+        // and every iteration sweeps down the segment and back up.  The
+        // labels of the side neighbours (lanes lj - 1 and lj + 1 of the same
+        // wave) and of the segments above and below are read from LDS in
+        // batches, each timed so that it sees what the neighbouring lanes of
+        // the same wave wrote in the steps before it: the side labels of all
+        // four rows and the label above at the start of the down pass, the
+        // label below after the first step (the segment below has just
+        // written its top node), the side labels of rows 2..0 and the label
+        // above after the down pass.  Labels only decrease, so any value read
+        // is a valid label.  Every step stores its node's label, changed or
+        // not (the owner is the only writer of a cell).  A node outside the
+        // image has no in-arc (all four reduced costs RC_NONE), so no
+        // candidate ever passes for it.  Wave w owns the TH / 4 rows of band
+        // w (its segments are consecutive); it skips an iteration when no
+        // label changed in its band or the two adjacent bands during the
+        // previous one.
         const int lj = threadIdx.x % TW, q = threadIdx.x / TW, wv = threadIdx.x >> 6;
         const int r0 = q * 4;
+        const int near_bands = ((7 << wv) >> 1) & 15;  // bits of bands wv - 1, wv, wv + 1
         unsigned long long init[4], y[4];
         int4 rc[4];
         bool ok[4];
@@ -731,45 +740,69 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         // label is valid) and lists the tile again for the next round, so
         // that one slow tile does not hold up the whole round.
         bool unconverged = true;
+        int rd = 2, wr = 0, cl = 1;  // flag slots: read, written, cleared in this sweep
         for (int it = 0; it < VISIT_ITERS; ++it) {
-            const int rd = (it + 2) % 3, wr = it % 3;
-            const bool live = wchg[rd][wv] || (wv > 0 && wchg[rd][wv - 1]) || (wv < 3 && wchg[rd][wv + 1]);
-            int changed = 0;
-            if (live) {
+            const int4 f = *reinterpret_cast<const int4 *>(&wchg[rd][0]);
+            const int fm = __builtin_amdgcn_readfirstlane((f.x ? 1 : 0) | (f.y ? 2 : 0) | (f.z ? 4 : 0) |
+                                                          (f.w ? 8 : 0));
+            if (fm & near_bands) {
+                bool changed = false;
 // the smallest of the four candidates is taken when it is inside the window
 // and below the node's label: one comparison with min(label, lb + 1)
-#define WW_RELAX_NODE(k, PREV, NEXT)                                                  \
-    if (ok[k]) {                                                                      \
-        const unsigned long long c = umin64(                                          \
+#define WW_RELAX_NODE(k, PREV, NEXT, LEFT, RIGHT)                                          \
+    {                                                                                      \
+        const unsigned long long c = umin64(                                               \
             umin64(cand_of(PREV, (unsigned)rc[k].x, 1u), cand_of(NEXT, (unsigned)rc[k].y, 2u)), \
-            umin64(cand_of(L[r0 + k + 1][lj], (unsigned)rc[k].z, 3u),                  \
-                   cand_of(L[r0 + k + 1][lj + 2], (unsigned)rc[k].w, 4u)));            \
-        if (c < umin64(y[k], lb1)) {                                                  \
-            y[k] = c;                                                                 \
-            L[r0 + k + 1][lj + 1] = c;                                                \
-            changed = 1;                                                              \
-        }                                                                             \
+            umin64(cand_of(LEFT, (unsigned)rc[k].z, 3u), cand_of(RIGHT, (unsigned)rc[k].w, 4u))); \
+        const bool upd = c < umin64(y[k], lb1);                                            \
+        y[k] = upd ? c : y[k];                                                             \
+        changed |= upd;                                                                    \
+        L[r0 + k + 1][lj + 1] = y[k];                                                      \
     }
-                WW_RELAX_NODE(0, L[r0][lj + 1], y[1])
-                WW_RELAX_NODE(1, y[0], y[2])
-                WW_RELAX_NODE(2, y[1], y[3])
-                WW_RELAX_NODE(3, y[2], L[r0 + 5][lj + 1])
-                WW_RELAX_NODE(2, y[1], y[3])
-                WW_RELAX_NODE(1, y[0], y[2])
-                WW_RELAX_NODE(0, L[r0][lj + 1], y[1])
+                unsigned long long sl[4], sr[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    sl[k] = L[r0 + k + 1][lj];
+                    sr[k] = L[r0 + k + 1][lj + 2];
+                }
+                unsigned long long above = L[r0][lj + 1];
+                WW_RELAX_NODE(0, above, y[1], sl[0], sr[0])
+                // (the empty asm statements keep the LDS accesses in program
+                // order: each store stays, and each read follows the stores
+                // before it)
+                asm volatile("" ::: "memory");
+                const unsigned long long below = L[r0 + 5][lj + 1];
+                WW_RELAX_NODE(1, y[0], y[2], sl[1], sr[1])
+                WW_RELAX_NODE(2, y[1], y[3], sl[2], sr[2])
+                WW_RELAX_NODE(3, y[2], below, sl[3], sr[3])
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    sl[k] = L[r0 + k + 1][lj];
+                    sr[k] = L[r0 + k + 1][lj + 2];
+                }
+                above = L[r0][lj + 1];
+                WW_RELAX_NODE(2, y[1], y[3], sl[2], sr[2])
+                WW_RELAX_NODE(1, y[0], y[2], sl[1], sr[1])
+                WW_RELAX_NODE(0, above, y[1], sl[0], sr[0])
 #undef WW_RELAX_NODE
                 if (changed) wchg[wr][wv] = 1;
             }
-            if (threadIdx.x < 4) wchg[(it + 1) % 3][threadIdx.x] = 0;
+            if (threadIdx.x < 4) wchg[cl][threadIdx.x] = 0;
             // the waves' change flags of this sweep decide for the whole
             // workgroup after one barrier (slot wr is next cleared two sweeps
             // later, after another barrier)
             __syncthreads();
-            if (!(wchg[wr][0] | wchg[wr][1] | wchg[wr][2] | wchg[wr][3])) {
+            const int4 w = *reinterpret_cast<const int4 *>(&wchg[wr][0]);
+            if (!__builtin_amdgcn_readfirstlane(w.x | w.y | w.z | w.w)) {
                 if (stats && threadIdx.x == 0) atomicAdd(&ctl->iters, (unsigned long long)(it + 1));
                 unconverged = false;
                 break;
             }
+            const int t = rd;
+            rd = wr;
+            wr = cl;
+            cl = t;
         }
         if (unconverged && stats && threadIdx.x == 0)
             atomicAdd(&ctl->iters, (unsigned long long)VISIT_ITERS);
