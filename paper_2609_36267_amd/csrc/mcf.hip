@@ -522,6 +522,18 @@ __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsig
     return a < b ? a : b;
 }
 
+// Element idx of an array whose bytes all lie below 2^32 from base (a job's
+// node and arc arrays: fewer than 2^29 loops): a 32-bit byte offset from a
+// workgroup-uniform base, which the loads and stores take as is.
+template <typename T>
+__device__ __forceinline__ T &at32(T *base, unsigned int idx) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (idx * (unsigned int)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T &at32(const T *base, unsigned int idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (idx * (unsigned int)sizeof(T)));
+}
+
 // A candidate beyond the window for a node without a label, kept in rej
 // (the smallest such over the tile parks the tile for a later window).
 // Every label lies inside the window, so a beyond-window candidate can
@@ -538,7 +550,7 @@ __device__ __forceinline__ void rej_one(unsigned long long &rej, unsigned long l
 // Sweeps per tile visit at most (a speed knob: the labels are the same for
 // any value).
 #ifndef WW_VISIT_ITERS
-#define WW_VISIT_ITERS 8
+#define WW_VISIT_ITERS 12
 #endif
 constexpr int VISIT_ITERS = WW_VISIT_ITERS;  // sweeps per tile visit at most
 
@@ -579,6 +591,8 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         const int gpot = MULTI ? (int)g.gs[job].gpot : gpot0;
         const int R = J.R, C = J.C;
         const long long noff = J.noff;
+        unsigned long long *const labJ = g.lab + noff;  // the job's labels and potentials
+        const int *const potJ = g.pot + noff;
         ++my_visits;
         const unsigned long long t_start = stats ? wall_clock64() : 0ull;
         const int ti = lt / J.TC, tj = lt % J.TC;
@@ -608,9 +622,9 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 const int i = i0 - 1 + r, j = j0 - 1 + c;
                 halo[s] = t < (TH + 2) * (TW + 2) && r <= rows + 1 && c <= cols + 1;
                 inside[s] = halo[s] && i >= 0 && i < R && j >= 0 && j < C;
-                const long long v = noff + (long long)(inside[s] ? i : i0) * C + (inside[s] ? j : j0);
-                lv[s] = g.lab[v];
-                pv[s] = g.pot[v];
+                const unsigned int v = (unsigned int)((inside[s] ? i : i0) * C + (inside[s] ? j : j0));
+                lv[s] = at32(labJ, v);
+                pv[s] = at32(potJ, v);
             }
             // arc flows and both costs of the four in-arcs of every node
             int8_t af[NRC][4];
@@ -622,14 +636,14 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
                 const int li = t / TW, lj = t % TW;
                 own[s] = li < rows && lj < cols;
                 const int i = i0 + (own[s] ? li : 0), j = j0 + (own[s] ? lj : 0);
-                const long long ex0 = (long long)i * C + j;        // hx(i,j): from above, +1
-                const long long ex1 = (long long)(i + 1) * C + j;  // hx(i+1,j): from below, -1
-                const long long ey0 = (long long)i * J.n + j;      // vy(i,j): from the left, -1
-                const long long ey1 = ey0 + 1;                     // vy(i,j+1): from the right, +1
-                af[s][0] = J.fx[ex0]; ap[s][0] = J.cxp[ex0]; an[s][0] = J.cxn[ex0];
-                af[s][1] = J.fx[ex1]; ap[s][1] = J.cxp[ex1]; an[s][1] = J.cxn[ex1];
-                af[s][2] = J.fy[ey0]; ap[s][2] = J.cyp[ey0]; an[s][2] = J.cyn[ey0];
-                af[s][3] = J.fy[ey1]; ap[s][3] = J.cyp[ey1]; an[s][3] = J.cyn[ey1];
+                const unsigned int ex0 = (unsigned int)(i * C + j);      // hx(i,j): from above, +1
+                const unsigned int ex1 = ex0 + (unsigned int)C;           // hx(i+1,j): from below, -1
+                const unsigned int ey0 = (unsigned int)(i * J.n + j);    // vy(i,j): from the left, -1
+                const unsigned int ey1 = ey0 + 1u;                        // vy(i,j+1): from the right, +1
+                af[s][0] = at32(J.fx, ex0); ap[s][0] = at32(J.cxp, ex0); an[s][0] = at32(J.cxn, ex0);
+                af[s][1] = at32(J.fx, ex1); ap[s][1] = at32(J.cxp, ex1); an[s][1] = at32(J.cxn, ex1);
+                af[s][2] = at32(J.fy, ey0); ap[s][2] = at32(J.cyp, ey0); an[s][2] = at32(J.cyn, ey0);
+                af[s][3] = at32(J.fy, ey1); ap[s][3] = at32(J.cyp, ey1); an[s][3] = at32(J.cyn, ey1);
             }
             // (the empty asm statements use every loaded value here, so that
             // no load is moved into the conditional code below and waited
@@ -827,7 +841,7 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             if (li >= rows || lj >= cols) continue;
             const unsigned long long l = L[li + 1][lj + 1];
             if (l != init[k]) {
-                g.lab[noff + (long long)(i0 + li) * C + (j0 + lj)] = l;
+                at32(labJ, (unsigned int)((i0 + li) * C + (j0 + lj))) = l;
                 if (li == 0) flags[0] = 1;
                 if (li == rows - 1) flags[1] = 1;
                 if (lj == 0) flags[2] = 1;
