@@ -692,26 +692,27 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
             }
         }
         __syncthreads();
-        // reduced costs of the four in-arcs of every node
+        // reduced costs of the four in-arcs of every node (an arc exists
+        // only at an owned node, cst != RC_INF; the potentials are read for
+        // every position, all inside the staged array, so that the reads go
+        // out in one batch)
+        bool neg = false;
 #pragma unroll
         for (int s = 0; s < NRC; ++s) {
             const int t = threadIdx.x + 256 * s;
             const int li = t / TW, lj = t % TW;
-            int ru = RC_INF, rd = RC_INF, rl = RC_INF, rr = RC_INF;
-            if (li < rows && lj < cols) {
-                const int pv = P[li + 1][lj + 1];
-                if (cst[s][0] != RC_INF) ru = cst[s][0] - P[li][lj + 1] + pv;
-                if (cst[s][1] != RC_INF) rd = cst[s][1] - P[li + 2][lj + 1] + pv;
-                if (cst[s][2] != RC_INF) rl = cst[s][2] - P[li + 1][lj] + pv;
-                if (cst[s][3] != RC_INF) rr = cst[s][3] - P[li + 1][lj + 2] + pv;
-                if (ru < 0 || rd < 0 || rl < 0 || rr < 0) {
-                    atomicOr(&ctl->error, ERR_NEG_RC);
-                    ru = max(ru, 0); rd = max(rd, 0); rl = max(rl, 0); rr = max(rr, 0);
-                }
-            }
+            const int pv = P[li + 1][lj + 1];
+            const int pu = P[li][lj + 1], pd = P[li + 2][lj + 1], pl = P[li + 1][lj], pr = P[li + 1][lj + 2];
+            int ru = cst[s][0] != RC_INF ? cst[s][0] - pu + pv : RC_INF;
+            int rd = cst[s][1] != RC_INF ? cst[s][1] - pd + pv : RC_INF;
+            int rl = cst[s][2] != RC_INF ? cst[s][2] - pl + pv : RC_INF;
+            int rr = cst[s][3] != RC_INF ? cst[s][3] - pr + pv : RC_INF;
+            neg |= (ru < 0) | (rd < 0) | (rl < 0) | (rr < 0);
+            ru = max(ru, 0); rd = max(rd, 0); rl = max(rl, 0); rr = max(rr, 0);
             RC4[li][lj] = make_int4(ru == RC_INF ? (int)RC_NONE : ru, rd == RC_INF ? (int)RC_NONE : rd,
                                     rl == RC_INF ? (int)RC_NONE : rl, rr == RC_INF ? (int)RC_NONE : rr);
         }
+        if (neg) atomicOr(&ctl->error, ERR_NEG_RC);
         __syncthreads();
         const unsigned long long t_staged = stats ? wall_clock64() : 0ull;
         // Each thread owns a column segment of 4 nodes (column lj, rows
@@ -820,46 +821,49 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
         }
         if (unconverged && stats && threadIdx.x == 0)
             atomicAdd(&ctl->iters, (unsigned long long)VISIT_ITERS);
-        // beyond-window candidates of the nodes still without a label, from
-        // the final labels of the visit (all LDS writes are done: the loop
-        // above ends on a barrier)
+        // The rest of the visit needs the labels around each segment, the
+        // ground moves and the potentials of its own nodes: read from LDS in
+        // one batch (the loop above ended on a barrier, so every LDS write
+        // is done).  A node's own label is y[k], equal to its LDS cell.
+        unsigned long long sl[4], sr[4];
+        int gak[4], pk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sl[k] = L[r0 + k + 1][lj];
+            sr[k] = L[r0 + k + 1][lj + 2];
+            gak[k] = GA[r0 + k][lj];
+            pk[k] = P[r0 + k + 1][lj + 1];
+        }
+        const unsigned long long above = L[r0][lj + 1], below = L[r0 + 5][lj + 1];
+        // beyond-window candidates of the nodes still without a label
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!ok[k] || y[k] != LINF) continue;
-            const unsigned long long up = k == 0 ? L[r0][lj + 1] : y[k > 0 ? k - 1 : 0];
-            const unsigned long long dn = k == 3 ? L[r0 + 5][lj + 1] : y[k < 3 ? k + 1 : 3];
-            rej_one(rej, up, (unsigned)rc[k].x, 1u, lb);
-            rej_one(rej, dn, (unsigned)rc[k].y, 2u, lb);
-            rej_one(rej, L[r0 + k + 1][lj], (unsigned)rc[k].z, 3u, lb);
-            rej_one(rej, L[r0 + k + 1][lj + 2], (unsigned)rc[k].w, 4u, lb);
+            rej_one(rej, k == 0 ? above : y[k > 0 ? k - 1 : 0], (unsigned)rc[k].x, 1u, lb);
+            rej_one(rej, k == 3 ? below : y[k < 3 ? k + 1 : 3], (unsigned)rc[k].y, 2u, lb);
+            rej_one(rej, sl[k], (unsigned)rc[k].z, 3u, lb);
+            rej_one(rej, sr[k], (unsigned)rc[k].w, 4u, lb);
         }
         const unsigned long long t_swept = stats ? wall_clock64() : 0ull;
         // write back, note changed borders
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int li = q * 4 + k;
-            if (li >= rows || lj >= cols) continue;
-            const unsigned long long l = L[li + 1][lj + 1];
-            if (l != init[k]) {
-                at32(labJ, (unsigned int)((i0 + li) * C + (j0 + lj))) = l;
-                if (li == 0) flags[0] = 1;
-                if (li == rows - 1) flags[1] = 1;
-                if (lj == 0) flags[2] = 1;
-                if (lj == cols - 1) flags[3] = 1;
-            }
+            if (!ok[k] || y[k] == init[k]) continue;
+            const int li = r0 + k;
+            at32(labJ, (unsigned int)((i0 + li) * C + (j0 + lj))) = y[k];
+            if (li == 0) flags[0] = 1;
+            if (li == rows - 1) flags[1] = 1;
+            if (lj == 0) flags[2] = 1;
+            if (lj == cols - 1) flags[3] = 1;
         }
         // candidate labels for the ground from perimeter nodes of this tile
         // (the cheapest of a corner's two moves gives its smallest candidate)
         unsigned long long gc = LINF;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int li = q * 4 + k;
-            if (li >= rows || lj >= cols) continue;
-            const int c = GA[li][lj];
-            if (c == RC_INF) continue;
-            const unsigned long long l = L[li + 1][lj + 1];
-            if (l == LINF) continue;
-            int rc = c - P[li + 1][lj + 1] + gpot;
+            const unsigned long long l = y[k];
+            if (!ok[k] || gak[k] == RC_INF || l == LINF) continue;
+            int rc = gak[k] - pk[k] + gpot;
             if (rc < 0) {
                 atomicOr(&ctl->error, ERR_NEG_RC);
                 rc = 0;
