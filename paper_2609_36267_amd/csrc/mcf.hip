@@ -1546,15 +1546,19 @@ __device__ __forceinline__ void negate_span(T *a, long long n, long long tid, lo
 // forward search in the reversed frame is a search towards the demands in
 // the original one.  Applying the map twice restores the original state.
 // The flow planes of all jobs are two contiguous arrays (fx: nx entries,
-// fy: ny).
+// fy: ny).  nodes = 0 leaves the node excesses and potentials as they are:
+// the way back after the last pass, when only the flows, the grounds and
+// (negated on export) the potentials are read any more.
 __global__ void k_reverse_frame(Graph g, Ctl *ctl, int8_t *fx, long long nx, int8_t *fy,
-                                long long ny) {
+                                long long ny, int nodes) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     negate_span(fx, nx, tid, stride);
     negate_span(fy, ny, tid, stride);
-    negate_span(g.ex, g.N, tid, stride);
-    negate_span(g.pot, g.N, tid, stride);
+    if (nodes) {
+        negate_span(g.ex, g.N, tid, stride);
+        negate_span(g.pot, g.N, tid, stride);
+    }
     for (long long k = tid; k < g.njobs; k += stride) {
         g.gs[k].gex = -g.gs[k].gex;
         g.gs[k].gpot = -g.gs[k].gpot;
@@ -1616,10 +1620,11 @@ __global__ __launch_bounds__(256) void k_total_cost(Graph g) {
     }
 }
 
-__global__ void k_export_pot(const int *pot, const GState *gs, long long N, int64_t *out) {
+// (sign -1: the node potentials were left in the reversed frame)
+__global__ void k_export_pot(const int *pot, const GState *gs, long long N, int64_t *out, int sign) {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v <= N;
          v += (long long)gridDim.x * blockDim.x)
-        out[v] = v < N ? (int64_t)pot[v] : (int64_t)gs[0].gpot;
+        out[v] = v < N ? (int64_t)sign * pot[v] : (int64_t)gs[0].gpot;
 }
 
 // ------------------------------------------------------------------ host ---
@@ -1875,9 +1880,11 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     bool reversed = false;
     const int rev_grid =
         (int)std::min<long long>(8192, std::max<long long>(1, ceil_div(std::max(nx_all + ny_all, N), 256 * 16)));
-    auto flip_frame = [&]() -> ww_status {
+    int pot_sign = 1;  // -1: node potentials left in the reversed frame
+    auto flip_frame = [&](int nodes) -> ww_status {
         hipLaunchKernelGGL(k_reverse_frame, dim3(rev_grid), dim3(256), 0, st, g, ctl, fx_all, nx_all,
-                           fy_all, ny_all);
+                           fy_all, ny_all, nodes);
+        if (!nodes) pot_sign = -pot_sign;
         WW_LAUNCH_CHECK();
         reversed = !reversed;
         if (MULTI) g.jobs = jobs_dev[reversed ? 1 : 0];
@@ -1939,7 +1946,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             // reversed frame), where the plateaus that earlier passes made
             // tight around the supplies do not lie
             if (!reversed && reverse_below > 0 && (long long)h->nsrc + ground_surplus() <= reverse_below)
-                WW_TRY(flip_frame());
+                WW_TRY(flip_frame(1));
         }
         const auto tp0 = std::chrono::steady_clock::now();
         const long long r0 = S.rounds, w0 = S.windows;
@@ -2140,7 +2147,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         if (h->naug == 0)
             return fail(WW_E_INFEASIBLE, "min-cost flow: a pass augmented no path");
     }
-    if (reversed) WW_TRY(flip_frame());
+    if (reversed) WW_TRY(flip_frame(0));
     {
         // each job's cost from its flows (original frame)
         long long mx_e = 0;
@@ -2151,7 +2158,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         WW_LAUNCH_CHECK();
     }
     if (pot_out && !MULTI) {
-        hipLaunchKernelGGL(k_export_pot, dim3(IB), dim3(256), 0, st, g.pot, g.gs, N, pot_out);
+        hipLaunchKernelGGL(k_export_pot, dim3(IB), dim3(256), 0, st, g.pot, g.gs, N, pot_out, pot_sign);
         WW_LAUNCH_CHECK();
     }
     WW_TRY(sync_ctl());
