@@ -105,6 +105,7 @@ ww_status scratch(int slot, size_t bytes, void **out) {
             WW_HIP(hipFree(b.ptr));
             b.ptr = nullptr;
             b.bytes = 0;
+            b.clean = 0;
         }
         size_t want = bytes + bytes / 8;
         void *p = nullptr;
@@ -119,10 +120,13 @@ ww_status scratch(int slot, size_t bytes, void **out) {
         }
         b.ptr = p;
         b.bytes = want;
+        b.clean = 0;
     }
     *out = b.ptr;
     return WW_OK;
 }
+
+size_t *scratch_clean(int slot) { return &current_workspace()->slot[slot].clean; }
 
 ww_status host_scratch(size_t bytes, void **out) {
     Workspace *ws = current_workspace();

@@ -280,11 +280,11 @@ __device__ __forceinline__ bool load_res16(const int8_t *res, long long v0, long
 
 // Node state of a block's chunk of INIT_CHUNK nodes, each thread taking
 // INIT_PER consecutive nodes: the excess is a copy of the residues, the
-// potentials zero, the labels and path keys infinite, all in 16-byte
-// stores.  A deficit's flip word needs no clearing: each pass writes it
-// (k_roots) before anything reads it.
+// potentials zero, and (keys != 0) the labels and path keys infinite, all
+// in 16-byte stores.  A deficit's flip word needs no clearing: each pass
+// writes it (k_roots) before anything reads it.
 __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const int8_t *__restrict__ res,
-                                                                int *__restrict__ bc) {
+                                                                int *__restrict__ bc, int keys) {
     __shared__ int red[INIT_THREADS / 64];
     const long long N = g.N;
     const long long c0 = (long long)blockIdx.x * INIT_CHUNK;
@@ -315,16 +315,20 @@ __global__ __launch_bounds__(INIT_THREADS) void k_mcf_init_count(Graph g, const 
                                      (unsigned int)(LINF >> 32));
 #pragma unroll
         for (int k = 0; k < INIT_CHUNK / 4 / INIT_THREADS; ++k) pot[k * INIT_THREADS + threadIdx.x] = zero;
+        if (keys) {
 #pragma unroll
-        for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) {
-            lab[k * INIT_THREADS + threadIdx.x] = inf;
-            best[k * INIT_THREADS + threadIdx.x] = inf;
+            for (int k = 0; k < INIT_CHUNK / 2 / INIT_THREADS; ++k) {
+                lab[k * INIT_THREADS + threadIdx.x] = inf;
+                best[k * INIT_THREADS + threadIdx.x] = inf;
+            }
         }
     } else {
         for (long long v = c0 + threadIdx.x; v < N; v += INIT_THREADS) {
             g.pot[v] = 0;
-            g.lab[v] = LINF;
-            g.best[v] = LINF;
+            if (keys) {
+                g.lab[v] = LINF;
+                g.best[v] = LINF;
+            }
         }
     }
     np = block_sum_int(np, red);
@@ -1808,7 +1812,17 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     unsigned int *flip = nullptr;
     WW_TRY(scratch(SLOT_MCF_FLIP, (sizeof(unsigned int) + 1) * (size_t)N + 256, (void **)&flip));
     uint8_t *tag = reinterpret_cast<uint8_t *>(flip + N);
-    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc);
+    // Every solve that ends well leaves all labels and path keys at
+    // infinity again (each pass's potential update resets those of the
+    // nodes it reached, and only those carry any), so a solve whose buffers
+    // are known to be in that state does not write them.  The marks stay
+    // cleared until this solve ends well.
+    size_t *const clean_lab = scratch_clean(SLOT_MCF_LAB), *const clean_best = scratch_clean(SLOT_MCF_BEST);
+    const size_t key_bytes = sizeof(unsigned long long) * (size_t)N;
+    const size_t was_clean = std::min(*clean_lab, *clean_best);
+    *clean_lab = *clean_best = 0;
+    hipLaunchKernelGGL(k_mcf_init_count, dim3(nib), dim3(INIT_THREADS), 0, st, g, res_all, bc,
+                       was_clean >= key_bytes ? 0 : 1);
     WW_LAUNCH_CHECK();
     const int gx = MULTI ? (int)std::min<long long>(64, std::max<long long>(1, ceil_div(N / nj, 4096)))
                          : std::max(1, ceil_div(max_arcs, 256));
@@ -2172,6 +2186,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     last_mcf_stats() = S;
     if (stats) *stats = S;
+    *clean_lab = *clean_best = std::max(was_clean, key_bytes);
     return WW_OK;
 }
 

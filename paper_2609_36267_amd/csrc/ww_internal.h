@@ -46,6 +46,7 @@ void clear_error();
 struct Buffer {
     void *ptr = nullptr;
     size_t bytes = 0;
+    size_t clean = 0;  // leading bytes its user knows to hold its rest value
 };
 
 struct Workspace;
@@ -63,6 +64,9 @@ size_t workspace_bytes(const Workspace *ws);
 // Returns a device buffer of at least `bytes` for (workspace, slot);
 // contents are unspecified.
 ww_status scratch(int slot, size_t bytes, void **out);
+// The clean mark of (workspace, slot): the leading bytes that the slot's
+// user left in a known rest state (reset to 0 when the buffer is replaced).
+size_t *scratch_clean(int slot);
 // Pinned host staging area (for counters read back by the solver loop).
 ww_status host_scratch(size_t bytes, void **out);
 // Two timing events of the current workspace.
