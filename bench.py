@@ -44,9 +44,9 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
-TRAFFIC_SOURCE_SHA = "abec533f277945a1"
+TRAFFIC_SOURCE_SHA = "35702ae99af0f0ee"
 TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 8, 32)
-TRAFFIC_BYTES_PER_LAUNCH = 14.98e6
+TRAFFIC_BYTES_PER_LAUNCH = 14.89e6
 
 
 def round_kernel_sha() -> str:
