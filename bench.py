@@ -45,8 +45,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
 TRAFFIC_SOURCE_SHA = "35702ae99af0f0ee"
-TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 8, 32)
-TRAFFIC_BYTES_PER_LAUNCH = 14.89e6
+TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 6, 32)
+TRAFFIC_BYTES_PER_LAUNCH = 14.49e6
 
 
 def round_kernel_sha() -> str:
@@ -603,12 +603,13 @@ def main():
     sc = synth.config(args.workload)
     m, n = sc.psi.shape
     print(f"# generated {args.workload} {m}x{n} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    # a sibling of the timed scene (same recipe, half the size, another
-    # seed) on which the solve schedule is tuned: the timed scene is never
-    # used for tuning
+    # a sibling of the timed scene (same recipe and size, another seed) on
+    # which the solve schedule is tuned: the timed scene is never used for
+    # tuning (a half-size sibling picked tile shapes and distance steps that
+    # lose on the full size, where fronts cross more tiles)
     sib = None
     if not args.no_tune and args.schedule is None and args.workload == "c2":
-        sib = synth.make_fault(m // 2, n // 2, looks=sc.looks, seed=3, mask_frac=0.03)
+        sib = synth.make_fault(m, n, looks=sc.looks, seed=3, mask_frac=0.03)
     stack = stack_scenes(args, synth) if args.stack_jobs > 0 else None
     # the oracle's smaller workloads, also generated before the GPU is used
     # (the generator forks worker processes)
@@ -623,6 +624,7 @@ def main():
     torch.cuda.synchronize()
 
     tuned_on = "library default (not tuned)"
+    tune_top = None  # the five fastest candidates on the sibling scene (schedule, ms)
     if args.schedule:
         ww.set_mcf_params(*[int(x) for x in args.schedule.split(",")])
         tuned_on = "given on the command line"
@@ -634,6 +636,8 @@ def main():
         choice, table = autotune.tune_schedule(sjob, reps=2)
         tuned_on = (f"fault recipe {sib.psi.shape[0]}x{sib.psi.shape[1]} seed 3 (not the timed "
                     f"scene), {len(table)} candidates, {time.perf_counter() - t:.1f} s")
+        tune_top = [[list(autotune.pad(c)), round(1e3 * s, 3)]
+                    for c, s in sorted(table.items(), key=lambda kv: kv[1])[:5]]
         del sjob, sib
         print(f"# schedule {choice} tuned on the sibling scene", file=sys.stderr, flush=True)
     sched_main = ww.get_mcf_params()
@@ -725,7 +729,8 @@ def main():
                      "tile_visits_per_step": visits // args.steps,
                      "bytes_per_tile_visit": BYTES_PER_TILE_VISIT},
         "mcf": stats[-1],
-        "schedule": {**_sched_dict(sched_main.as_tuple()), "tuned_on": tuned_on},
+        "schedule": {**_sched_dict(sched_main.as_tuple()), "tuned_on": tuned_on,
+                     **({"sibling_top5_ms": tune_top} if tune_top else {})},
         "paper_context": {"whirlwind_74mpix_s": 209, "derived_mpix_s": 0.356,
                           "note": "unstated CPU, real Sentinel-1 scene; context, not the target"},
     }
