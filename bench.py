@@ -759,6 +759,15 @@ def main():
         st_o = out["cpu_baseline"]["configs"].get("stack")
         if st_o and "stack" in out:
             st_o["equals_gpu_sum"] = st_o["total_cost_sum"] == out["stack"]["total_cost_sum"]
+        if args.workload == "c2" and os.path.exists(GOLDEN):
+            # the oracle's one run on the whole scene (context: measured once,
+            # on the host that wrote the golden file, not timed here)
+            gd = json.load(open(GOLDEN))
+            if "oracle_mcf_seconds" in gd:
+                out["cpu_baseline"]["whole_scene_once"] = {
+                    "mcf_seconds": gd["oracle_mcf_seconds"], "total_cost": gd["total_cost"],
+                    "what": "oracle min-cost flow alone on the whole timed scene, single-threaded, "
+                            "measured once when tests/golden was written (not on this host)"}
     print(json.dumps(out), flush=True)
 
 
