@@ -410,6 +410,47 @@ def test_mcf_degenerate_shapes(torch_cuda):
         assert not np_(r.dk_x).any() and not np_(r.dk_y).any()
 
 
+def test_mcf_workspace_reuse_across_sizes(torch_cuda):
+    """Solves on one workspace skip the label and path-key fill while the
+    buffers are known to be at rest: a large solve, a small one, the large
+    one again (with a reversing schedule) and then a failing one followed by
+    the large one give the same flows, potentials and cost every time, and
+    the oracle's."""
+    rng = np.random.default_rng(31)
+
+    def case(m, n, seed):
+        r = np.random.default_rng(seed)
+        psi = r.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+        res, _, _ = oracle.residues(psi)
+        costs = tuple(r.integers(0, 300, sz).astype(np.int16)
+                      for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+        return res, costs
+
+    big, small = case(160, 190, 1), case(40, 50, 2)
+    old = ww.get_mcf_params()
+    try:
+        ww.set_mcf_params(64, 256, 2, 0, 64, 4)
+        first = _mcf_case_res(big[0], big[1], 160, 190)[0]
+        _mcf_case_res(small[0], small[1], 40, 50)
+        again = _mcf_case_res(big[0], big[1], 160, 190)[0]
+        # a solve that fails part-way (supply beyond a cut), then the big one
+        m = n = 12
+        res = np.zeros((m - 1, n - 1), np.int8)
+        res[3:8, 3:8] = 1
+        costs = tuple(rng.integers(0, 101, sz).astype(np.int16)
+                      for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+        with pytest.raises(ww.WWError):
+            ww.mcf_solve(res, costs, m, n)
+        after = _mcf_case_res(big[0], big[1], 160, 190)[0]
+    finally:
+        ww.set_mcf_params(*old.as_tuple())
+    for r in (again, after):
+        assert np.array_equal(np_(r.dk_x), np_(first.dk_x))
+        assert np.array_equal(np_(r.dk_y), np_(first.dk_y))
+        assert np.array_equal(np_(r.potentials), np_(first.potentials))
+        assert r.total_cost == first.total_cost
+
+
 INFEASIBLE_SCHEDULES = [None, (64, 256, 0, 0, 1 << 30), (64, 256, 8, 1, 0), (64, 256, 4, 0, 16, 8)]
 
 
