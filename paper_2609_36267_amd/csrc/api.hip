@@ -8,8 +8,6 @@
 #include <map>
 #include <vector>
 
-#include <cstdlib>
-
 #include "ww_internal.h"
 
 namespace ww {
