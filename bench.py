@@ -568,7 +568,7 @@ def _cpu_model():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+        print("bench.py: the library runs on exactly one GPU (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
