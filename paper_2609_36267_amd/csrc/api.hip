@@ -42,6 +42,8 @@ struct Workspace {
     Buffer slot[SLOT_COUNT];
     void *host = nullptr;
     size_t host_bytes = 0;
+    void *mirror = nullptr;  // coherent pinned block the device writes counters into
+    size_t mirror_bytes = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t wait_ev = nullptr;  // marks the point a host wait returns at
     ww_mcf_stats stats{};
@@ -62,6 +64,7 @@ void workspace_destroy(Workspace *ws) {
     for (auto &b : ws->slot)
         if (b.ptr) (void)hipFree(b.ptr);
     if (ws->host) (void)hipHostFree(ws->host);
+    if (ws->mirror) (void)hipHostFree(ws->mirror);
     for (auto &e : ws->ev)
         if (e) (void)hipEventDestroy(e);
     if (ws->wait_ev) (void)hipEventDestroy(ws->wait_ev);
@@ -139,6 +142,22 @@ ww_status host_scratch(size_t bytes, void **out) {
         ws->host_bytes = bytes;
     }
     *out = ws->host;
+    return WW_OK;
+}
+
+ww_status host_mirror(size_t bytes, void **out) {
+    Workspace *ws = current_workspace();
+    if (ws->mirror_bytes < bytes) {
+        if (ws->mirror) WW_HIP(hipHostFree(ws->mirror));
+        ws->mirror = nullptr;
+        ws->mirror_bytes = 0;
+        if (hipHostMalloc(&ws->mirror, bytes, hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(WW_E_OOM, "pinned host allocation of %zu bytes failed", bytes);
+        }
+        ws->mirror_bytes = bytes;
+    }
+    *out = ws->mirror;
     return WW_OK;
 }
 

@@ -1625,6 +1625,21 @@ __global__ __launch_bounds__(256) void k_total_cost(Graph g) {
 }
 
 // (sign -1: the node potentials were left in the reversed frame)
+// The solver's counters and ground records (bytes, a multiple of 16)
+// copied into coherent pinned host memory, then the sequence word seq after
+// a system-scope fence: a host that sees seq there reads counters that are
+// complete, and knows that all work queued before this kernel is done.
+__global__ void k_mirror(const uint4 *__restrict__ src, uint4 *dst, size_t bytes, unsigned int *flag,
+                         unsigned int seq) {
+    for (size_t k = threadIdx.x; k < bytes / 16; k += blockDim.x) dst[k] = src[k];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __threadfence_system();
+    }
+}
+
 __global__ void k_export_pot(const int *pot, const GState *gs, long long N, int64_t *out, int sign) {
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v <= N;
          v += (long long)gridDim.x * blockDim.x)
@@ -1778,8 +1793,16 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     Job *jobs_dev[2] = {nullptr, nullptr};
     char *hc = nullptr;
     WW_TRY(host_scratch(cg_round + 2 * jobs_bytes, (void **)&hc));
-    Ctl *h = (Ctl *)hc;
-    GState *hg = (GState *)(hc + CTL_BYTES);
+    // the host's copy of the counters and ground records, in a coherent
+    // pinned block that k_mirror writes after each batch of rounds, with
+    // the sequence word behind it
+    char *hm = nullptr;
+    WW_TRY(host_mirror(cg_round + 64, (void **)&hm));
+    unsigned int *const hflag = reinterpret_cast<unsigned int *>(hm + cg_round);
+    __atomic_store_n(hflag, 0u, __ATOMIC_RELEASE);  // no mirror kernel is in flight here
+    unsigned int mseq = 0;
+    Ctl *h = (Ctl *)hm;
+    GState *hg = (GState *)(hm + CTL_BYTES);
     g.jobs = nullptr;
     if (MULTI) {
         // the job tables of both frames, uploaded once (a frame reversal
@@ -1835,6 +1858,28 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     auto sync_ctl = [&]() -> ww_status {
         WW_HIP(hipMemcpyAsync(h, ctl, cg_bytes, hipMemcpyDeviceToHost, st));
         WW_TRY(wait_stream(st));
+        if (h->error) return decode_error(h->error);
+        return WW_OK;
+    };
+    // The same after a batch of rounds, without a copy or an event: the
+    // device writes the counters into the host's block and then a sequence
+    // word, which the host polls (about 8 us sooner than a copy and an event
+    // poll).  A wait longer than 2 ms (a failed kernel among them) goes
+    // through the stream wait, which reports errors.
+    auto mirror_ctl = [&]() -> ww_status {
+        const unsigned int seq = ++mseq;
+        hipLaunchKernelGGL(k_mirror, dim3(1), dim3(256), 0, st, reinterpret_cast<const uint4 *>(ctl),
+                           reinterpret_cast<uint4 *>(hm), cg_bytes, hflag, seq);
+        WW_LAUNCH_CHECK();
+        const auto t0 = std::chrono::steady_clock::now();
+        while (__atomic_load_n(hflag, __ATOMIC_ACQUIRE) != seq) {
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+                WW_TRY(wait_stream(st));
+                if (__atomic_load_n(hflag, __ATOMIC_ACQUIRE) != seq)
+                    return fail(WW_E_DEVICE, "min-cost flow: counters did not arrive");
+                break;
+            }
+        }
         if (h->error) return decode_error(h->error);
         return WW_OK;
     };
@@ -2003,7 +2048,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
                     return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
-                WW_TRY(sync_ctl());
+                WW_TRY(mirror_ctl());
                 if (check) {
                     for (int q = 0; q < 3; ++q)
                         if (h->count[q][0] > list_stride(NT))
@@ -2024,7 +2069,14 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
                                     rr, hb[0], hb[1], hb[2], hb[3], h->count[rr % 3][0]);
                 }
                 float ms = 0.f;
-                WW_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                // (the event was recorded before the mirrored counters: done,
+                // though the runtime may not have seen it yet)
+                hipError_t ee = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (ee == hipErrorNotReady) {
+                    WW_HIP(hipEventSynchronize(ev[1]));
+                    ee = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                }
+                WW_HIP(ee);
                 S.relax_ms += ms;
                 if (prev_unread) {  // the previous pass's end
                     prev_unread = false;
@@ -2140,7 +2192,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             prev_unread = true;
             continue;
         }
-        WW_TRY(sync_ctl());
+        WW_TRY(mirror_ctl());
         ++S.passes;
         S.augmentations += h->naug;
         S.path_arcs += (long long)h->arcs;

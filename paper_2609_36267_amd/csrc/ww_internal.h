@@ -69,6 +69,9 @@ ww_status scratch(int slot, size_t bytes, void **out);
 size_t *scratch_clean(int slot);
 // Pinned host staging area (for counters read back by the solver loop).
 ww_status host_scratch(size_t bytes, void **out);
+// Coherent pinned host block of the current workspace that kernels write
+// into directly (the solver's counters after each batch of rounds).
+ww_status host_mirror(size_t bytes, void **out);
 // Two timing events of the current workspace.
 ww_status workspace_events(hipEvent_t *ev0, hipEvent_t *ev1);
 // Waits for all work queued on `st` so far (polls briefly, then blocks).
