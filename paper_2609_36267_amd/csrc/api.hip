@@ -44,7 +44,7 @@ struct Workspace {
     size_t host_bytes = 0;
     void *mirror = nullptr;  // coherent pinned block the device writes counters into
     size_t mirror_bytes = 0;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t wait_ev = nullptr;  // marks the point a host wait returns at
     ww_mcf_stats stats{};
 };
@@ -161,14 +161,12 @@ ww_status host_mirror(size_t bytes, void **out) {
     return WW_OK;
 }
 
-ww_status workspace_events(hipEvent_t *ev0, hipEvent_t *ev1) {
+ww_status workspace_events(hipEvent_t ev[4]) {
     Workspace *ws = current_workspace();
-    if (!ws->ev[0]) {
-        WW_HIP(hipEventCreate(&ws->ev[0]));
-        WW_HIP(hipEventCreate(&ws->ev[1]));
+    for (int k = 0; k < 4; ++k) {
+        if (!ws->ev[k]) WW_HIP(hipEventCreate(&ws->ev[k]));
+        ev[k] = ws->ev[k];
     }
-    *ev0 = ws->ev[0];
-    *ev1 = ws->ev[1];
     return WW_OK;
 }
 

@@ -1712,8 +1712,8 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     last_mcf_stats() = S;
     const auto t_start = std::chrono::steady_clock::now();
     const int nj = (int)mj.size();
-    hipEvent_t ev[2];
-    WW_TRY(workspace_events(&ev[0], &ev[1]));
+    hipEvent_t ev[4];  // timing pairs (0, 1) and (2, 3), by batch parity
+    WW_TRY(workspace_events(ev));
     // job layout: nodes, tiles, perimeter tiles and ground-subtree slots
     std::vector<Job> jobs(nj);
     std::vector<unsigned int> ptiles;
@@ -1883,6 +1883,24 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         if (h->error) return decode_error(h->error);
         return WW_OK;
     };
+    // The rounds' time of each batch, timed by a pair of events and added
+    // to relax_ms once the next batch is queued (or at the end), so that
+    // reading it never delays the next launch.
+    int pending_pair = -1;
+    auto add_pending_time = [&]() -> ww_status {
+        if (pending_pair < 0) return WW_OK;
+        hipEvent_t e0 = ev[2 * pending_pair], e1 = ev[2 * pending_pair + 1];
+        float ms = 0.f;
+        hipError_t ee = hipEventElapsedTime(&ms, e0, e1);
+        if (ee == hipErrorNotReady) {
+            WW_HIP(hipEventSynchronize(e1));
+            ee = hipEventElapsedTime(&ms, e0, e1);
+        }
+        WW_HIP(ee);
+        S.relax_ms += ms;
+        pending_pair = -1;
+        return WW_OK;
+    };
     // units still to route: supplies plus the grounds' surplus
     auto ground_surplus = [&]() {
         long long s = 0;
@@ -2030,14 +2048,15 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             ++S.windows;
             const long long rw0 = S.rounds;
             for (;;) {  // rounds
-                WW_HIP(hipEventRecord(ev[0], st));
+                const int tp = (int)(nbatch & 1);  // this batch's timing pair
+                WW_HIP(hipEventRecord(ev[2 * tp], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
                     hipLaunchKernelGGL((k_sssp_round<MULTI, TW>), dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
                                        rr, pass, lb, trace ? 1 : 0);
                     WW_LAUNCH_CHECK();
                     ++rr;
                 }
-                WW_HIP(hipEventRecord(ev[1], st));
+                WW_HIP(hipEventRecord(ev[2 * tp + 1], st));
                 // the window-end counts after every batch, so that the batch
                 // that ends the window needs no further round trip (each run
                 // writes the slot of its batch parity and clears the other)
@@ -2045,6 +2064,10 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
                 hipLaunchKernelGGL(k_window_end, dim3(lgrid(std::max<long long>(nd_h, NT))), dim3(SB), 0,
                                    st, g, ctl, def, lb, ra.pstamp, pass, ra.tile_rej, NT, wslot, rr);
                 WW_LAUNCH_CHECK();
+                // the previous batch's time, read now that this batch is
+                // queued (its events are long done)
+                WW_TRY(add_pending_time());
+                pending_pair = tp;
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
                     return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
@@ -2068,16 +2091,6 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
                                     "stamped %u, read %u, count %u",
                                     rr, hb[0], hb[1], hb[2], hb[3], h->count[rr % 3][0]);
                 }
-                float ms = 0.f;
-                // (the event was recorded before the mirrored counters: done,
-                // though the runtime may not have seen it yet)
-                hipError_t ee = hipEventElapsedTime(&ms, ev[0], ev[1]);
-                if (ee == hipErrorNotReady) {
-                    WW_HIP(hipEventSynchronize(ev[1]));
-                    ee = hipEventElapsedTime(&ms, ev[0], ev[1]);
-                }
-                WW_HIP(ee);
-                S.relax_ms += ms;
                 if (prev_unread) {  // the previous pass's end
                     prev_unread = false;
                     ++S.passes;
@@ -2228,6 +2241,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         WW_LAUNCH_CHECK();
     }
     WW_TRY(sync_ctl());
+    WW_TRY(add_pending_time());
     for (int k = 0; k < nj; ++k) *mj[k].total = hg[k].total_cost;
     S.tile_visits = (long long)host_visits();
     long long mxp = h->max_pot;
