@@ -88,6 +88,7 @@ struct Ctl {
     unsigned long long prev_arcs;  // the pass set-up when it clears them
     unsigned long long settled;   // work counters (counting solves only): nodes
     unsigned long long scanned;   // settled and their residual out-arcs
+    unsigned int nlong;           // long walks left to the wave walk (this pass)
 };
 constexpr size_t CTL_BYTES = (sizeof(Ctl) + 63) / 64 * 64;
 
@@ -484,6 +485,7 @@ __global__ void k_pass_init(Graph g, Ctl *ctl, const unsigned int *src, unsigned
         ctl->arcs = 0;
         ctl->nsrc2 = 0;
         ctl->ndef2 = 0;
+        ctl->nlong = 0;
     }
 }
 
@@ -1115,10 +1117,12 @@ __device__ long long walk_root(const Graph &g, const Job &J, const GState &G, Ct
 // to its tree's root and offers its key (distance, deficit) there; the
 // walks also tag their nodes (walk_root).  A deficit's own flip word
 // records the pass, and whether its walk crossed the ground (bit 2).
+// A deficit whose label is more than defer_hops arcs from its root (when
+// defer_hops > 0) is left to the wave walk instead: its index goes to longw.
 template <bool MULTI>
 __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned long long lb,
                         unsigned int *gsub_list, unsigned int *flip, uint8_t *tag,
-                        unsigned int pass) {
+                        unsigned int pass, unsigned int *longw, unsigned int defer_hops) {
     const unsigned int nd = ctl->ndef;
     for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < nd + (unsigned)g.njobs;
          k += gridDim.x * blockDim.x) {
@@ -1129,6 +1133,10 @@ __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned lon
             const unsigned int t = def[k];
             const unsigned long long l = g.lab[t];
             if (l > lb) continue;
+            if (defer_hops && lhops(l) > defer_hops) {
+                longw[atomicAdd(&ctl->nlong, 1u)] = k;
+                continue;
+            }
             start = t;
             key = ((unsigned long long)ldist(l) << 32) | t;
             job = MULTI ? job_of_node(g, t) : 0;
@@ -1159,6 +1167,203 @@ __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned lon
         tag[root] = (uint8_t)pass;
         const unsigned long long old = atomicMin(&g.best[root], key);
         if (gsub && old == LINF) gsub_list[J.aoff + atomicAdd(&G.gsub_count, 1u)] = (unsigned int)root;
+    }
+}
+
+// The same walks with one wave per walk, for passes that settle few
+// deficits: their walks are few but long (up to the pass's hop bound), and a
+// walk of one thread waits a memory round trip per step.  The wave stages
+// the RW_H x RW_W region of its job that holds the current node (regions
+// aligned to multiples of that shape) in LDS, from one coalesced read of the
+// labels' low words: per node the region index of its predecessor, or
+// RW_OUT with the predecessor's direction when the predecessor lies outside
+// the region or the job (or the node is a root).  A step inside the region
+// is one LDS read; the nodes passed are kept one per lane (their region
+// index) and offered their key and tag 64 at a time and before the next
+// region.  Every value the walk branches on is the same in all lanes.
+constexpr int RW_H = 64, RW_W = 64;
+constexpr unsigned int RW_OUT = 0x8000u;
+constexpr int ROOTS_WAVE_MAX = 1024;  // walks (deficits + grounds) that all take this kernel
+constexpr unsigned int RW_SHORT = 16;  // walks of at most this many arcs take one lane
+constexpr unsigned int RW_LONG = 64;   // in larger passes, walks of more arcs take a wave
+constexpr int ROOTS_WAVE_GRID = 1024;  // workgroups of the wave walk over the long walks
+
+__device__ __forceinline__ void stage_region(const Graph &g, const Job &J, int ri0, int rj0, uint16_t *sd) {
+    const int lane = threadIdx.x & 63;
+    const unsigned int *lo = reinterpret_cast<const unsigned int *>(g.lab);
+    // rows and columns past the job's edge read its last row or column (in
+    // bounds; a walk never steps there)
+    const long long col = J.noff + min(rj0 + lane, J.C - 1);
+    unsigned int w[RW_H];
+#pragma unroll
+    for (int r = 0; r < RW_H; ++r) w[r] = lo[2 * (col + (long long)min(ri0 + r, J.R - 1) * J.C)];
+    // the wave's reads of the previous region have completed (each was
+    // waited for before its step branched on it)
+    asm volatile("" ::: "memory");
+    // a node's code: RW_OUT | dir when it is a root (dir 0) or its
+    // predecessor lies past the region's or the job's edge (bit dir of the
+    // exit mask), else its predecessor's region index (index + the offset
+    // for dir, one signed byte per direction in RW_STEP)
+    const int rmax = min(RW_H, J.R - ri0), cmax = min(RW_W, J.C - rj0);
+    const unsigned int lane_exit = 1u | (lane == 0 ? 1u << DIR_LEFT : 0u) | (lane == cmax - 1 ? 0xf0u : 0u);
+    constexpr unsigned long long RW_STEP = 0x01010101ff40c000ull;  // 0, -64, +64, -1, +1, +1, +1, +1
+    static_assert(RW_W == 64, "RW_STEP holds the row offset of 64-column regions");
+#pragma unroll
+    for (int r = 0; r < RW_H; ++r) {
+        const unsigned int dir = w[r] & 7u;
+        const unsigned int ex = lane_exit | (r == 0 ? 1u << DIR_UP : 0u) | (r == rmax - 1 ? 1u << DIR_DOWN : 0u);
+        const int off = (int)(signed char)(unsigned char)(RW_STEP >> (8u * dir));
+        const unsigned int e = (ex >> dir) & 1u, in = (unsigned int)(r * RW_W + lane + off);
+        sd[r * RW_W + lane] = (uint16_t)(in + e * ((RW_OUT | dir) - in));  // a select without a branch
+    }
+    asm volatile("" ::: "memory");
+}
+
+__device__ long long walk_root_wave(const Graph &g, const Job &J, const GState &G, Ctl *ctl, long long v,
+                                    int gsrc, int *gsub, unsigned long long key, int *crossed, uint8_t *tag,
+                                    uint8_t stamp, uint16_t *sd) {
+    const int lane = threadIdx.x & 63;
+    *gsub = 0;
+    *crossed = 0;
+    const long long limit = (long long)J.R * J.C + 2;
+    int i, j;
+    node_rc(J, v, i, j);
+    int mine = 0;  // region index of a node passed, one per lane
+    int np = 0;
+    long long steps = 0, res = -1;
+    bool broken = false;
+    for (;;) {
+        const int ri0 = i & ~(RW_H - 1), rj0 = j & ~(RW_W - 1);
+        // key and tag to the np nodes passed in this region
+        auto offer = [&]() {
+            if (lane < np) {
+                const long long u = J.noff + (long long)(ri0 + mine / RW_W) * J.C + rj0 + mine % RW_W;
+                atomicMin(&g.best[u], key);
+                tag[u] = stamp;
+            }
+            steps += np;
+            np = 0;
+            broken = broken || steps > limit;
+        };
+        stage_region(g, J, ri0, rj0, sd);
+        int li = (i - ri0) * RW_W + (j - rj0);
+        unsigned int code;
+        for (;;) {
+            code = (unsigned int)__builtin_amdgcn_readfirstlane((int)sd[li]);
+            if (code & RW_OUT) break;
+            mine = lane == np ? li : mine;
+            if (++np == 64) {
+                offer();
+                if (broken) break;
+            }
+            li = (int)code;
+        }
+        if (broken) break;
+        const int dir = (int)(code & 7u);
+        i = ri0 + li / RW_W;
+        j = rj0 + li % RW_W;
+        v = J.noff + (long long)i * J.C + j;
+        if (dir == DIR_NONE) {
+            offer();
+            res = v;
+            break;
+        }
+        int ui = i, uj = j;
+        bool ground;
+        switch (dir) {
+            case DIR_UP: ui = i - 1; ground = i == 0; break;
+            case DIR_DOWN: ui = i + 1; ground = i == J.R - 1; break;
+            case DIR_LEFT: uj = j - 1; ground = j == 0; break;
+            default: uj = j + 1; ground = j == J.C - 1; break;
+        }
+        if (ground) {
+            if (gsrc) {
+                offer();
+                *gsub = 1;
+                res = v;
+                break;
+            }
+            const unsigned int a = G.gpred;
+            if (a >= 2u * J.C + 2u * J.R) {  // no ground predecessor: reported below
+                offer();
+                break;
+            }
+            int kind, delta;
+            long long e;
+            ground_arc(J, a, ui, uj, kind, e, delta);
+            *crossed = 1;
+        }
+        mine = lane == np ? li : mine;
+        ++np;
+        offer();
+        if (broken) break;
+        i = ui;
+        j = uj;
+    }
+    if (res < 0 && lane == 0) atomicOr(&ctl->error, ERR_WALK);
+    return res;
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_roots_wave(Graph g, Ctl *ctl, const unsigned int *def,
+                                                    unsigned long long lb, unsigned int *gsub_list,
+                                                    unsigned int *flip, uint8_t *tag, unsigned int pass,
+                                                    const unsigned int *longw) {
+    __shared__ uint16_t sdir[4][RW_H * RW_W];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const unsigned int nd = ctl->ndef;
+    // every walk of the pass, or (longw) the long walks k_roots left
+    const unsigned int items = longw ? ctl->nlong : nd + (unsigned)g.njobs;
+    for (unsigned int q = blockIdx.x * 4u + wv; q < items; q += gridDim.x * 4u) {
+        const unsigned int k = longw ? longw[q] : q;
+        long long start;
+        unsigned long long key;
+        unsigned int hops;  // arcs from the root
+        int job;
+        if (k < nd) {
+            const unsigned int t = def[k];
+            const unsigned long long l = g.lab[t];
+            if (l > lb) continue;
+            hops = lhops(l);
+            start = t;
+            key = ((unsigned long long)ldist(l) << 32) | t;
+            job = MULTI ? job_of_node(g, t) : 0;
+        } else {
+            job = (int)(k - nd);
+            const GState &G = g.gs[job];
+            const unsigned long long gl = G.glab;
+            if (!(G.gex < 0 && gl <= lb)) continue;
+            const Job J = job_at<MULTI>(g, job);
+            if (G.gpred >= 2u * J.C + 2u * J.R) {
+                if (lane == 0) atomicOr(&ctl->error, ERR_WALK);
+                continue;
+            }
+            int pi, pj, kind, delta;
+            long long e;
+            ground_arc(J, G.gpred, pi, pj, kind, e, delta);
+            start = J.noff + (long long)pi * J.C + pj;
+            key = ((unsigned long long)ldist(gl) << 32) | (unsigned long long)(g.N + job);
+            hops = lhops(gl);
+        }
+        const Job J = job_at<MULTI>(g, job);
+        GState &G = g.gs[job];
+        int gsub = 0, crossed = 0;
+        long long root = -1;
+        if (hops > RW_SHORT) {
+            root = walk_root_wave(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass,
+                                  sdir[wv]);
+        } else if (lane == 0) {
+            // a short walk: fewer memory round trips than staging a region takes
+            root = walk_root(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass);
+        }
+        if (lane == 0) {
+            if (k < nd) flip[start] = (pass << 3) | (crossed ? 4u : 0u);
+            if (root >= 0) {
+                tag[root] = (uint8_t)pass;
+                const unsigned long long old = atomicMin(&g.best[root], key);
+                if (gsub && old == LINF) gsub_list[J.aoff + atomicAdd(&G.gsub_count, 1u)] = (unsigned int)root;
+            }
+        }
     }
 }
 
@@ -1273,33 +1478,33 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 }
 
 // pot(v) += B - d(v) on every reached node, labels and path tags back to
-// infinity, and the arc into every node of a chosen path flipped.  Each
-// workgroup checks the stamps of POT_CHUNK tiles at once and then updates
-// only the tiles relaxed in this pass, so that a pass that reached a few
-// tiles costs little more than one read of the stamps.  The relaxed tiles
-// of a pass lie close together, so chunks are kept small: a workgroup
-// updates at most POT_CHUNK tiles one after another.  A counting solve also
-// adds up the settled nodes and their residual out-arcs (the work of a
-// textbook search that settles the same nodes).
-constexpr int POT_CHUNK = 8;
+// infinity, and the arc into every node of a chosen path flipped.  A grid
+// of at most POT_GRID workgroups reads every tile's stamp once (workgroup w
+// owns the tiles w, w + G, w + 2G, ... of a grid of G, all read in one
+// batch while there are at most 256 of them) and updates only the tiles
+// relaxed in this pass, so that a pass that reached a few tiles costs one
+// small launch and one read of the stamps.  The relaxed tiles of a pass lie
+// close together, and the stride spreads neighbouring tiles over different
+// workgroups.  A counting solve also adds up the settled nodes and their
+// residual out-arcs (the work of a textbook search that settles the same
+// nodes).
+constexpr int POT_GRID = 2048;
 
 template <bool MULTI, int TW>
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
                                                     unsigned int pass, unsigned int NT,
                                                     unsigned long long lb, const unsigned int *flip,
                                                     const uint8_t *tag, int count, int pot_limit) {
-    __shared__ unsigned int todo[POT_CHUNK];
+    __shared__ unsigned int todo[256];
     __shared__ int ntodo;
     const unsigned int bound = ldist(lb);
     int mx = 0;
     unsigned long long n_set = 0, n_arc = 0, n_flip = 0;
-    for (unsigned int base = blockIdx.x * POT_CHUNK; base < NT; base += gridDim.x * POT_CHUNK) {
+    for (unsigned long long base = blockIdx.x; base < NT; base += 256ull * gridDim.x) {
         if (threadIdx.x == 0) ntodo = 0;
         __syncthreads();
-        if (threadIdx.x < POT_CHUNK) {
-            const unsigned int tile = base + threadIdx.x;
-            if (tile < NT && tstamp[tile] == pass) todo[atomicAdd(&ntodo, 1)] = tile;
-        }
+        const unsigned long long tile = base + (unsigned long long)threadIdx.x * gridDim.x;
+        if (tile < NT && tstamp[tile] == pass) todo[atomicAdd(&ntodo, 1)] = (unsigned int)tile;
         __syncthreads();
         const int nt = ntodo;
         for (int k = 0; k < nt; ++k) {
@@ -1990,7 +2195,7 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         per_cu = 4;
     (void)hipGetLastError();
     const int round_grid = (int)std::min<long long>(NT, (long long)ncu * per_cu);
-    const int pot_grid = (int)std::min<unsigned int>((NT + POT_CHUNK - 1) / POT_CHUNK, 16384u);
+    const int pot_grid = (int)std::min<unsigned int>(NT, (unsigned int)POT_GRID);
     unsigned long long nbatch = 0;  // round batches so far (their parity picks the window-end slot)
     int wslot = 0;
     unsigned int rr = 1, pass = 0;  // next round, current pass
@@ -2160,8 +2365,19 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             hipLaunchKernelGGL(k_ground_pred, dim3(pg, nj), dim3(SB), 0, st, g, lb);
             WW_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb, gsub_list,
-                           flip, tag, pass);
+        // few walks: one wave each; more: one thread each, the long ones
+        // (listed in def2, free until the compaction) one wave each
+        if (nd_h + nj <= ROOTS_WAVE_MAX) {
+            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)ceil_div(nd_h + nj, 4)), dim3(SB), 0, st, g, ctl,
+                               def, lb, gsub_list, flip, tag, pass, (const unsigned int *)nullptr);
+        } else {
+            hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb,
+                               gsub_list, flip, tag, pass, def2, RW_LONG);
+            WW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)std::min<long long>(ROOTS_WAVE_GRID, ceil_div(nd_h, 4))),
+                               dim3(SB), 0, st, g, ctl, def, lb, gsub_list, flip, tag, pass,
+                               (const unsigned int *)def2);
+        }
         WW_LAUNCH_CHECK();
         if (ground_source) {
             hipLaunchKernelGGL(k_gsub_select, dim3(pg, nj), dim3(SB), 0, st, g, gsub_list, drop);
