@@ -1170,36 +1170,36 @@ __global__ void k_roots(Graph g, Ctl *ctl, const unsigned int *def, unsigned lon
     }
 }
 
-// The same walks with one wave per walk, for passes that settle few
-// deficits: their walks are few but long (up to the pass's hop bound), and a
-// walk of one thread waits a memory round trip per step.  The wave stages
-// the RW_H x RW_W region of its job that holds the current node (regions
-// aligned to multiples of that shape) in LDS, from one coalesced read of the
-// labels' low words: per node the region index of its predecessor, or
-// RW_OUT with the predecessor's direction when the predecessor lies outside
-// the region or the job (or the node is a root).  A step inside the region
-// is one LDS read; the nodes passed are kept one per lane (their region
-// index) and offered their key and tag 64 at a time and before the next
-// region.  Every value the walk branches on is the same in all lanes.
+// The same walks with one workgroup per walk, for the long walks: a walk of
+// one thread waits a memory round trip per step.  The workgroup stages an
+// RW_H x RW_W region of the walk's job in LDS around the current node (at
+// the start centred on it, later with the node near the edge the walk came
+// in through; clamped to the job), from one coalesced read of the labels' low words
+// shared by its four waves: per node the region index of its predecessor,
+// or RW_OUT with the predecessor's direction when the predecessor lies
+// outside the region or the job (or the node is a root).  A step inside the
+// region is one LDS read.  All four waves take every step (the same values,
+// so that they meet at the barriers around each staging); wave 0 keeps the
+// nodes passed one per lane (their region index) and offers them their key
+// and tag 64 at a time and before the next region.
 constexpr int RW_H = 64, RW_W = 64;
+constexpr int RW_WAVES = 4;            // waves per walk (rows staged: RW_H / RW_WAVES each)
 constexpr unsigned int RW_OUT = 0x8000u;
-constexpr int ROOTS_WAVE_MAX = 1024;  // walks (deficits + grounds) that all take this kernel
-constexpr unsigned int RW_SHORT = 16;  // walks of at most this many arcs take one lane
-constexpr unsigned int RW_LONG = 64;   // in larger passes, walks of more arcs take a wave
-constexpr int ROOTS_WAVE_GRID = 1024;  // workgroups of the wave walk over the long walks
+constexpr int ROOTS_WAVE_MAX = 1024;   // walks (deficits + grounds) that all take this kernel
+constexpr unsigned int RW_SHORT = 16;  // walks of at most this many arcs take one thread
+constexpr unsigned int RW_LONG = 64;   // in larger passes, walks of more arcs take a workgroup
+constexpr int ROOTS_WAVE_GRID = 1024;  // workgroups of the walk over the long walks
 
 __device__ __forceinline__ void stage_region(const Graph &g, const Job &J, int ri0, int rj0, uint16_t *sd) {
-    const int lane = threadIdx.x & 63;
+    constexpr int RPW = RW_H / RW_WAVES;
+    const int lane = threadIdx.x & 63, r0 = (int)(threadIdx.x >> 6) * RPW;
     const unsigned int *lo = reinterpret_cast<const unsigned int *>(g.lab);
     // rows and columns past the job's edge read its last row or column (in
     // bounds; a walk never steps there)
     const long long col = J.noff + min(rj0 + lane, J.C - 1);
-    unsigned int w[RW_H];
+    unsigned int w[RPW];
 #pragma unroll
-    for (int r = 0; r < RW_H; ++r) w[r] = lo[2 * (col + (long long)min(ri0 + r, J.R - 1) * J.C)];
-    // the wave's reads of the previous region have completed (each was
-    // waited for before its step branched on it)
-    asm volatile("" ::: "memory");
+    for (int r = 0; r < RPW; ++r) w[r] = lo[2 * (col + (long long)min(ri0 + r0 + r, J.R - 1) * J.C)];
     // a node's code: RW_OUT | dir when it is a root (dir 0) or its
     // predecessor lies past the region's or the job's edge (bit dir of the
     // exit mask), else its predecessor's region index (index + the offset
@@ -1209,34 +1209,38 @@ __device__ __forceinline__ void stage_region(const Graph &g, const Job &J, int r
     constexpr unsigned long long RW_STEP = 0x01010101ff40c000ull;  // 0, -64, +64, -1, +1, +1, +1, +1
     static_assert(RW_W == 64, "RW_STEP holds the row offset of 64-column regions");
 #pragma unroll
-    for (int r = 0; r < RW_H; ++r) {
+    for (int r = 0; r < RPW; ++r) {
+        const int rr = r0 + r;
         const unsigned int dir = w[r] & 7u;
-        const unsigned int ex = lane_exit | (r == 0 ? 1u << DIR_UP : 0u) | (r == rmax - 1 ? 1u << DIR_DOWN : 0u);
+        const unsigned int ex = lane_exit | (rr == 0 ? 1u << DIR_UP : 0u) | (rr == rmax - 1 ? 1u << DIR_DOWN : 0u);
         const int off = (int)(signed char)(unsigned char)(RW_STEP >> (8u * dir));
-        const unsigned int e = (ex >> dir) & 1u, in = (unsigned int)(r * RW_W + lane + off);
-        sd[r * RW_W + lane] = (uint16_t)(in + e * ((RW_OUT | dir) - in));  // a select without a branch
+        const unsigned int e = (ex >> dir) & 1u, in = (unsigned int)(rr * RW_W + lane + off);
+        sd[rr * RW_W + lane] = (uint16_t)(in + e * ((RW_OUT | dir) - in));  // a select without a branch
     }
-    asm volatile("" ::: "memory");
 }
 
 __device__ long long walk_root_wave(const Graph &g, const Job &J, const GState &G, Ctl *ctl, long long v,
                                     int gsrc, int *gsub, unsigned long long key, int *crossed, uint8_t *tag,
                                     uint8_t stamp, uint16_t *sd) {
     const int lane = threadIdx.x & 63;
+    const bool w0 = threadIdx.x < 64;  // the wave that offers
     *gsub = 0;
     *crossed = 0;
     const long long limit = (long long)J.R * J.C + 2;
     int i, j;
     node_rc(J, v, i, j);
-    int mine = 0;  // region index of a node passed, one per lane
+    int mine = 0;  // region index of a node passed, one per lane of wave 0
     int np = 0;
     long long steps = 0, res = -1;
     bool broken = false;
+    // where the current node sits in the next region: centred at the start
+    // and after the ground; else near the edge the walk came in through
+    int at_r = RW_H / 2, at_c = RW_W / 2;
     for (;;) {
-        const int ri0 = i & ~(RW_H - 1), rj0 = j & ~(RW_W - 1);
+        const int ri0 = max(0, min(i - at_r, J.R - RW_H)), rj0 = max(0, min(j - at_c, J.C - RW_W));
         // key and tag to the np nodes passed in this region
         auto offer = [&]() {
-            if (lane < np) {
+            if (w0 && lane < np) {
                 const long long u = J.noff + (long long)(ri0 + mine / RW_W) * J.C + rj0 + mine % RW_W;
                 atomicMin(&g.best[u], key);
                 tag[u] = stamp;
@@ -1245,13 +1249,18 @@ __device__ long long walk_root_wave(const Graph &g, const Job &J, const GState &
             np = 0;
             broken = broken || steps > limit;
         };
+        __syncthreads();  // every wave is done with the previous region
         stage_region(g, J, ri0, rj0, sd);
+        __syncthreads();
         int li = (i - ri0) * RW_W + (j - rj0);
         unsigned int code;
         for (;;) {
-            code = (unsigned int)__builtin_amdgcn_readfirstlane((int)sd[li]);
-            if (code & RW_OUT) break;
+            const int raw = sd[li];
+            // kept while the read is in flight; counted once the node is
+            // known to be passed
             mine = lane == np ? li : mine;
+            code = (unsigned int)__builtin_amdgcn_readfirstlane(raw);
+            if (code & RW_OUT) break;
             if (++np == 64) {
                 offer();
                 if (broken) break;
@@ -1270,13 +1279,17 @@ __device__ long long walk_root_wave(const Graph &g, const Job &J, const GState &
         }
         int ui = i, uj = j;
         bool ground;
+        at_r = RW_H / 2;
+        at_c = RW_W / 2;
         switch (dir) {
-            case DIR_UP: ui = i - 1; ground = i == 0; break;
-            case DIR_DOWN: ui = i + 1; ground = i == J.R - 1; break;
-            case DIR_LEFT: uj = j - 1; ground = j == 0; break;
-            default: uj = j + 1; ground = j == J.C - 1; break;
+            case DIR_UP: ui = i - 1; ground = i == 0; at_r = RW_H - 8; break;
+            case DIR_DOWN: ui = i + 1; ground = i == J.R - 1; at_r = 7; break;
+            case DIR_LEFT: uj = j - 1; ground = j == 0; at_c = RW_W - 8; break;
+            default: uj = j + 1; ground = j == J.C - 1; at_c = 7; break;
         }
         if (ground) {
+            at_r = RW_H / 2;
+            at_c = RW_W / 2;
             if (gsrc) {
                 offer();
                 *gsub = 1;
@@ -1300,21 +1313,20 @@ __device__ long long walk_root_wave(const Graph &g, const Job &J, const GState &
         i = ui;
         j = uj;
     }
-    if (res < 0 && lane == 0) atomicOr(&ctl->error, ERR_WALK);
+    if (res < 0 && threadIdx.x == 0) atomicOr(&ctl->error, ERR_WALK);
     return res;
 }
 
 template <bool MULTI>
-__global__ __launch_bounds__(256) void k_roots_wave(Graph g, Ctl *ctl, const unsigned int *def,
-                                                    unsigned long long lb, unsigned int *gsub_list,
-                                                    unsigned int *flip, uint8_t *tag, unsigned int pass,
-                                                    const unsigned int *longw) {
-    __shared__ uint16_t sdir[4][RW_H * RW_W];
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+__global__ __launch_bounds__(64 * RW_WAVES) void k_roots_wave(Graph g, Ctl *ctl, const unsigned int *def,
+                                                              unsigned long long lb, unsigned int *gsub_list,
+                                                              unsigned int *flip, uint8_t *tag, unsigned int pass,
+                                                              const unsigned int *longw) {
+    __shared__ uint16_t sdir[RW_H * RW_W];
     const unsigned int nd = ctl->ndef;
     // every walk of the pass, or (longw) the long walks k_roots left
     const unsigned int items = longw ? ctl->nlong : nd + (unsigned)g.njobs;
-    for (unsigned int q = blockIdx.x * 4u + wv; q < items; q += gridDim.x * 4u) {
+    for (unsigned int q = blockIdx.x; q < items; q += gridDim.x) {
         const unsigned int k = longw ? longw[q] : q;
         long long start;
         unsigned long long key;
@@ -1335,7 +1347,7 @@ __global__ __launch_bounds__(256) void k_roots_wave(Graph g, Ctl *ctl, const uns
             if (!(G.gex < 0 && gl <= lb)) continue;
             const Job J = job_at<MULTI>(g, job);
             if (G.gpred >= 2u * J.C + 2u * J.R) {
-                if (lane == 0) atomicOr(&ctl->error, ERR_WALK);
+                if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_WALK);
                 continue;
             }
             int pi, pj, kind, delta;
@@ -1350,13 +1362,12 @@ __global__ __launch_bounds__(256) void k_roots_wave(Graph g, Ctl *ctl, const uns
         int gsub = 0, crossed = 0;
         long long root = -1;
         if (hops > RW_SHORT) {
-            root = walk_root_wave(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass,
-                                  sdir[wv]);
-        } else if (lane == 0) {
+            root = walk_root_wave(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass, sdir);
+        } else if (threadIdx.x == 0) {
             // a short walk: fewer memory round trips than staging a region takes
             root = walk_root(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass);
         }
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             if (k < nd) flip[start] = (pass << 3) | (crossed ? 4u : 0u);
             if (root >= 0) {
                 tag[root] = (uint8_t)pass;
@@ -2365,17 +2376,17 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             hipLaunchKernelGGL(k_ground_pred, dim3(pg, nj), dim3(SB), 0, st, g, lb);
             WW_LAUNCH_CHECK();
         }
-        // few walks: one wave each; more: one thread each, the long ones
-        // (listed in def2, free until the compaction) one wave each
+        // few walks: one workgroup each; more: one thread each, the long
+        // ones (listed in def2, free until the compaction) one workgroup each
         if (nd_h + nj <= ROOTS_WAVE_MAX) {
-            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)ceil_div(nd_h + nj, 4)), dim3(SB), 0, st, g, ctl,
-                               def, lb, gsub_list, flip, tag, pass, (const unsigned int *)nullptr);
+            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)(nd_h + nj)), dim3(64 * RW_WAVES), 0, st, g,
+                               ctl, def, lb, gsub_list, flip, tag, pass, (const unsigned int *)nullptr);
         } else {
             hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb,
                                gsub_list, flip, tag, pass, def2, RW_LONG);
             WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)std::min<long long>(ROOTS_WAVE_GRID, ceil_div(nd_h, 4))),
-                               dim3(SB), 0, st, g, ctl, def, lb, gsub_list, flip, tag, pass,
+            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)std::min<long long>(ROOTS_WAVE_GRID, nd_h)),
+                               dim3(64 * RW_WAVES), 0, st, g, ctl, def, lb, gsub_list, flip, tag, pass,
                                (const unsigned int *)def2);
         }
         WW_LAUNCH_CHECK();
