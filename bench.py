@@ -10,7 +10,7 @@ and phi; the cost table is cached per L, as the library always does.
 Prints one JSON line: Mpixel/s, the roofline of the dominant kernel (the
 tile relaxation rounds of the shortest-path search; algorithmic bytes =
 tile visits x bytes one visit must move, over the rounds' device time
-measured with HIP events inside the library on the solve's stream) and the
+measured inside the library on the device clock, batch by batch) and the
 CPU oracle timed on a bounded sample of the same scene.
 """
 from __future__ import annotations
@@ -44,9 +44,9 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "fault_6912x10752_L15_cost.json")
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 1 GiB copy's readings
 # (fetch x 2.0, write x 1.0), valid for the round-kernel source of that hash
 # (see round_kernel_sha) and the solve schedule they were taken with only.
-TRAFFIC_SOURCE_SHA = "35702ae99af0f0ee"
+TRAFFIC_SOURCE_SHA = "027a9462dcaf84a4"
 TRAFFIC_SCHEDULE = (64, 256, 4, 0, 1024, 6, 32)
-TRAFFIC_BYTES_PER_LAUNCH = 14.48e6
+TRAFFIC_BYTES_PER_LAUNCH = 14.40e6
 
 
 def round_kernel_sha() -> str:

@@ -44,7 +44,6 @@ struct Workspace {
     size_t host_bytes = 0;
     void *mirror = nullptr;  // coherent pinned block the device writes counters into
     size_t mirror_bytes = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t wait_ev = nullptr;  // marks the point a host wait returns at
     ww_mcf_stats stats{};
 };
@@ -65,8 +64,6 @@ void workspace_destroy(Workspace *ws) {
         if (b.ptr) (void)hipFree(b.ptr);
     if (ws->host) (void)hipHostFree(ws->host);
     if (ws->mirror) (void)hipHostFree(ws->mirror);
-    for (auto &e : ws->ev)
-        if (e) (void)hipEventDestroy(e);
     if (ws->wait_ev) (void)hipEventDestroy(ws->wait_ev);
     delete ws;
 }
@@ -158,15 +155,6 @@ ww_status host_mirror(size_t bytes, void **out) {
         ws->mirror_bytes = bytes;
     }
     *out = ws->mirror;
-    return WW_OK;
-}
-
-ww_status workspace_events(hipEvent_t ev[4]) {
-    Workspace *ws = current_workspace();
-    for (int k = 0; k < 4; ++k) {
-        if (!ws->ev[k]) WW_HIP(hipEventCreate(&ws->ev[k]));
-        ev[k] = ws->ev[k];
-    }
     return WW_OK;
 }
 

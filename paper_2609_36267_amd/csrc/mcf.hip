@@ -89,6 +89,8 @@ struct Ctl {
     unsigned long long settled;   // work counters (counting solves only): nodes
     unsigned long long scanned;   // settled and their residual out-arcs
     unsigned int nlong;           // long walks left to the wave walk (this pass)
+    unsigned long long t_batch;   // device clock at the start of the current batch of rounds
+    unsigned long long relax_ticks;  // device clock ticks spent in batches of rounds
 };
 constexpr size_t CTL_BYTES = (sizeof(Ctl) + 63) / 64 * 64;
 
@@ -563,7 +565,7 @@ constexpr int VISIT_ITERS = WW_VISIT_ITERS;  // sweeps per tile visit at most
 template <bool MULTI, int TW>
 __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs ra,
                                                    unsigned int round, unsigned int pass_stamp,
-                                                   unsigned long long lb, int stats) {
+                                                   unsigned long long lb, int stats, int batch_start) {
     constexpr int TH = TILE_NODES / TW;  // tile rows
     __shared__ unsigned long long L[TH + 2][TW + 3];
     __shared__ int P[TH + 2][TW + 2];
@@ -574,6 +576,9 @@ __global__ __launch_bounds__(256) void k_sssp_round(Graph g, Ctl *ctl, RoundArgs
     __shared__ int sh_any;
     __shared__ unsigned long long sh_gcand, sh_rej;
 
+    // the first round of a batch stamps its start on the device clock (the
+    // window-end count that follows the batch adds up the span)
+    if (batch_start && blockIdx.x == 0 && threadIdx.x == 0) ctl->t_batch = (unsigned long long)wall_clock64();
     const unsigned int NT = ra.NT;
     const unsigned int *list = ra.lists + (size_t)(round % 3) * list_stride(NT);
     // the first entry is read together with the length (the slot lies inside
@@ -973,6 +978,7 @@ __global__ void k_window_end(Graph g, Ctl *ctl, const unsigned int *def, unsigne
                              const unsigned long long *tile_rej, unsigned int NT, int w,
                              unsigned int rr) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->relax_ticks += (unsigned long long)wall_clock64() - ctl->t_batch;
         ctl->wsettled[w ^ 1] = 0;
         ctl->wminrej[w ^ 1] = LINF;
     }
@@ -1928,8 +1934,6 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     last_mcf_stats() = S;
     const auto t_start = std::chrono::steady_clock::now();
     const int nj = (int)mj.size();
-    hipEvent_t ev[4];  // timing pairs (0, 1) and (2, 3), by batch parity
-    WW_TRY(workspace_events(ev));
     // job layout: nodes, tiles, perimeter tiles and ground-subtree slots
     std::vector<Job> jobs(nj);
     std::vector<unsigned int> ptiles;
@@ -2099,24 +2103,6 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         if (h->error) return decode_error(h->error);
         return WW_OK;
     };
-    // The rounds' time of each batch, timed by a pair of events and added
-    // to relax_ms once the next batch is queued (or at the end), so that
-    // reading it never delays the next launch.
-    int pending_pair = -1;
-    auto add_pending_time = [&]() -> ww_status {
-        if (pending_pair < 0) return WW_OK;
-        hipEvent_t e0 = ev[2 * pending_pair], e1 = ev[2 * pending_pair + 1];
-        float ms = 0.f;
-        hipError_t ee = hipEventElapsedTime(&ms, e0, e1);
-        if (ee == hipErrorNotReady) {
-            WW_HIP(hipEventSynchronize(e1));
-            ee = hipEventElapsedTime(&ms, e0, e1);
-        }
-        WW_HIP(ee);
-        S.relax_ms += ms;
-        pending_pair = -1;
-        return WW_OK;
-    };
     // units still to route: supplies plus the grounds' surplus
     auto ground_surplus = [&]() {
         long long s = 0;
@@ -2204,6 +2190,9 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sssp_round<MULTI, TW>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 4;
+    int clock_khz = 0;  // rate of the device clock that times the rounds
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || clock_khz < 1)
+        clock_khz = 100000;
     (void)hipGetLastError();
     const int round_grid = (int)std::min<long long>(NT, (long long)ncu * per_cu);
     const int pot_grid = (int)std::min<unsigned int>(NT, (unsigned int)POT_GRID);
@@ -2264,15 +2253,12 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             ++S.windows;
             const long long rw0 = S.rounds;
             for (;;) {  // rounds
-                const int tp = (int)(nbatch & 1);  // this batch's timing pair
-                WW_HIP(hipEventRecord(ev[2 * tp], st));
                 for (int k = 0; k < rounds_per_sync; ++k) {
                     hipLaunchKernelGGL((k_sssp_round<MULTI, TW>), dim3(round_grid), dim3(256), 0, st, g, ctl, ra,
-                                       rr, pass, lb, trace ? 1 : 0);
+                                       rr, pass, lb, trace ? 1 : 0, k == 0 ? 1 : 0);
                     WW_LAUNCH_CHECK();
                     ++rr;
                 }
-                WW_HIP(hipEventRecord(ev[2 * tp + 1], st));
                 // the window-end counts after every batch, so that the batch
                 // that ends the window needs no further round trip (each run
                 // writes the slot of its batch parity and clears the other)
@@ -2280,10 +2266,6 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
                 hipLaunchKernelGGL(k_window_end, dim3(lgrid(std::max<long long>(nd_h, NT))), dim3(SB), 0,
                                    st, g, ctl, def, lb, ra.pstamp, pass, ra.tile_rej, NT, wslot, rr);
                 WW_LAUNCH_CHECK();
-                // the previous batch's time, read now that this batch is
-                // queued (its events are long done)
-                WW_TRY(add_pending_time());
-                pending_pair = tp;
                 S.rounds += rounds_per_sync;
                 if (S.rounds > 50000000)
                     return fail(WW_E_DEVICE, "min-cost flow: relaxation rounds exceeded the limit");
@@ -2468,7 +2450,9 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         WW_LAUNCH_CHECK();
     }
     WW_TRY(sync_ctl());
-    WW_TRY(add_pending_time());
+    // the rounds' time: batches timed on the device clock (timing events
+    // between the launches delayed the next kernel by several microseconds)
+    S.relax_ms = (double)h->relax_ticks / (double)clock_khz;
     for (int k = 0; k < nj; ++k) *mj[k].total = hg[k].total_cost;
     S.tile_visits = (long long)host_visits();
     long long mxp = h->max_pot;

@@ -72,8 +72,6 @@ ww_status host_scratch(size_t bytes, void **out);
 // Coherent pinned host block of the current workspace that kernels write
 // into directly (the solver's counters after each batch of rounds).
 ww_status host_mirror(size_t bytes, void **out);
-// Four timing events of the current workspace (two pairs, used by turns).
-ww_status workspace_events(hipEvent_t ev[4]);
 // Waits for all work queued on `st` so far (polls briefly, then blocks).
 ww_status wait_stream(hipStream_t st);
 // Serialises construction of the shared cost-table cache.
