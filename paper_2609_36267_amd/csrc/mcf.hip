@@ -1327,7 +1327,7 @@ template <bool MULTI>
 __global__ __launch_bounds__(64 * RW_WAVES) void k_roots_wave(Graph g, Ctl *ctl, const unsigned int *def,
                                                               unsigned long long lb, unsigned int *gsub_list,
                                                               unsigned int *flip, uint8_t *tag, unsigned int pass,
-                                                              const unsigned int *longw) {
+                                                              const unsigned int *longw, unsigned int short_hops) {
     __shared__ uint16_t sdir[RW_H * RW_W];
     const unsigned int nd = ctl->ndef;
     // every walk of the pass, or (longw) the long walks k_roots left
@@ -1367,7 +1367,7 @@ __global__ __launch_bounds__(64 * RW_WAVES) void k_roots_wave(Graph g, Ctl *ctl,
         GState &G = g.gs[job];
         int gsub = 0, crossed = 0;
         long long root = -1;
-        if (hops > RW_SHORT) {
+        if (hops > short_hops) {
             root = walk_root_wave(g, J, G, ctl, start, G.gex > 0, &gsub, key, &crossed, tag, (uint8_t)pass, sdir);
         } else if (threadIdx.x == 0) {
             // a short walk: fewer memory round trips than staging a region takes
@@ -2118,6 +2118,14 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
     const bool check = check_env && check_env[0] == '1';
     const char *count_env = getenv("WW_MCF_COUNT");
     const int count = (count_env && count_env[0] == '1') ? 1 : 0;
+    // how the root walks are taken (the results do not depend on it; tests
+    // compare the ways): by size (default), every walk by one thread
+    // (WW_MCF_ROOTS=t), or every walk by a workgroup (WW_MCF_ROOTS=w)
+    const char *roots_env = getenv("WW_MCF_ROOTS");
+    const char roots_mode = roots_env ? roots_env[0] : 'a';
+    const long long wave_max = roots_mode == 't' ? -1 : roots_mode == 'w' ? (1ll << 40) : ROOTS_WAVE_MAX;
+    const unsigned int short_hops = roots_mode == 'w' ? 0u : RW_SHORT;
+    const unsigned int defer_hops = roots_mode == 't' ? 0u : RW_LONG;
     // range guards (lowered only by tests of the error path): the largest
     // potential, and the largest distance bound of a window
     int pot_limit = POT_LIMIT;
@@ -2360,16 +2368,18 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
         }
         // few walks: one workgroup each; more: one thread each, the long
         // ones (listed in def2, free until the compaction) one workgroup each
-        if (nd_h + nj <= ROOTS_WAVE_MAX) {
-            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)(nd_h + nj)), dim3(64 * RW_WAVES), 0, st, g,
-                               ctl, def, lb, gsub_list, flip, tag, pass, (const unsigned int *)nullptr);
+        if (nd_h + nj <= wave_max) {
+            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)std::min<long long>(nd_h + nj, 1ll << 30)),
+                               dim3(64 * RW_WAVES), 0, st, g, ctl, def, lb, gsub_list, flip, tag, pass,
+                               (const unsigned int *)nullptr, short_hops);
         } else {
             hipLaunchKernelGGL(k_roots<MULTI>, dim3(lgrid(nd_h + nj)), dim3(SB), 0, st, g, ctl, def, lb,
-                               gsub_list, flip, tag, pass, def2, RW_LONG);
+                               gsub_list, flip, tag, pass, def2, defer_hops);
             WW_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)std::min<long long>(ROOTS_WAVE_GRID, nd_h)),
-                               dim3(64 * RW_WAVES), 0, st, g, ctl, def, lb, gsub_list, flip, tag, pass,
-                               (const unsigned int *)def2);
+            if (defer_hops)
+                hipLaunchKernelGGL(k_roots_wave<MULTI>, dim3((unsigned)std::min<long long>(ROOTS_WAVE_GRID, nd_h)),
+                                   dim3(64 * RW_WAVES), 0, st, g, ctl, def, lb, gsub_list, flip, tag, pass,
+                                   (const unsigned int *)def2, short_hops);
         }
         WW_LAUNCH_CHECK();
         if (ground_source) {

@@ -401,6 +401,60 @@ def test_mcf_long_paths(torch_cuda, kind, sched):
                                     "ground_demand": 150}[kind], r.stats
 
 
+def _many_long_walks_case():
+    """More than 1,024 supplies, one per row, with their demands 210 columns
+    away (an arc carries one unit each way, so every row gets its own path):
+    the first passes settle over a thousand deficits whose walks run for
+    hundreds of arcs (the walks a thread leaves to a workgroup)."""
+    rng = np.random.default_rng(21)
+    m, n = 1200, 240
+    res = np.zeros((m - 1, n - 1), np.int8)
+    res[20:1181, 14] = 1
+    res[20:1181, 224] = -1
+    costs = tuple(rng.integers(1, 60, sz).astype(np.int16)
+                  for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+    for c in costs:  # a costly rim keeps the paths off the ground
+        c[:4] = c[-4:] = 3000
+        c[:, :4] = c[:, -4:] = 3000
+    return res, costs, m, n
+
+
+@pytest.mark.parametrize("case", ["dipoles", "ground_supply", "ground_demand", "many_long", "random"])
+def test_mcf_root_walk_modes_identical(torch_cuda, monkeypatch, case):
+    """The root walks' results (each path node's smallest key, each root's
+    deficit) do not depend on who walks: one thread per walk, a workgroup
+    per walk through LDS-staged regions, or the default split by length
+    give the same flows, potentials and pass structure byte for byte, and
+    the oracle's optimal cost."""
+    if case == "many_long":
+        res, costs, m, n = _many_long_walks_case()
+    elif case == "random":
+        m, n = 130, 257
+        rng = np.random.default_rng(5)
+        psi = rng.uniform(-np.pi, np.pi, (m, n)).astype(np.float32)
+        res, _, _ = oracle.residues(psi)
+        costs = tuple(rng.integers(0, 3000, sz).astype(np.int16)
+                      for sz in ((m, n - 1), (m, n - 1), (m - 1, n), (m - 1, n)))
+    else:
+        res, costs, m, n = _long_path_case(case)
+    out = {}
+    for mode in ("a", "t", "w"):
+        monkeypatch.setenv("WW_MCF_ROOTS", mode)
+        r = ww.mcf_solve(res, costs, m, n, want_potentials=True)
+        out[mode] = (np_(r.dk_x), np_(r.dk_y), np_(r.potentials), r.total_cost, r.stats)
+    monkeypatch.delenv("WW_MCF_ROOTS")
+    a = out["a"]
+    for mode in ("t", "w"):
+        b = out[mode]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), mode
+        assert np.array_equal(a[2], b[2]) and a[3] == b[3], mode
+        for k in ("passes", "windows", "augmentations", "path_arcs"):
+            assert a[4][k] == b[4][k], (mode, k, a[4][k], b[4][k])
+    assert a[3] == oracle.mcf(res, costs, m=m, n=n)[3]
+    if case == "many_long":
+        assert a[4]["supplies"] > 1024 and a[4]["path_arcs"] > 1024 * 200, a[4]
+
+
 def test_mcf_degenerate_shapes(torch_cuda):
     for m, n in ((1, 1), (1, 12), (12, 1)):
         costs = (np.ones((m, max(n - 1, 0)), np.int16), np.ones((m, max(n - 1, 0)), np.int16),
