@@ -91,6 +91,7 @@ struct Ctl {
     unsigned int nlong;           // long walks left to the wave walk (this pass)
     unsigned long long t_batch;   // device clock at the start of the current batch of rounds
     unsigned long long relax_ticks;  // device clock ticks spent in batches of rounds
+    unsigned int compact_done;    // workgroups of the list compaction that have finished
 };
 constexpr size_t CTL_BYTES = (sizeof(Ctl) + 63) / 64 * 64;
 
@@ -1729,11 +1730,21 @@ __global__ void k_compact(Graph g, Ctl *ctl, const unsigned int *src, const unsi
         if (keep_s) src2[bs + __popcll(ms & below)] = v;
         if (keep_d) def2[bd + __popcll(md & below)] = v;
     }
-}
-
-__global__ void k_swap_lists(Ctl *ctl) {
-    ctl->nsrc = ctl->nsrc2;
-    ctl->ndef = ctl->ndef2;
+    // the last workgroup to finish makes the compacted lists current (their
+    // lengths; the host swaps the pointers): no launch of its own per pass
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&ctl->compact_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        ctl->nsrc = atomicAdd(&ctl->nsrc2, 0u);  // read at the device's coherence point
+        ctl->ndef = atomicAdd(&ctl->ndef2, 0u);
+        ctl->compact_done = 0;
+    }
 }
 
 // a[k] = -a[k] for k < n, 16 bytes per thread and step (SWAR negation of
@@ -2415,8 +2426,6 @@ static ww_status solve(const std::vector<McfJob> &mj, const int8_t *res_all, int
             }
         }
         hipLaunchKernelGGL(k_compact, dim3(lgrid(ns_h + nd_h)), dim3(SB), 0, st, g, ctl, src, def, src2, def2);
-        WW_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_swap_lists, dim3(1), dim3(1), 0, st, ctl);
         WW_LAUNCH_CHECK();
         std::swap(src, src2);
         std::swap(def, def2);
