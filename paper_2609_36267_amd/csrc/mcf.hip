@@ -1506,7 +1506,7 @@ __global__ void k_augment(Graph g, Ctl *ctl, const unsigned int *src, const unsi
 // workgroups.  A counting solve also adds up the settled nodes and their
 // residual out-arcs (the work of a textbook search that settles the same
 // nodes).
-constexpr int POT_GRID = 2048;
+constexpr int POT_GRID = 1024;
 
 template <bool MULTI, int TW>
 __global__ __launch_bounds__(256) void k_potentials(Graph g, Ctl *ctl, const unsigned int *tstamp,
