@@ -124,6 +124,31 @@ def test_batch_schedules_and_checks(torch_cuda, scenes, certs, sched, monkeypatc
         check_batch_job(sc, cert, K, phi, tot)
 
 
+@pytest.mark.parametrize("sched", [None, (64, 256, 4, 0, 1024, 8)])
+def test_batch_root_walk_modes_identical(torch_cuda, scenes, certs, sched, monkeypatch):
+    """One solve over all jobs with the root walks taken by one thread each
+    (WW_MCF_ROOTS=t), by a workgroup each (w) and split by length (the
+    default): every job's K, phi and cost byte-identical across the three,
+    and the oracle's optimum."""
+    torch = torch_cuda
+    jobs = [(torch.from_numpy(sc.psi).cuda(), torch.from_numpy(sc.coh).cuda(),
+             torch.from_numpy(sc.valid).cuda(), sc.looks) for sc in scenes]
+    out = {}
+    for mode in ("a", "t", "w"):
+        monkeypatch.setenv("WW_MCF_ROOTS", mode)
+        results, arr = ww.unwrap_batch(jobs, sched=sched)
+        assert all(j.status == 0 for j in arr), mode
+        out[mode] = [(K.cpu().numpy(), phi.cpu().numpy(), tot) for K, phi, tot in results]
+    monkeypatch.delenv("WW_MCF_ROOTS")
+    for mode in ("t", "w"):
+        for (Ka, pa, ta), (Kb, pb, tb) in zip(out["a"], out[mode]):
+            assert ta == tb, mode
+            assert np.array_equal(Ka, Kb), mode
+            assert same_phi(pa, pb), mode
+    for sc, cert, (K, phi, tot) in zip(scenes, certs, out["a"]):
+        check_batch_job(sc, cert, K, phi, tot)
+
+
 def test_batch_stack_of_many_jobs(torch_cuda):
     """24 jobs of the stack recipe at reduced size (rows 64-300, cols
     64-420, L in {5, 9, 15}) in one solve, host-side arrays for every third:
