@@ -1194,7 +1194,7 @@ constexpr int RW_WAVES = 4;            // waves per walk (rows staged: RW_H / RW
 constexpr unsigned int RW_OUT = 0x8000u;
 constexpr int ROOTS_WAVE_MAX = 1024;   // walks (deficits + grounds) that all take this kernel
 constexpr unsigned int RW_SHORT = 16;  // walks of at most this many arcs take one thread
-constexpr unsigned int RW_LONG = 64;   // in larger passes, walks of more arcs take a workgroup
+constexpr unsigned int RW_LONG = 32;   // in larger passes, walks of more arcs take a workgroup
 constexpr int ROOTS_WAVE_GRID = 1024;  // workgroups of the walk over the long walks
 
 __device__ __forceinline__ void stage_region(const Graph &g, const Job &J, int ri0, int rj0, uint16_t *sd) {
